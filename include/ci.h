@@ -1,0 +1,223 @@
+/*
+ * ci.h -- C ABI of the MI355X (gfx950) batched matched-filter library.
+ *
+ * The library runs the per-template search loop of Bosi, "cuInspiral"
+ * (arXiv:1006.4644), section "Matched filtering": for every template of a
+ * bank, generate the chirp, correlate it with one data chunk through the
+ * coloured-noise inner product of eq. (matchedfilter), combine both
+ * quadratures, keep the maxima above a threshold, and reduce the candidates
+ * of all templates to local maxima.  The function split follows the
+ * section "Pipeline main details":
+ *
+ *   ci_make_bank        bank file + host_template_init     (host only)
+ *   ci_gen_templates    device_template_init + device_template_proc
+ *   ci_matched_filter   device_complex_mf + device_cufft_C2R + device_madd2
+ *   ci_find_triggers    device_maxfind + the clusterization step
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Every call returns an int32 status (CI_OK or a negative CI_E* code).
+ *   Argument and shape errors are detected synchronously and leave a
+ *   message readable through ci_last_error().  HIP launch failures map to
+ *   CI_EHIP.
+ * - GPU work is enqueued asynchronously on the caller's hipStream_t (passed
+ *   as void*; NULL means the default stream).  The library never
+ *   synchronises the stream itself; results are valid after the caller
+ *   synchronises.
+ * - The caller owns every buffer it passes.  No call keeps a caller pointer
+ *   after it returns.  The library owns only ci_ctx and ci_segment objects
+ *   and their device workspaces, released by the matching *_destroy call.
+ * - "d_" arguments are device pointers (hipMalloc'd or torch CUDA tensors);
+ *   "host" arguments are host pointers.
+ * - One ci_ctx per host thread.  Calls that share a ctx must not overlap.
+ * - Frequencies f_k = k fs/n, k = 0..n/2; df = fs/n; T = n/fs.
+ * - Spectra are one-sided.  The inner product is
+ *   <a, b> = 4 Re sum_k df a_k conj(b_k) / S_k (eq. (matchedfilter) taken at
+ *   positive frequencies), summed over the template band
+ *   k_low = ceil(f_low T) <= k <= k_high = min(floor(f_isco T), n/2 - 1),
+ *   f_isco = 1 / (6^{3/2} pi M).
+ */
+#ifndef CI_H
+#define CI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define CI_OK 0
+#define CI_EINVAL (-1)        /* bad argument or shape                     */
+#define CI_ENOMEM (-2)        /* device or host allocation failed          */
+#define CI_EHIP (-3)          /* a HIP runtime call or launch failed       */
+#define CI_ETRUNC (-4)        /* reserved: a host-visible capacity overflow */
+#define CI_EUNSUPPORTED (-5)  /* valid request this build does not handle  */
+
+/* arithmetic of the inverse transform */
+#define CI_FP32 0        /* FP32 VALU butterflies, FP32 intermediate       */
+#define CI_SPLIT_BF16 1  /* reserved: split-BF16 DFT-matrix stages (MFMA)  */
+#define CI_SPLIT_FP16 2  /* reserved: split-FP16 DFT-matrix stages (MFMA)  */
+
+/* bank kinds for ci_make_bank */
+#define CI_BANK_GRID 0
+#define CI_BANK_UNIFORM 1
+#define CI_BANK_LOGUNIFORM 2
+
+/* template flags (ci_tparams.flags) */
+#define CI_TMPL_EMPTY 1  /* chirp ends below f_low: no band, no output     */
+
+typedef struct ci_ctx ci_ctx;          /* opaque: device, workspaces, last error */
+typedef struct ci_segment ci_segment;  /* opaque: one data chunk on one grid     */
+
+/* One point of the template bank, in solar masses.  The mass-space grid of
+ * the "Matched filtering" section: one (m1, m2)_i per template. */
+typedef struct {
+  double m1, m2;
+} ci_template;
+
+typedef struct {
+  int32_t kind;      /* CI_BANK_GRID | CI_BANK_UNIFORM | CI_BANK_LOGUNIFORM */
+  int32_t reserved;  /* must be 0 */
+  double m_min, m_max;
+  uint64_t seed;     /* ignored by CI_BANK_GRID */
+} ci_bank_spec;
+
+typedef struct {
+  int64_t n;         /* samples per chunk: a power of two, 2^16 .. 2^21 */
+  double fs;         /* sample rate, Hz */
+  double f_low;      /* lower frequency cutoff, Hz (1 <= ceil(f_low T) < n/2) */
+} ci_segment_spec;
+
+/* One trigger: sample index, rho^2 = |z|^2/sigma^2 and the complex SNR
+ * z/sigma at that sample (real part: the 0-phase quadrature correlator,
+ * imaginary part: the pi/2 quadrature).  32 bytes. */
+typedef struct {
+  int64_t tmpl;      /* bank index, -1 if none */
+  int64_t index;     /* sample index j in [0, n), -1 if none */
+  float rho2;
+  float re, im;
+  int32_t window;    /* index / W, -1 if none */
+} ci_trigger;
+
+/* Per-template generator constants (the paper's host_template_init output),
+ * device-resident, 96 bytes, plain old data.  Phase in revolutions:
+ *   Psi_k / (2 pi) = -1/8 + c0 u^5 + c2 u^3 + c3 u^2 + c4 u,
+ *   u = (x0 k)^{-1/3} = 1 / v_k,  v_k = (pi M f_k)^{1/3},
+ * the restricted 2PN stationary-phase chirp with t_c = phi_c = 0. */
+typedef struct ci_tparams {
+  double m1, m2;          /* canonical masses, m1 >= m2 */
+  double x0;              /* pi M df, M = (m1 + m2) G Msun / c^3 */
+  double c0, c2, c3, c4;  /* phase coefficients, revolutions */
+  double sigma2;          /* <h, h> of the unit-amplitude template */
+  double tau;             /* 2PN chirp duration from f_low, seconds */
+  float scale;            /* 4 df / (sigma g): g is the chunk's data scale */
+  int32_t k_low, k_high;  /* band; k_high < k_low for an empty template */
+  int32_t flags;          /* CI_TMPL_* */
+  int32_t reserved[2];
+} ci_tparams;
+
+/* --- context ------------------------------------------------------------ */
+
+/* Create a context bound to HIP device `device`.  *out receives the handle. */
+int ci_ctx_create(int device, ci_ctx** out);
+int ci_ctx_destroy(ci_ctx* ctx);
+
+/* Message of the last failed call on `ctx` (or, with ctx == NULL, of the
+ * last failed context-free call on this thread).  Valid until the next call. */
+const char* ci_last_error(const ci_ctx* ctx);
+
+/* Library version string. */
+const char* ci_version(void);
+
+/* --- bank (host only) ----------------------------------------------------
+ * The template grid of the "Matched filtering" section.  GRID: g = ceil(
+ * sqrt(n)) masses evenly spaced on [m_min, m_max], template t takes
+ * (m[t / g], m[t % g]).  UNIFORM / LOGUNIFORM: m1 and m2 of template t are
+ * draws 2t and 2t+1 of the counter-based SplitMix64 generator (Steele, Lea
+ * & Flood 2014): u = (mix(seed + (i+1) 0x9E3779B97F4A7C15) >> 11) 2^-53,
+ * m = m_min + u (m_max - m_min) or m = m_min exp(u log(m_max / m_min)).
+ * Pairs are canonicalised to m1 >= m2.  Writes n entries to out_host.
+ * CI_EINVAL when 0 < m_min <= m_max fails or n < 0. */
+int ci_make_bank(const ci_bank_spec* spec, int64_t n, ci_template* out_host);
+
+/* --- segment --------------------------------------------------------------
+ * Prepare one data chunk (the "input data chunk" that device_complex_mf
+ * correlates with).  d_xtilde: complex64[n/2+1] (interleaved re, im), the
+ * data spectrum x~_k = dt sum_j x_j exp(-2 pi i jk/n).  d_psd: float64
+ * [n/2+1], the one-sided noise PSD S_k > 0 on [k_low, n/2-1] (other bins
+ * are ignored).  Both are read on `stream` before the call's work
+ * completes and are not retained.  The segment holds the PSD-weighted
+ * spectrum g x~_k f_k^{-7/6} / S_k (complex64; g a power of two) and the
+ * FP64 running sum of 4 df f_k^{-7/3} / S_k from k_low, from which every
+ * template's sigma^2 is one lookup.
+ * CI_EINVAL for a non-power-of-two n, n outside 2^16..2^21, or a band
+ * that is empty. */
+int ci_segment_create(ci_ctx* ctx, const ci_segment_spec* spec,
+                      const void* d_xtilde, const double* d_psd, void* stream,
+                      ci_segment** out);
+int ci_segment_destroy(ci_segment* seg);
+
+/* --- templates -------------------------------------------------------------
+ * Generator constants for n bank entries on `seg`'s grid (the paper's
+ * host_template_init + device_template_init), and optionally the templates
+ * themselves (device_template_proc).  bank_host: n ci_template (host),
+ * copied before return.  d_params: ci_tparams[n] (device), written on
+ * `stream`; sigma2 and scale are computed on the device from the segment's
+ * FP64 running sum.  d_htilde_opt: NULL, or complex64[n][n_seg/2+1] that
+ * receives h~_k = f_k^{-7/6} exp(-i Psi_k) inside the band and 0 outside
+ * (unit amplitude, t_c = phi_c = 0).  The search itself never materialises
+ * templates.  CI_EINVAL for non-positive masses. */
+int ci_gen_templates(ci_ctx* ctx, const ci_segment* seg,
+                     const ci_template* bank_host, int64_t n,
+                     ci_tparams* d_params, void* d_htilde_opt, void* stream);
+
+/* --- matched filter: the complex SNR series ---------------------------------
+ * For each of n templates, z_j / sigma for j = 0..n_seg-1, where
+ *   z_j = sum_{k=k_low}^{k_high} 4 df x~_k conj(h~_k) / S_k exp(2 pi i jk/n),
+ * i.e. both quadrature correlators at every lag (eq. (matchedfilter)) in
+ * SNR units: |z_j|^2 / sigma^2 is the quadrature sum c_+^2 + c_x^2.
+ * d_z: complex64[n][n_seg] (device).  precision: CI_FP32
+ * (CI_EUNSUPPORTED otherwise).  An empty template yields zeros. */
+int ci_matched_filter(ci_ctx* ctx, const ci_segment* seg,
+                      const ci_tparams* d_params, int64_t n, int32_t precision,
+                      void* d_z, void* stream);
+
+/* --- search: peaks and threshold triggers ------------------------------------
+ * The hot path.  Runs the same filter as ci_matched_filter without storing
+ * the series and, per template t, reports:
+ *  - d_peaks[t]: the largest rho^2 over samples j in [j_lo, j_hi) (ties to
+ *    the smallest j), with z/sigma at that sample; index -1 for an empty
+ *    template.
+ *  - threshold triggers: for every aligned window [wW, (w+1)W) intersected
+ *    with [j_lo, j_hi), the window's argmax m_w (ties to the smallest index)
+ *    when rho2[m_w] > snr_threshold^2 (strict, the paper's c(t) > lambda).
+ * merge_across_templates == 0: d_trig receives every (template, window)
+ *   trigger, ordered by (template, window).
+ * merge_across_templates != 0: d_trig receives one entry per window that has
+ *   any trigger, the one with the largest rho^2 over all templates (ties to
+ *   the smaller template id), ordered by window (the reduction of the
+ *   candidate set to local maxima).
+ * d_count (int64, device): receives the total number of triggers.  When it
+ * exceeds `cap`, only the first `cap` in the stated order are written.
+ * rho2 of a trigger is the value that decided it; re/im are recomputed at
+ * that index from the same transform's intermediate with FP64 accumulation.
+ * window: W >= 1.  j_hi <= 0 means n_seg.  precision: CI_FP32. */
+int ci_find_triggers(ci_ctx* ctx, const ci_segment* seg,
+                     const ci_tparams* d_params, int64_t n, int32_t precision,
+                     float snr_threshold, int64_t window, int64_t j_lo,
+                     int64_t j_hi, ci_trigger* d_peaks, ci_trigger* d_trig,
+                     int64_t cap, int64_t* d_count,
+                     int32_t merge_across_templates, void* stream);
+
+/* --- tuning -----------------------------------------------------------------
+ * Templates per batch of the two-pass transform (0 = the built-in choice for
+ * the segment length).  The intermediate workspace is 2 x batch x n_seg x 8
+ * bytes. */
+int ci_set_batch(ci_ctx* ctx, int64_t templates_per_batch);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CI_H */

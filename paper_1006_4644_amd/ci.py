@@ -1,0 +1,273 @@
+"""Python binding of the C-ABI library ``libci.so`` (argument marshalling only).
+
+Every step of the search runs in the library's HIP kernels; this module only
+turns torch tensors into device pointers and the current torch stream into a
+``hipStream_t``.  Loading fails loudly when the library has not been built:
+there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+__all__ = [
+    "load", "LibraryMissing", "CiError", "Library", "Context", "Segment",
+    "TRIGGER_DTYPE", "TPARAMS_DTYPE", "FP32", "SPLIT_BF16", "SPLIT_FP16",
+    "BANK_GRID", "BANK_UNIFORM", "BANK_LOGUNIFORM", "EXPORTED_SYMBOLS",
+]
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libci.so")
+
+OK, EINVAL, ENOMEM, EHIP, ETRUNC, EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+FP32, SPLIT_BF16, SPLIT_FP16 = 0, 1, 2
+BANK_GRID, BANK_UNIFORM, BANK_LOGUNIFORM = 0, 1, 2
+TMPL_EMPTY = 1
+
+EXPORTED_SYMBOLS = (
+    "ci_version", "ci_last_error", "ci_ctx_create", "ci_ctx_destroy",
+    "ci_set_batch", "ci_make_bank", "ci_segment_create", "ci_segment_destroy",
+    "ci_gen_templates", "ci_matched_filter", "ci_find_triggers",
+)
+
+# ci_trigger: {int64 tmpl, int64 index, float rho2, re, im, int32 window}
+TRIGGER_DTYPE = np.dtype([("tmpl", "<i8"), ("index", "<i8"), ("rho2", "<f4"),
+                          ("re", "<f4"), ("im", "<f4"), ("window", "<i4")])
+# ci_tparams (96 bytes)
+TPARAMS_DTYPE = np.dtype([("m1", "<f8"), ("m2", "<f8"), ("x0", "<f8"),
+                          ("c0", "<f8"), ("c2", "<f8"), ("c3", "<f8"),
+                          ("c4", "<f8"), ("sigma2", "<f8"), ("tau", "<f8"),
+                          ("scale", "<f4"), ("k_low", "<i4"),
+                          ("k_high", "<i4"), ("flags", "<i4"),
+                          ("reserved", "<i4", (2,))])
+assert TRIGGER_DTYPE.itemsize == 32 and TPARAMS_DTYPE.itemsize == 96
+
+
+class LibraryMissing(RuntimeError):
+    pass
+
+
+class CiError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"ci error {code}: {msg}")
+        self.code = code
+
+
+class _Template(ctypes.Structure):
+    _fields_ = [("m1", ctypes.c_double), ("m2", ctypes.c_double)]
+
+
+class _BankSpec(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("m_min", ctypes.c_double), ("m_max", ctypes.c_double),
+                ("seed", ctypes.c_uint64)]
+
+
+class _SegSpec(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("fs", ctypes.c_double),
+                ("f_low", ctypes.c_double)]
+
+
+_vp, _i32, _i64, _f32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_float
+
+_SIGS = {
+    "ci_version": (ctypes.c_char_p, []),
+    "ci_last_error": (ctypes.c_char_p, [_vp]),
+    "ci_ctx_create": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(_vp)]),
+    "ci_ctx_destroy": (ctypes.c_int, [_vp]),
+    "ci_set_batch": (ctypes.c_int, [_vp, _i64]),
+    "ci_make_bank": (ctypes.c_int, [ctypes.POINTER(_BankSpec), _i64, _vp]),
+    "ci_segment_create": (ctypes.c_int, [_vp, ctypes.POINTER(_SegSpec), _vp,
+                                         _vp, _vp, ctypes.POINTER(_vp)]),
+    "ci_segment_destroy": (ctypes.c_int, [_vp]),
+    "ci_gen_templates": (ctypes.c_int, [_vp, _vp, _vp, _i64, _vp, _vp, _vp]),
+    "ci_matched_filter": (ctypes.c_int, [_vp, _vp, _vp, _i64, _i32, _vp, _vp]),
+    "ci_find_triggers": (ctypes.c_int, [_vp, _vp, _vp, _i64, _i32, _f32, _i64,
+                                        _i64, _i64, _vp, _vp, _i64, _vp, _i32,
+                                        _vp]),
+}
+
+_LIB = None
+
+
+def load(path: str | None = None) -> "Library":
+    """Load libci.so (built in-tree by ``paper_1006_4644_amd.build``)."""
+    global _LIB
+    if _LIB is not None and path is None:
+        return _LIB
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise LibraryMissing(
+            f"{p} not found: build it with "
+            "`python -c 'import __graft_entry__ as g; g.build()'`")
+    lib = Library(ctypes.CDLL(p))
+    if path is None:
+        _LIB = lib
+    return lib
+
+
+def _ptr(t) -> int:
+    return 0 if t is None else int(t.data_ptr())
+
+
+def _stream(stream=None) -> int:
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+class Library:
+    """Thin wrapper over the exported C functions."""
+
+    def __init__(self, dll):
+        self.dll = dll
+        for name, (res, args) in _SIGS.items():
+            f = getattr(dll, name)
+            f.restype = res
+            f.argtypes = args
+
+    def version(self) -> str:
+        return self.dll.ci_version().decode()
+
+    def check(self, rc, ctx=None):
+        if rc != OK:
+            msg = self.dll.ci_last_error(ctx)
+            raise CiError(rc, msg.decode() if msg else "")
+
+    def make_bank(self, kind: int, m_min: float, m_max: float, seed: int,
+                  n: int) -> np.ndarray:
+        out = np.empty((n, 2), dtype=np.float64)
+        spec = _BankSpec(kind, 0, m_min, m_max, seed)
+        rc = self.dll.ci_make_bank(ctypes.byref(spec), n,
+                                   out.ctypes.data if n else None)
+        self.check(rc)
+        return out
+
+    def context(self, device: int = 0) -> "Context":
+        return Context(self, device)
+
+
+class Segment:
+    def __init__(self, ctx: "Context", handle: int, n: int, fs: float,
+                 f_low: float):
+        self.ctx, self.handle, self.n, self.fs, self.f_low = ctx, handle, n, fs, f_low
+
+    def close(self):
+        if self.handle:
+            self.ctx.lib.dll.ci_segment_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Context:
+    """A ci_ctx; device memory comes from torch tensors on `cuda:device`."""
+
+    def __init__(self, lib: Library, device: int = 0):
+        self.lib = lib
+        self.device = device
+        h = _vp()
+        lib.check(lib.dll.ci_ctx_create(device, ctypes.byref(h)))
+        self.handle = h.value
+
+    def close(self):
+        if self.handle:
+            self.lib.dll.ci_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _chk(self, rc):
+        self.lib.check(rc, self.handle)
+
+    def set_batch(self, b: int):
+        self._chk(self.lib.dll.ci_set_batch(self.handle, b))
+
+    def segment(self, xtilde, psd, n: int, fs: float, f_low: float,
+                stream=None) -> Segment:
+        """xtilde: complex64 CUDA tensor [n/2+1]; psd: float64 CUDA [n/2+1]."""
+        import torch
+        assert xtilde.dtype == torch.complex64 and xtilde.is_cuda
+        assert psd.dtype == torch.float64 and psd.is_cuda
+        assert xtilde.numel() == n // 2 + 1 and psd.numel() == n // 2 + 1
+        xtilde = xtilde.contiguous()
+        psd = psd.contiguous()
+        spec = _SegSpec(n, fs, f_low)
+        h = _vp()
+        self._chk(self.lib.dll.ci_segment_create(
+            self.handle, ctypes.byref(spec), _ptr(xtilde), _ptr(psd),
+            _stream(stream), ctypes.byref(h)))
+        return Segment(self, h.value, n, fs, f_low)
+
+    def gen_templates(self, seg: Segment, bank, htilde: bool = False,
+                      stream=None):
+        """Generator constants (uint8 CUDA tensor [n, 96]) for a (n, 2)
+        bank; with htilde=True also the templates (complex64 [n, N/2+1])."""
+        import torch
+        bank = np.ascontiguousarray(np.asarray(bank, dtype=np.float64).reshape(-1, 2))
+        n = bank.shape[0]
+        dev = torch.device("cuda", self.device)
+        params = torch.empty((max(n, 1), 96), dtype=torch.uint8, device=dev)
+        ht = None
+        if htilde:
+            ht = torch.empty((max(n, 1), seg.n // 2 + 1), dtype=torch.complex64,
+                             device=dev)
+        self._chk(self.lib.dll.ci_gen_templates(
+            self.handle, seg.handle, bank.ctypes.data if n else None, n,
+            _ptr(params), _ptr(ht), _stream(stream)))
+        return (params, ht) if htilde else params
+
+    def matched_filter(self, seg: Segment, params, n: int | None = None,
+                       precision: int = FP32, out=None, stream=None):
+        """Complex SNR series z/sigma, complex64 [n, N]."""
+        import torch
+        n = params.shape[0] if n is None else n
+        if out is None:
+            out = torch.empty((max(n, 1), seg.n), dtype=torch.complex64,
+                              device=params.device)
+        self._chk(self.lib.dll.ci_matched_filter(
+            self.handle, seg.handle, _ptr(params), n, precision, _ptr(out),
+            _stream(stream)))
+        return out
+
+    def find_triggers(self, seg: Segment, params, thr: float, window: int,
+                      n: int | None = None, j_lo: int = 0, j_hi: int = 0,
+                      cap: int = 1 << 16, merge: bool = False,
+                      precision: int = FP32, peaks=None, trig=None,
+                      count=None, stream=None):
+        """Enqueue the search; returns the device tensors (peaks [n, 4] int64
+        rows of ci_trigger, trig [cap, 4], count [1] int64)."""
+        import torch
+        n = params.shape[0] if n is None else n
+        dev = params.device
+        if peaks is None:
+            peaks = torch.empty((max(n, 1), 4), dtype=torch.int64, device=dev)
+        if trig is None:
+            trig = torch.empty((max(cap, 1), 4), dtype=torch.int64, device=dev)
+        if count is None:
+            count = torch.zeros(1, dtype=torch.int64, device=dev)
+        self._chk(self.lib.dll.ci_find_triggers(
+            self.handle, seg.handle, _ptr(params), n, precision, float(thr),
+            window, j_lo, j_hi, _ptr(peaks), _ptr(trig), cap, _ptr(count),
+            1 if merge else 0, _stream(stream)))
+        return peaks, trig, count
+
+
+def triggers_to_numpy(t, count: int | None = None) -> np.ndarray:
+    """View ci_trigger rows of a (m, 4) int64 tensor as a structured array."""
+    a = t.detach().cpu().numpy().view(TRIGGER_DTYPE).reshape(-1)
+    return a if count is None else a[:count]
+
+
+def params_to_numpy(p) -> np.ndarray:
+    return p.detach().cpu().numpy().view(TPARAMS_DTYPE).reshape(-1)

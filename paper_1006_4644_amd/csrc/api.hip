@@ -1,0 +1,525 @@
+// api.hip -- the C ABI declared in include/ci.h.
+//
+// Host side of the search: argument validation, the bank generator, the
+// per-template generator constants (the paper's host_template_init, in
+// FP64), workspace management and the batch loop that enqueues the two
+// transform passes on the caller's stream.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <new>
+#include <string>
+
+#include "ci_impl.h"
+
+using namespace ci;
+
+namespace {
+
+thread_local std::string g_err;
+
+// G M_sun / c^3 in seconds (IAU nominal solar mass parameter / c^3).
+constexpr double kTSun = 4.925490947641267e-6;
+constexpr double kPi = 3.14159265358979323846;
+
+int fail(Ctx* ctx, int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (ctx) ctx->err = buf;
+  else g_err = buf;
+  return code;
+}
+
+int hipfail(Ctx* ctx, hipError_t e, const char* what) {
+  return fail(ctx, CI_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+// Selects the context's device for the duration of a call.
+struct DeviceGuard {
+  int prev = -1;
+  bool ok = true;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) ok = hipSetDevice(dev) == hipSuccess;
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+// SplitMix64 (Steele, Lea & Flood, OOPSLA 2014) in counter form.
+uint64_t splitmix64(uint64_t i, uint64_t seed) {
+  uint64_t z = seed + (i + 1) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+double uniform01(uint64_t i, uint64_t seed) {
+  return (double)(splitmix64(i, seed) >> 11) * (1.0 / 9007199254740992.0);
+}
+
+int ilog2_exact(int64_t n) {
+  if (n <= 0 || (n & (n - 1)) != 0) return -1;
+  int l = 0;
+  while ((1ll << l) < n) ++l;
+  return l;
+}
+
+// 2PN time to coalescence from f (seconds).
+double tau_2pn(double f, double m1, double m2) {
+  const double M = (m1 + m2) * kTSun;
+  const double eta = m1 * m2 / ((m1 + m2) * (m1 + m2));
+  const double v = cbrt(kPi * M * f);
+  const double v2 = v * v;
+  return 5.0 * M / (256.0 * eta) / (v2 * v2 * v2 * v2) *
+         (1.0 + (743.0 / 252.0 + 11.0 * eta / 3.0) * v2 - 32.0 * kPi / 5.0 * v2 * v +
+          (3058673.0 / 508032.0 + 5429.0 * eta / 504.0 + 617.0 * eta * eta / 72.0) * v2 * v2);
+}
+
+// Generator constants of one template on a grid (host_template_init).
+void host_params(const ci_template& tm, const SegDev& sd, ci_tparams* P) {
+  const double m1 = tm.m1 >= tm.m2 ? tm.m1 : tm.m2;
+  const double m2 = tm.m1 >= tm.m2 ? tm.m2 : tm.m1;
+  memset(P, 0, sizeof *P);
+  P->m1 = m1;
+  P->m2 = m2;
+  const double M = (m1 + m2) * kTSun;
+  const double eta = m1 * m2 / ((m1 + m2) * (m1 + m2));
+  const double T = (double)sd.n / sd.fs;
+  const double f_isco = 1.0 / (6.0 * sqrt(6.0) * kPi * M);
+  const double kh = floor(f_isco * T);
+  const int64_t kmax = sd.half - 1;
+  P->k_low = sd.k_low;
+  P->k_high = (int32_t)(kh < (double)kmax ? kh : (double)kmax);
+  P->x0 = kPi * M * sd.df;
+  // Psi/(2 pi) = -1/8 + 3/(128 eta) [u^5 + a2 u^3 + a3 u^2 + a4 u] / (2 pi)
+  const double a2 = 3715.0 / 756.0 + 55.0 * eta / 9.0;
+  const double a3 = -16.0 * kPi;
+  const double a4 = 15293365.0 / 508032.0 + 27145.0 * eta / 504.0 + 3085.0 * eta * eta / 72.0;
+  P->c0 = 3.0 / (128.0 * eta) / (2.0 * kPi);
+  P->c2 = P->c0 * a2;
+  P->c3 = P->c0 * a3;
+  P->c4 = P->c0 * a4;
+  P->tau = tau_2pn(sd.f_low, m1, m2);
+  P->flags = P->k_high < P->k_low ? CI_TMPL_EMPTY : 0;
+}
+
+void free_seg(Seg* s) {
+  if (!s) return;
+  if (s->dev) (void)hipFree(s->dev);
+  if (s->w) (void)hipFree(s->w);
+  if (s->psum) (void)hipFree(s->psum);
+  if (s->tw2048) (void)hipFree(s->tw2048);
+  if (s->twa) (void)hipFree(s->twa);
+  if (s->twb) (void)hipFree(s->twb);
+  delete s;
+}
+
+// Templates per batch: the intermediate of one slot set is about 256 MiB.
+int64_t default_batch(const Ctx* ctx, int64_t nseg) {
+  if (ctx->batch_override > 0) return ctx->batch_override;
+  int64_t b = (int64_t(1) << 25) / nseg;
+  return b < 1 ? 1 : b;
+}
+
+int ensure_ybuf(Ctx* ctx, size_t bytes) {
+  if (ctx->ybytes >= bytes) return CI_OK;
+  if (ctx->ybuf) (void)hipFree(ctx->ybuf);
+  ctx->ybuf = nullptr;
+  ctx->ybytes = 0;
+  hipError_t e = hipMalloc(&ctx->ybuf, bytes);
+  if (e != hipSuccess) return fail(ctx, CI_ENOMEM, "intermediate workspace of %zu bytes: %s",
+                                   bytes, hipGetErrorString(e));
+  ctx->ybytes = bytes;
+  return CI_OK;
+}
+
+size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+int ensure_trig(Ctx* ctx, int64_t bmax, int64_t nwin, TrigWork* tw) {
+  const size_t s_pk = align256(sizeof(unsigned long long) * 2 * bmax);
+  const size_t s_wk = align256(sizeof(unsigned long long) * 2 * bmax * nwin);
+  const size_t s_td = align256(sizeof(unsigned int) * 2 * bmax);
+  const size_t s_bd = align256(sizeof(unsigned int) * 2);
+  const size_t s_cn = align256(sizeof(int) * 2 * bmax);
+  const size_t s_si = align256(sizeof(int) * 2 * bmax * nwin);
+  const size_t s_st = align256(sizeof(ci_trigger) * 2 * bmax * nwin);
+  const size_t s_mr = align256(sizeof(ci_trigger) * nwin);
+  const size_t s_rn = align256(sizeof(unsigned long long));
+  const size_t total = s_pk + s_wk + s_td + s_bd + s_cn + s_si + s_st + s_mr + s_rn;
+  if (ctx->tbytes < total) {
+    if (ctx->tbuf) (void)hipFree(ctx->tbuf);
+    ctx->tbuf = nullptr;
+    ctx->tbytes = 0;
+    hipError_t e = hipMalloc(&ctx->tbuf, total);
+    if (e != hipSuccess)
+      return fail(ctx, CI_ENOMEM, "trigger workspace of %zu bytes: %s", total,
+                  hipGetErrorString(e));
+    ctx->tbytes = total;
+  }
+  char* p = static_cast<char*>(ctx->tbuf);
+  tw->pkeys = reinterpret_cast<unsigned long long*>(p); p += s_pk;
+  tw->wkeys = reinterpret_cast<unsigned long long*>(p); p += s_wk;
+  tw->tdone = reinterpret_cast<unsigned int*>(p); p += s_td;
+  tw->bdone = reinterpret_cast<unsigned int*>(p); p += s_bd;
+  tw->cnt = reinterpret_cast<int*>(p); p += s_cn;
+  tw->sidx = reinterpret_cast<int*>(p); p += s_si;
+  tw->stage = reinterpret_cast<ci_trigger*>(p); p += s_st;
+  tw->mrec = reinterpret_cast<ci_trigger*>(p); p += s_mr;
+  tw->run = reinterpret_cast<unsigned long long*>(p);
+  return CI_OK;
+}
+
+int check_filter_args(Ctx* ctx, const ci_segment* seg, const ci_tparams* d_params, int64_t n,
+                      int32_t precision) {
+  if (!ctx) return fail(nullptr, CI_EINVAL, "null context");
+  if (!seg) return fail(ctx, CI_EINVAL, "null segment");
+  if (n < 0) return fail(ctx, CI_EINVAL, "negative template count %lld", (long long)n);
+  if (n > 0 && !d_params) return fail(ctx, CI_EINVAL, "null d_params");
+  if (precision != CI_FP32) {
+    if (precision == CI_SPLIT_BF16 || precision == CI_SPLIT_FP16)
+      return fail(ctx, CI_EUNSUPPORTED, "split-precision transform is not built");
+    return fail(ctx, CI_EINVAL, "unknown precision %d", precision);
+  }
+  return CI_OK;
+}
+
+}  // namespace
+
+struct ci_ctx : Ctx {};
+struct ci_segment : Seg {};
+
+extern "C" {
+
+const char* ci_version(void) { return "ci 0.1 (gfx950)"; }
+
+const char* ci_last_error(const ci_ctx* ctx) {
+  return ctx ? ctx->err.c_str() : g_err.c_str();
+}
+
+int ci_ctx_create(int device, ci_ctx** out) {
+  if (!out) return fail(nullptr, CI_EINVAL, "null output handle");
+  int ndev = 0;
+  hipError_t e = hipGetDeviceCount(&ndev);
+  if (e != hipSuccess) return fail(nullptr, CI_EHIP, "hipGetDeviceCount: %s", hipGetErrorString(e));
+  if (device < 0 || device >= ndev)
+    return fail(nullptr, CI_EINVAL, "device %d out of range (%d devices)", device, ndev);
+  ci_ctx* c = new (std::nothrow) ci_ctx();
+  if (!c) return fail(nullptr, CI_ENOMEM, "context allocation");
+  c->device = device;
+  *out = c;
+  return CI_OK;
+}
+
+int ci_ctx_destroy(ci_ctx* ctx) {
+  if (!ctx) return CI_OK;
+  DeviceGuard g(ctx->device);
+  if (ctx->pin_ev) {
+    (void)hipEventSynchronize(ctx->pin_ev);
+    (void)hipEventDestroy(ctx->pin_ev);
+  }
+  if (ctx->pin) (void)hipHostFree(ctx->pin);
+  if (ctx->ybuf) (void)hipFree(ctx->ybuf);
+  if (ctx->tbuf) (void)hipFree(ctx->tbuf);
+  delete ctx;
+  return CI_OK;
+}
+
+int ci_set_batch(ci_ctx* ctx, int64_t templates_per_batch) {
+  if (!ctx) return fail(nullptr, CI_EINVAL, "null context");
+  if (templates_per_batch < 0 || templates_per_batch > (1 << 16))
+    return fail(ctx, CI_EINVAL, "batch %lld outside 0..65536", (long long)templates_per_batch);
+  ctx->batch_override = templates_per_batch;
+  return CI_OK;
+}
+
+int ci_make_bank(const ci_bank_spec* spec, int64_t n, ci_template* out_host) {
+  if (!spec) return fail(nullptr, CI_EINVAL, "null bank spec");
+  if (n < 0) return fail(nullptr, CI_EINVAL, "negative bank size");
+  if (n > 0 && !out_host) return fail(nullptr, CI_EINVAL, "null output");
+  if (!(spec->m_min > 0.0) || !(spec->m_max >= spec->m_min) || !isfinite(spec->m_max))
+    return fail(nullptr, CI_EINVAL, "need 0 < m_min <= m_max");
+  if (spec->reserved != 0) return fail(nullptr, CI_EINVAL, "reserved field must be 0");
+  const double lo = spec->m_min, hi = spec->m_max;
+  if (spec->kind == CI_BANK_GRID) {
+    int64_t g = (int64_t)sqrt((double)n);
+    while (g * g < n) ++g;
+    while (g > 1 && (g - 1) * (g - 1) >= n) --g;
+    for (int64_t t = 0; t < n; ++t) {
+      const int64_t i1 = t / g, i2 = t % g;
+      const double a = g == 1 ? lo : lo + (hi - lo) * (double)i1 / (double)(g - 1);
+      const double b = g == 1 ? lo : lo + (hi - lo) * (double)i2 / (double)(g - 1);
+      out_host[t].m1 = a >= b ? a : b;
+      out_host[t].m2 = a >= b ? b : a;
+    }
+    return CI_OK;
+  }
+  if (spec->kind != CI_BANK_UNIFORM && spec->kind != CI_BANK_LOGUNIFORM)
+    return fail(nullptr, CI_EINVAL, "unknown bank kind %d", spec->kind);
+  const double lr = log(hi / lo);
+  for (int64_t t = 0; t < n; ++t) {
+    double m[2];
+    for (int d = 0; d < 2; ++d) {
+      const double u = uniform01((uint64_t)(2 * t + d), spec->seed);
+      m[d] = spec->kind == CI_BANK_UNIFORM ? lo + u * (hi - lo) : lo * exp(u * lr);
+    }
+    out_host[t].m1 = m[0] >= m[1] ? m[0] : m[1];
+    out_host[t].m2 = m[0] >= m[1] ? m[1] : m[0];
+  }
+  return CI_OK;
+}
+
+int ci_segment_create(ci_ctx* ctx, const ci_segment_spec* spec, const void* d_xtilde,
+                      const double* d_psd, void* stream, ci_segment** out) {
+  if (!ctx) return fail(nullptr, CI_EINVAL, "null context");
+  if (!spec || !out) return fail(ctx, CI_EINVAL, "null spec or output handle");
+  if (!d_xtilde || !d_psd) return fail(ctx, CI_EINVAL, "null data or PSD pointer");
+  const int l2 = ilog2_exact(spec->n);
+  if (l2 < 0) return fail(ctx, CI_EINVAL, "n = %lld is not a power of two", (long long)spec->n);
+  if (l2 < 16 || l2 > 21)
+    return fail(ctx, CI_EINVAL, "n = 2^%d outside the supported 2^16 .. 2^21", l2);
+  if (!(spec->fs > 0.0) || !isfinite(spec->fs)) return fail(ctx, CI_EINVAL, "fs must be > 0");
+  if (!(spec->f_low > 0.0) || !isfinite(spec->f_low))
+    return fail(ctx, CI_EINVAL, "f_low must be > 0");
+  const double T = (double)spec->n / spec->fs;
+  const double klo = ceil(spec->f_low * T);
+  if (!(klo >= 1.0) || !(klo < (double)(spec->n / 2)))
+    return fail(ctx, CI_EINVAL, "band is empty: k_low = %g with n/2 = %lld", klo,
+                (long long)(spec->n / 2));
+  DeviceGuard dg(ctx->device);
+  if (!dg.ok) return fail(ctx, CI_EHIP, "cannot select device %d", ctx->device);
+
+  ci_segment* s = new (std::nothrow) ci_segment();
+  if (!s) return fail(ctx, CI_ENOMEM, "segment allocation");
+  s->ctx = ctx;
+  s->spec = *spec;
+  s->plan = plan_for(l2);
+  SegDev& h = s->host;
+  h.n = spec->n;
+  h.half = spec->n / 2;
+  h.fs = spec->fs;
+  h.f_low = spec->f_low;
+  h.df = spec->fs / (double)spec->n;
+  h.k_low = (int32_t)klo;
+  h.log2n = l2;
+  h.g = 1.0;
+  h.p_total = 0.0;
+  const int64_t half = h.half;
+  const int64_t nb = spec->n / 2048;
+  hipError_t e;
+#define ALLOC(ptr, bytes)                                            \
+  e = hipMalloc(reinterpret_cast<void**>(&(ptr)), (bytes));          \
+  if (e != hipSuccess) {                                             \
+    free_seg(s);                                                     \
+    return fail(ctx, CI_ENOMEM, "segment buffer: %s", hipGetErrorString(e)); \
+  }
+  ALLOC(s->dev, sizeof(SegDev));
+  ALLOC(s->w, sizeof(float2) * half);
+  ALLOC(s->psum, sizeof(double) * half);
+  ALLOC(s->tw2048, sizeof(float2) * 2048);
+  ALLOC(s->twa, sizeof(float2) * 2048);
+  ALLOC(s->twb, sizeof(float2) * (nb > 0 ? nb : 1));
+#undef ALLOC
+  // twiddle tables in FP64, rounded once to FP32
+  std::string fails;
+  {
+    float2* t1 = new (std::nothrow) float2[2048];
+    float2* t2 = new (std::nothrow) float2[2048];
+    float2* t3 = new (std::nothrow) float2[nb > 0 ? nb : 1];
+    if (!t1 || !t2 || !t3) {
+      delete[] t1; delete[] t2; delete[] t3;
+      free_seg(s);
+      return fail(ctx, CI_ENOMEM, "host table allocation");
+    }
+    for (int i = 0; i < 2048; ++i) {
+      const double a = 2.0 * kPi * (double)i / 2048.0;
+      t1[i] = make_float2((float)cos(a), (float)sin(a));
+      const double b = 2.0 * kPi * (double)i / (double)spec->n;
+      t2[i] = make_float2((float)cos(b), (float)sin(b));
+    }
+    for (int64_t i = 0; i < nb; ++i) {
+      const double c = 2.0 * kPi * (double)(2048 * i) / (double)spec->n;
+      t3[i] = make_float2((float)cos(c), (float)sin(c));
+    }
+    e = hipMemcpy(s->tw2048, t1, sizeof(float2) * 2048, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(s->twa, t2, sizeof(float2) * 2048, hipMemcpyHostToDevice);
+    if (e == hipSuccess && nb > 0)
+      e = hipMemcpy(s->twb, t3, sizeof(float2) * nb, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(s->dev, &h, sizeof(SegDev), hipMemcpyHostToDevice);
+    delete[] t1; delete[] t2; delete[] t3;
+    if (e != hipSuccess) {
+      free_seg(s);
+      return hipfail(ctx, e, "segment table upload");
+    }
+  }
+  e = launch_segment(s, d_xtilde, d_psd, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) {
+    free_seg(s);
+    return hipfail(ctx, e, "segment setup launch");
+  }
+  *out = s;
+  return CI_OK;
+}
+
+int ci_segment_destroy(ci_segment* seg) {
+  if (!seg) return CI_OK;
+  DeviceGuard g(seg->ctx->device);
+  // buffers may still be read by enqueued work: wait for the device
+  (void)hipDeviceSynchronize();
+  free_seg(seg);
+  return CI_OK;
+}
+
+int ci_gen_templates(ci_ctx* ctx, const ci_segment* seg, const ci_template* bank_host, int64_t n,
+                     ci_tparams* d_params, void* d_htilde_opt, void* stream) {
+  if (!ctx) return fail(nullptr, CI_EINVAL, "null context");
+  if (!seg) return fail(ctx, CI_EINVAL, "null segment");
+  if (n < 0) return fail(ctx, CI_EINVAL, "negative template count");
+  if (n == 0) return CI_OK;
+  if (!bank_host || !d_params) return fail(ctx, CI_EINVAL, "null bank or d_params");
+  for (int64_t i = 0; i < n; ++i) {
+    if (!(bank_host[i].m1 > 0.0) || !(bank_host[i].m2 > 0.0) || !isfinite(bank_host[i].m1) ||
+        !isfinite(bank_host[i].m2))
+      return fail(ctx, CI_EINVAL, "template %lld has non-positive mass", (long long)i);
+  }
+  DeviceGuard dg(ctx->device);
+  if (!dg.ok) return fail(ctx, CI_EHIP, "cannot select device %d", ctx->device);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const size_t bytes = sizeof(ci_tparams) * (size_t)n;
+  hipError_t e;
+  if (!ctx->pin_ev) {
+    e = hipEventCreateWithFlags(&ctx->pin_ev, hipEventDisableTiming);
+    if (e != hipSuccess) return hipfail(ctx, e, "event create");
+  }
+  // the previous upload from the pinned buffer must have completed
+  if (ctx->pin_ev_armed) {
+    e = hipEventSynchronize(ctx->pin_ev);
+    if (e != hipSuccess) return hipfail(ctx, e, "pinned staging wait");
+    ctx->pin_ev_armed = false;
+  }
+  if (ctx->pinbytes < bytes) {
+    if (ctx->pin) (void)hipHostFree(ctx->pin);
+    ctx->pin = nullptr;
+    ctx->pinbytes = 0;
+    e = hipHostMalloc(&ctx->pin, bytes, hipHostMallocDefault);
+    if (e != hipSuccess) return fail(ctx, CI_ENOMEM, "pinned staging: %s", hipGetErrorString(e));
+    ctx->pinbytes = bytes;
+  }
+  ci_tparams* hp = static_cast<ci_tparams*>(ctx->pin);
+  for (int64_t i = 0; i < n; ++i) host_params(bank_host[i], seg->host, &hp[i]);
+  e = hipMemcpyAsync(d_params, hp, bytes, hipMemcpyHostToDevice, st);
+  if (e != hipSuccess) return hipfail(ctx, e, "parameter upload");
+  e = hipEventRecord(ctx->pin_ev, st);
+  if (e != hipSuccess) return hipfail(ctx, e, "event record");
+  ctx->pin_ev_armed = true;
+  e = launch_params(seg, d_params, n, d_htilde_opt, st);
+  if (e != hipSuccess) return hipfail(ctx, e, "parameter kernel launch");
+  return CI_OK;
+}
+
+int ci_matched_filter(ci_ctx* ctx, const ci_segment* seg, const ci_tparams* d_params, int64_t n,
+                      int32_t precision, void* d_z, void* stream) {
+  int rc = check_filter_args(ctx, seg, d_params, n, precision);
+  if (rc != CI_OK) return rc;
+  if (n == 0) return CI_OK;
+  if (!d_z) return fail(ctx, CI_EINVAL, "null d_z");
+  DeviceGuard dg(ctx->device);
+  if (!dg.ok) return fail(ctx, CI_EHIP, "cannot select device %d", ctx->device);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int64_t N = seg->host.n;
+  int64_t B = default_batch(ctx, N);
+  if (B > n) B = n;
+  rc = ensure_ybuf(ctx, sizeof(float2) * 2 * (size_t)B * (size_t)N);
+  if (rc != CI_OK) return rc;
+  BatchArgs a;
+  memset(&a, 0, sizeof a);
+  a.seg = seg;
+  a.bmax = (int)B;
+  for (int64_t b = 0, t0 = 0; t0 < n; ++b, t0 += B) {
+    a.t0 = t0;
+    a.nb = (int)((n - t0) < B ? (n - t0) : B);
+    a.slot = (int)(b & 1);
+    a.params = d_params + t0;
+    a.y = static_cast<float2*>(ctx->ybuf) + (size_t)a.slot * B * N;
+    a.d_z = static_cast<float2*>(d_z) + (size_t)t0 * N;
+    hipError_t e = launch_pass1(a, false, st);
+    if (e != hipSuccess) return hipfail(ctx, e, "pass-1 launch");
+    e = launch_pass2_series(a, st);
+    if (e != hipSuccess) return hipfail(ctx, e, "pass-2 launch");
+  }
+  return CI_OK;
+}
+
+int ci_find_triggers(ci_ctx* ctx, const ci_segment* seg, const ci_tparams* d_params, int64_t n,
+                     int32_t precision, float snr_threshold, int64_t window, int64_t j_lo,
+                     int64_t j_hi, ci_trigger* d_peaks, ci_trigger* d_trig, int64_t cap,
+                     int64_t* d_count, int32_t merge_across_templates, void* stream) {
+  int rc = check_filter_args(ctx, seg, d_params, n, precision);
+  if (rc != CI_OK) return rc;
+  const int64_t N = seg->host.n;
+  if (window < 1 || window > N) return fail(ctx, CI_EINVAL, "window %lld outside 1..n", (long long)window);
+  if (j_hi <= 0) j_hi = N;
+  if (j_lo < 0 || j_hi > N || j_lo >= j_hi)
+    return fail(ctx, CI_EINVAL, "search range [%lld, %lld) invalid for n = %lld", (long long)j_lo,
+                (long long)j_hi, (long long)N);
+  if (!isfinite(snr_threshold) || snr_threshold < 0.f)
+    return fail(ctx, CI_EINVAL, "threshold must be finite and >= 0");
+  if (cap < 0) return fail(ctx, CI_EINVAL, "negative capacity");
+  if (!d_count) return fail(ctx, CI_EINVAL, "null d_count");
+  if (n > 0 && !d_peaks) return fail(ctx, CI_EINVAL, "null d_peaks");
+  if (cap > 0 && !d_trig) return fail(ctx, CI_EINVAL, "null d_trig with cap > 0");
+  DeviceGuard dg(ctx->device);
+  if (!dg.ok) return fail(ctx, CI_EHIP, "cannot select device %d", ctx->device);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int64_t nwin = (N + window - 1) / window;
+  int64_t B = default_batch(ctx, N);
+  const int64_t wlimit = (int64_t(1) << 22) / nwin;
+  if (B > wlimit) B = wlimit > 0 ? wlimit : 1;
+  if (B > n) B = n > 0 ? n : 1;
+  TrigWork tw;
+  rc = ensure_trig(ctx, B, nwin, &tw);
+  if (rc != CI_OK) return rc;
+  hipError_t e = launch_init_call(tw, (int)nwin, d_count, st);
+  if (e != hipSuccess) return hipfail(ctx, e, "init launch");
+  if (n == 0) return CI_OK;
+  rc = ensure_ybuf(ctx, sizeof(float2) * 2 * (size_t)B * (size_t)N);
+  if (rc != CI_OK) return rc;
+  BatchArgs a;
+  memset(&a, 0, sizeof a);
+  a.seg = seg;
+  a.bmax = (int)B;
+  a.tw = tw;
+  a.nwin = (int)nwin;
+  a.window = window;
+  a.j_lo = j_lo;
+  a.j_hi = j_hi;
+  a.thr2 = snr_threshold * snr_threshold;
+  a.d_peaks = d_peaks;
+  a.d_trig = d_trig;
+  a.cap = cap;
+  a.d_count = d_count;
+  a.merge = merge_across_templates ? 1 : 0;
+  for (int64_t b = 0, t0 = 0; t0 < n; ++b, t0 += B) {
+    a.t0 = t0;
+    a.nb = (int)((n - t0) < B ? (n - t0) : B);
+    a.slot = (int)(b & 1);
+    a.params = d_params + t0;
+    a.y = static_cast<float2*>(ctx->ybuf) + (size_t)a.slot * B * N;
+    a.last_batch = (t0 + B >= n) ? 1 : 0;
+    e = launch_pass1(a, true, st);
+    if (e != hipSuccess) return hipfail(ctx, e, "pass-1 launch");
+    e = launch_pass2_trig(a, st);
+    if (e != hipSuccess) return hipfail(ctx, e, "pass-2 launch");
+  }
+  return CI_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,117 @@
+// ci_impl.h -- internal structures shared by the host library and kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "../../include/ci.h"
+
+namespace ci {
+
+// Device-resident description of one data chunk.
+struct SegDev {
+  int64_t n;        // samples
+  int64_t half;     // n / 2
+  double fs, f_low, df;
+  int32_t k_low;    // first band bin
+  int32_t log2n;
+  double g;         // power-of-two data scale folded into w
+  double p_total;   // running sum at n/2 - 1
+};
+
+// Four-step factorisation n = N1 x N2 and the workgroup tiling.
+struct Plan {
+  int log2n;
+  int n1, n2;       // pass 1: column DFTs of length n2 over k2 (one per k1)
+                    // pass 2: column DFTs of length n1 over k1 (one per j2)
+  int c;            // k1 columns per pass-1 workgroup
+  int j;            // j2 columns per pass-2 workgroup
+};
+
+Plan plan_for(int log2n);
+
+// Per-call trigger bookkeeping (device).  Two slot sets alternate between
+// consecutive batches so that batch b+1's first pass can clear its keys
+// while batch b's second pass still reads its own.
+struct TrigWork {
+  unsigned long long* pkeys;   // [2][B]        peak key per template
+  unsigned long long* wkeys;   // [2][B][nwin]  window key per template
+  unsigned int* tdone;         // [2][B]        finished pass-2 tiles
+  unsigned int* bdone;         // [2]           finished templates
+  int* cnt;                    // [2][B]        triggers per template
+  int* sidx;                   // [2][B][nwin]  staging slot of window w
+  ci_trigger* stage;           // [2][B][nwin]  compacted triggers
+  ci_trigger* mrec;            // [nwin]        merged record per window
+  unsigned long long* run;     // [1]           triggers placed so far
+};
+
+// Host-side state.
+struct Ctx {
+  int device = 0;
+  std::string err;
+  int64_t batch_override = 0;
+  // intermediate workspace (2 slot sets)
+  void* ybuf = nullptr;
+  size_t ybytes = 0;
+  // trigger workspace
+  void* tbuf = nullptr;
+  size_t tbytes = 0;
+  // pinned staging for parameter upload
+  void* pin = nullptr;
+  size_t pinbytes = 0;
+  hipEvent_t pin_ev = nullptr;
+  bool pin_ev_armed = false;
+};
+
+struct Seg {
+  Ctx* ctx;
+  ci_segment_spec spec;
+  SegDev host;       // host copy (g and p_total are only valid on device)
+  SegDev* dev;       // device copy
+  float2* w;         // [n/2]  PSD-weighted, scaled data spectrum
+  double* psum;      // [n/2]  running sum of 4 df f^-7/3 / S from k_low
+  float2* tw2048;    // [2048] exp(2 pi i e / 2048)
+  float2* twa;       // [2048] exp(2 pi i e / n)
+  float2* twb;       // [n/2048] exp(2 pi i 2048 e / n)
+  Plan plan;
+};
+
+// Kernel launchers (kernels.hip).
+hipError_t launch_segment(Seg* s, const void* d_xtilde, const double* d_psd,
+                          hipStream_t st);
+hipError_t launch_params(const Seg* s, ci_tparams* d_params, int64_t n,
+                         void* d_htilde, hipStream_t st);
+hipError_t launch_init_call(const TrigWork& tw, int nwin, int64_t* d_count,
+                            hipStream_t st);
+
+struct BatchArgs {
+  const Seg* seg;
+  const ci_tparams* params;   // first template of the batch
+  int64_t t0;                 // bank index of the first template
+  int nb;                     // templates in this batch
+  int slot;                   // slot set 0/1
+  int bmax;                   // slot stride (templates per slot set)
+  float2* y;                  // intermediate of this slot set
+  // trigger mode
+  TrigWork tw;
+  int nwin;
+  int64_t window;
+  int64_t j_lo, j_hi;
+  float thr2;
+  ci_trigger* d_peaks;
+  ci_trigger* d_trig;
+  int64_t cap;
+  int64_t* d_count;
+  int merge;
+  int last_batch;
+  // series mode
+  float2* d_z;                // first template's series
+};
+
+hipError_t launch_pass1(const BatchArgs& a, bool zero_trig, hipStream_t st);
+hipError_t launch_pass2_trig(const BatchArgs& a, hipStream_t st);
+hipError_t launch_pass2_series(const BatchArgs& a, hipStream_t st);
+
+}  // namespace ci

@@ -1,0 +1,176 @@
+// fft_device.h -- register/LDS building blocks of the inverse transform.
+//
+// The correlator of eq. (matchedfilter) is taken back to the time domain by
+// an unnormalised inverse DFT, z_j = sum_k Z_k w^{jk}, w = exp(+2 pi i/N)
+// (the paper's device_cufft_C2R step).  On gfx950 it is a four-step
+// transform N = N1 x N2 whose column DFTs (length L = 256 .. 2048) run
+// inside one workgroup: 16 complex values per lane, radix-16 register
+// butterflies, and Stockham exchanges through LDS between stages.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace ci {
+
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) {
+  return make_float2(a.x + b.x, a.y + b.y);
+}
+__device__ __forceinline__ float2 csub(float2 a, float2 b) {
+  return make_float2(a.x - b.x, a.y - b.y);
+}
+// a * b
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+  return make_float2(fmaf(a.x, b.x, -a.y * b.y), fmaf(a.x, b.y, a.y * b.x));
+}
+// a * (+i)
+__device__ __forceinline__ float2 mul_i(float2 a) { return make_float2(-a.y, a.x); }
+// a * (-i)
+__device__ __forceinline__ float2 mul_mi(float2 a) { return make_float2(a.y, -a.x); }
+
+// 4-point inverse DFT in place: y_a = sum_q x_q i^{aq}.
+__device__ __forceinline__ void idft4(float2& x0, float2& x1, float2& x2, float2& x3) {
+  const float2 a = cadd(x0, x2), b = csub(x0, x2);
+  const float2 c = cadd(x1, x3), d = csub(x1, x3);
+  x0 = cadd(a, c);
+  x2 = csub(a, c);
+  x1 = cadd(b, mul_i(d));
+  x3 = csub(b, mul_i(d));
+}
+
+__device__ __forceinline__ void idft2(float2& x0, float2& x1) {
+  const float2 a = x0;
+  x0 = cadd(a, x1);
+  x1 = csub(a, x1);
+}
+
+// Multiply by w16^e = exp(2 pi i e / 16) for a compile-time e.
+template <int E>
+__device__ __forceinline__ float2 tw16(float2 v) {
+  constexpr int e = E & 15;
+  constexpr float C1 = 0.92387953251128674f;  // cos(pi/8)
+  constexpr float S1 = 0.38268343236508977f;  // sin(pi/8)
+  constexpr float R2 = 0.70710678118654752f;  // 1/sqrt(2)
+  if constexpr (e == 0) return v;
+  else if constexpr (e == 4) return mul_i(v);
+  else if constexpr (e == 8) return make_float2(-v.x, -v.y);
+  else if constexpr (e == 12) return mul_mi(v);
+  else if constexpr (e == 2) return make_float2((v.x - v.y) * R2, (v.x + v.y) * R2);
+  else if constexpr (e == 6) return make_float2(-(v.x + v.y) * R2, (v.x - v.y) * R2);
+  else if constexpr (e == 10) return make_float2((v.y - v.x) * R2, -(v.x + v.y) * R2);
+  else if constexpr (e == 14) return make_float2((v.x + v.y) * R2, (v.y - v.x) * R2);
+  else {
+    // general odd multiple of pi/8
+    constexpr float cs[16] = {1.f, C1, R2, S1, 0.f, -S1, -R2, -C1,
+                              -1.f, -C1, -R2, -S1, 0.f, S1, R2, C1};
+    constexpr float c = cs[e], s = cs[(e + 12) & 15];  // sin(t) = cos(t - pi/2)
+    return cmul(v, make_float2(c, s));
+  }
+}
+
+// 16-point inverse DFT in place, X_a = sum_q x_q w16^{aq}, as 4 x 4:
+// q = q1 + 4 q2, a = a1 + 4 a2.
+__device__ __forceinline__ void idft16(float2 (&x)[16]) {
+  float2 A[4][4];  // A[q1][a1]
+#pragma unroll
+  for (int q1 = 0; q1 < 4; ++q1) {
+    float2 y0 = x[q1], y1 = x[q1 + 4], y2 = x[q1 + 8], y3 = x[q1 + 12];
+    idft4(y0, y1, y2, y3);
+    A[q1][0] = y0; A[q1][1] = y1; A[q1][2] = y2; A[q1][3] = y3;
+  }
+  A[1][1] = tw16<1>(A[1][1]); A[1][2] = tw16<2>(A[1][2]); A[1][3] = tw16<3>(A[1][3]);
+  A[2][1] = tw16<2>(A[2][1]); A[2][2] = tw16<4>(A[2][2]); A[2][3] = tw16<6>(A[2][3]);
+  A[3][1] = tw16<3>(A[3][1]); A[3][2] = tw16<6>(A[3][2]); A[3][3] = tw16<9>(A[3][3]);
+#pragma unroll
+  for (int a1 = 0; a1 < 4; ++a1) {
+    float2 y0 = A[0][a1], y1 = A[1][a1], y2 = A[2][a1], y3 = A[3][a1];
+    idft4(y0, y1, y2, y3);
+    x[a1] = y0; x[a1 + 4] = y1; x[a1 + 8] = y2; x[a1 + 12] = y3;
+  }
+}
+
+// 8-point inverse DFT on x[o .. o+7]: q = q1 + 2 q2, a = a1 + 4 a2.
+template <int O>
+__device__ __forceinline__ void idft8(float2 (&x)[16]) {
+  float2 e0 = x[O + 0], e1 = x[O + 2], e2 = x[O + 4], e3 = x[O + 6];
+  float2 o0 = x[O + 1], o1 = x[O + 3], o2 = x[O + 5], o3 = x[O + 7];
+  idft4(e0, e1, e2, e3);
+  idft4(o0, o1, o2, o3);
+  o1 = tw16<2>(o1);  // w8^1
+  o2 = mul_i(o2);    // w8^2
+  o3 = tw16<6>(o3);  // w8^3
+  x[O + 0] = cadd(e0, o0); x[O + 4] = csub(e0, o0);
+  x[O + 1] = cadd(e1, o1); x[O + 5] = csub(e1, o1);
+  x[O + 2] = cadd(e2, o2); x[O + 6] = csub(e2, o2);
+  x[O + 3] = cadd(e3, o3); x[O + 7] = csub(e3, o3);
+}
+
+// Radix-R3 DFTs on the 16/R3 groups x[i R3 .. i R3 + R3).
+template <int R3>
+__device__ __forceinline__ void idft_groups(float2 (&x)[16]) {
+  if constexpr (R3 == 2) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) idft2(x[2 * i], x[2 * i + 1]);
+  } else if constexpr (R3 == 4) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) idft4(x[4 * i], x[4 * i + 1], x[4 * i + 2], x[4 * i + 3]);
+  } else if constexpr (R3 == 8) {
+    idft8<0>(x);
+    idft8<8>(x);
+  }
+}
+
+// Column DFT of length L = 256 R3 over NC columns held by a workgroup of
+// NC * L/16 lanes.  Lane (c, t) with t in [0, L/16) enters with
+// x[q] = X_c[t + (L/16) q] and leaves holding, for register r,
+//   R3 == 1:  x[r] = Y_c[t + 16 r]
+//   R3 >  1:  x[i R3 + b] = Y_c[t + (L/16) i + 256 b]
+// where Y_c[j] = sum_s X_c[s] exp(2 pi i js/L).  Three Stockham steps:
+//   1) radix 16 over s = t + (L/16) m, twiddle w_L^{a t};
+//   2) radix 16 over the next digit, twiddle w_{16 R3}^{a2 s2};
+//   3) radix R3.
+// tw: exp(2 pi i e / 2048) for e in [0, 2048).  lds: L * NC float2.
+template <int L, int NC>
+__device__ __forceinline__ void fft_col(float2 (&x)[16], float2* lds, int t, int c,
+                                        const float2* __restrict__ tw) {
+  constexpr int Lp = L / 16;
+  constexpr int R3 = L / 256;
+  static_assert(R3 == 1 || R3 == 2 || R3 == 4 || R3 == 8, "L in 256..2048");
+
+  idft16(x);
+#pragma unroll
+  for (int a = 1; a < 16; ++a) x[a] = cmul(x[a], tw[(a * t) * (2048 / L)]);
+#pragma unroll
+  for (int a = 0; a < 16; ++a) lds[(a * Lp + t) * NC + c] = x[a];
+  __syncthreads();
+
+  const int a0 = t / R3, s2 = t % R3;
+#pragma unroll
+  for (int q = 0; q < 16; ++q) x[q] = lds[(a0 * Lp + s2 + R3 * q) * NC + c];
+  idft16(x);
+  if constexpr (R3 > 1) {
+#pragma unroll
+    for (int a2 = 1; a2 < 16; ++a2) x[a2] = cmul(x[a2], tw[(a2 * s2) * (2048 / (16 * R3))]);
+    __syncthreads();
+#pragma unroll
+    for (int a2 = 0; a2 < 16; ++a2) lds[((a0 + 16 * a2) * R3 + s2) * NC + c] = x[a2];
+    __syncthreads();
+    constexpr int G = 16 / R3;
+#pragma unroll
+    for (int i = 0; i < G; ++i) {
+      const int d = t + Lp * i;
+#pragma unroll
+      for (int s = 0; s < R3; ++s) x[i * R3 + s] = lds[(d * R3 + s) * NC + c];
+    }
+    idft_groups<R3>(x);
+  }
+}
+
+// Output index (within the column) held in register r after fft_col.
+template <int L>
+__device__ __forceinline__ int fft_col_out(int t, int r) {
+  constexpr int R3 = L / 256;
+  if constexpr (R3 == 1) return t + 16 * r;
+  else return t + (L / 16) * (r / R3) + 256 * (r % R3);
+}
+
+}  // namespace ci

@@ -1,0 +1,754 @@
+// kernels.hip -- gfx950 kernels of the batched matched-filter search.
+//
+// Per template (the per-template loop of the "Matched filtering" section):
+//   pass 1: generate the chirp bins on chip, form the correlator integrand
+//           Z_k = 4 df x~_k conj(h~_k) / (S_k sigma), and run the first
+//           four-step pass (column DFTs over k2 for a tile of k1), writing
+//           the twiddled intermediate once;
+//   pass 2: read it once, run the second pass (column DFTs over k1 for a
+//           tile of j2), and reduce |z|^2 to the peak and the window
+//           maxima above threshold on the fly (or store the series).
+// Template normalisation (sigma^2) is one lookup in the chunk's FP64
+// running sum; the chirp phase is evaluated in FP64 and reduced mod 2 pi
+// before FP32 trigonometry.
+#include <hip/hip_runtime.h>
+
+#include "ci_impl.h"
+#include "fft_device.h"
+
+namespace ci {
+
+typedef unsigned long long u64;
+
+// ---------------------------------------------------------------------------
+// chirp phase
+// ---------------------------------------------------------------------------
+
+// Fractional part (revolutions, in [-1/2, 1/2]) of Psi_k / (2 pi) for the
+// restricted 2PN stationary-phase chirp with t_c = phi_c = 0:
+//   Psi/(2 pi) = -1/8 + c0 u^5 + c2 u^3 + c3 u^2 + c4 u,  u = (x0 k)^{-1/3}.
+// u starts from an FP32 estimate and takes one FP64 Newton step
+// (u <- u (4 - x u^3) / 3), enough for ~1e-13 relative error; the
+// polynomial and the reduction mod 1 are FP64, so the phase error stays
+// below 1e-7 rad even where |Psi| reaches 1e5 rad.
+__device__ __forceinline__ float phase_frac(const ci_tparams& P, int k) {
+  const double x = P.x0 * (double)k;
+  const float y0 = __builtin_amdgcn_exp2f(-0.333333343f * __builtin_amdgcn_logf((float)x));
+  double u = (double)y0;
+  u = u * (4.0 - x * (u * u * u)) * (1.0 / 3.0);
+  const double in = fma(u * u, P.c0, P.c2);
+  const double t3 = fma(u, in, P.c3);
+  const double t4 = fma(u, t3, P.c4);
+  const double r = fma(u, t4, -0.125);
+  return (float)(r - rint(r));
+}
+
+// ---------------------------------------------------------------------------
+// segment setup (once per data chunk)
+// ---------------------------------------------------------------------------
+
+// Running FP64 sum P[k] = 4 df sum_{k'=k_low}^{k} f^{-7/3} / S (0 below
+// k_low) and the power-of-two data scale g.  One workgroup.
+__global__ __launch_bounds__(1024) void k_seg_psum(SegDev* sd, const double* __restrict__ psd,
+                                                   double* __restrict__ psum) {
+  __shared__ double sh[1024];
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int64_t half = sd->half;
+  const int64_t kl = sd->k_low;
+  const double df = sd->df;
+  const int64_t len = half - kl;
+  const int64_t per = (len + nt - 1) / nt;
+  const int64_t a = kl + (int64_t)tid * per;
+  const int64_t b = (a + per < half) ? a + per : half;
+  double s = 0.0;
+  for (int64_t k = a; k < b; ++k) s += pow((double)k * df, -7.0 / 3.0) / psd[k];
+  sh[tid] = s;
+  __syncthreads();
+  // inclusive Hillis-Steele scan of the per-thread sums
+  for (int off = 1; off < nt; off <<= 1) {
+    const double v = (tid >= off) ? sh[tid - off] : 0.0;
+    __syncthreads();
+    sh[tid] += v;
+    __syncthreads();
+  }
+  double run = sh[tid] - s;
+  for (int64_t k = a; k < b; ++k) {
+    run += pow((double)k * df, -7.0 / 3.0) / psd[k];
+    psum[k] = 4.0 * df * run;
+  }
+  for (int64_t k = tid; k < kl; k += nt) psum[k] = 0.0;
+  if (tid == nt - 1) {
+    const double tot = 4.0 * df * sh[nt - 1];
+    sd->p_total = tot;
+    // E|x~ f^{-7/6} / S|^2 = (T/2) f^{-7/3} / S for data with PSD S: scale
+    // the weighted spectrum to unit mean power by an exact power of two.
+    const double T = (double)sd->n / sd->fs;
+    const double mean = 0.5 * T * (tot / (4.0 * df)) / (double)len;
+    sd->g = exp2(rint(-0.5 * log2(mean)));
+  }
+}
+
+// w_k = g x~_k f_k^{-7/6} / S_k on [k_low, n/2), 0 elsewhere (FP64 -> FP32).
+__global__ __launch_bounds__(256) void k_seg_w(const SegDev* __restrict__ sd,
+                                               const float2* __restrict__ xt,
+                                               const double* __restrict__ psd,
+                                               float2* __restrict__ w) {
+  const int64_t half = sd->half;
+  const int64_t kl = sd->k_low;
+  const double df = sd->df, g = sd->g;
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < half;
+       k += (int64_t)gridDim.x * blockDim.x) {
+    float2 o = make_float2(0.f, 0.f);
+    if (k >= kl) {
+      const double fac = g * pow((double)k * df, -7.0 / 6.0) / psd[k];
+      const float2 x = xt[k];
+      o = make_float2((float)((double)x.x * fac), (float)((double)x.y * fac));
+    }
+    w[k] = o;
+  }
+}
+
+// sigma^2 and the per-template scale 4 df / (sigma g).
+__global__ __launch_bounds__(256) void k_params(const SegDev* __restrict__ sd,
+                                                const double* __restrict__ psum,
+                                                ci_tparams* __restrict__ prm, int64_t n) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  ci_tparams P = prm[i];
+  if (P.flags & CI_TMPL_EMPTY) {
+    P.sigma2 = 0.0;
+    P.scale = 0.f;
+  } else {
+    P.sigma2 = psum[P.k_high];
+    P.scale = (float)(4.0 * sd->df / (sqrt(P.sigma2) * sd->g));
+  }
+  prm[i] = P;
+}
+
+// Materialised templates h~_k = f^{-7/6} exp(-i Psi_k) in the band, 0 out.
+__global__ __launch_bounds__(256) void k_htilde(const SegDev* __restrict__ sd,
+                                                const ci_tparams* __restrict__ prm,
+                                                float2* __restrict__ h) {
+  const int64_t t = blockIdx.y;
+  const ci_tparams P = prm[t];
+  const int64_t m = sd->half + 1;
+  float2* ht = h + t * m;
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < m;
+       k += (int64_t)gridDim.x * blockDim.x) {
+    float2 o = make_float2(0.f, 0.f);
+    if (k >= P.k_low && k <= P.k_high) {
+      const float fr = phase_frac(P, (int)k);
+      float s, c;
+      sincospif(2.0f * fr, &s, &c);
+      const float amp = (float)pow((double)k * sd->df, -7.0 / 6.0);
+      o = make_float2(amp * c, -amp * s);
+    }
+    ht[k] = o;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// workgroup -> tile mapping
+// ---------------------------------------------------------------------------
+
+// Consecutive workgroup ids are dealt round-robin over the 8 XCDs; remap
+// them so that each XCD walks a contiguous range of tiles (neighbouring
+// k1 tiles share cache lines of the weighted spectrum).
+__device__ __forceinline__ int xcd_remap(int bid, int nblk) {
+  if ((nblk & 7) != 0) return bid;
+  return (bid & 7) * (nblk >> 3) + (bid >> 3);
+}
+
+// ---------------------------------------------------------------------------
+// pass 1: generate + correlate + first four-step pass
+// ---------------------------------------------------------------------------
+
+struct P1Args {
+  const ci_tparams* prm;   // batch's first template
+  const float2* w;         // weighted data spectrum [n/2]
+  const float2* tw;        // exp(2 pi i e / 2048)
+  const float2* twa;       // exp(2 pi i e / n), e < 2048
+  const float2* twb;       // exp(2 pi i 2048 e / n)
+  float2* y;               // intermediate, [nb][n] in tile layout
+  // per-batch trigger state to clear (null when not searching)
+  u64* pkeys;
+  u64* wkeys;
+  unsigned int* tdone;
+  unsigned int* bdone;
+  int64_t nzero_w;         // entries of wkeys to clear
+  int nb;
+};
+
+template <int N1, int N2, int C>
+__global__ __launch_bounds__(C * N2 / 16) void k_pass1(P1Args a) {
+  constexpr int N = N1 * N2;
+  constexpr int Lp = N2 / 16;
+  constexpr int TILES = N1 / C;
+  extern __shared__ float2 lds[];
+  const int tid = threadIdx.x;
+  const int c = tid % C, t = tid / C;
+
+  if (a.pkeys) {
+    const int64_t gid = blockIdx.x * (int64_t)blockDim.x + tid;
+    const int64_t gsz = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = gid; i < a.nzero_w; i += gsz) a.wkeys[i] = 0ull;
+    for (int64_t i = gid; i < a.nb; i += gsz) {
+      a.pkeys[i] = 0ull;
+      a.tdone[i] = 0u;
+    }
+    if (gid == 0) a.bdone[0] = 0u;
+  }
+
+  const int bid = xcd_remap(blockIdx.x, gridDim.x);
+  const int b = bid / TILES, tile = bid % TILES;
+  const ci_tparams P = a.prm[b];
+  const int k1 = tile * C + c;
+
+  float2 x[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int k = k1 + N1 * (t + Lp * q);
+    float2 v = make_float2(0.f, 0.f);
+    if (k >= P.k_low && k <= P.k_high) {
+      const float fr = phase_frac(P, k);
+      float s, co;
+      sincospif(2.0f * fr, &s, &co);
+      v = cmul(a.w[k], make_float2(co * P.scale, s * P.scale));
+    }
+    x[q] = v;
+  }
+
+  fft_col<N2, C>(x, lds, t, c, a.tw);
+
+  float2* yt = a.y + (size_t)b * N + (size_t)tile * N2 * C;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int j2 = fft_col_out<N2>(t, r);
+    const int e = j2 * k1;  // < N
+    const float2 wv = cmul(a.twa[e & 2047], a.twb[e >> 11]);
+    yt[j2 * C + c] = cmul(x[r], wv);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// pass 2 helpers
+// ---------------------------------------------------------------------------
+
+// Load the pass-2 column inputs: lane (cc, t) of tile `tile` gets
+// x[q] = Y[k1 = t + (N1/16) q][j2 = tile J + cc].
+template <int N1, int N2, int C, int J>
+__device__ __forceinline__ void load_pass2(float2 (&x)[16], const float2* __restrict__ yb, int j2,
+                                           int t) {
+  constexpr int Lp = N1 / 16;
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int k1 = t + Lp * q;
+    x[q] = yb[((size_t)(k1 / C) * N2 + j2) * C + (k1 % C)];
+  }
+}
+
+// z_j = sum_{k1} exp(2 pi i j1 k1 / N1) Y[k1][j2] for j = j2 + N2 j1, with
+// FP64 twiddles and accumulation, reduced over the workgroup.  Every lane
+// returns the result.  scratch: >= 2 * blockDim.x doubles.
+template <int N1, int N2, int C>
+__device__ double2 direct_z(const float2* __restrict__ yb, int64_t j, double* scratch) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int j2 = (int)(j % N2), j1 = (int)(j / N2);
+  double re = 0.0, im = 0.0;
+  for (int k1 = tid; k1 < N1; k1 += nt) {
+    const float2 v = yb[((size_t)(k1 / C) * N2 + j2) * C + (k1 % C)];
+    const int e = (int)(((int64_t)j1 * k1) % N1);
+    double s, c;
+    sincospi(2.0 * (double)e / (double)N1, &s, &c);
+    re += (double)v.x * c - (double)v.y * s;
+    im += (double)v.x * s + (double)v.y * c;
+  }
+  __syncthreads();
+  scratch[2 * tid] = re;
+  scratch[2 * tid + 1] = im;
+  __syncthreads();
+  for (int off = nt / 2; off > 0; off >>= 1) {
+    if (tid < off) {
+      scratch[2 * tid] += scratch[2 * (tid + off)];
+      scratch[2 * tid + 1] += scratch[2 * (tid + off) + 1];
+    }
+    __syncthreads();
+  }
+  const double2 z = make_double2(scratch[0], scratch[1]);
+  __syncthreads();
+  return z;
+}
+
+__device__ __forceinline__ u64 aload(const u64* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Exclusive scan of one int per lane over the workgroup (Hillis-Steele in
+// LDS).  Returns the exclusive prefix; *total receives the sum.
+__device__ int block_excl_scan(int v, int* sh, int* total) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+  __syncthreads();
+  sh[tid] = v;
+  __syncthreads();
+  for (int off = 1; off < nt; off <<= 1) {
+    const int u = (tid >= off) ? sh[tid - off] : 0;
+    __syncthreads();
+    sh[tid] += u;
+    __syncthreads();
+  }
+  const int incl = sh[tid];
+  *total = sh[nt - 1];
+  __syncthreads();
+  return incl - v;
+}
+
+struct P2Args {
+  const ci_tparams* prm;     // batch's first template
+  const float2* tw;
+  const float2* y;           // intermediate of this batch
+  int64_t t0;                // bank index of the batch's first template
+  int nb;
+  // trigger mode
+  u64* pkeys;                // [nb]
+  u64* wkeys;                // [nb][nwin]
+  unsigned int* tdone;       // [nb]
+  unsigned int* bdone;       // [1]
+  int* cnt;                  // [nb]
+  int* sidx;                 // [nb][nwin]
+  ci_trigger* stage;         // [nb][nwin]
+  ci_trigger* mrec;          // [nwin]
+  u64* run;                  // [1]
+  int nwin;
+  int64_t window;
+  int64_t j_lo, j_hi;
+  float thr2;
+  ci_trigger* d_peaks;       // whole bank
+  ci_trigger* d_trig;
+  int64_t cap;
+  int64_t* d_count;
+  int merge;
+  int last_batch;
+  // series mode
+  float2* z;                 // batch's first series
+};
+
+// Peak and triggers of template b once all its pass-2 tiles are done.
+template <int N1, int N2, int C>
+__device__ void finalize_template(const P2Args& a, int b, void* ldsv) {
+  constexpr int N = N1 * N2;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  double* dscr = reinterpret_cast<double*>(ldsv);
+  int* iscr = reinterpret_cast<int*>(ldsv);
+  const ci_tparams P = a.prm[b];
+  const int64_t tg = a.t0 + b;
+  const float2* yb = a.y + (size_t)b * N;
+  const u64 pk = aload(&a.pkeys[b]);
+  if ((P.flags & CI_TMPL_EMPTY) || pk == 0ull) {
+    if (tid == 0) {
+      ci_trigger e;
+      e.tmpl = tg; e.index = -1; e.rho2 = 0.f; e.re = 0.f; e.im = 0.f; e.window = -1;
+      a.d_peaks[tg] = e;
+      a.cnt[b] = 0;
+    }
+    return;
+  }
+  {
+    const int64_t j = (int64_t)(0xFFFFFFFFu - (unsigned int)(pk & 0xFFFFFFFFull));
+    const double2 z = direct_z<N1, N2, C>(yb, j, dscr);
+    if (tid == 0) {
+      ci_trigger e;
+      e.tmpl = tg; e.index = j; e.rho2 = __uint_as_float((unsigned int)(pk >> 32));
+      e.re = (float)z.x; e.im = (float)z.y; e.window = (int)(j / a.window);
+      a.d_peaks[tg] = e;
+    }
+  }
+  // compact the windows whose key is set, in window order
+  const u64* wk = a.wkeys + (size_t)b * a.nwin;
+  const int per = (a.nwin + nt - 1) / nt;
+  const int w0 = tid * per;
+  const int w1 = min(w0 + per, a.nwin);
+  int mine = 0;
+  for (int w = w0; w < w1; ++w) mine += (aload(&wk[w]) != 0ull);
+  if (__syncthreads_or(mine) == 0) {
+    if (tid == 0) a.cnt[b] = 0;
+    return;
+  }
+  int total = 0;
+  int pos = block_excl_scan(mine, iscr, &total);
+  ci_trigger* st = a.stage + (size_t)b * a.nwin;
+  int* sx = a.sidx + (size_t)b * a.nwin;
+  for (int w = w0; w < w1; ++w) {
+    const u64 key = aload(&wk[w]);
+    if (key != 0ull) {
+      ci_trigger e;
+      e.tmpl = tg;
+      e.index = (int64_t)(0xFFFFFFFFu - (unsigned int)(key & 0xFFFFFFFFull));
+      e.rho2 = __uint_as_float((unsigned int)(key >> 32));
+      e.re = 0.f; e.im = 0.f; e.window = w;
+      st[pos] = e;
+      sx[w] = pos;
+      ++pos;
+    }
+  }
+  __threadfence_block();
+  __syncthreads();
+  for (int i = 0; i < total; ++i) {
+    const int64_t j = st[i].index;
+    const double2 z = direct_z<N1, N2, C>(yb, j, dscr);
+    if (tid == 0) {
+      st[i].re = (float)z.x;
+      st[i].im = (float)z.y;
+    }
+  }
+  if (tid == 0) a.cnt[b] = total;
+}
+
+// Place the batch's triggers into the caller's list (or merge them), once
+// every template of the batch is finalised.
+__device__ void place_batch(const P2Args& a, void* ldsv) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+  int* iscr = reinterpret_cast<int*>(ldsv);
+  if (!a.merge) {
+    // offsets in template order
+    __shared__ long long s_base;
+    if (tid == 0) s_base = (long long)a.run[0];
+    __syncthreads();
+    const long long base = s_base;
+    long long acc = 0;
+    // serial prefix over the batch (nb is small)
+    if (tid == 0) {
+      for (int b = 0; b < a.nb; ++b) {
+        iscr[b] = (int)acc;
+        acc += a.cnt[b];
+      }
+      a.run[0] = (u64)(base + acc);
+      a.d_count[0] = base + acc;
+    }
+    __syncthreads();
+    for (int b = tid; b < a.nb; b += nt) {
+      const int c = a.cnt[b];
+      const ci_trigger* st = a.stage + (size_t)b * a.nwin;
+      for (int i = 0; i < c; ++i) {
+        const long long p = base + iscr[b] + i;
+        if (p < a.cap) a.d_trig[p] = st[i];
+      }
+    }
+    return;
+  }
+  // merge: per window, largest rho^2 over templates, earlier template wins ties
+  for (int w = tid; w < a.nwin; w += nt) {
+    ci_trigger best = a.mrec[w];
+    for (int b = 0; b < a.nb; ++b) {
+      const u64 key = aload(&a.wkeys[(size_t)b * a.nwin + w]);
+      if (key == 0ull) continue;
+      const float r2 = __uint_as_float((unsigned int)(key >> 32));
+      if (best.tmpl < 0 || r2 > best.rho2)
+        best = a.stage[(size_t)b * a.nwin + a.sidx[(size_t)b * a.nwin + w]];
+    }
+    a.mrec[w] = best;
+  }
+  if (!a.last_batch) return;
+  __syncthreads();
+  // compact the merged records in window order
+  const int per = (a.nwin + nt - 1) / nt;
+  const int w0 = tid * per;
+  const int w1 = min(w0 + per, a.nwin);
+  int mine = 0;
+  for (int w = w0; w < w1; ++w) mine += (a.mrec[w].tmpl >= 0);
+  int total = 0;
+  int pos = block_excl_scan(mine, iscr, &total);
+  for (int w = w0; w < w1; ++w) {
+    if (a.mrec[w].tmpl >= 0) {
+      if (pos < a.cap) a.d_trig[pos] = a.mrec[w];
+      ++pos;
+    }
+  }
+  if (tid == 0) a.d_count[0] = total;
+}
+
+// ---------------------------------------------------------------------------
+// pass 2: second four-step pass + post-pass
+// ---------------------------------------------------------------------------
+
+template <int N1, int N2, int C, int J>
+__global__ __launch_bounds__(J * N1 / 16) void k_pass2_trig(P2Args a) {
+  constexpr int N = N1 * N2;
+  constexpr int TILES = N2 / J;
+  extern __shared__ float2 lds[];
+  const int tid = threadIdx.x;
+  const int cc = tid % J, t = tid / J;
+  const int bid = xcd_remap(blockIdx.x, gridDim.x);
+  const int b = bid / TILES, tile = bid % TILES;
+  const int j2 = tile * J + cc;
+  const float2* yb = a.y + (size_t)b * N;
+
+  float2 x[16];
+  load_pass2<N1, N2, C, J>(x, yb, j2, t);
+  fft_col<N1, J>(x, lds, t, cc, a.tw);
+
+  u64 best = 0ull;
+  u64* wk = a.wkeys + (size_t)b * a.nwin;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int j1 = fft_col_out<N1>(t, r);
+    const int j = j2 + N2 * j1;
+    const float r2 = fmaf(x[r].x, x[r].x, x[r].y * x[r].y);
+    if (j >= a.j_lo && j < a.j_hi) {
+      const u64 key = ((u64)__float_as_uint(r2) << 32) | (u64)(0xFFFFFFFFu - (unsigned int)j);
+      best = key > best ? key : best;
+      if (r2 > a.thr2) atomicMax(&wk[j / a.window], key);
+    }
+  }
+  // workgroup max of the peak key
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const u64 o = __shfl_xor(best, off, 64);
+    best = o > best ? o : best;
+  }
+  __shared__ u64 s_best[16];
+  __shared__ int s_flag;
+  __syncthreads();
+  if ((tid & 63) == 0) s_best[tid >> 6] = best;
+  __syncthreads();
+  if (tid == 0) {
+    u64 m = 0ull;
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) m = s_best[i] > m ? s_best[i] : m;
+    atomicMax(&a.pkeys[b], m);
+  }
+  __threadfence();
+  __syncthreads();
+  if (tid == 0) s_flag = (atomicAdd(&a.tdone[b], 1u) == (unsigned int)(TILES - 1));
+  __syncthreads();
+  if (!s_flag) return;
+  __threadfence();
+  finalize_template<N1, N2, C>(a, b, lds);
+  __threadfence();
+  __syncthreads();
+  if (tid == 0) s_flag = (atomicAdd(&a.bdone[0], 1u) == (unsigned int)(a.nb - 1));
+  __syncthreads();
+  if (!s_flag) return;
+  __threadfence();
+  place_batch(a, lds);
+}
+
+template <int N1, int N2, int C, int J>
+__global__ __launch_bounds__(J * N1 / 16) void k_pass2_series(P2Args a) {
+  constexpr int N = N1 * N2;
+  constexpr int TILES = N2 / J;
+  extern __shared__ float2 lds[];
+  const int tid = threadIdx.x;
+  const int cc = tid % J, t = tid / J;
+  const int bid = xcd_remap(blockIdx.x, gridDim.x);
+  const int b = bid / TILES, tile = bid % TILES;
+  const int j2 = tile * J + cc;
+  const float2* yb = a.y + (size_t)b * N;
+
+  float2 x[16];
+  load_pass2<N1, N2, C, J>(x, yb, j2, t);
+  fft_col<N1, J>(x, lds, t, cc, a.tw);
+
+  float2* zt = a.z + (size_t)b * N;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int j1 = fft_col_out<N1>(t, r);
+    zt[j2 + N2 * j1] = x[r];
+  }
+}
+
+__global__ void k_init_call(ci_trigger* mrec, int nwin, u64* run, int64_t* d_count) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nwin) {
+    ci_trigger e;
+    e.tmpl = -1; e.index = -1; e.rho2 = -1.f; e.re = 0.f; e.im = 0.f; e.window = -1;
+    mrec[i] = e;
+  }
+  if (i == 0) {
+    run[0] = 0ull;
+    d_count[0] = 0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// host launchers
+// ---------------------------------------------------------------------------
+
+Plan plan_for(int log2n) {
+  Plan p;
+  p.log2n = log2n;
+  switch (log2n) {
+    case 16: p.n1 = 256; p.n2 = 256; break;
+    case 17: p.n1 = 512; p.n2 = 256; break;
+    case 18: p.n1 = 512; p.n2 = 512; break;
+    case 19: p.n1 = 1024; p.n2 = 512; break;
+    case 20: p.n1 = 1024; p.n2 = 1024; break;
+    case 21: p.n1 = 2048; p.n2 = 1024; break;
+    default: p.n1 = p.n2 = 0;
+  }
+  p.c = 8;
+  p.j = 8;
+  return p;
+}
+
+hipError_t launch_segment(Seg* s, const void* d_xtilde, const double* d_psd, hipStream_t st) {
+  hipLaunchKernelGGL(k_seg_psum, dim3(1), dim3(1024), 0, st, s->dev, d_psd, s->psum);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int64_t half = s->host.half;
+  int blocks = (int)((half + 255) / 256);
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_seg_w, dim3(blocks), dim3(256), 0, st, s->dev,
+                     reinterpret_cast<const float2*>(d_xtilde), d_psd, s->w);
+  return hipGetLastError();
+}
+
+hipError_t launch_params(const Seg* s, ci_tparams* d_params, int64_t n, void* d_htilde,
+                         hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_params, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, s->dev,
+                     s->psum, d_params, n);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || d_htilde == nullptr) return e;
+  const int64_t m = s->host.half + 1;
+  int bx = (int)((m + 255) / 256);
+  if (bx > 1024) bx = 1024;
+  for (int64_t t0 = 0; t0 < n; t0 += 65535) {
+    const int64_t cnt = (n - t0 < 65535) ? n - t0 : 65535;
+    hipLaunchKernelGGL(k_htilde, dim3(bx, (unsigned)cnt), dim3(256), 0, st, s->dev,
+                       d_params + t0, reinterpret_cast<float2*>(d_htilde) + t0 * m);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_init_call(const TrigWork& tw, int nwin, int64_t* d_count, hipStream_t st) {
+  const int blocks = (nwin + 255) / 256 + 1;
+  hipLaunchKernelGGL(k_init_call, dim3(blocks), dim3(256), 0, st, tw.mrec, nwin, tw.run,
+                     d_count);
+  return hipGetLastError();
+}
+
+namespace {
+
+template <typename K>
+hipError_t set_lds(K kern, size_t bytes) {
+  if (bytes <= 65536) return hipSuccess;
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+P1Args make_p1(const BatchArgs& a, bool zero_trig) {
+  P1Args p;
+  p.prm = a.params;
+  p.w = a.seg->w;
+  p.tw = a.seg->tw2048;
+  p.twa = a.seg->twa;
+  p.twb = a.seg->twb;
+  p.y = a.y;
+  p.nb = a.nb;
+  if (zero_trig) {
+    const int s = a.slot;
+    p.pkeys = a.tw.pkeys + (size_t)s * a.bmax;
+    p.wkeys = a.tw.wkeys + (size_t)s * a.bmax * a.nwin;
+    p.tdone = a.tw.tdone + (size_t)s * a.bmax;
+    p.bdone = a.tw.bdone + s;
+    p.nzero_w = (int64_t)a.nb * a.nwin;
+  } else {
+    p.pkeys = nullptr;
+    p.wkeys = nullptr;
+    p.tdone = nullptr;
+    p.bdone = nullptr;
+    p.nzero_w = 0;
+  }
+  return p;
+}
+
+P2Args make_p2(const BatchArgs& a) {
+  P2Args p;
+  const int s = a.slot;
+  p.prm = a.params;
+  p.tw = a.seg->tw2048;
+  p.y = a.y;
+  p.t0 = a.t0;
+  p.nb = a.nb;
+  p.pkeys = a.tw.pkeys ? a.tw.pkeys + (size_t)s * a.bmax : nullptr;
+  p.wkeys = a.tw.wkeys ? a.tw.wkeys + (size_t)s * a.bmax * a.nwin : nullptr;
+  p.tdone = a.tw.tdone ? a.tw.tdone + (size_t)s * a.bmax : nullptr;
+  p.bdone = a.tw.bdone ? a.tw.bdone + s : nullptr;
+  p.cnt = a.tw.cnt ? a.tw.cnt + (size_t)s * a.bmax : nullptr;
+  p.sidx = a.tw.sidx ? a.tw.sidx + (size_t)s * a.bmax * a.nwin : nullptr;
+  p.stage = a.tw.stage ? a.tw.stage + (size_t)s * a.bmax * a.nwin : nullptr;
+  p.mrec = a.tw.mrec;
+  p.run = a.tw.run;
+  p.nwin = a.nwin;
+  p.window = a.window;
+  p.j_lo = a.j_lo;
+  p.j_hi = a.j_hi;
+  p.thr2 = a.thr2;
+  p.d_peaks = a.d_peaks;
+  p.d_trig = a.d_trig;
+  p.cap = a.cap;
+  p.d_count = a.d_count;
+  p.merge = a.merge;
+  p.last_batch = a.last_batch;
+  p.z = a.d_z;
+  return p;
+}
+
+template <int N1, int N2, int C, int J>
+struct Inst {
+  static hipError_t p1(const BatchArgs& a, bool zero, hipStream_t st) {
+    const size_t lds = (size_t)N2 * C * sizeof(float2);
+    auto kern = k_pass1<N1, N2, C>;
+    hipError_t e = set_lds(kern, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(kern, dim3((unsigned)(a.nb * (N1 / C))), dim3(C * N2 / 16), lds, st,
+                       make_p1(a, zero));
+    return hipGetLastError();
+  }
+  static hipError_t p2t(const BatchArgs& a, hipStream_t st) {
+    const size_t lds = (size_t)N1 * J * sizeof(float2);
+    auto kern = k_pass2_trig<N1, N2, C, J>;
+    hipError_t e = set_lds(kern, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(kern, dim3((unsigned)(a.nb * (N2 / J))), dim3(J * N1 / 16), lds, st,
+                       make_p2(a));
+    return hipGetLastError();
+  }
+  static hipError_t p2s(const BatchArgs& a, hipStream_t st) {
+    const size_t lds = (size_t)N1 * J * sizeof(float2);
+    auto kern = k_pass2_series<N1, N2, C, J>;
+    hipError_t e = set_lds(kern, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(kern, dim3((unsigned)(a.nb * (N2 / J))), dim3(J * N1 / 16), lds, st,
+                       make_p2(a));
+    return hipGetLastError();
+  }
+};
+
+template <typename F>
+hipError_t dispatch(int log2n, F f) {
+  switch (log2n) {
+    case 16: return f(Inst<256, 256, 8, 8>());
+    case 17: return f(Inst<512, 256, 8, 8>());
+    case 18: return f(Inst<512, 512, 8, 8>());
+    case 19: return f(Inst<1024, 512, 8, 8>());
+    case 20: return f(Inst<1024, 1024, 8, 8>());
+    case 21: return f(Inst<2048, 1024, 8, 8>());
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_pass1(const BatchArgs& a, bool zero_trig, hipStream_t st) {
+  return dispatch(a.seg->plan.log2n, [&](auto inst) { return decltype(inst)::p1(a, zero_trig, st); });
+}
+hipError_t launch_pass2_trig(const BatchArgs& a, hipStream_t st) {
+  return dispatch(a.seg->plan.log2n, [&](auto inst) { return decltype(inst)::p2t(a, st); });
+}
+hipError_t launch_pass2_series(const BatchArgs& a, hipStream_t st) {
+  return dispatch(a.seg->plan.log2n, [&](auto inst) { return decltype(inst)::p2s(a, st); });
+}
+
+}  // namespace ci
