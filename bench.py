@@ -1,0 +1,241 @@
+#!/usr/bin/env python3
+"""Throughput of the batched matched-filter search on one MI355X.
+
+One step is one pass of the whole search over one data chunk: segment
+setup (PSD weighting and the FP64 running sum for sigma^2), the bank's
+generator constants, and the search itself (on-chip chirp generation,
+correlation, the inverse transform, |z|^2 peaks, threshold triggers per
+window and their merge across templates).  Inputs are resident in HBM when
+the timed region starts.  The default workload is the 2^20-sample (256 s at
+4096 Hz), 1024-template FP32 search with five injections.
+
+Prints one JSON line.  The dominant kernel's roofline figure uses its
+algorithmic bytes per launch (the FP32 intermediate: 8 n bytes written by
+pass 1 or read by pass 2, per template) over its average launch time,
+measured with HIP events on the launch stream.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "templates/sec (N=2^20 SNR series) FP32 vs split-BF16 MFMA; % HBM roofline"
+HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_fp32-2^20.json")
+KERNEL_SOURCES = ["paper_1006_4644_amd/csrc/kernels.hip",
+                  "paper_1006_4644_amd/csrc/fft_device.h"]
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def parse():
+    p = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=20)
+    p.add_argument("--warmup", type=int, default=3)
+    p.add_argument("--workload", default="fp32-2^20")
+    p.add_argument("--batch", type=int, default=0, help="templates per batch (0: built-in)")
+    p.add_argument("--cpu-seconds", type=float, default=15.0,
+                   help="time budget of the CPU oracle baseline")
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--no-copy-probe", action="store_true")
+    return p.parse_args()
+
+
+def inject_on_gpu(ctx, seg, xt, wl, injs):
+    """Add the injections to the data spectrum, using the library's own
+    materialised templates (unit amplitude, t_c = phi_c = 0), shifted to
+    t_c = j0/fs and rotated by phi_c, scaled to the target optimal SNR."""
+    import torch
+    from paper_1006_4644_amd import ci
+    if not injs:
+        return xt
+    ib = np.array([[i.m1, i.m2] for i in injs])
+    p, ht = ctx.gen_templates(seg, ib, htilde=True)
+    torch.cuda.synchronize()
+    s2 = ci.params_to_numpy(p)["sigma2"]
+    k = torch.arange(wl.n // 2 + 1, device=xt.device, dtype=torch.int64)
+    acc = xt.to(torch.complex128)
+    for i, inj in enumerate(injs):
+        ph = 2 * math.pi * ((k * inj.j0) % wl.n).to(torch.float64) / wl.n - inj.phi
+        rot = torch.polar(torch.ones_like(ph), -ph)
+        acc = acc + ht[i].to(torch.complex128) * rot * (inj.snr / math.sqrt(s2[i]))
+    return acc.to(torch.complex64).contiguous()
+
+
+def copy_probe_gbs():
+    """Achieved bandwidth of a plain 2 GiB device copy (read + write)."""
+    import torch
+    n = 1 << 28  # float64 elements = 2 GiB
+    a = torch.empty(n, dtype=torch.float64, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    for _ in range(2):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 10
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return 2 * (n * 8) / (ms / 1e3) / 1e9
+
+
+def cpu_baseline(xt_host, psd, wl, bank, budget_s):
+    """The FP64 oracle, as it stands, on a bounded sample of the workload."""
+    from oracle import mf_oracle as O
+    rng = np.random.default_rng(2024)
+    order = rng.permutation(len(bank))
+    x = xt_host.astype(np.complex128)
+    thr2 = wl.snr_threshold ** 2
+    t0 = time.perf_counter()
+    done = 0
+    for i in order[:256]:
+        zs, s2 = O.snr_series(x, psd, wl.n, wl.fs, wl.f_low, *bank[i])
+        r2 = zs.real ** 2 + zs.imag ** 2
+        O.peak(r2)
+        O.window_triggers(r2, wl.window, thr2)
+        done += 1
+        if time.perf_counter() - t0 >= budget_s:
+            break
+    el = time.perf_counter() - t0
+    return {"value": done / el, "unit": "templates/s", "cores": 1, "kind": "oracle",
+            "sample": f"{done} seeded-random templates of the {wl.name} bank, "
+                      f"full per-template search (series, peak, window triggers), "
+                      f"FP64 numpy, one thread, {el:.1f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the search "
+              "shards by template bank across GPUs, but this build measures one "
+              "GPU's share.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1006_4644_amd import ci, synth
+
+    lib = ci.load()
+    ctx = lib.context(0)
+    if args.batch:
+        ctx.set_batch(args.batch)
+    wl = synth.WORKLOADS[args.workload]
+    bank = synth.draw_masses(wl.n_templates, wl.m_min, wl.m_max, wl.dist, wl.bank_seed)
+    injs = synth.draw_injections(wl, bank)
+    psd = synth.make_psd(wl.n, wl.fs)
+    noise = synth.make_noise(wl.n, wl.fs, wl.f_low, psd, wl.noise_seed)
+    psd_d = torch.from_numpy(psd).cuda()
+    xt = torch.from_numpy(noise.astype(np.complex64)).cuda()
+    seg = ctx.segment(xt, psd_d, wl.n, wl.fs, wl.f_low)
+    xt = inject_on_gpu(ctx, seg, xt, wl, injs)
+    ctx.segment_update(seg, xt, psd_d)
+    n_t = len(bank)
+    cap = 1 << 20
+    dev = torch.device("cuda", 0)
+    params = torch.empty((n_t, 96), dtype=torch.uint8, device=dev)
+    peaks = torch.empty((n_t, 4), dtype=torch.int64, device=dev)
+    trig = torch.empty((cap, 4), dtype=torch.int64, device=dev)
+    count = torch.zeros(1, dtype=torch.int64, device=dev)
+    log(f"[bench] workload {wl.name}: n={wl.n}, {n_t} templates, {len(injs)} injections")
+
+    def step():
+        ctx.segment_update(seg, xt, psd_d)
+        ctx.gen_templates(seg, bank, out=params)
+        ctx.find_triggers(seg, params, wl.snr_threshold, wl.window, cap=cap, merge=True,
+                          peaks=peaks, trig=trig, count=count)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    log(f"[bench] warmup done ({args.warmup} steps)")
+    ctx.set_timing(True)
+    ctx.kernel_times()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(args.steps):
+        step()
+    e1.record()
+    torch.cuda.synchronize()
+    total_ms = e0.elapsed_time(e1)
+    kt = ctx.kernel_times()
+    ctx.set_timing(False)
+    ms_step = total_ms / args.steps
+    value = n_t * args.steps / (total_ms / 1e3)
+    nwin_found = int(count.cpu()[0])
+    log(f"[bench] timed {args.steps} steps: {ms_step:.3f} ms/step, {value:.0f} templates/s, "
+        f"{nwin_found} merged windows")
+
+    # roofline of the dominant kernel
+    name = max(kt, key=lambda k: kt[k][2])
+    launches, tmpls, kms = kt[name]
+    per_launch_ms = kms / launches
+    bytes_per_launch = 8.0 * wl.n * (tmpls / launches)
+    achieved = bytes_per_launch / (per_launch_ms / 1e3) / 1e9
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        with open(TRAFFIC_FILE) as fh:
+            tr = json.load(fh)
+        if tr.get("source_hash") == kernel_source_hash() and name in tr.get("kernels", {}):
+            k = tr["kernels"][name]
+            traffic = k["bytes_per_template"] * (tmpls / launches)
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": traffic, "kernel": name,
+                "avg_launch_ms": round(per_launch_ms, 4),
+                "templates_per_launch": tmpls / launches}
+    path_gbs = 16.0 * wl.n * n_t / (ms_step / 1e3) / 1e9
+    out = {
+        "metric": METRIC, "value": round(value, 1), "unit": "templates/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": wl.name, "n": wl.n, "fs": wl.fs, "f_low": wl.f_low,
+                   "templates": n_t, "masses": f"{wl.dist} [{wl.m_min}, {wl.m_max}]",
+                   "injections": len(injs), "snr_threshold": wl.snr_threshold,
+                   "window": wl.window, "merge": True, "precision": "fp32"},
+        "roofline": roofline,
+        "path_hbm": {"algorithmic_bytes_per_template": 16 * wl.n,
+                     "achieved_gbs": round(path_gbs, 1),
+                     "frac": round(path_gbs / HBM_PEAK_GBS, 4)},
+        "kernels_ms_per_step": {k: round(v[2] / args.steps, 4) for k, v in kt.items()},
+        "merged_windows": nwin_found,
+    }
+    if not args.no_copy_probe:
+        out["copy_probe_gbs"] = round(copy_probe_gbs(), 1)
+    if not args.no_cpu_baseline:
+        log("[bench] CPU oracle baseline ...")
+        out["cpu_baseline"] = cpu_baseline(xt.cpu().numpy(), psd, wl, bank, args.cpu_seconds)
+    seg.close()
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -158,6 +158,13 @@ int ci_segment_create(ci_ctx* ctx, const ci_segment_spec* spec,
                       ci_segment** out);
 int ci_segment_destroy(ci_segment* seg);
 
+/* Recompute a segment in place from a new data chunk and PSD on the same
+ * grid (same n, fs, f_low): no allocation, asynchronous on `stream`.
+ * Templates generated on the segment must be regenerated (sigma^2 depends
+ * on the PSD). */
+int ci_segment_update(ci_segment* seg, const void* d_xtilde, const double* d_psd,
+                      void* stream);
+
 /* --- templates -------------------------------------------------------------
  * Generator constants for n bank entries on `seg`'s grid (the paper's
  * host_template_init + device_template_init), and optionally the templates
@@ -215,6 +222,22 @@ int ci_find_triggers(ci_ctx* ctx, const ci_segment* seg,
  * the segment length).  The intermediate workspace is 2 x batch x n_seg x 8
  * bytes. */
 int ci_set_batch(ci_ctx* ctx, int64_t templates_per_batch);
+
+/* --- instrumentation ---------------------------------------------------------
+ * With timing enabled, every transform-pass launch is bracketed by HIP
+ * events recorded on its launch stream.  ci_kernel_times() waits for the
+ * recorded events, reports per pass the number of launches, the templates
+ * they processed and their summed duration in milliseconds, and clears the
+ * record.  kind: 0 = pass 1 (generate + first pass), 1 = pass 2 (second
+ * pass + post-pass). */
+typedef struct {
+  int64_t launches;
+  int64_t templates;
+  double ms;
+} ci_kernel_time;
+
+int ci_set_timing(ci_ctx* ctx, int32_t enable);
+int ci_kernel_times(ci_ctx* ctx, ci_kernel_time* pass1, ci_kernel_time* pass2);
 
 #ifdef __cplusplus
 }

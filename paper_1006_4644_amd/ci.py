@@ -30,6 +30,7 @@ EXPORTED_SYMBOLS = (
     "ci_version", "ci_last_error", "ci_ctx_create", "ci_ctx_destroy",
     "ci_set_batch", "ci_make_bank", "ci_segment_create", "ci_segment_destroy",
     "ci_gen_templates", "ci_matched_filter", "ci_find_triggers",
+    "ci_segment_update", "ci_set_timing", "ci_kernel_times",
 )
 
 # ci_trigger: {int64 tmpl, int64 index, float rho2, re, im, int32 window}
@@ -65,6 +66,11 @@ class _BankSpec(ctypes.Structure):
                 ("seed", ctypes.c_uint64)]
 
 
+class _KernelTime(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_int64), ("templates", ctypes.c_int64),
+                ("ms", ctypes.c_double)]
+
+
 class _SegSpec(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("fs", ctypes.c_double),
                 ("f_low", ctypes.c_double)]
@@ -82,6 +88,10 @@ _SIGS = {
     "ci_segment_create": (ctypes.c_int, [_vp, ctypes.POINTER(_SegSpec), _vp,
                                          _vp, _vp, ctypes.POINTER(_vp)]),
     "ci_segment_destroy": (ctypes.c_int, [_vp]),
+    "ci_segment_update": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
+    "ci_set_timing": (ctypes.c_int, [_vp, _i32]),
+    "ci_kernel_times": (ctypes.c_int, [_vp, ctypes.POINTER(_KernelTime),
+                                       ctypes.POINTER(_KernelTime)]),
     "ci_gen_templates": (ctypes.c_int, [_vp, _vp, _vp, _i64, _vp, _vp, _vp]),
     "ci_matched_filter": (ctypes.c_int, [_vp, _vp, _vp, _i64, _i32, _vp, _vp]),
     "ci_find_triggers": (ctypes.c_int, [_vp, _vp, _vp, _i64, _i32, _f32, _i64,
@@ -209,15 +219,33 @@ class Context:
             _stream(stream), ctypes.byref(h)))
         return Segment(self, h.value, n, fs, f_low)
 
+    def segment_update(self, seg: Segment, xtilde, psd, stream=None):
+        """Recompute `seg` in place from new data (same grid)."""
+        self._chk(self.lib.dll.ci_segment_update(
+            seg.handle, _ptr(xtilde), _ptr(psd), _stream(stream)))
+
+    def set_timing(self, on: bool):
+        self._chk(self.lib.dll.ci_set_timing(self.handle, 1 if on else 0))
+
+    def kernel_times(self):
+        """{'pass1': (launches, templates, ms), 'pass2': (...)} since the
+        last call; waits for the recorded events."""
+        a, b = _KernelTime(), _KernelTime()
+        self._chk(self.lib.dll.ci_kernel_times(self.handle, ctypes.byref(a),
+                                               ctypes.byref(b)))
+        return {"pass1": (a.launches, a.templates, a.ms),
+                "pass2": (b.launches, b.templates, b.ms)}
+
     def gen_templates(self, seg: Segment, bank, htilde: bool = False,
-                      stream=None):
+                      stream=None, out=None):
         """Generator constants (uint8 CUDA tensor [n, 96]) for a (n, 2)
         bank; with htilde=True also the templates (complex64 [n, N/2+1])."""
         import torch
         bank = np.ascontiguousarray(np.asarray(bank, dtype=np.float64).reshape(-1, 2))
         n = bank.shape[0]
         dev = torch.device("cuda", self.device)
-        params = torch.empty((max(n, 1), 96), dtype=torch.uint8, device=dev)
+        params = out if out is not None else torch.empty(
+            (max(n, 1), 96), dtype=torch.uint8, device=dev)
         ht = None
         if htilde:
             ht = torch.empty((max(n, 1), seg.n // 2 + 1), dtype=torch.complex64,

@@ -117,6 +117,7 @@ void free_seg(Seg* s) {
   if (s->dev) (void)hipFree(s->dev);
   if (s->w) (void)hipFree(s->w);
   if (s->psum) (void)hipFree(s->psum);
+  if (s->bsum) (void)hipFree(s->bsum);
   if (s->tw2048) (void)hipFree(s->tw2048);
   if (s->twa) (void)hipFree(s->twa);
   if (s->twb) (void)hipFree(s->twb);
@@ -144,17 +145,16 @@ int ensure_ybuf(Ctx* ctx, size_t bytes) {
 
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
-int ensure_trig(Ctx* ctx, int64_t bmax, int64_t nwin, TrigWork* tw) {
-  const size_t s_pk = align256(sizeof(unsigned long long) * 2 * bmax);
+int ensure_trig(Ctx* ctx, int64_t bmax, int64_t nwin, int64_t ntile2, TrigWork* tw) {
+  const size_t s_pk = align256(sizeof(unsigned long long) * 2 * bmax * ntile2);
   const size_t s_wk = align256(sizeof(unsigned long long) * 2 * bmax * nwin);
-  const size_t s_td = align256(sizeof(unsigned int) * 2 * bmax);
   const size_t s_bd = align256(sizeof(unsigned int) * 2);
   const size_t s_cn = align256(sizeof(int) * 2 * bmax);
   const size_t s_si = align256(sizeof(int) * 2 * bmax * nwin);
   const size_t s_st = align256(sizeof(ci_trigger) * 2 * bmax * nwin);
   const size_t s_mr = align256(sizeof(ci_trigger) * nwin);
   const size_t s_rn = align256(sizeof(unsigned long long));
-  const size_t total = s_pk + s_wk + s_td + s_bd + s_cn + s_si + s_st + s_mr + s_rn;
+  const size_t total = s_pk + s_wk + s_bd + s_cn + s_si + s_st + s_mr + s_rn;
   if (ctx->tbytes < total) {
     if (ctx->tbuf) (void)hipFree(ctx->tbuf);
     ctx->tbuf = nullptr;
@@ -166,9 +166,8 @@ int ensure_trig(Ctx* ctx, int64_t bmax, int64_t nwin, TrigWork* tw) {
     ctx->tbytes = total;
   }
   char* p = static_cast<char*>(ctx->tbuf);
-  tw->pkeys = reinterpret_cast<unsigned long long*>(p); p += s_pk;
+  tw->ppart = reinterpret_cast<unsigned long long*>(p); p += s_pk;
   tw->wkeys = reinterpret_cast<unsigned long long*>(p); p += s_wk;
-  tw->tdone = reinterpret_cast<unsigned int*>(p); p += s_td;
   tw->bdone = reinterpret_cast<unsigned int*>(p); p += s_bd;
   tw->cnt = reinterpret_cast<int*>(p); p += s_cn;
   tw->sidx = reinterpret_cast<int*>(p); p += s_si;
@@ -190,6 +189,33 @@ int check_filter_args(Ctx* ctx, const ci_segment* seg, const ci_tparams* d_param
     return fail(ctx, CI_EINVAL, "unknown precision %d", precision);
   }
   return CI_OK;
+}
+
+hipEvent_t pool_event(Ctx* ctx) {
+  if (!ctx->ev_pool.empty()) {
+    hipEvent_t e = ctx->ev_pool.back();
+    ctx->ev_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Enqueue one pass launch, bracketed by events when timing is enabled.
+template <typename F>
+hipError_t timed(Ctx* ctx, int kind, int64_t templates, hipStream_t st, F launch) {
+  if (!ctx->timing) return launch();
+  TimedLaunch t{kind, templates, pool_event(ctx), pool_event(ctx)};
+  if (!t.e0 || !t.e1) return hipErrorOutOfMemory;
+  hipError_t e = hipEventRecord(t.e0, st);
+  if (e != hipSuccess) return e;
+  e = launch();
+  if (e != hipSuccess) return e;
+  e = hipEventRecord(t.e1, st);
+  if (e != hipSuccess) return e;
+  ctx->launches.push_back(t);
+  return hipSuccess;
 }
 
 }  // namespace
@@ -227,6 +253,12 @@ int ci_ctx_destroy(ci_ctx* ctx) {
     (void)hipEventDestroy(ctx->pin_ev);
   }
   if (ctx->pin) (void)hipHostFree(ctx->pin);
+  for (auto& t : ctx->launches) {
+    (void)hipEventSynchronize(t.e1);
+    ctx->ev_pool.push_back(t.e0);
+    ctx->ev_pool.push_back(t.e1);
+  }
+  for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
   if (ctx->ybuf) (void)hipFree(ctx->ybuf);
   if (ctx->tbuf) (void)hipFree(ctx->tbuf);
   delete ctx;
@@ -324,6 +356,7 @@ int ci_segment_create(ci_ctx* ctx, const ci_segment_spec* spec, const void* d_xt
   ALLOC(s->dev, sizeof(SegDev));
   ALLOC(s->w, sizeof(float2) * half);
   ALLOC(s->psum, sizeof(double) * half);
+  ALLOC(s->bsum, sizeof(double) * (half / kSegBlock));
   ALLOC(s->tw2048, sizeof(float2) * 2048);
   ALLOC(s->twa, sizeof(float2) * 2048);
   ALLOC(s->twb, sizeof(float2) * (nb > 0 ? nb : 1));
@@ -376,6 +409,46 @@ int ci_segment_destroy(ci_segment* seg) {
   (void)hipDeviceSynchronize();
   free_seg(seg);
   return CI_OK;
+}
+
+int ci_segment_update(ci_segment* seg, const void* d_xtilde, const double* d_psd, void* stream) {
+  if (!seg) return fail(nullptr, CI_EINVAL, "null segment");
+  Ctx* ctx = seg->ctx;
+  if (!d_xtilde || !d_psd) return fail(ctx, CI_EINVAL, "null data or PSD pointer");
+  DeviceGuard dg(ctx->device);
+  if (!dg.ok) return fail(ctx, CI_EHIP, "cannot select device %d", ctx->device);
+  hipError_t e = launch_segment(seg, d_xtilde, d_psd, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hipfail(ctx, e, "segment update launch");
+  return CI_OK;
+}
+
+int ci_set_timing(ci_ctx* ctx, int32_t enable) {
+  if (!ctx) return fail(nullptr, CI_EINVAL, "null context");
+  ctx->timing = enable != 0;
+  return CI_OK;
+}
+
+int ci_kernel_times(ci_ctx* ctx, ci_kernel_time* pass1, ci_kernel_time* pass2) {
+  if (!ctx) return fail(nullptr, CI_EINVAL, "null context");
+  if (!pass1 || !pass2) return fail(ctx, CI_EINVAL, "null output");
+  DeviceGuard dg(ctx->device);
+  ci_kernel_time acc[2] = {{0, 0, 0.0}, {0, 0, 0.0}};
+  int rc = CI_OK;
+  for (auto& t : ctx->launches) {
+    float ms = 0.f;
+    hipError_t e = hipEventSynchronize(t.e1);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, t.e0, t.e1);
+    if (e != hipSuccess && rc == CI_OK) rc = hipfail(ctx, e, "event timing");
+    acc[t.kind].launches += 1;
+    acc[t.kind].templates += t.templates;
+    acc[t.kind].ms += ms;
+    ctx->ev_pool.push_back(t.e0);
+    ctx->ev_pool.push_back(t.e1);
+  }
+  ctx->launches.clear();
+  *pass1 = acc[0];
+  *pass2 = acc[1];
+  return rc;
 }
 
 int ci_gen_templates(ci_ctx* ctx, const ci_segment* seg, const ci_template* bank_host, int64_t n,
@@ -450,9 +523,9 @@ int ci_matched_filter(ci_ctx* ctx, const ci_segment* seg, const ci_tparams* d_pa
     a.params = d_params + t0;
     a.y = static_cast<float2*>(ctx->ybuf) + (size_t)a.slot * B * N;
     a.d_z = static_cast<float2*>(d_z) + (size_t)t0 * N;
-    hipError_t e = launch_pass1(a, false, st);
+    hipError_t e = timed(ctx, 0, a.nb, st, [&] { return launch_pass1(a, false, st); });
     if (e != hipSuccess) return hipfail(ctx, e, "pass-1 launch");
-    e = launch_pass2_series(a, st);
+    e = timed(ctx, 1, a.nb, st, [&] { return launch_pass2_series(a, st); });
     if (e != hipSuccess) return hipfail(ctx, e, "pass-2 launch");
   }
   return CI_OK;
@@ -483,9 +556,11 @@ int ci_find_triggers(ci_ctx* ctx, const ci_segment* seg, const ci_tparams* d_par
   int64_t B = default_batch(ctx, N);
   const int64_t wlimit = (int64_t(1) << 22) / nwin;
   if (B > wlimit) B = wlimit > 0 ? wlimit : 1;
+  // the batch placement keeps one offset per template in LDS (>= 4096 ints)
+  if (B > 4096) B = 4096;
   if (B > n) B = n > 0 ? n : 1;
   TrigWork tw;
-  rc = ensure_trig(ctx, B, nwin, &tw);
+  rc = ensure_trig(ctx, B, nwin, seg->plan.n2 / seg->plan.j, &tw);
   if (rc != CI_OK) return rc;
   hipError_t e = launch_init_call(tw, (int)nwin, d_count, st);
   if (e != hipSuccess) return hipfail(ctx, e, "init launch");
@@ -514,10 +589,12 @@ int ci_find_triggers(ci_ctx* ctx, const ci_segment* seg, const ci_tparams* d_par
     a.params = d_params + t0;
     a.y = static_cast<float2*>(ctx->ybuf) + (size_t)a.slot * B * N;
     a.last_batch = (t0 + B >= n) ? 1 : 0;
-    e = launch_pass1(a, true, st);
+    e = timed(ctx, 0, a.nb, st, [&] { return launch_pass1(a, true, st); });
     if (e != hipSuccess) return hipfail(ctx, e, "pass-1 launch");
-    e = launch_pass2_trig(a, st);
+    e = timed(ctx, 1, a.nb, st, [&] { return launch_pass2_trig(a, st); });
     if (e != hipSuccess) return hipfail(ctx, e, "pass-2 launch");
+    e = launch_fin(a, st);
+    if (e != hipSuccess) return hipfail(ctx, e, "finalise launch");
   }
   return CI_OK;
 }

@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include <string>
+#include <vector>
 
 #include "../../include/ci.h"
 
@@ -36,15 +37,21 @@ Plan plan_for(int log2n);
 // consecutive batches so that batch b+1's first pass can clear its keys
 // while batch b's second pass still reads its own.
 struct TrigWork {
-  unsigned long long* pkeys;   // [2][B]        peak key per template
+  unsigned long long* ppart;   // [2][B][n2/j]  peak key per pass-2 workgroup
   unsigned long long* wkeys;   // [2][B][nwin]  window key per template
-  unsigned int* tdone;         // [2][B]        finished pass-2 tiles
   unsigned int* bdone;         // [2]           finished templates
   int* cnt;                    // [2][B]        triggers per template
   int* sidx;                   // [2][B][nwin]  staging slot of window w
   ci_trigger* stage;           // [2][B][nwin]  compacted triggers
   ci_trigger* mrec;            // [nwin]        merged record per window
   unsigned long long* run;     // [1]           triggers placed so far
+};
+
+// One instrumented launch: events bracketing it on its stream.
+struct TimedLaunch {
+  int kind;            // 0 pass 1, 1 pass 2
+  int64_t templates;
+  hipEvent_t e0, e1;
 };
 
 // Host-side state.
@@ -63,6 +70,10 @@ struct Ctx {
   size_t pinbytes = 0;
   hipEvent_t pin_ev = nullptr;
   bool pin_ev_armed = false;
+  // instrumentation
+  bool timing = false;
+  std::vector<TimedLaunch> launches;
+  std::vector<hipEvent_t> ev_pool;
 };
 
 struct Seg {
@@ -72,11 +83,15 @@ struct Seg {
   SegDev* dev;       // device copy
   float2* w;         // [n/2]  PSD-weighted, scaled data spectrum
   double* psum;      // [n/2]  running sum of 4 df f^-7/3 / S from k_low
+  double* bsum;      // [n/2 / kSegBlock] block sums, then block offsets
   float2* tw2048;    // [2048] exp(2 pi i e / 2048)
   float2* twa;       // [2048] exp(2 pi i e / n)
   float2* twb;       // [n/2048] exp(2 pi i 2048 e / n)
   Plan plan;
 };
+
+// Elements per workgroup of the segment-setup scan.
+constexpr int kSegBlock = 2048;
 
 // Kernel launchers (kernels.hip).
 hipError_t launch_segment(Seg* s, const void* d_xtilde, const double* d_psd,
@@ -113,5 +128,6 @@ struct BatchArgs {
 hipError_t launch_pass1(const BatchArgs& a, bool zero_trig, hipStream_t st);
 hipError_t launch_pass2_trig(const BatchArgs& a, hipStream_t st);
 hipError_t launch_pass2_series(const BatchArgs& a, hipStream_t st);
+hipError_t launch_fin(const BatchArgs& a, hipStream_t st);
 
 }  // namespace ci

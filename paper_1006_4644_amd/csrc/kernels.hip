@@ -47,57 +47,105 @@ __device__ __forceinline__ float phase_frac(const ci_tparams& P, int k) {
 // segment setup (once per data chunk)
 // ---------------------------------------------------------------------------
 
-// Running FP64 sum P[k] = 4 df sum_{k'=k_low}^{k} f^{-7/3} / S (0 below
-// k_low) and the power-of-two data scale g.  One workgroup.
-__global__ __launch_bounds__(1024) void k_seg_psum(SegDev* sd, const double* __restrict__ psd,
-                                                   double* __restrict__ psum) {
-  __shared__ double sh[1024];
+// Segment setup in three deterministic FP64 steps over blocks of kSegBlock
+// bins: (1) the terms 4 df f_k^{-7/3} / S_k on [k_low, n/2) and their
+// block sums, (2) the scan of the block sums, the total and the data scale
+// g, (3) the running sum inside each block plus the weighted spectrum.
+constexpr int kSegThreads = 256;
+constexpr int kSegPer = kSegBlock / kSegThreads;
+
+__device__ __forceinline__ double seg_term(int64_t k, int64_t kl, double df, const double* psd) {
+  return k >= kl ? 4.0 * df * pow((double)k * df, -7.0 / 3.0) / psd[k] : 0.0;
+}
+
+// Exclusive scan of one double per lane over a 256-lane workgroup.
+__device__ double block_excl_scan_d(double v, double* sh, double* total) {
   const int tid = threadIdx.x, nt = blockDim.x;
-  const int64_t half = sd->half;
+  __syncthreads();
+  sh[tid] = v;
+  __syncthreads();
+  for (int off = 1; off < nt; off <<= 1) {
+    const double u = (tid >= off) ? sh[tid - off] : 0.0;
+    __syncthreads();
+    sh[tid] += u;
+    __syncthreads();
+  }
+  const double incl = sh[tid];
+  *total = sh[nt - 1];
+  __syncthreads();
+  return incl - v;
+}
+
+__global__ __launch_bounds__(kSegThreads) void k_seg_terms(const SegDev* __restrict__ sd,
+                                                           const double* __restrict__ psd,
+                                                           double* __restrict__ psum,
+                                                           double* __restrict__ bsum) {
+  __shared__ double sh[kSegThreads];
   const int64_t kl = sd->k_low;
   const double df = sd->df;
-  const int64_t len = half - kl;
-  const int64_t per = (len + nt - 1) / nt;
-  const int64_t a = kl + (int64_t)tid * per;
-  const int64_t b = (a + per < half) ? a + per : half;
+  const int64_t base = (int64_t)blockIdx.x * kSegBlock + threadIdx.x * kSegPer;
   double s = 0.0;
-  for (int64_t k = a; k < b; ++k) s += pow((double)k * df, -7.0 / 3.0) / psd[k];
-  sh[tid] = s;
+#pragma unroll
+  for (int i = 0; i < kSegPer; ++i) {
+    const double v = seg_term(base + i, kl, df, psd);
+    psum[base + i] = v;
+    s += v;
+  }
+  double tot;
+  (void)block_excl_scan_d(s, sh, &tot);
+  if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(1024) void k_seg_scan(SegDev* sd, double* __restrict__ bsum,
+                                                   int nblk) {
+  __shared__ double sh[1024];
+  const int tid = threadIdx.x;
+  const double v = tid < nblk ? bsum[tid] : 0.0;
+  sh[tid] = v;
   __syncthreads();
-  // inclusive Hillis-Steele scan of the per-thread sums
-  for (int off = 1; off < nt; off <<= 1) {
-    const double v = (tid >= off) ? sh[tid - off] : 0.0;
+  for (int off = 1; off < 1024; off <<= 1) {
+    const double u = (tid >= off) ? sh[tid - off] : 0.0;
     __syncthreads();
-    sh[tid] += v;
+    sh[tid] += u;
     __syncthreads();
   }
-  double run = sh[tid] - s;
-  for (int64_t k = a; k < b; ++k) {
-    run += pow((double)k * df, -7.0 / 3.0) / psd[k];
-    psum[k] = 4.0 * df * run;
-  }
-  for (int64_t k = tid; k < kl; k += nt) psum[k] = 0.0;
-  if (tid == nt - 1) {
-    const double tot = 4.0 * df * sh[nt - 1];
+  if (tid < nblk) bsum[tid] = sh[tid] - v;
+  if (tid == 1023) {
+    const double tot = sh[1023];
     sd->p_total = tot;
     // E|x~ f^{-7/6} / S|^2 = (T/2) f^{-7/3} / S for data with PSD S: scale
     // the weighted spectrum to unit mean power by an exact power of two.
     const double T = (double)sd->n / sd->fs;
-    const double mean = 0.5 * T * (tot / (4.0 * df)) / (double)len;
+    const double len = (double)(sd->half - sd->k_low);
+    const double mean = 0.5 * T * (tot / (4.0 * sd->df)) / len;
     sd->g = exp2(rint(-0.5 * log2(mean)));
   }
 }
 
-// w_k = g x~_k f_k^{-7/6} / S_k on [k_low, n/2), 0 elsewhere (FP64 -> FP32).
-__global__ __launch_bounds__(256) void k_seg_w(const SegDev* __restrict__ sd,
-                                               const float2* __restrict__ xt,
-                                               const double* __restrict__ psd,
-                                               float2* __restrict__ w) {
-  const int64_t half = sd->half;
+__global__ __launch_bounds__(kSegThreads) void k_seg_final(const SegDev* __restrict__ sd,
+                                                           const float2* __restrict__ xt,
+                                                           const double* __restrict__ psd,
+                                                           double* __restrict__ psum,
+                                                           const double* __restrict__ boff,
+                                                           float2* __restrict__ w) {
+  __shared__ double sh[kSegThreads];
   const int64_t kl = sd->k_low;
   const double df = sd->df, g = sd->g;
-  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < half;
-       k += (int64_t)gridDim.x * blockDim.x) {
+  const int64_t base = (int64_t)blockIdx.x * kSegBlock + threadIdx.x * kSegPer;
+  double v[kSegPer];
+  double s = 0.0;
+#pragma unroll
+  for (int i = 0; i < kSegPer; ++i) {
+    v[i] = psum[base + i];
+    s += v[i];
+  }
+  double tot;
+  double run = boff[blockIdx.x] + block_excl_scan_d(s, sh, &tot);
+#pragma unroll
+  for (int i = 0; i < kSegPer; ++i) {
+    const int64_t k = base + i;
+    run += v[i];
+    psum[k] = k >= kl ? run : 0.0;
     float2 o = make_float2(0.f, 0.f);
     if (k >= kl) {
       const double fac = g * pow((double)k * df, -7.0 / 6.0) / psd[k];
@@ -171,9 +219,7 @@ struct P1Args {
   const float2* twb;       // exp(2 pi i 2048 e / n)
   float2* y;               // intermediate, [nb][n] in tile layout
   // per-batch trigger state to clear (null when not searching)
-  u64* pkeys;
   u64* wkeys;
-  unsigned int* tdone;
   unsigned int* bdone;
   int64_t nzero_w;         // entries of wkeys to clear
   int nb;
@@ -188,14 +234,10 @@ __global__ __launch_bounds__(C * N2 / 16) void k_pass1(P1Args a) {
   const int tid = threadIdx.x;
   const int c = tid % C, t = tid / C;
 
-  if (a.pkeys) {
+  if (a.wkeys) {
     const int64_t gid = blockIdx.x * (int64_t)blockDim.x + tid;
     const int64_t gsz = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = gid; i < a.nzero_w; i += gsz) a.wkeys[i] = 0ull;
-    for (int64_t i = gid; i < a.nb; i += gsz) {
-      a.pkeys[i] = 0ull;
-      a.tdone[i] = 0u;
-    }
     if (gid == 0) a.bdone[0] = 0u;
   }
 
@@ -309,9 +351,9 @@ struct P2Args {
   int64_t t0;                // bank index of the batch's first template
   int nb;
   // trigger mode
-  u64* pkeys;                // [nb]
+  u64* ppart;                // [nb][ntile2] per-workgroup peak keys
+  int ntile2;                // pass-2 workgroups per template
   u64* wkeys;                // [nb][nwin]
-  unsigned int* tdone;       // [nb]
   unsigned int* bdone;       // [1]
   int* cnt;                  // [nb]
   int* sidx;                 // [nb][nwin]
@@ -342,7 +384,24 @@ __device__ void finalize_template(const P2Args& a, int b, void* ldsv) {
   const ci_tparams P = a.prm[b];
   const int64_t tg = a.t0 + b;
   const float2* yb = a.y + (size_t)b * N;
-  const u64 pk = aload(&a.pkeys[b]);
+  // peak key: max over the pass-2 workgroups' partials
+  u64 pk = 0ull;
+  for (int i = tid; i < a.ntile2; i += nt) {
+    const u64 v = a.ppart[(size_t)b * a.ntile2 + i];
+    pk = v > pk ? v : pk;
+  }
+  {
+    u64* ush = reinterpret_cast<u64*>(ldsv);
+    __syncthreads();
+    ush[tid] = pk;
+    __syncthreads();
+    for (int off = nt / 2; off > 0; off >>= 1) {
+      if (tid < off) ush[tid] = ush[tid + off] > ush[tid] ? ush[tid + off] : ush[tid];
+      __syncthreads();
+    }
+    pk = ush[0];
+    __syncthreads();
+  }
   if ((P.flags & CI_TMPL_EMPTY) || pk == 0ull) {
     if (tid == 0) {
       ci_trigger e;
@@ -499,28 +558,33 @@ __global__ __launch_bounds__(J * N1 / 16) void k_pass2_trig(P2Args a) {
       if (r2 > a.thr2) atomicMax(&wk[j / a.window], key);
     }
   }
-  // workgroup max of the peak key
+  // workgroup max of the peak key, stored as this tile's partial
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) {
     const u64 o = __shfl_xor(best, off, 64);
     best = o > best ? o : best;
   }
   __shared__ u64 s_best[16];
-  __shared__ int s_flag;
-  __syncthreads();
   if ((tid & 63) == 0) s_best[tid >> 6] = best;
   __syncthreads();
   if (tid == 0) {
     u64 m = 0ull;
     for (int i = 0; i < (int)(blockDim.x >> 6); ++i) m = s_best[i] > m ? s_best[i] : m;
-    atomicMax(&a.pkeys[b], m);
+    a.ppart[(size_t)b * TILES + tile] = m;
   }
-  __threadfence();
-  __syncthreads();
-  if (tid == 0) s_flag = (atomicAdd(&a.tdone[b], 1u) == (unsigned int)(TILES - 1));
-  __syncthreads();
-  if (!s_flag) return;
-  __threadfence();
+}
+
+// Per-batch finalisation: one workgroup per template reduces the pass-2
+// partials to the peak, recomputes z at the peak and at every window
+// trigger, and compacts the triggers; the last workgroup to finish places
+// the batch's triggers (or merges them) in order.  Only these few
+// workgroups use device-scope fences.
+template <int N1, int N2, int C>
+__global__ __launch_bounds__(256) void k_fin(P2Args a) {
+  extern __shared__ float2 lds[];
+  const int tid = threadIdx.x;
+  const int b = blockIdx.x;
+  __shared__ int s_flag;
   finalize_template<N1, N2, C>(a, b, lds);
   __threadfence();
   __syncthreads();
@@ -590,14 +654,16 @@ Plan plan_for(int log2n) {
 }
 
 hipError_t launch_segment(Seg* s, const void* d_xtilde, const double* d_psd, hipStream_t st) {
-  hipLaunchKernelGGL(k_seg_psum, dim3(1), dim3(1024), 0, st, s->dev, d_psd, s->psum);
+  const int nblk = (int)(s->host.half / kSegBlock);
+  hipLaunchKernelGGL(k_seg_terms, dim3(nblk), dim3(kSegThreads), 0, st, s->dev, d_psd, s->psum,
+                     s->bsum);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const int64_t half = s->host.half;
-  int blocks = (int)((half + 255) / 256);
-  if (blocks > 4096) blocks = 4096;
-  hipLaunchKernelGGL(k_seg_w, dim3(blocks), dim3(256), 0, st, s->dev,
-                     reinterpret_cast<const float2*>(d_xtilde), d_psd, s->w);
+  hipLaunchKernelGGL(k_seg_scan, dim3(1), dim3(1024), 0, st, s->dev, s->bsum, nblk);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_seg_final, dim3(nblk), dim3(kSegThreads), 0, st, s->dev,
+                     reinterpret_cast<const float2*>(d_xtilde), d_psd, s->psum, s->bsum, s->w);
   return hipGetLastError();
 }
 
@@ -630,6 +696,10 @@ hipError_t launch_init_call(const TrigWork& tw, int nwin, int64_t* d_count, hipS
 
 namespace {
 
+// finaliser LDS: 2 doubles per lane (256 lanes) or one int per template of
+// the batch (<= 4096)
+constexpr size_t kFinLds = 16384;
+
 template <typename K>
 hipError_t set_lds(K kern, size_t bytes) {
   if (bytes <= 65536) return hipSuccess;
@@ -648,15 +718,11 @@ P1Args make_p1(const BatchArgs& a, bool zero_trig) {
   p.nb = a.nb;
   if (zero_trig) {
     const int s = a.slot;
-    p.pkeys = a.tw.pkeys + (size_t)s * a.bmax;
     p.wkeys = a.tw.wkeys + (size_t)s * a.bmax * a.nwin;
-    p.tdone = a.tw.tdone + (size_t)s * a.bmax;
     p.bdone = a.tw.bdone + s;
     p.nzero_w = (int64_t)a.nb * a.nwin;
   } else {
-    p.pkeys = nullptr;
     p.wkeys = nullptr;
-    p.tdone = nullptr;
     p.bdone = nullptr;
     p.nzero_w = 0;
   }
@@ -671,9 +737,9 @@ P2Args make_p2(const BatchArgs& a) {
   p.y = a.y;
   p.t0 = a.t0;
   p.nb = a.nb;
-  p.pkeys = a.tw.pkeys ? a.tw.pkeys + (size_t)s * a.bmax : nullptr;
+  p.ntile2 = a.seg->plan.n2 / a.seg->plan.j;
+  p.ppart = a.tw.ppart ? a.tw.ppart + (size_t)s * a.bmax * p.ntile2 : nullptr;
   p.wkeys = a.tw.wkeys ? a.tw.wkeys + (size_t)s * a.bmax * a.nwin : nullptr;
-  p.tdone = a.tw.tdone ? a.tw.tdone + (size_t)s * a.bmax : nullptr;
   p.bdone = a.tw.bdone ? a.tw.bdone + s : nullptr;
   p.cnt = a.tw.cnt ? a.tw.cnt + (size_t)s * a.bmax : nullptr;
   p.sidx = a.tw.sidx ? a.tw.sidx + (size_t)s * a.bmax * a.nwin : nullptr;
@@ -715,6 +781,11 @@ struct Inst {
                        make_p2(a));
     return hipGetLastError();
   }
+  static hipError_t fin(const BatchArgs& a, hipStream_t st) {
+    hipLaunchKernelGGL((k_fin<N1, N2, C>), dim3((unsigned)a.nb), dim3(256), kFinLds, st,
+                       make_p2(a));
+    return hipGetLastError();
+  }
   static hipError_t p2s(const BatchArgs& a, hipStream_t st) {
     const size_t lds = (size_t)N1 * J * sizeof(float2);
     auto kern = k_pass2_series<N1, N2, C, J>;
@@ -746,6 +817,9 @@ hipError_t launch_pass1(const BatchArgs& a, bool zero_trig, hipStream_t st) {
 }
 hipError_t launch_pass2_trig(const BatchArgs& a, hipStream_t st) {
   return dispatch(a.seg->plan.log2n, [&](auto inst) { return decltype(inst)::p2t(a, st); });
+}
+hipError_t launch_fin(const BatchArgs& a, hipStream_t st) {
+  return dispatch(a.seg->plan.log2n, [&](auto inst) { return decltype(inst)::fin(a, st); });
 }
 hipError_t launch_pass2_series(const BatchArgs& a, hipStream_t st) {
   return dispatch(a.seg->plan.log2n, [&](auto inst) { return decltype(inst)::p2s(a, st); });
