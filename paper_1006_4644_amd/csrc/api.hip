@@ -124,10 +124,10 @@ void free_seg(Seg* s) {
   delete s;
 }
 
-// Templates per batch: the intermediate of one slot set is about 256 MiB.
+// Templates per batch: the intermediate of one slot set is 512 MiB.
 int64_t default_batch(const Ctx* ctx, int64_t nseg) {
   if (ctx->batch_override > 0) return ctx->batch_override;
-  int64_t b = (int64_t(1) << 25) / nseg;
+  int64_t b = (int64_t(1) << 26) / nseg;
   return b < 1 ? 1 : b;
 }
 

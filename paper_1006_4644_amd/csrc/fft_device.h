@@ -6,6 +6,20 @@
 // transform N = N1 x N2 whose column DFTs (length L = 256 .. 2048) run
 // inside one workgroup: 16 complex values per lane, radix-16 register
 // butterflies, and Stockham exchanges through LDS between stages.
+//
+// Column DFT of length L = 256 R3 over NC interleaved columns (lane (c, t),
+// c fastest, t in [0, L/16)):
+//   stage 1: lane t holds X[t + (L/16) m], m = 0..15; radix 16 over m,
+//            twiddle w_L^{a t};
+//   stage 2: lane (a0, s2) = (t / R3, t % R3) holds the stage-1 outputs of
+//            row a0 at s = s2 + R3 q; radix 16 over q, twiddle
+//            w_{16 R3}^{a2 s2};
+//   stage 3: lane t holds rows d = t + (L/16) i of the radix-R3 step;
+//            output b lands at j = d + 256 b.
+// R3 == 1 stops after stage 2 with outputs j = t + 16 a2.
+// The LDS exchanges use rotated rows so that the lanes of one access hit
+// distinct banks (row a of exchange 1 is rotated by a * rho1, row d of
+// exchange 2 by d, or by d/2 when R3 == 2).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -37,6 +51,15 @@ __device__ __forceinline__ void idft4(float2& x0, float2& x1, float2& x2, float2
   x3 = csub(b, mul_i(d));
 }
 
+// 4-point inverse DFT of (x0, x1, 0, 0).
+__device__ __forceinline__ void idft4_half(float2& x0, float2& x1, float2& x2, float2& x3) {
+  const float2 a = x0, d = x1;
+  x0 = cadd(a, d);
+  x2 = csub(a, d);
+  x1 = cadd(a, mul_i(d));
+  x3 = csub(a, mul_i(d));
+}
+
 __device__ __forceinline__ void idft2(float2& x0, float2& x1) {
   const float2 a = x0;
   x0 = cadd(a, x1);
@@ -59,7 +82,6 @@ __device__ __forceinline__ float2 tw16(float2 v) {
   else if constexpr (e == 10) return make_float2((v.y - v.x) * R2, -(v.x + v.y) * R2);
   else if constexpr (e == 14) return make_float2((v.x + v.y) * R2, (v.y - v.x) * R2);
   else {
-    // general odd multiple of pi/8
     constexpr float cs[16] = {1.f, C1, R2, S1, 0.f, -S1, -R2, -C1,
                               -1.f, -C1, -R2, -S1, 0.f, S1, R2, C1};
     constexpr float c = cs[e], s = cs[(e + 12) & 15];  // sin(t) = cos(t - pi/2)
@@ -68,13 +90,20 @@ __device__ __forceinline__ float2 tw16(float2 v) {
 }
 
 // 16-point inverse DFT in place, X_a = sum_q x_q w16^{aq}, as 4 x 4:
-// q = q1 + 4 q2, a = a1 + 4 a2.
+// q = q1 + 4 q2, a = a1 + 4 a2.  HALF: x_q = 0 for q >= 8 (not read).
+template <bool HALF = false>
 __device__ __forceinline__ void idft16(float2 (&x)[16]) {
   float2 A[4][4];  // A[q1][a1]
 #pragma unroll
   for (int q1 = 0; q1 < 4; ++q1) {
-    float2 y0 = x[q1], y1 = x[q1 + 4], y2 = x[q1 + 8], y3 = x[q1 + 12];
-    idft4(y0, y1, y2, y3);
+    float2 y0 = x[q1], y1 = x[q1 + 4], y2, y3;
+    if constexpr (HALF) {
+      idft4_half(y0, y1, y2, y3);
+    } else {
+      y2 = x[q1 + 8];
+      y3 = x[q1 + 12];
+      idft4(y0, y1, y2, y3);
+    }
     A[q1][0] = y0; A[q1][1] = y1; A[q1][2] = y2; A[q1][3] = y3;
   }
   A[1][1] = tw16<1>(A[1][1]); A[1][2] = tw16<2>(A[1][2]); A[1][3] = tw16<3>(A[1][3]);
@@ -88,7 +117,7 @@ __device__ __forceinline__ void idft16(float2 (&x)[16]) {
   }
 }
 
-// 8-point inverse DFT on x[o .. o+7]: q = q1 + 2 q2, a = a1 + 4 a2.
+// 8-point inverse DFT on x[O .. O+7]: q = q1 + 2 q2, a = a1 + 4 a2.
 template <int O>
 __device__ __forceinline__ void idft8(float2 (&x)[16]) {
   float2 e0 = x[O + 0], e1 = x[O + 2], e2 = x[O + 4], e3 = x[O + 6];
@@ -119,58 +148,100 @@ __device__ __forceinline__ void idft_groups(float2 (&x)[16]) {
   }
 }
 
-// Column DFT of length L = 256 R3 over NC columns held by a workgroup of
-// NC * L/16 lanes.  Lane (c, t) with t in [0, L/16) enters with
-// x[q] = X_c[t + (L/16) q] and leaves holding, for register r,
-//   R3 == 1:  x[r] = Y_c[t + 16 r]
-//   R3 >  1:  x[i R3 + b] = Y_c[t + (L/16) i + 256 b]
-// where Y_c[j] = sum_s X_c[s] exp(2 pi i js/L).  Three Stockham steps:
-//   1) radix 16 over s = t + (L/16) m, twiddle w_L^{a t};
-//   2) radix 16 over the next digit, twiddle w_{16 R3}^{a2 s2};
-//   3) radix R3.
-// tw: exp(2 pi i e / 2048) for e in [0, 2048).  lds: L * NC float2.
+// ---------------------------------------------------------------------------
+// the column transform, stage by stage
+// ---------------------------------------------------------------------------
+
+template <int L>
+struct Col {
+  static constexpr int Lp = L / 16;
+  static constexpr int R3 = L / 256;
+  static constexpr int RHO1 = R3 == 1 ? 1 : (R3 == 2 ? 2 : 0);
+  static_assert(R3 == 1 || R3 == 2 || R3 == 4 || R3 == 8, "L in 256..2048");
+
+  // exchange-1 slot of stage-1 output (row a, column position s)
+  __device__ static __forceinline__ int x1(int a, int s) {
+    return a * Lp + ((s + a * RHO1) & (Lp - 1));
+  }
+  // exchange-2 slot of stage-2 output (row d, position s)
+  __device__ static __forceinline__ int x2(int d, int s) {
+    if constexpr (R3 == 2) return d * 2 + ((s + (d >> 1)) & 1);
+    else return d * R3 + ((s + d) & (R3 - 1));
+  }
+
+  // Stage 1: radix 16 in registers (HALF: inputs m >= 8 are zero), table
+  // twiddle w_L^{a t}, store to LDS.
+  template <int NC, bool HALF>
+  __device__ static __forceinline__ void stage1(float2 (&x)[16], float2* lds, int t, int c,
+                                                const float2* __restrict__ tw) {
+    idft16<HALF>(x);
+#pragma unroll
+    for (int a = 1; a < 16; ++a) x[a] = cmul(x[a], tw[(a * t) * (2048 / L)]);
+#pragma unroll
+    for (int a = 0; a < 16; ++a) lds[x1(a, t) * NC + c] = x[a];
+    __syncthreads();
+  }
+
+  // Stage 2 load + radix 16 (no twiddle yet).
+  template <int NC>
+  __device__ static __forceinline__ void stage2(float2 (&x)[16], const float2* lds, int t, int c) {
+    const int a0 = t / R3, s2 = t % R3;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) x[q] = lds[x1(a0, s2 + R3 * q) * NC + c];
+    idft16(x);
+  }
+
+  // Stage-2 table twiddle w_{16 R3}^{a2 s2} (R3 > 1).
+  __device__ static __forceinline__ void stage2_twiddle(float2 (&x)[16], int t,
+                                                        const float2* __restrict__ tw) {
+    if constexpr (R3 > 1) {
+      const int s2 = t % R3;
+#pragma unroll
+      for (int a2 = 1; a2 < 16; ++a2) x[a2] = cmul(x[a2], tw[(a2 * s2) * (2048 / (16 * R3))]);
+    }
+  }
+
+  // Stage 3 (R3 > 1): store stage-2 outputs, reload by row, radix R3.
+  template <int NC>
+  __device__ static __forceinline__ void stage3(float2 (&x)[16], float2* lds, int t, int c) {
+    if constexpr (R3 > 1) {
+      const int a0 = t / R3, s2 = t % R3;
+      __syncthreads();
+#pragma unroll
+      for (int a2 = 0; a2 < 16; ++a2) lds[x2(a0 + 16 * a2, s2) * NC + c] = x[a2];
+      __syncthreads();
+#pragma unroll
+      for (int i = 0; i < 16 / R3; ++i) {
+        const int d = t + Lp * i;
+#pragma unroll
+        for (int s = 0; s < R3; ++s) x[i * R3 + s] = lds[x2(d, s) * NC + c];
+      }
+      idft_groups<R3>(x);
+    }
+  }
+
+  // Output index j in [0, L) held in register r after the transform.
+  __device__ static __forceinline__ int out(int t, int r) {
+    if constexpr (R3 == 1) return t + 16 * r;
+    else return t + Lp * (r / R3) + 256 * (r % R3);
+  }
+  // Register holding the k-th smallest output of lane t (outputs of a lane
+  // increase with k).
+  __host__ __device__ static constexpr int reg_by_order(int k) {
+    if constexpr (R3 == 1) return k;
+    else return (k % (16 / R3)) * R3 + k / (16 / R3);
+  }
+};
+
+// Full column DFT with table twiddles (pass 2): see Col<L>.
 template <int L, int NC>
 __device__ __forceinline__ void fft_col(float2 (&x)[16], float2* lds, int t, int c,
                                         const float2* __restrict__ tw) {
-  constexpr int Lp = L / 16;
-  constexpr int R3 = L / 256;
-  static_assert(R3 == 1 || R3 == 2 || R3 == 4 || R3 == 8, "L in 256..2048");
-
-  idft16(x);
-#pragma unroll
-  for (int a = 1; a < 16; ++a) x[a] = cmul(x[a], tw[(a * t) * (2048 / L)]);
-#pragma unroll
-  for (int a = 0; a < 16; ++a) lds[(a * Lp + t) * NC + c] = x[a];
-  __syncthreads();
-
-  const int a0 = t / R3, s2 = t % R3;
-#pragma unroll
-  for (int q = 0; q < 16; ++q) x[q] = lds[(a0 * Lp + s2 + R3 * q) * NC + c];
-  idft16(x);
-  if constexpr (R3 > 1) {
-#pragma unroll
-    for (int a2 = 1; a2 < 16; ++a2) x[a2] = cmul(x[a2], tw[(a2 * s2) * (2048 / (16 * R3))]);
-    __syncthreads();
-#pragma unroll
-    for (int a2 = 0; a2 < 16; ++a2) lds[((a0 + 16 * a2) * R3 + s2) * NC + c] = x[a2];
-    __syncthreads();
-    constexpr int G = 16 / R3;
-#pragma unroll
-    for (int i = 0; i < G; ++i) {
-      const int d = t + Lp * i;
-#pragma unroll
-      for (int s = 0; s < R3; ++s) x[i * R3 + s] = lds[(d * R3 + s) * NC + c];
-    }
-    idft_groups<R3>(x);
-  }
-}
-
-// Output index (within the column) held in register r after fft_col.
-template <int L>
-__device__ __forceinline__ int fft_col_out(int t, int r) {
-  constexpr int R3 = L / 256;
-  if constexpr (R3 == 1) return t + 16 * r;
-  else return t + (L / 16) * (r / R3) + 256 * (r % R3);
+  using K = Col<L>;
+  K::template stage1<NC, false>(x, lds, t, c, tw);
+  K::template stage2<NC>(x, lds, t, c);
+  K::stage2_twiddle(x, t, tw);
+  K::template stage3<NC>(x, lds, t, c);
 }
 
 }  // namespace ci

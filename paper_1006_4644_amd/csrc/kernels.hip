@@ -43,6 +43,13 @@ __device__ __forceinline__ float phase_frac(const ci_tparams& P, int k) {
   return (float)(r - rint(r));
 }
 
+// (cos Psi_k, sin Psi_k) through the hardware sine/cosine, whose input is
+// in revolutions (|error| <= 1.3e-7 on [-1/2, 1/2]).
+__device__ __forceinline__ float2 chirp_phasor(const ci_tparams& P, int k) {
+  const float fr = phase_frac(P, k);
+  return make_float2(__builtin_amdgcn_cosf(fr), __builtin_amdgcn_sinf(fr));
+}
+
 // ---------------------------------------------------------------------------
 // segment setup (once per data chunk)
 // ---------------------------------------------------------------------------
@@ -185,11 +192,9 @@ __global__ __launch_bounds__(256) void k_htilde(const SegDev* __restrict__ sd,
        k += (int64_t)gridDim.x * blockDim.x) {
     float2 o = make_float2(0.f, 0.f);
     if (k >= P.k_low && k <= P.k_high) {
-      const float fr = phase_frac(P, (int)k);
-      float s, c;
-      sincospif(2.0f * fr, &s, &c);
+      const float2 e = chirp_phasor(P, (int)k);
       const float amp = (float)pow((double)k * sd->df, -7.0 / 6.0);
-      o = make_float2(amp * c, -amp * s);
+      o = make_float2(amp * e.x, -amp * e.y);
     }
     ht[k] = o;
   }
@@ -225,10 +230,18 @@ struct P1Args {
   int nb;
 };
 
+// w_N^e for 0 <= e < N from the two-level table.
+__device__ __forceinline__ float2 tw_n(const float2* __restrict__ twa,
+                                       const float2* __restrict__ twb, int e) {
+  return cmul(twa[e & 2047], twb[e >> 11]);
+}
+
 template <int N1, int N2, int C>
 __global__ __launch_bounds__(C * N2 / 16) void k_pass1(P1Args a) {
+  using K = Col<N2>;
   constexpr int N = N1 * N2;
-  constexpr int Lp = N2 / 16;
+  constexpr int Lp = K::Lp;
+  constexpr int R3 = K::R3;
   constexpr int TILES = N1 / C;
   extern __shared__ float2 lds[];
   const int tid = threadIdx.x;
@@ -246,30 +259,56 @@ __global__ __launch_bounds__(C * N2 / 16) void k_pass1(P1Args a) {
   const ci_tparams P = a.prm[b];
   const int k1 = tile * C + c;
 
+  // Z_k for k = k1 + N1 k2, k2 = t + Lp m.  Every band bin lies below n/2,
+  // i.e. k2 < N2/2: only m < 8 can be nonzero.
   float2 x[16];
 #pragma unroll
-  for (int q = 0; q < 16; ++q) {
-    const int k = k1 + N1 * (t + Lp * q);
+  for (int m = 0; m < 8; ++m) {
+    const int k = k1 + N1 * (t + Lp * m);
     float2 v = make_float2(0.f, 0.f);
     if (k >= P.k_low && k <= P.k_high) {
-      const float fr = phase_frac(P, k);
-      float s, co;
-      sincospif(2.0f * fr, &s, &co);
-      v = cmul(a.w[k], make_float2(co * P.scale, s * P.scale));
+      const float2 e = chirp_phasor(P, k);
+      v = cmul(a.w[k], make_float2(e.x * P.scale, e.y * P.scale));
     }
-    x[q] = v;
+    x[m] = v;
   }
 
-  fft_col<N2, C>(x, lds, t, c, a.tw);
+  K::template stage1<C, true>(x, lds, t, c, a.tw);
+  K::template stage2<C>(x, lds, t, c);
+  // Stage-2 twiddle merged with the four-step twiddle w_N^{k1 j2}: the
+  // factor of output a2 is base * w^{a2} (a geometric sequence).
+  float2 base, w;
+  if constexpr (R3 == 1) {
+    // j2 = t + 16 a2 is final here
+    base = tw_n(a.twa, a.twb, k1 * t);
+    w = tw_n(a.twa, a.twb, 16 * k1);
+  } else {
+    // rows d = a0 + 16 a2 of the radix-R3 step; output b adds 256 b to j2
+    const int a0 = t / R3, s2 = t % R3;
+    base = tw_n(a.twa, a.twb, k1 * a0);
+    w = cmul(a.tw[s2 * (2048 / (16 * R3))], tw_n(a.twa, a.twb, 16 * k1));
+  }
+  x[0] = cmul(x[0], base);
+#pragma unroll
+  for (int a2 = 1; a2 < 16; ++a2) {
+    base = cmul(base, w);
+    x[a2] = cmul(x[a2], base);
+  }
+  K::template stage3<C>(x, lds, t, c);
+  if constexpr (R3 > 1) {
+    const float2 v = tw_n(a.twa, a.twb, 256 * k1);
+    float2 vb = v;
+#pragma unroll
+    for (int bb = 1; bb < R3; ++bb) {
+#pragma unroll
+      for (int i = 0; i < 16 / R3; ++i) x[i * R3 + bb] = cmul(x[i * R3 + bb], vb);
+      vb = cmul(vb, v);
+    }
+  }
 
   float2* yt = a.y + (size_t)b * N + (size_t)tile * N2 * C;
 #pragma unroll
-  for (int r = 0; r < 16; ++r) {
-    const int j2 = fft_col_out<N2>(t, r);
-    const int e = j2 * k1;  // < N
-    const float2 wv = cmul(a.twa[e & 2047], a.twb[e >> 11]);
-    yt[j2 * C + c] = cmul(x[r], wv);
-  }
+  for (int r = 0; r < 16; ++r) yt[K::out(t, r) * C + c] = x[r];
 }
 
 // ---------------------------------------------------------------------------
@@ -363,6 +402,8 @@ struct P2Args {
   int nwin;
   int64_t window;
   int64_t j_lo, j_hi;
+  int jlo32, jhi32, full;    // the same range as int32, and whether it is [0, n)
+  unsigned int win32;        // window as uint32
   float thr2;
   ci_trigger* d_peaks;       // whole bank
   ci_trigger* d_trig;
@@ -545,18 +586,44 @@ __global__ __launch_bounds__(J * N1 / 16) void k_pass2_trig(P2Args a) {
   load_pass2<N1, N2, C, J>(x, yb, j2, t);
   fft_col<N1, J>(x, lds, t, cc, a.tw);
 
-  u64 best = 0ull;
-  u64* wk = a.wkeys + (size_t)b * a.nwin;
+  // Post-pass: rho^2 = |z|^2 (already in SNR units).  Registers are
+  // visited in increasing j, so a strict ">" keeps the smallest index
+  // among equal values.
+  using K = Col<N1>;
+  float bv = -1.f;
+  int br = 0;
+  bool hot = false;
 #pragma unroll
-  for (int r = 0; r < 16; ++r) {
-    const int j1 = fft_col_out<N1>(t, r);
-    const int j = j2 + N2 * j1;
-    const float r2 = fmaf(x[r].x, x[r].x, x[r].y * x[r].y);
-    if (j >= a.j_lo && j < a.j_hi) {
-      const u64 key = ((u64)__float_as_uint(r2) << 32) | (u64)(0xFFFFFFFFu - (unsigned int)j);
-      best = key > best ? key : best;
-      if (r2 > a.thr2) atomicMax(&wk[j / a.window], key);
+  for (int kk = 0; kk < 16; ++kk) {
+    const int r = K::reg_by_order(kk);
+    float r2 = fmaf(x[r].x, x[r].x, x[r].y * x[r].y);
+    if (!a.full) {
+      const int j = j2 + N2 * K::out(t, r);
+      if (j < a.jlo32 || j >= a.jhi32) r2 = -1.f;
     }
+    if (r2 > bv) {
+      bv = r2;
+      br = r;
+    }
+    hot |= r2 > a.thr2;
+  }
+  if (__any(hot)) {
+    // rare: samples above threshold update their window's key
+    u64* wk = a.wkeys + (size_t)b * a.nwin;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const float r2 = fmaf(x[r].x, x[r].x, x[r].y * x[r].y);
+      const int j = j2 + N2 * K::out(t, r);
+      if (r2 > a.thr2 && (a.full || (j >= a.jlo32 && j < a.jhi32))) {
+        const u64 key = ((u64)__float_as_uint(r2) << 32) | (u64)(0xFFFFFFFFu - (unsigned int)j);
+        atomicMax(&wk[(unsigned int)j / a.win32], key);
+      }
+    }
+  }
+  u64 best = 0ull;
+  if (bv >= 0.f) {
+    const unsigned int j = (unsigned int)(j2 + N2 * K::out(t, br));
+    best = ((u64)__float_as_uint(bv) << 32) | (u64)(0xFFFFFFFFu - j);
   }
   // workgroup max of the peak key, stored as this tile's partial
 #pragma unroll
@@ -614,7 +681,7 @@ __global__ __launch_bounds__(J * N1 / 16) void k_pass2_series(P2Args a) {
   float2* zt = a.z + (size_t)b * N;
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
-    const int j1 = fft_col_out<N1>(t, r);
+    const int j1 = Col<N1>::out(t, r);
     zt[j2 + N2 * j1] = x[r];
   }
 }
@@ -750,6 +817,10 @@ P2Args make_p2(const BatchArgs& a) {
   p.window = a.window;
   p.j_lo = a.j_lo;
   p.j_hi = a.j_hi;
+  p.jlo32 = (int)a.j_lo;
+  p.jhi32 = (int)a.j_hi;
+  p.full = (a.j_lo == 0 && a.j_hi == a.seg->host.n) ? 1 : 0;
+  p.win32 = (unsigned int)(a.window > 0 ? a.window : 1);
   p.thr2 = a.thr2;
   p.d_peaks = a.d_peaks;
   p.d_trig = a.d_trig;
