@@ -8,6 +8,7 @@
 #include <math.h>
 #include <stdarg.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <new>
@@ -119,6 +120,7 @@ void free_seg(Seg* s) {
   if (s->psum) (void)hipFree(s->psum);
   if (s->bsum) (void)hipFree(s->bsum);
   if (s->tw2048) (void)hipFree(s->tw2048);
+  if (s->tw64) (void)hipFree(s->tw64);
   if (s->twa) (void)hipFree(s->twa);
   if (s->twb) (void)hipFree(s->twb);
   delete s;
@@ -218,6 +220,21 @@ hipError_t timed(Ctx* ctx, int kind, int64_t templates, hipStream_t st, F launch
   return hipSuccess;
 }
 
+// Internal streams and fork/join events (created on first use).
+int ensure_streams(Ctx* ctx) {
+  for (int i = 0; i < 2; ++i)
+    if (!ctx->ws[i]) {
+      hipError_t e = hipStreamCreateWithFlags(&ctx->ws[i], hipStreamNonBlocking);
+      if (e != hipSuccess) return hipfail(ctx, e, "internal stream");
+    }
+  for (int i = 0; i < 3; ++i)
+    if (!ctx->sev[i]) {
+      hipError_t e = hipEventCreateWithFlags(&ctx->sev[i], hipEventDisableTiming);
+      if (e != hipSuccess) return hipfail(ctx, e, "internal event");
+    }
+  return CI_OK;
+}
+
 }  // namespace
 
 struct ci_ctx : Ctx {};
@@ -259,6 +276,13 @@ int ci_ctx_destroy(ci_ctx* ctx) {
     ctx->ev_pool.push_back(t.e1);
   }
   for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
+  for (int i = 0; i < 2; ++i)
+    if (ctx->ws[i]) {
+      (void)hipStreamSynchronize(ctx->ws[i]);
+      (void)hipStreamDestroy(ctx->ws[i]);
+    }
+  for (int i = 0; i < 3; ++i)
+    if (ctx->sev[i]) (void)hipEventDestroy(ctx->sev[i]);
   if (ctx->ybuf) (void)hipFree(ctx->ybuf);
   if (ctx->tbuf) (void)hipFree(ctx->tbuf);
   delete ctx;
@@ -333,7 +357,12 @@ int ci_segment_create(ci_ctx* ctx, const ci_segment_spec* spec, const void* d_xt
   if (!s) return fail(ctx, CI_ENOMEM, "segment allocation");
   s->ctx = ctx;
   s->spec = *spec;
-  s->plan = plan_for(l2);
+  {
+    // tile shape: environment overrides for tuning runs, else 4 x 4
+    const char* ec = getenv("CI_TILE_C");
+    const char* ej = getenv("CI_TILE_J");
+    s->plan = plan_for(l2, ec ? atoi(ec) : 4, ej ? atoi(ej) : 4);
+  }
   SegDev& h = s->host;
   h.n = spec->n;
   h.half = spec->n / 2;
@@ -358,22 +387,25 @@ int ci_segment_create(ci_ctx* ctx, const ci_segment_spec* spec, const void* d_xt
   ALLOC(s->psum, sizeof(double) * half);
   ALLOC(s->bsum, sizeof(double) * (half / kSegBlock));
   ALLOC(s->tw2048, sizeof(float2) * 2048);
+  ALLOC(s->tw64, sizeof(double2) * 2048);
   ALLOC(s->twa, sizeof(float2) * 2048);
   ALLOC(s->twb, sizeof(float2) * (nb > 0 ? nb : 1));
 #undef ALLOC
   // twiddle tables in FP64, rounded once to FP32
   std::string fails;
   {
+    double2* t0 = new (std::nothrow) double2[2048];
     float2* t1 = new (std::nothrow) float2[2048];
     float2* t2 = new (std::nothrow) float2[2048];
     float2* t3 = new (std::nothrow) float2[nb > 0 ? nb : 1];
-    if (!t1 || !t2 || !t3) {
-      delete[] t1; delete[] t2; delete[] t3;
+    if (!t0 || !t1 || !t2 || !t3) {
+      delete[] t0; delete[] t1; delete[] t2; delete[] t3;
       free_seg(s);
       return fail(ctx, CI_ENOMEM, "host table allocation");
     }
     for (int i = 0; i < 2048; ++i) {
       const double a = 2.0 * kPi * (double)i / 2048.0;
+      t0[i] = make_double2(cos(a), sin(a));
       t1[i] = make_float2((float)cos(a), (float)sin(a));
       const double b = 2.0 * kPi * (double)i / (double)spec->n;
       t2[i] = make_float2((float)cos(b), (float)sin(b));
@@ -383,11 +415,12 @@ int ci_segment_create(ci_ctx* ctx, const ci_segment_spec* spec, const void* d_xt
       t3[i] = make_float2((float)cos(c), (float)sin(c));
     }
     e = hipMemcpy(s->tw2048, t1, sizeof(float2) * 2048, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(s->tw64, t0, sizeof(double2) * 2048, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(s->twa, t2, sizeof(float2) * 2048, hipMemcpyHostToDevice);
     if (e == hipSuccess && nb > 0)
       e = hipMemcpy(s->twb, t3, sizeof(float2) * nb, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(s->dev, &h, sizeof(SegDev), hipMemcpyHostToDevice);
-    delete[] t1; delete[] t2; delete[] t3;
+    delete[] t0; delete[] t1; delete[] t2; delete[] t3;
     if (e != hipSuccess) {
       free_seg(s);
       return hipfail(ctx, e, "segment table upload");
@@ -582,20 +615,44 @@ int ci_find_triggers(ci_ctx* ctx, const ci_segment* seg, const ci_tparams* d_par
   a.cap = cap;
   a.d_count = d_count;
   a.merge = merge_across_templates ? 1 : 0;
+  {
+    const char* ep = getenv("CI_P2_WG_PER_CU");
+    a.p2_per_cu = ep ? atoi(ep) : 0;
+  }
+  rc = ensure_streams(ctx);
+  if (rc != CI_OK) return rc;
+  // Batches alternate between two internal streams (batch b uses slot set
+  // b & 1 and stream b & 1), so one batch's second pass overlaps the next
+  // batch's first pass.  The finalisers are chained in batch order, which
+  // keeps the trigger list ordered; the caller's stream joins the last one.
+  e = hipEventRecord(ctx->sev[2], st);
+  for (int i = 0; i < 2 && e == hipSuccess; ++i) e = hipStreamWaitEvent(ctx->ws[i], ctx->sev[2], 0);
+  if (e != hipSuccess) return hipfail(ctx, e, "stream fork");
+  hipEvent_t prev_fin = nullptr;
   for (int64_t b = 0, t0 = 0; t0 < n; ++b, t0 += B) {
+    hipStream_t sb = ctx->ws[b & 1];
     a.t0 = t0;
     a.nb = (int)((n - t0) < B ? (n - t0) : B);
     a.slot = (int)(b & 1);
     a.params = d_params + t0;
     a.y = static_cast<float2*>(ctx->ybuf) + (size_t)a.slot * B * N;
     a.last_batch = (t0 + B >= n) ? 1 : 0;
-    e = timed(ctx, 0, a.nb, st, [&] { return launch_pass1(a, true, st); });
+    e = timed(ctx, 0, a.nb, sb, [&] { return launch_pass1(a, true, sb); });
     if (e != hipSuccess) return hipfail(ctx, e, "pass-1 launch");
-    e = timed(ctx, 1, a.nb, st, [&] { return launch_pass2_trig(a, st); });
+    e = timed(ctx, 1, a.nb, sb, [&] { return launch_pass2_trig(a, sb); });
     if (e != hipSuccess) return hipfail(ctx, e, "pass-2 launch");
-    e = launch_fin(a, st);
+    if (prev_fin) {
+      e = hipStreamWaitEvent(sb, prev_fin, 0);
+      if (e != hipSuccess) return hipfail(ctx, e, "finaliser ordering");
+    }
+    e = launch_fin(a, sb);
     if (e != hipSuccess) return hipfail(ctx, e, "finalise launch");
+    prev_fin = ctx->sev[b & 1];
+    e = hipEventRecord(prev_fin, sb);
+    if (e != hipSuccess) return hipfail(ctx, e, "finaliser event");
   }
+  e = hipStreamWaitEvent(st, prev_fin, 0);
+  if (e != hipSuccess) return hipfail(ctx, e, "stream join");
   return CI_OK;
 }
 

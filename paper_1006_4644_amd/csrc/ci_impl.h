@@ -31,7 +31,7 @@ struct Plan {
   int j;            // j2 columns per pass-2 workgroup
 };
 
-Plan plan_for(int log2n);
+Plan plan_for(int log2n, int c, int j);
 
 // Per-call trigger bookkeeping (device).  Two slot sets alternate between
 // consecutive batches so that batch b+1's first pass can clear its keys
@@ -70,6 +70,10 @@ struct Ctx {
   size_t pinbytes = 0;
   hipEvent_t pin_ev = nullptr;
   bool pin_ev_armed = false;
+  // two internal streams that alternate batches, and events to fork from
+  // and join back to the caller's stream
+  hipStream_t ws[2] = {nullptr, nullptr};
+  hipEvent_t sev[3] = {nullptr, nullptr, nullptr};
   // instrumentation
   bool timing = false;
   std::vector<TimedLaunch> launches;
@@ -85,6 +89,7 @@ struct Seg {
   double* psum;      // [n/2]  running sum of 4 df f^-7/3 / S from k_low
   double* bsum;      // [n/2 / kSegBlock] block sums, then block offsets
   float2* tw2048;    // [2048] exp(2 pi i e / 2048)
+  double2* tw64;     // [2048] exp(2 pi i e / 2048) in FP64
   float2* twa;       // [2048] exp(2 pi i e / n)
   float2* twb;       // [n/2048] exp(2 pi i 2048 e / n)
   Plan plan;
@@ -123,6 +128,7 @@ struct BatchArgs {
   int last_batch;
   // series mode
   float2* d_z;                // first template's series
+  int p2_per_cu;              // pass-2 workgroups per CU (0: as many as fit)
 };
 
 hipError_t launch_pass1(const BatchArgs& a, bool zero_trig, hipStream_t st);

@@ -17,9 +17,9 @@
 //   stage 3: lane t holds rows d = t + (L/16) i of the radix-R3 step;
 //            output b lands at j = d + 256 b.
 // R3 == 1 stops after stage 2 with outputs j = t + 16 a2.
-// The LDS exchanges use rotated rows so that the lanes of one access hit
-// distinct banks (row a of exchange 1 is rotated by a * rho1, row d of
-// exchange 2 by d, or by d/2 when R3 == 2).
+// The LDS exchanges are laid out so that the lanes of one access hit
+// distinct banks: exchange 1 pads its rows, exchange 2 rotates row d by d
+// (by d/2 when R3 == 2).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -152,96 +152,115 @@ __device__ __forceinline__ void idft_groups(float2 (&x)[16]) {
 // the column transform, stage by stage
 // ---------------------------------------------------------------------------
 
-template <int L>
+// Every LDS access below is a per-lane base pointer plus a compile-time
+// offset, so the address arithmetic costs a few instructions per stage.
+// Exchange 1 pads its 16 rows to S1 = L/16 + P1 slots; exchange 2 rotates
+// row d by d (or d/2 when R3 == 2), which is constant per lane.
+template <int L, int NC>
 struct Col {
   static constexpr int Lp = L / 16;
   static constexpr int R3 = L / 256;
-  static constexpr int RHO1 = R3 == 1 ? 1 : (R3 == 2 ? 2 : 0);
+  static constexpr int P1 = R3 == 1 ? 1 : (R3 == 2 ? 2 : (NC == 4 ? 4 : 0));
+  static constexpr int S1 = Lp + P1;
+  static constexpr int LDS_ELEMS = (16 * S1 > L ? 16 * S1 : L) * NC;
   static_assert(R3 == 1 || R3 == 2 || R3 == 4 || R3 == 8, "L in 256..2048");
 
-  // exchange-1 slot of stage-1 output (row a, column position s)
-  __device__ static __forceinline__ int x1(int a, int s) {
-    return a * Lp + ((s + a * RHO1) & (Lp - 1));
-  }
-  // exchange-2 slot of stage-2 output (row d, position s)
-  __device__ static __forceinline__ int x2(int d, int s) {
-    if constexpr (R3 == 2) return d * 2 + ((s + (d >> 1)) & 1);
-    else return d * R3 + ((s + d) & (R3 - 1));
-  }
-
   // Stage 1: radix 16 in registers (HALF: inputs m >= 8 are zero), table
-  // twiddle w_L^{a t}, store to LDS.
-  template <int NC, bool HALF>
-  __device__ static __forceinline__ void stage1(float2 (&x)[16], float2* lds, int t, int c,
-                                                const float2* __restrict__ tw) {
+  // twiddle w_L^{a t}, store row a, position t.
+  // tw: w_{L TS}^e at tw[e] (TS = 2048 / L for the global w_2048 table,
+  // 1 for an LDS copy of w_L).
+  template <bool HALF, int TS = 2048 / L>
+  __device__ static __forceinline__ void stage1(float2 (&x)[16], float2* lds, unsigned t,
+                                                unsigned c, const float2* tw) {
     idft16<HALF>(x);
+    // twiddle index a t TS, walked as a byte offset
+    const char* twb = reinterpret_cast<const char*>(tw);
+    const unsigned step = t * (unsigned)TS * (unsigned)sizeof(float2);
+    unsigned off = 0;
 #pragma unroll
-    for (int a = 1; a < 16; ++a) x[a] = cmul(x[a], tw[(a * t) * (2048 / L)]);
+    for (int a = 1; a < 16; ++a) {
+      off += step;
+      x[a] = cmul(x[a], *reinterpret_cast<const float2*>(twb + off));
+    }
+    float2* p = lds + t * NC + c;
 #pragma unroll
-    for (int a = 0; a < 16; ++a) lds[x1(a, t) * NC + c] = x[a];
+    for (int a = 0; a < 16; ++a) p[a * S1 * NC] = x[a];
     __syncthreads();
   }
 
-  // Stage 2 load + radix 16 (no twiddle yet).
-  template <int NC>
-  __device__ static __forceinline__ void stage2(float2 (&x)[16], const float2* lds, int t, int c) {
-    const int a0 = t / R3, s2 = t % R3;
+  // Stage 2 load (row a0 = t / R3, positions s2 + R3 q) and radix 16.
+  __device__ static __forceinline__ void stage2(float2 (&x)[16], const float2* lds, unsigned t,
+                                                unsigned c) {
+    const unsigned a0 = t / R3, s2 = t % R3;
+    const float2* p = lds + (a0 * S1 + s2) * NC + c;
 #pragma unroll
-    for (int q = 0; q < 16; ++q) x[q] = lds[x1(a0, s2 + R3 * q) * NC + c];
+    for (int q = 0; q < 16; ++q) x[q] = p[q * R3 * NC];
     idft16(x);
   }
 
-  // Stage-2 table twiddle w_{16 R3}^{a2 s2} (R3 > 1).
-  __device__ static __forceinline__ void stage2_twiddle(float2 (&x)[16], int t,
-                                                        const float2* __restrict__ tw) {
+  // Stage-2 table twiddle w_{16 R3}^{a2 s2} = w_L^{16 a2 s2} (R3 > 1).
+  template <int TS = 2048 / L>
+  __device__ static __forceinline__ void stage2_twiddle(float2 (&x)[16], unsigned t,
+                                                        const float2* tw) {
     if constexpr (R3 > 1) {
-      const int s2 = t % R3;
+      const char* twb = reinterpret_cast<const char*>(tw);
+      const unsigned step = (t % R3) * 16u * (unsigned)TS * (unsigned)sizeof(float2);
+      unsigned off = 0;
 #pragma unroll
-      for (int a2 = 1; a2 < 16; ++a2) x[a2] = cmul(x[a2], tw[(a2 * s2) * (2048 / (16 * R3))]);
+      for (int a2 = 1; a2 < 16; ++a2) {
+        off += step;
+        x[a2] = cmul(x[a2], *reinterpret_cast<const float2*>(twb + off));
+      }
     }
   }
 
-  // Stage 3 (R3 > 1): store stage-2 outputs, reload by row, radix R3.
-  template <int NC>
-  __device__ static __forceinline__ void stage3(float2 (&x)[16], float2* lds, int t, int c) {
+  // Stage 3 (R3 > 1): store stage-2 outputs (row d = a0 + 16 a2, position
+  // s2), reload rows d = t + Lp i, radix R3.
+  __device__ static __forceinline__ void stage3(float2 (&x)[16], float2* lds, unsigned t,
+                                                unsigned c) {
     if constexpr (R3 > 1) {
-      const int a0 = t / R3, s2 = t % R3;
+      const unsigned a0 = t / R3, s2 = t % R3;
+      const unsigned rw = R3 == 2 ? ((s2 + (a0 >> 1)) & 1u) : ((s2 + a0) & (R3 - 1));
+      __syncthreads();
+      float2* pw = lds + (a0 * R3 + rw) * NC + c;
+#pragma unroll
+      for (int a2 = 0; a2 < 16; ++a2) pw[a2 * 16 * R3 * NC] = x[a2];
       __syncthreads();
 #pragma unroll
-      for (int a2 = 0; a2 < 16; ++a2) lds[x2(a0 + 16 * a2, s2) * NC + c] = x[a2];
-      __syncthreads();
+      for (int s = 0; s < R3; ++s) {
+        const unsigned rr = R3 == 2 ? ((s + (t >> 1)) & 1u) : ((s + t) & (R3 - 1));
+        const float2* pr = lds + (t * R3 + rr) * NC + c;
 #pragma unroll
-      for (int i = 0; i < 16 / R3; ++i) {
-        const int d = t + Lp * i;
-#pragma unroll
-        for (int s = 0; s < R3; ++s) x[i * R3 + s] = lds[x2(d, s) * NC + c];
+        for (int i = 0; i < 16 / R3; ++i) x[i * R3 + s] = pr[i * Lp * R3 * NC];
       }
       idft_groups<R3>(x);
     }
   }
 
-  // Output index j in [0, L) held in register r after the transform.
-  __device__ static __forceinline__ int out(int t, int r) {
-    if constexpr (R3 == 1) return t + 16 * r;
-    else return t + Lp * (r / R3) + 256 * (r % R3);
+  // Output index j in [0, L) held in register r, relative to lane t:
+  // j = t + off(r).
+  __host__ __device__ static constexpr int off(int r) {
+    if constexpr (R3 == 1) return 16 * r;
+    else return Lp * (r / R3) + 256 * (r % R3);
   }
-  // Register holding the k-th smallest output of lane t (outputs of a lane
-  // increase with k).
+  __device__ static __forceinline__ int out(int t, int r) { return t + off(r); }
+  // Register holding the k-th smallest output of a lane.
   __host__ __device__ static constexpr int reg_by_order(int k) {
     if constexpr (R3 == 1) return k;
     else return (k % (16 / R3)) * R3 + k / (16 / R3);
   }
 };
 
-// Full column DFT with table twiddles (pass 2): see Col<L>.
-template <int L, int NC>
-__device__ __forceinline__ void fft_col(float2 (&x)[16], float2* lds, int t, int c,
-                                        const float2* __restrict__ tw) {
-  using K = Col<L>;
-  K::template stage1<NC, false>(x, lds, t, c, tw);
-  K::template stage2<NC>(x, lds, t, c);
-  K::stage2_twiddle(x, t, tw);
-  K::template stage3<NC>(x, lds, t, c);
+// Full column DFT with table twiddles (pass 2): see Col<L, NC>.  TS as in
+// Col::stage1.
+template <int L, int NC, int TS = 2048 / L>
+__device__ __forceinline__ void fft_col(float2 (&x)[16], float2* lds, unsigned t, unsigned c,
+                                        const float2* tw) {
+  using K = Col<L, NC>;
+  K::template stage1<false, TS>(x, lds, t, c, tw);
+  K::stage2(x, lds, t, c);
+  K::template stage2_twiddle<TS>(x, t, tw);
+  K::stage3(x, lds, t, c);
 }
 
 }  // namespace ci

@@ -238,14 +238,14 @@ __device__ __forceinline__ float2 tw_n(const float2* __restrict__ twa,
 
 template <int N1, int N2, int C>
 __global__ __launch_bounds__(C * N2 / 16) void k_pass1(P1Args a) {
-  using K = Col<N2>;
+  using K = Col<N2, C>;
   constexpr int N = N1 * N2;
   constexpr int Lp = K::Lp;
   constexpr int R3 = K::R3;
   constexpr int TILES = N1 / C;
   extern __shared__ float2 lds[];
-  const int tid = threadIdx.x;
-  const int c = tid % C, t = tid / C;
+  const unsigned tid = threadIdx.x;
+  const unsigned c = tid % C, t = tid / C;
 
   if (a.wkeys) {
     const int64_t gid = blockIdx.x * (int64_t)blockDim.x + tid;
@@ -257,14 +257,14 @@ __global__ __launch_bounds__(C * N2 / 16) void k_pass1(P1Args a) {
   const int bid = xcd_remap(blockIdx.x, gridDim.x);
   const int b = bid / TILES, tile = bid % TILES;
   const ci_tparams P = a.prm[b];
-  const int k1 = tile * C + c;
+  const unsigned k1 = tile * C + c;
 
   // Z_k for k = k1 + N1 k2, k2 = t + Lp m.  Every band bin lies below n/2,
   // i.e. k2 < N2/2: only m < 8 can be nonzero.
   float2 x[16];
 #pragma unroll
   for (int m = 0; m < 8; ++m) {
-    const int k = k1 + N1 * (t + Lp * m);
+    const int k = (int)(k1 + N1 * (t + Lp * m));
     float2 v = make_float2(0.f, 0.f);
     if (k >= P.k_low && k <= P.k_high) {
       const float2 e = chirp_phasor(P, k);
@@ -273,20 +273,20 @@ __global__ __launch_bounds__(C * N2 / 16) void k_pass1(P1Args a) {
     x[m] = v;
   }
 
-  K::template stage1<C, true>(x, lds, t, c, a.tw);
-  K::template stage2<C>(x, lds, t, c);
+  K::template stage1<true>(x, lds, t, c, a.tw);
+  K::stage2(x, lds, t, c);
   // Stage-2 twiddle merged with the four-step twiddle w_N^{k1 j2}: the
   // factor of output a2 is base * w^{a2} (a geometric sequence).
   float2 base, w;
   if constexpr (R3 == 1) {
     // j2 = t + 16 a2 is final here
-    base = tw_n(a.twa, a.twb, k1 * t);
-    w = tw_n(a.twa, a.twb, 16 * k1);
+    base = tw_n(a.twa, a.twb, (int)(k1 * t));
+    w = tw_n(a.twa, a.twb, (int)(16 * k1));
   } else {
     // rows d = a0 + 16 a2 of the radix-R3 step; output b adds 256 b to j2
     const int a0 = t / R3, s2 = t % R3;
-    base = tw_n(a.twa, a.twb, k1 * a0);
-    w = cmul(a.tw[s2 * (2048 / (16 * R3))], tw_n(a.twa, a.twb, 16 * k1));
+    base = tw_n(a.twa, a.twb, (int)(k1 * a0));
+    w = cmul(a.tw[s2 * (2048 / (16 * R3))], tw_n(a.twa, a.twb, (int)(16 * k1)));
   }
   x[0] = cmul(x[0], base);
 #pragma unroll
@@ -294,9 +294,9 @@ __global__ __launch_bounds__(C * N2 / 16) void k_pass1(P1Args a) {
     base = cmul(base, w);
     x[a2] = cmul(x[a2], base);
   }
-  K::template stage3<C>(x, lds, t, c);
+  K::stage3(x, lds, t, c);
   if constexpr (R3 > 1) {
-    const float2 v = tw_n(a.twa, a.twb, 256 * k1);
+    const float2 v = tw_n(a.twa, a.twb, (int)(256 * k1));
     float2 vb = v;
 #pragma unroll
     for (int bb = 1; bb < R3; ++bb) {
@@ -307,8 +307,9 @@ __global__ __launch_bounds__(C * N2 / 16) void k_pass1(P1Args a) {
   }
 
   float2* yt = a.y + (size_t)b * N + (size_t)tile * N2 * C;
+  const unsigned o = t * C + c;
 #pragma unroll
-  for (int r = 0; r < 16; ++r) yt[K::out(t, r) * C + c] = x[r];
+  for (int r = 0; r < 16; ++r) yt[o + K::off(r) * C] = x[r];
 }
 
 // ---------------------------------------------------------------------------
@@ -318,31 +319,30 @@ __global__ __launch_bounds__(C * N2 / 16) void k_pass1(P1Args a) {
 // Load the pass-2 column inputs: lane (cc, t) of tile `tile` gets
 // x[q] = Y[k1 = t + (N1/16) q][j2 = tile J + cc].
 template <int N1, int N2, int C, int J>
-__device__ __forceinline__ void load_pass2(float2 (&x)[16], const float2* __restrict__ yb, int j2,
-                                           int t) {
-  constexpr int Lp = N1 / 16;
+__device__ __forceinline__ void load_pass2(float2 (&x)[16], const float2* __restrict__ yb,
+                                           unsigned j2, unsigned t) {
+  constexpr unsigned Lp = N1 / 16;
+  static_assert(Lp % C == 0, "tile width divides the stage stride");
+  const float2* p = yb + ((t / C) * N2 + j2) * C + (t % C);
 #pragma unroll
-  for (int q = 0; q < 16; ++q) {
-    const int k1 = t + Lp * q;
-    x[q] = yb[((size_t)(k1 / C) * N2 + j2) * C + (k1 % C)];
-  }
+  for (int q = 0; q < 16; ++q) x[q] = p[q * (Lp * N2)];
 }
 
 // z_j = sum_{k1} exp(2 pi i j1 k1 / N1) Y[k1][j2] for j = j2 + N2 j1, with
 // FP64 twiddles and accumulation, reduced over the workgroup.  Every lane
 // returns the result.  scratch: >= 2 * blockDim.x doubles.
 template <int N1, int N2, int C>
-__device__ double2 direct_z(const float2* __restrict__ yb, int64_t j, double* scratch) {
+__device__ double2 direct_z(const float2* __restrict__ yb, const double2* __restrict__ tw64,
+                            int64_t j, double* scratch) {
   const int tid = threadIdx.x, nt = blockDim.x;
   const int j2 = (int)(j % N2), j1 = (int)(j / N2);
   double re = 0.0, im = 0.0;
   for (int k1 = tid; k1 < N1; k1 += nt) {
     const float2 v = yb[((size_t)(k1 / C) * N2 + j2) * C + (k1 % C)];
     const int e = (int)(((int64_t)j1 * k1) % N1);
-    double s, c;
-    sincospi(2.0 * (double)e / (double)N1, &s, &c);
-    re += (double)v.x * c - (double)v.y * s;
-    im += (double)v.x * s + (double)v.y * c;
+    const double2 w = tw64[e * (2048 / N1)];
+    re += (double)v.x * w.x - (double)v.y * w.y;
+    im += (double)v.x * w.y + (double)v.y * w.x;
   }
   __syncthreads();
   scratch[2 * tid] = re;
@@ -386,6 +386,7 @@ __device__ int block_excl_scan(int v, int* sh, int* total) {
 struct P2Args {
   const ci_tparams* prm;     // batch's first template
   const float2* tw;
+  const double2* tw64;
   const float2* y;           // intermediate of this batch
   int64_t t0;                // bank index of the batch's first template
   int nb;
@@ -454,7 +455,7 @@ __device__ void finalize_template(const P2Args& a, int b, void* ldsv) {
   }
   {
     const int64_t j = (int64_t)(0xFFFFFFFFu - (unsigned int)(pk & 0xFFFFFFFFull));
-    const double2 z = direct_z<N1, N2, C>(yb, j, dscr);
+    const double2 z = direct_z<N1, N2, C>(yb, a.tw64, j, dscr);
     if (tid == 0) {
       ci_trigger e;
       e.tmpl = tg; e.index = j; e.rho2 = __uint_as_float((unsigned int)(pk >> 32));
@@ -494,7 +495,7 @@ __device__ void finalize_template(const P2Args& a, int b, void* ldsv) {
   __syncthreads();
   for (int i = 0; i < total; ++i) {
     const int64_t j = st[i].index;
-    const double2 z = direct_z<N1, N2, C>(yb, j, dscr);
+    const double2 z = direct_z<N1, N2, C>(yb, a.tw64, j, dscr);
     if (tid == 0) {
       st[i].re = (float)z.x;
       st[i].im = (float)z.y;
@@ -570,74 +571,99 @@ __device__ void place_batch(const P2Args& a, void* ldsv) {
 // pass 2: second four-step pass + post-pass
 // ---------------------------------------------------------------------------
 
+// Persistent pass 2: each workgroup walks tiles item = blockIdx.x + k G
+// and prefetches the next tile's column inputs into registers while it
+// transforms the current one, so that a CU keeps loads in flight during
+// its butterflies.
 template <int N1, int N2, int C, int J>
-__global__ __launch_bounds__(J * N1 / 16) void k_pass2_trig(P2Args a) {
+__global__ __launch_bounds__(J * N1 / 16, 4) void k_pass2_trig(P2Args a) {
   constexpr int N = N1 * N2;
   constexpr int TILES = N2 / J;
+  using K = Col<N1, J>;
   extern __shared__ float2 lds[];
-  const int tid = threadIdx.x;
-  const int cc = tid % J, t = tid / J;
-  const int bid = xcd_remap(blockIdx.x, gridDim.x);
-  const int b = bid / TILES, tile = bid % TILES;
-  const int j2 = tile * J + cc;
-  const float2* yb = a.y + (size_t)b * N;
+  __shared__ u64 s_best[16];
+  const unsigned tid = threadIdx.x;
+  const unsigned cc = tid % J, t = tid / J;
+  const int total = a.nb * TILES;
 
-  float2 x[16];
-  load_pass2<N1, N2, C, J>(x, yb, j2, t);
-  fft_col<N1, J>(x, lds, t, cc, a.tw);
+  // w_{N1}^e, e < N1, copied once into LDS behind the exchange buffer: the
+  // stage twiddles then never wait behind the prefetched tile's loads
+  // (vector-memory loads retire in order).
+  float2* twl = lds + K::LDS_ELEMS;
+  for (unsigned e = tid; e < (unsigned)N1; e += blockDim.x) twl[e] = a.tw[e * (2048 / N1)];
+  __syncthreads();
 
-  // Post-pass: rho^2 = |z|^2 (already in SNR units).  Registers are
-  // visited in increasing j, so a strict ">" keeps the smallest index
-  // among equal values.
-  using K = Col<N1>;
-  float bv = -1.f;
-  int br = 0;
-  bool hot = false;
-#pragma unroll
-  for (int kk = 0; kk < 16; ++kk) {
-    const int r = K::reg_by_order(kk);
-    float r2 = fmaf(x[r].x, x[r].x, x[r].y * x[r].y);
-    if (!a.full) {
-      const int j = j2 + N2 * K::out(t, r);
-      if (j < a.jlo32 || j >= a.jhi32) r2 = -1.f;
-    }
-    if (r2 > bv) {
-      bv = r2;
-      br = r;
-    }
-    hot |= r2 > a.thr2;
+  float2 xn[16];
+  int item = blockIdx.x;
+  if (item < total) {
+    const int b = item / TILES, tile = item % TILES;
+    load_pass2<N1, N2, C, J>(xn, a.y + (size_t)b * N, tile * J + cc, t);
   }
-  if (__any(hot)) {
-    // rare: samples above threshold update their window's key
-    u64* wk = a.wkeys + (size_t)b * a.nwin;
+  for (; item < total; item += gridDim.x) {
+    float2 x[16];
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      const float r2 = fmaf(x[r].x, x[r].x, x[r].y * x[r].y);
-      const int j = j2 + N2 * K::out(t, r);
-      if (r2 > a.thr2 && (a.full || (j >= a.jlo32 && j < a.jhi32))) {
-        const u64 key = ((u64)__float_as_uint(r2) << 32) | (u64)(0xFFFFFFFFu - (unsigned int)j);
-        atomicMax(&wk[(unsigned int)j / a.win32], key);
+    for (int r = 0; r < 16; ++r) x[r] = xn[r];
+    const int next = item + gridDim.x;
+    if (next < total) {
+      const int bn = next / TILES, tn = next % TILES;
+      load_pass2<N1, N2, C, J>(xn, a.y + (size_t)bn * N, tn * J + cc, t);
+    }
+    const int b = item / TILES, tile = item % TILES;
+    const unsigned j2 = tile * J + cc;
+    fft_col<N1, J, 1>(x, lds, t, cc, twl);
+
+    // Post-pass: rho^2 = |z|^2 (already in SNR units).  Registers are
+    // visited in increasing j, so a strict ">" keeps the smallest index
+    // among equal values.
+    float bv = -1.f;
+    int br = 0;
+    bool hot = false;
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk) {
+      const int r = K::reg_by_order(kk);
+      float r2 = fmaf(x[r].x, x[r].x, x[r].y * x[r].y);
+      if (!a.full) {
+        const int j = (int)j2 + N2 * K::out((int)t, r);
+        if (j < a.jlo32 || j >= a.jhi32) r2 = -1.f;
+      }
+      if (r2 > bv) {
+        bv = r2;
+        br = r;
+      }
+      hot |= r2 > a.thr2;
+    }
+    if (__any(hot)) {
+      // rare: samples above threshold update their window's key
+      u64* wk = a.wkeys + (size_t)b * a.nwin;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const float r2 = fmaf(x[r].x, x[r].x, x[r].y * x[r].y);
+        const int j = (int)j2 + N2 * K::out((int)t, r);
+        if (r2 > a.thr2 && (a.full || (j >= a.jlo32 && j < a.jhi32))) {
+          const u64 key = ((u64)__float_as_uint(r2) << 32) | (u64)(0xFFFFFFFFu - (unsigned int)j);
+          atomicMax(&wk[(unsigned int)j / a.win32], key);
+        }
       }
     }
-  }
-  u64 best = 0ull;
-  if (bv >= 0.f) {
-    const unsigned int j = (unsigned int)(j2 + N2 * K::out(t, br));
-    best = ((u64)__float_as_uint(bv) << 32) | (u64)(0xFFFFFFFFu - j);
-  }
-  // workgroup max of the peak key, stored as this tile's partial
+    u64 best = 0ull;
+    if (bv >= 0.f) {
+      const unsigned int j = (unsigned int)((int)j2 + N2 * K::out((int)t, br));
+      best = ((u64)__float_as_uint(bv) << 32) | (u64)(0xFFFFFFFFu - j);
+    }
+    // workgroup max of the peak key, stored as this tile's partial
 #pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    const u64 o = __shfl_xor(best, off, 64);
-    best = o > best ? o : best;
-  }
-  __shared__ u64 s_best[16];
-  if ((tid & 63) == 0) s_best[tid >> 6] = best;
-  __syncthreads();
-  if (tid == 0) {
-    u64 m = 0ull;
-    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) m = s_best[i] > m ? s_best[i] : m;
-    a.ppart[(size_t)b * TILES + tile] = m;
+    for (int off = 32; off > 0; off >>= 1) {
+      const u64 o = __shfl_xor(best, off, 64);
+      best = o > best ? o : best;
+    }
+    if ((tid & 63) == 0) s_best[tid >> 6] = best;
+    __syncthreads();
+    if (tid == 0) {
+      u64 m = 0ull;
+      for (int i = 0; i < (int)(blockDim.x >> 6); ++i) m = s_best[i] > m ? s_best[i] : m;
+      a.ppart[(size_t)b * TILES + tile] = m;
+    }
+    __syncthreads();
   }
 }
 
@@ -667,11 +693,11 @@ __global__ __launch_bounds__(J * N1 / 16) void k_pass2_series(P2Args a) {
   constexpr int N = N1 * N2;
   constexpr int TILES = N2 / J;
   extern __shared__ float2 lds[];
-  const int tid = threadIdx.x;
-  const int cc = tid % J, t = tid / J;
+  const unsigned tid = threadIdx.x;
+  const unsigned cc = tid % J, t = tid / J;
   const int bid = xcd_remap(blockIdx.x, gridDim.x);
   const int b = bid / TILES, tile = bid % TILES;
-  const int j2 = tile * J + cc;
+  const unsigned j2 = tile * J + cc;
   const float2* yb = a.y + (size_t)b * N;
 
   float2 x[16];
@@ -681,7 +707,7 @@ __global__ __launch_bounds__(J * N1 / 16) void k_pass2_series(P2Args a) {
   float2* zt = a.z + (size_t)b * N;
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
-    const int j1 = Col<N1>::out(t, r);
+    const int j1 = Col<N1, J>::out(t, r);
     zt[j2 + N2 * j1] = x[r];
   }
 }
@@ -703,7 +729,7 @@ __global__ void k_init_call(ci_trigger* mrec, int nwin, u64* run, int64_t* d_cou
 // host launchers
 // ---------------------------------------------------------------------------
 
-Plan plan_for(int log2n) {
+Plan plan_for(int log2n, int c, int j) {
   Plan p;
   p.log2n = log2n;
   switch (log2n) {
@@ -715,8 +741,8 @@ Plan plan_for(int log2n) {
     case 21: p.n1 = 2048; p.n2 = 1024; break;
     default: p.n1 = p.n2 = 0;
   }
-  p.c = 8;
-  p.j = 8;
+  p.c = (c == 4 || c == 8) ? c : 4;
+  p.j = (j == 4 || j == 8) ? j : 4;
   return p;
 }
 
@@ -801,6 +827,7 @@ P2Args make_p2(const BatchArgs& a) {
   const int s = a.slot;
   p.prm = a.params;
   p.tw = a.seg->tw2048;
+  p.tw64 = a.seg->tw64;
   p.y = a.y;
   p.t0 = a.t0;
   p.nb = a.nb;
@@ -835,7 +862,7 @@ P2Args make_p2(const BatchArgs& a) {
 template <int N1, int N2, int C, int J>
 struct Inst {
   static hipError_t p1(const BatchArgs& a, bool zero, hipStream_t st) {
-    const size_t lds = (size_t)N2 * C * sizeof(float2);
+    const size_t lds = (size_t)Col<N2, C>::LDS_ELEMS * sizeof(float2);
     auto kern = k_pass1<N1, N2, C>;
     hipError_t e = set_lds(kern, lds);
     if (e != hipSuccess) return e;
@@ -844,12 +871,26 @@ struct Inst {
     return hipGetLastError();
   }
   static hipError_t p2t(const BatchArgs& a, hipStream_t st) {
-    const size_t lds = (size_t)N1 * J * sizeof(float2);
+    const size_t lds = (size_t)(Col<N1, J>::LDS_ELEMS + N1) * sizeof(float2);
     auto kern = k_pass2_trig<N1, N2, C, J>;
     hipError_t e = set_lds(kern, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(kern, dim3((unsigned)(a.nb * (N2 / J))), dim3(J * N1 / 16), lds, st,
-                       make_p2(a));
+    // workgroups that fit at once, per CU, and the CU count (per instantiation)
+    static int per_cu = 0, cus = 0;
+    if (per_cu == 0) {
+      int dev = 0;
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, J * N1 / 16, lds);
+      if (e == hipSuccess) e = hipGetDevice(&dev);
+      if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+      if (e != hipSuccess) return e;
+      if (per_cu < 1) per_cu = 1;
+    }
+    const int wpc = (a.p2_per_cu > 0 && a.p2_per_cu < per_cu) ? a.p2_per_cu : per_cu;
+    const long long items = (long long)a.nb * (N2 / J);
+    long long grid = (long long)wpc * cus;
+    if (grid > items) grid = items;
+    if (grid < 1) grid = 1;
+    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(J * N1 / 16), lds, st, make_p2(a));
     return hipGetLastError();
   }
   static hipError_t fin(const BatchArgs& a, hipStream_t st) {
@@ -858,7 +899,7 @@ struct Inst {
     return hipGetLastError();
   }
   static hipError_t p2s(const BatchArgs& a, hipStream_t st) {
-    const size_t lds = (size_t)N1 * J * sizeof(float2);
+    const size_t lds = (size_t)Col<N1, J>::LDS_ELEMS * sizeof(float2);
     auto kern = k_pass2_series<N1, N2, C, J>;
     hipError_t e = set_lds(kern, lds);
     if (e != hipSuccess) return e;
@@ -868,32 +909,43 @@ struct Inst {
   }
 };
 
-template <typename F>
-hipError_t dispatch(int log2n, F f) {
+template <int C, int J, typename F>
+hipError_t dispatch_n(int log2n, F f) {
   switch (log2n) {
-    case 16: return f(Inst<256, 256, 8, 8>());
-    case 17: return f(Inst<512, 256, 8, 8>());
-    case 18: return f(Inst<512, 512, 8, 8>());
-    case 19: return f(Inst<1024, 512, 8, 8>());
-    case 20: return f(Inst<1024, 1024, 8, 8>());
-    case 21: return f(Inst<2048, 1024, 8, 8>());
+    case 16: return f(Inst<256, 256, C, J>());
+    case 17: return f(Inst<512, 256, C, J>());
+    case 18: return f(Inst<512, 512, C, J>());
+    case 19: return f(Inst<1024, 512, C, J>());
+    case 20: return f(Inst<1024, 1024, C, J>());
+    case 21: return f(Inst<2048, 1024, C, J>());
     default: return hipErrorInvalidValue;
   }
+}
+
+// Tile shapes: C k1-columns per pass-1 workgroup, J j2-columns per pass-2
+// workgroup (4 or 8 each).
+template <typename F>
+hipError_t dispatch(const Plan& p, F f) {
+  if (p.c == 4 && p.j == 4) return dispatch_n<4, 4>(p.log2n, f);
+  if (p.c == 4 && p.j == 8) return dispatch_n<4, 8>(p.log2n, f);
+  if (p.c == 8 && p.j == 4) return dispatch_n<8, 4>(p.log2n, f);
+  if (p.c == 8 && p.j == 8) return dispatch_n<8, 8>(p.log2n, f);
+  return hipErrorInvalidValue;
 }
 
 }  // namespace
 
 hipError_t launch_pass1(const BatchArgs& a, bool zero_trig, hipStream_t st) {
-  return dispatch(a.seg->plan.log2n, [&](auto inst) { return decltype(inst)::p1(a, zero_trig, st); });
+  return dispatch(a.seg->plan, [&](auto inst) { return decltype(inst)::p1(a, zero_trig, st); });
 }
 hipError_t launch_pass2_trig(const BatchArgs& a, hipStream_t st) {
-  return dispatch(a.seg->plan.log2n, [&](auto inst) { return decltype(inst)::p2t(a, st); });
+  return dispatch(a.seg->plan, [&](auto inst) { return decltype(inst)::p2t(a, st); });
 }
 hipError_t launch_fin(const BatchArgs& a, hipStream_t st) {
-  return dispatch(a.seg->plan.log2n, [&](auto inst) { return decltype(inst)::fin(a, st); });
+  return dispatch(a.seg->plan, [&](auto inst) { return decltype(inst)::fin(a, st); });
 }
 hipError_t launch_pass2_series(const BatchArgs& a, hipStream_t st) {
-  return dispatch(a.seg->plan.log2n, [&](auto inst) { return decltype(inst)::p2s(a, st); });
+  return dispatch(a.seg->plan, [&](auto inst) { return decltype(inst)::p2s(a, st); });
 }
 
 }  // namespace ci

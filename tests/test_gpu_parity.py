@@ -253,3 +253,30 @@ def test_full_size_fp32_workload_sampled(ctx):
         best = same[np.lexsort((same["tmpl"], -same["rho2"]))][0]
         assert (m["tmpl"], m["index"], m["rho2"]) == (best["tmpl"], best["index"],
                                                       best["rho2"])
+
+
+@pytest.mark.parametrize("tc,tj", [(4, 4), (4, 8), (8, 4), (8, 8)])
+@pytest.mark.parametrize("log2n", [16, 20, 21])
+def test_tile_shapes(ctx, tc, tj, log2n, monkeypatch):
+    """Every pass-1 / pass-2 tile shape gives the oracle's series and peaks."""
+    monkeypatch.setenv("CI_TILE_C", str(tc))
+    monkeypatch.setenv("CI_TILE_J", str(tj))
+    n, fs, fl = 1 << log2n, 4096.0, 20.0
+    bank = synth.draw_masses(3, 1.0, 20.0, "loguniform", 31 * tc + tj + log2n)
+    inj = synth.InjectionSpec(float(bank[1, 0]), float(bank[1, 1]), 9.0,
+                              n // 5 + 3, 1.1, 1)
+    x64, psd, x128 = C.make_case(n, fs, fl, bank, [inj], 2000 + log2n)
+    seg = _segment(ctx, x64, psd, n, fs, fl)
+    params = ctx.gen_templates(seg, bank)
+    z = ctx.matched_filter(seg, params)
+    peaks, trig, cnt = ctx.find_triggers(seg, params, 5.5, 4096, cap=256)
+    _sync()
+    zg = z.cpu().numpy()
+    P = ci.triggers_to_numpy(peaks)
+    T = ci.triggers_to_numpy(trig, int(cnt.cpu()[0]))
+    for i, (m1, m2) in enumerate(bank):
+        zo, _ = C.oracle_series(x128, psd, n, fs, fl, m1, m2)
+        assert C.series_error(zg[i], zo) <= C.TOL_FP32
+        C.check_peak(P[i], zo)
+        C.check_triggers(T[T["tmpl"] == i], zo, 4096, 5.5)
+    seg.close()
