@@ -90,29 +90,44 @@ __device__ __forceinline__ float2 tw16(float2 v) {
 }
 
 // 16-point inverse DFT in place, X_a = sum_q x_q w16^{aq}, as 4 x 4:
-// q = q1 + 4 q2, a = a1 + 4 a2.  HALF: x_q = 0 for q >= 8 (not read).
-template <bool HALF = false>
+// q = q1 + 4 q2, a = a1 + 4 a2.  Q: only x_q with q < Q can be nonzero (the
+// others are not read); Q = 16 is the full transform.
+template <int Q = 16>
 __device__ __forceinline__ void idft16(float2 (&x)[16]) {
-  float2 A[4][4];  // A[q1][a1]
+  static_assert(Q == 2 || Q == 4 || Q == 8 || Q == 16, "Q in {2, 4, 8, 16}");
+  constexpr int NQ1 = Q < 4 ? Q : 4;  // rows q1 that can be nonzero
+  float2 A[4][4];                      // A[q1][a1]
 #pragma unroll
-  for (int q1 = 0; q1 < 4; ++q1) {
-    float2 y0 = x[q1], y1 = x[q1 + 4], y2, y3;
-    if constexpr (HALF) {
-      idft4_half(y0, y1, y2, y3);
+  for (int q1 = 0; q1 < NQ1; ++q1) {
+    if constexpr (Q >= 8) {
+      float2 y0 = x[q1], y1 = x[q1 + 4], y2, y3;
+      if constexpr (Q == 8) {
+        idft4_half(y0, y1, y2, y3);
+      } else {
+        y2 = x[q1 + 8];
+        y3 = x[q1 + 12];
+        idft4(y0, y1, y2, y3);
+      }
+      A[q1][0] = y0; A[q1][1] = y1; A[q1][2] = y2; A[q1][3] = y3;
     } else {
-      y2 = x[q1 + 8];
-      y3 = x[q1 + 12];
-      idft4(y0, y1, y2, y3);
+      A[q1][0] = A[q1][1] = A[q1][2] = A[q1][3] = x[q1];  // only q2 = 0
     }
-    A[q1][0] = y0; A[q1][1] = y1; A[q1][2] = y2; A[q1][3] = y3;
   }
   A[1][1] = tw16<1>(A[1][1]); A[1][2] = tw16<2>(A[1][2]); A[1][3] = tw16<3>(A[1][3]);
-  A[2][1] = tw16<2>(A[2][1]); A[2][2] = tw16<4>(A[2][2]); A[2][3] = tw16<6>(A[2][3]);
-  A[3][1] = tw16<3>(A[3][1]); A[3][2] = tw16<6>(A[3][2]); A[3][3] = tw16<9>(A[3][3]);
+  if constexpr (NQ1 > 2) {
+    A[2][1] = tw16<2>(A[2][1]); A[2][2] = tw16<4>(A[2][2]); A[2][3] = tw16<6>(A[2][3]);
+    A[3][1] = tw16<3>(A[3][1]); A[3][2] = tw16<6>(A[3][2]); A[3][3] = tw16<9>(A[3][3]);
+  }
 #pragma unroll
   for (int a1 = 0; a1 < 4; ++a1) {
-    float2 y0 = A[0][a1], y1 = A[1][a1], y2 = A[2][a1], y3 = A[3][a1];
-    idft4(y0, y1, y2, y3);
+    float2 y0 = A[0][a1], y1 = A[1][a1], y2, y3;
+    if constexpr (NQ1 > 2) {
+      y2 = A[2][a1];
+      y3 = A[3][a1];
+      idft4(y0, y1, y2, y3);
+    } else {
+      idft4_half(y0, y1, y2, y3);
+    }
     x[a1] = y0; x[a1 + 4] = y1; x[a1 + 8] = y2; x[a1 + 12] = y3;
   }
 }
@@ -165,14 +180,14 @@ struct Col {
   static constexpr int LDS_ELEMS = (16 * S1 > L ? 16 * S1 : L) * NC;
   static_assert(R3 == 1 || R3 == 2 || R3 == 4 || R3 == 8, "L in 256..2048");
 
-  // Stage 1: radix 16 in registers (HALF: inputs m >= 8 are zero), table
-  // twiddle w_L^{a t}, store row a, position t.
+  // Stage 1: radix 16 in registers (inputs m >= Q are zero), table twiddle
+  // w_L^{a t}, store row a, position t.
   // tw: w_{L TS}^e at tw[e] (TS = 2048 / L for the global w_2048 table,
   // 1 for an LDS copy of w_L).
-  template <bool HALF, int TS = 2048 / L>
+  template <int Q, int TS = 2048 / L>
   __device__ static __forceinline__ void stage1(float2 (&x)[16], float2* lds, unsigned t,
                                                 unsigned c, const float2* tw) {
-    idft16<HALF>(x);
+    idft16<Q>(x);
     // twiddle index a t TS, walked as a byte offset
     const char* twb = reinterpret_cast<const char*>(tw);
     const unsigned step = t * (unsigned)TS * (unsigned)sizeof(float2);
@@ -257,7 +272,7 @@ template <int L, int NC, int TS = 2048 / L>
 __device__ __forceinline__ void fft_col(float2 (&x)[16], float2* lds, unsigned t, unsigned c,
                                         const float2* tw) {
   using K = Col<L, NC>;
-  K::template stage1<false, TS>(x, lds, t, c, tw);
+  K::template stage1<16, TS>(x, lds, t, c, tw);
   K::stage2(x, lds, t, c);
   K::template stage2_twiddle<TS>(x, t, tw);
   K::stage3(x, lds, t, c);

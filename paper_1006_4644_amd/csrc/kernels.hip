@@ -236,34 +236,21 @@ __device__ __forceinline__ float2 tw_n(const float2* __restrict__ twa,
   return cmul(twa[e & 2047], twb[e >> 11]);
 }
 
-template <int N1, int N2, int C>
-__global__ __launch_bounds__(C * N2 / 16) void k_pass1(P1Args a) {
+// Pass-1 body for one tile.  Q: number of stage-1 inputs per lane that can
+// be nonzero (m < Q), chosen per template from its upper band edge.
+template <int N1, int N2, int C, int Q>
+__device__ __forceinline__ void pass1_tile(const P1Args& a, const ci_tparams& P, int b, int tile,
+                                           float2* lds, unsigned t, unsigned c) {
   using K = Col<N2, C>;
   constexpr int N = N1 * N2;
   constexpr int Lp = K::Lp;
   constexpr int R3 = K::R3;
-  constexpr int TILES = N1 / C;
-  extern __shared__ float2 lds[];
-  const unsigned tid = threadIdx.x;
-  const unsigned c = tid % C, t = tid / C;
-
-  if (a.wkeys) {
-    const int64_t gid = blockIdx.x * (int64_t)blockDim.x + tid;
-    const int64_t gsz = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = gid; i < a.nzero_w; i += gsz) a.wkeys[i] = 0ull;
-    if (gid == 0) a.bdone[0] = 0u;
-  }
-
-  const int bid = xcd_remap(blockIdx.x, gridDim.x);
-  const int b = bid / TILES, tile = bid % TILES;
-  const ci_tparams P = a.prm[b];
   const unsigned k1 = tile * C + c;
 
-  // Z_k for k = k1 + N1 k2, k2 = t + Lp m.  Every band bin lies below n/2,
-  // i.e. k2 < N2/2: only m < 8 can be nonzero.
+  // Z_k for k = k1 + N1 k2, k2 = t + Lp m (zero outside the band).
   float2 x[16];
 #pragma unroll
-  for (int m = 0; m < 8; ++m) {
+  for (int m = 0; m < Q; ++m) {
     const int k = (int)(k1 + N1 * (t + Lp * m));
     float2 v = make_float2(0.f, 0.f);
     if (k >= P.k_low && k <= P.k_high) {
@@ -273,7 +260,7 @@ __global__ __launch_bounds__(C * N2 / 16) void k_pass1(P1Args a) {
     x[m] = v;
   }
 
-  K::template stage1<true>(x, lds, t, c, a.tw);
+  K::template stage1<Q>(x, lds, t, c, a.tw);
   K::stage2(x, lds, t, c);
   // Stage-2 twiddle merged with the four-step twiddle w_N^{k1 j2}: the
   // factor of output a2 is base * w^{a2} (a geometric sequence).
@@ -284,7 +271,7 @@ __global__ __launch_bounds__(C * N2 / 16) void k_pass1(P1Args a) {
     w = tw_n(a.twa, a.twb, (int)(16 * k1));
   } else {
     // rows d = a0 + 16 a2 of the radix-R3 step; output b adds 256 b to j2
-    const int a0 = t / R3, s2 = t % R3;
+    const unsigned a0 = t / R3, s2 = t % R3;
     base = tw_n(a.twa, a.twb, (int)(k1 * a0));
     w = cmul(a.tw[s2 * (2048 / (16 * R3))], tw_n(a.twa, a.twb, (int)(16 * k1)));
   }
@@ -312,6 +299,32 @@ __global__ __launch_bounds__(C * N2 / 16) void k_pass1(P1Args a) {
   for (int r = 0; r < 16; ++r) yt[o + K::off(r) * C] = x[r];
 }
 
+template <int N1, int N2, int C>
+__global__ __launch_bounds__(C * N2 / 16) void k_pass1(P1Args a) {
+  constexpr int Lp = N2 / 16;
+  constexpr int TILES = N1 / C;
+  extern __shared__ float2 lds[];
+  const unsigned tid = threadIdx.x;
+  const unsigned c = tid % C, t = tid / C;
+
+  if (a.wkeys) {
+    const int64_t gid = blockIdx.x * (int64_t)blockDim.x + tid;
+    const int64_t gsz = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = gid; i < a.nzero_w; i += gsz) a.wkeys[i] = 0ull;
+    if (gid == 0) a.bdone[0] = 0u;
+  }
+
+  const int bid = xcd_remap(blockIdx.x, gridDim.x);
+  const int b = bid / TILES, tile = bid % TILES;
+  const ci_tparams P = a.prm[b];
+  // Every band bin lies below n/2 (k2 < N2/2, so m < 8), and below k_high:
+  // m <= (k_high / N1) / Lp.  The choice is uniform over the workgroup.
+  const int mneed = P.k_high >= P.k_low ? (P.k_high / N1) / Lp + 1 : 1;
+  if (mneed <= 2) pass1_tile<N1, N2, C, 2>(a, P, b, tile, lds, t, c);
+  else if (mneed <= 4) pass1_tile<N1, N2, C, 4>(a, P, b, tile, lds, t, c);
+  else pass1_tile<N1, N2, C, 8>(a, P, b, tile, lds, t, c);
+}
+
 // ---------------------------------------------------------------------------
 // pass 2 helpers
 // ---------------------------------------------------------------------------
@@ -329,35 +342,35 @@ __device__ __forceinline__ void load_pass2(float2 (&x)[16], const float2* __rest
 }
 
 // z_j = sum_{k1} exp(2 pi i j1 k1 / N1) Y[k1][j2] for j = j2 + N2 j1, with
-// FP64 twiddles and accumulation, reduced over the workgroup.  Every lane
-// returns the result.  scratch: >= 2 * blockDim.x doubles.
+// FP64 twiddles and accumulation, computed by one wave (64 lanes, N1/64
+// terms each, then a butterfly reduction); every lane returns the result.
 template <int N1, int N2, int C>
-__device__ double2 direct_z(const float2* __restrict__ yb, const double2* __restrict__ tw64,
-                            int64_t j, double* scratch) {
-  const int tid = threadIdx.x, nt = blockDim.x;
+__device__ double2 wave_direct_z(const float2* __restrict__ yb, const double2* __restrict__ tw64,
+                                 int64_t j) {
+  const int lane = threadIdx.x & 63;
   const int j2 = (int)(j % N2), j1 = (int)(j / N2);
+  constexpr int PER = N1 / 64;
+  float2 v[PER];
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int k1 = lane + 64 * i;
+    v[i] = yb[((size_t)(k1 / C) * N2 + j2) * C + (k1 % C)];
+  }
   double re = 0.0, im = 0.0;
-  for (int k1 = tid; k1 < N1; k1 += nt) {
-    const float2 v = yb[((size_t)(k1 / C) * N2 + j2) * C + (k1 % C)];
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int k1 = lane + 64 * i;
     const int e = (int)(((int64_t)j1 * k1) % N1);
     const double2 w = tw64[e * (2048 / N1)];
-    re += (double)v.x * w.x - (double)v.y * w.y;
-    im += (double)v.x * w.y + (double)v.y * w.x;
+    re += (double)v[i].x * w.x - (double)v[i].y * w.y;
+    im += (double)v[i].x * w.y + (double)v[i].y * w.x;
   }
-  __syncthreads();
-  scratch[2 * tid] = re;
-  scratch[2 * tid + 1] = im;
-  __syncthreads();
-  for (int off = nt / 2; off > 0; off >>= 1) {
-    if (tid < off) {
-      scratch[2 * tid] += scratch[2 * (tid + off)];
-      scratch[2 * tid + 1] += scratch[2 * (tid + off) + 1];
-    }
-    __syncthreads();
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    re += __shfl_xor(re, off, 64);
+    im += __shfl_xor(im, off, 64);
   }
-  const double2 z = make_double2(scratch[0], scratch[1]);
-  __syncthreads();
-  return z;
+  return make_double2(re, im);
 }
 
 __device__ __forceinline__ u64 aload(const u64* p) {
@@ -416,12 +429,15 @@ struct P2Args {
   float2* z;                 // batch's first series
 };
 
-// Peak and triggers of template b once all its pass-2 tiles are done.
+// Peak and triggers of template b once all its pass-2 tiles are done: the
+// peak key is the max of the tiles' partials; the windows with a key are
+// compacted in window order; z at the peak and at every trigger is
+// recomputed from the intermediate, one sample per wave at a time.
 template <int N1, int N2, int C>
 __device__ void finalize_template(const P2Args& a, int b, void* ldsv) {
   constexpr int N = N1 * N2;
   const int tid = threadIdx.x, nt = blockDim.x;
-  double* dscr = reinterpret_cast<double*>(ldsv);
+  const int wave = tid >> 6, lane = tid & 63, nwaves = nt >> 6;
   int* iscr = reinterpret_cast<int*>(ldsv);
   const ci_tparams P = a.prm[b];
   const int64_t tg = a.t0 + b;
@@ -453,16 +469,6 @@ __device__ void finalize_template(const P2Args& a, int b, void* ldsv) {
     }
     return;
   }
-  {
-    const int64_t j = (int64_t)(0xFFFFFFFFu - (unsigned int)(pk & 0xFFFFFFFFull));
-    const double2 z = direct_z<N1, N2, C>(yb, a.tw64, j, dscr);
-    if (tid == 0) {
-      ci_trigger e;
-      e.tmpl = tg; e.index = j; e.rho2 = __uint_as_float((unsigned int)(pk >> 32));
-      e.re = (float)z.x; e.im = (float)z.y; e.window = (int)(j / a.window);
-      a.d_peaks[tg] = e;
-    }
-  }
   // compact the windows whose key is set, in window order
   const u64* wk = a.wkeys + (size_t)b * a.nwin;
   const int per = (a.nwin + nt - 1) / nt;
@@ -470,35 +476,42 @@ __device__ void finalize_template(const P2Args& a, int b, void* ldsv) {
   const int w1 = min(w0 + per, a.nwin);
   int mine = 0;
   for (int w = w0; w < w1; ++w) mine += (aload(&wk[w]) != 0ull);
-  if (__syncthreads_or(mine) == 0) {
-    if (tid == 0) a.cnt[b] = 0;
-    return;
-  }
   int total = 0;
-  int pos = block_excl_scan(mine, iscr, &total);
-  ci_trigger* st = a.stage + (size_t)b * a.nwin;
-  int* sx = a.sidx + (size_t)b * a.nwin;
-  for (int w = w0; w < w1; ++w) {
-    const u64 key = aload(&wk[w]);
-    if (key != 0ull) {
-      ci_trigger e;
-      e.tmpl = tg;
-      e.index = (int64_t)(0xFFFFFFFFu - (unsigned int)(key & 0xFFFFFFFFull));
-      e.rho2 = __uint_as_float((unsigned int)(key >> 32));
-      e.re = 0.f; e.im = 0.f; e.window = w;
-      st[pos] = e;
-      sx[w] = pos;
-      ++pos;
+  if (__syncthreads_or(mine) != 0) {
+    int pos = block_excl_scan(mine, iscr, &total);
+    ci_trigger* st = a.stage + (size_t)b * a.nwin;
+    int* sx = a.sidx + (size_t)b * a.nwin;
+    for (int w = w0; w < w1; ++w) {
+      const u64 key = aload(&wk[w]);
+      if (key != 0ull) {
+        ci_trigger e;
+        e.tmpl = tg;
+        e.index = (int64_t)(0xFFFFFFFFu - (unsigned int)(key & 0xFFFFFFFFull));
+        e.rho2 = __uint_as_float((unsigned int)(key >> 32));
+        e.re = 0.f; e.im = 0.f; e.window = w;
+        st[pos] = e;
+        sx[w] = pos;
+        ++pos;
+      }
     }
+    __syncthreads();
   }
-  __threadfence_block();
-  __syncthreads();
-  for (int i = 0; i < total; ++i) {
-    const int64_t j = st[i].index;
-    const double2 z = direct_z<N1, N2, C>(yb, a.tw64, j, dscr);
-    if (tid == 0) {
-      st[i].re = (float)z.x;
-      st[i].im = (float)z.y;
+  // item 0: the peak; items 1..total: the triggers, one wave per item
+  ci_trigger* st = a.stage + (size_t)b * a.nwin;
+  for (int it = wave; it <= total; it += nwaves) {
+    const int64_t j = it == 0 ? (int64_t)(0xFFFFFFFFu - (unsigned int)(pk & 0xFFFFFFFFull))
+                              : st[it - 1].index;
+    const double2 z = wave_direct_z<N1, N2, C>(yb, a.tw64, j);
+    if (lane == 0) {
+      if (it == 0) {
+        ci_trigger e;
+        e.tmpl = tg; e.index = j; e.rho2 = __uint_as_float((unsigned int)(pk >> 32));
+        e.re = (float)z.x; e.im = (float)z.y; e.window = (int)(j / a.window);
+        a.d_peaks[tg] = e;
+      } else {
+        st[it - 1].re = (float)z.x;
+        st[it - 1].im = (float)z.y;
+      }
     }
   }
   if (tid == 0) a.cnt[b] = total;
@@ -571,6 +584,80 @@ __device__ void place_batch(const P2Args& a, void* ldsv) {
 // pass 2: second four-step pass + post-pass
 // ---------------------------------------------------------------------------
 
+template <int N1, int N2, int C, int J>
+__device__ __forceinline__ void load_item(float2 (&x)[16], const P2Args& a, int item, unsigned cc,
+                                          unsigned t) {
+  constexpr int N = N1 * N2;
+  constexpr int TILES = N2 / J;
+  const int b = item / TILES, tile = item % TILES;
+  load_pass2<N1, N2, C, J>(x, a.y + (size_t)b * N, tile * J + cc, t);
+}
+
+// Second four-step pass and post-pass of one tile (J columns j2).
+template <int N1, int N2, int C, int J>
+__device__ __forceinline__ void pass2_tile(float2 (&x)[16], const P2Args& a, int item,
+                                           float2* lds, const float2* twl, u64* s_best,
+                                           unsigned tid, unsigned cc, unsigned t) {
+  constexpr int TILES = N2 / J;
+  using K = Col<N1, J>;
+  const int b = item / TILES, tile = item % TILES;
+  const unsigned j2 = tile * J + cc;
+  fft_col<N1, J, 1>(x, lds, t, cc, twl);
+
+  // Post-pass: rho^2 = |z|^2 (already in SNR units).  Registers are
+  // visited in increasing j, so a strict ">" keeps the smallest index
+  // among equal values.
+  float bv = -1.f;
+  int br = 0;
+  bool hot = false;
+#pragma unroll
+  for (int kk = 0; kk < 16; ++kk) {
+    const int r = K::reg_by_order(kk);
+    float r2 = fmaf(x[r].x, x[r].x, x[r].y * x[r].y);
+    if (!a.full) {
+      const int j = (int)j2 + N2 * K::out((int)t, r);
+      if (j < a.jlo32 || j >= a.jhi32) r2 = -1.f;
+    }
+    if (r2 > bv) {
+      bv = r2;
+      br = r;
+    }
+    hot |= r2 > a.thr2;
+  }
+  if (__any(hot)) {
+    // rare: samples above threshold update their window's key
+    u64* wk = a.wkeys + (size_t)b * a.nwin;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const float r2 = fmaf(x[r].x, x[r].x, x[r].y * x[r].y);
+      const int j = (int)j2 + N2 * K::out((int)t, r);
+      if (r2 > a.thr2 && (a.full || (j >= a.jlo32 && j < a.jhi32))) {
+        const u64 key = ((u64)__float_as_uint(r2) << 32) | (u64)(0xFFFFFFFFu - (unsigned int)j);
+        atomicMax(&wk[(unsigned int)j / a.win32], key);
+      }
+    }
+  }
+  u64 best = 0ull;
+  if (bv >= 0.f) {
+    const unsigned int j = (unsigned int)((int)j2 + N2 * K::out((int)t, br));
+    best = ((u64)__float_as_uint(bv) << 32) | (u64)(0xFFFFFFFFu - j);
+  }
+  // workgroup max of the peak key, stored as this tile's partial
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const u64 o = __shfl_xor(best, off, 64);
+    best = o > best ? o : best;
+  }
+  if ((tid & 63) == 0) s_best[tid >> 6] = best;
+  __syncthreads();
+  if (tid == 0) {
+    u64 m = 0ull;
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) m = s_best[i] > m ? s_best[i] : m;
+    a.ppart[(size_t)b * TILES + tile] = m;
+  }
+  __syncthreads();
+}
+
 // Persistent pass 2: each workgroup walks tiles item = blockIdx.x + k G
 // and prefetches the next tile's column inputs into registers while it
 // transforms the current one, so that a CU keeps loads in flight during
@@ -594,76 +681,15 @@ __global__ __launch_bounds__(J * N1 / 16, 4) void k_pass2_trig(P2Args a) {
   __syncthreads();
 
   float2 xn[16];
+  const int G = gridDim.x;
   int item = blockIdx.x;
-  if (item < total) {
-    const int b = item / TILES, tile = item % TILES;
-    load_pass2<N1, N2, C, J>(xn, a.y + (size_t)b * N, tile * J + cc, t);
-  }
-  for (; item < total; item += gridDim.x) {
+  if (item < total) load_item<N1, N2, C, J>(xn, a, item, cc, t);
+  for (; item < total; item += G) {
     float2 x[16];
 #pragma unroll
     for (int r = 0; r < 16; ++r) x[r] = xn[r];
-    const int next = item + gridDim.x;
-    if (next < total) {
-      const int bn = next / TILES, tn = next % TILES;
-      load_pass2<N1, N2, C, J>(xn, a.y + (size_t)bn * N, tn * J + cc, t);
-    }
-    const int b = item / TILES, tile = item % TILES;
-    const unsigned j2 = tile * J + cc;
-    fft_col<N1, J, 1>(x, lds, t, cc, twl);
-
-    // Post-pass: rho^2 = |z|^2 (already in SNR units).  Registers are
-    // visited in increasing j, so a strict ">" keeps the smallest index
-    // among equal values.
-    float bv = -1.f;
-    int br = 0;
-    bool hot = false;
-#pragma unroll
-    for (int kk = 0; kk < 16; ++kk) {
-      const int r = K::reg_by_order(kk);
-      float r2 = fmaf(x[r].x, x[r].x, x[r].y * x[r].y);
-      if (!a.full) {
-        const int j = (int)j2 + N2 * K::out((int)t, r);
-        if (j < a.jlo32 || j >= a.jhi32) r2 = -1.f;
-      }
-      if (r2 > bv) {
-        bv = r2;
-        br = r;
-      }
-      hot |= r2 > a.thr2;
-    }
-    if (__any(hot)) {
-      // rare: samples above threshold update their window's key
-      u64* wk = a.wkeys + (size_t)b * a.nwin;
-#pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const float r2 = fmaf(x[r].x, x[r].x, x[r].y * x[r].y);
-        const int j = (int)j2 + N2 * K::out((int)t, r);
-        if (r2 > a.thr2 && (a.full || (j >= a.jlo32 && j < a.jhi32))) {
-          const u64 key = ((u64)__float_as_uint(r2) << 32) | (u64)(0xFFFFFFFFu - (unsigned int)j);
-          atomicMax(&wk[(unsigned int)j / a.win32], key);
-        }
-      }
-    }
-    u64 best = 0ull;
-    if (bv >= 0.f) {
-      const unsigned int j = (unsigned int)((int)j2 + N2 * K::out((int)t, br));
-      best = ((u64)__float_as_uint(bv) << 32) | (u64)(0xFFFFFFFFu - j);
-    }
-    // workgroup max of the peak key, stored as this tile's partial
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-      const u64 o = __shfl_xor(best, off, 64);
-      best = o > best ? o : best;
-    }
-    if ((tid & 63) == 0) s_best[tid >> 6] = best;
-    __syncthreads();
-    if (tid == 0) {
-      u64 m = 0ull;
-      for (int i = 0; i < (int)(blockDim.x >> 6); ++i) m = s_best[i] > m ? s_best[i] : m;
-      a.ppart[(size_t)b * TILES + tile] = m;
-    }
-    __syncthreads();
+    if (item + G < total) load_item<N1, N2, C, J>(xn, a, item + G, cc, t);
+    pass2_tile<N1, N2, C, J>(x, a, item, lds, twl, s_best, tid, cc, t);
   }
 }
 
