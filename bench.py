@@ -60,6 +60,8 @@ def parse():
                    help="time budget of the CPU oracle baseline")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-copy-probe", action="store_true")
+    p.add_argument("--no-split", action="store_true",
+                   help="skip the split-precision (matrix-core) comparison runs")
     return p.parse_args()
 
 
@@ -164,33 +166,38 @@ def main():
     count = torch.zeros(1, dtype=torch.int64, device=dev)
     log(f"[bench] workload {wl.name}: n={wl.n}, {n_t} templates, {len(injs)} injections")
 
-    def step():
+    def step(precision):
         ctx.segment_update(seg, xt, psd_d)
         ctx.gen_templates(seg, bank, out=params)
         ctx.find_triggers(seg, params, wl.snr_threshold, wl.window, cap=cap, merge=True,
-                          peaks=peaks, trig=trig, count=count)
+                          peaks=peaks, trig=trig, count=count, precision=precision)
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    log(f"[bench] warmup done ({args.warmup} steps)")
-    ctx.set_timing(True)
-    ctx.kernel_times()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    e0.record()
-    for _ in range(args.steps):
-        step()
-    e1.record()
-    torch.cuda.synchronize()
-    total_ms = e0.elapsed_time(e1)
-    kt = ctx.kernel_times()
-    ctx.set_timing(False)
+    def timed(precision, tag):
+        for _ in range(args.warmup):
+            step(precision)
+        torch.cuda.synchronize()
+        log(f"[bench] {tag}: warmup done ({args.warmup} steps)")
+        ctx.set_timing(True)
+        ctx.kernel_times()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(args.steps):
+            step(precision)
+        e1.record()
+        torch.cuda.synchronize()
+        total_ms = e0.elapsed_time(e1)
+        kt = ctx.kernel_times()
+        ctx.set_timing(False)
+        found = int(count.cpu()[0])
+        pk = ci.triggers_to_numpy(peaks).copy()
+        log(f"[bench] {tag}: {args.steps} steps, {total_ms / args.steps:.3f} ms/step, "
+            f"{n_t * args.steps / (total_ms / 1e3):.0f} templates/s, {found} merged windows")
+        return total_ms, kt, found, pk
+
+    total_ms, kt, nwin_found, pk32 = timed(ci.FP32, "fp32")
     ms_step = total_ms / args.steps
     value = n_t * args.steps / (total_ms / 1e3)
-    nwin_found = int(count.cpu()[0])
-    log(f"[bench] timed {args.steps} steps: {ms_step:.3f} ms/step, {value:.0f} templates/s, "
-        f"{nwin_found} merged windows")
 
     # roofline of the dominant kernel
     name = max(kt, key=lambda k: kt[k][2])
@@ -227,6 +234,26 @@ def main():
         "kernels_ms_per_step": {k: round(v[2] / args.steps, 4) for k, v in kt.items()},
         "merged_windows": nwin_found,
     }
+    if not args.no_split:
+        # the matrix-core paths on the same workload; accuracy against the
+        # FP64 oracle is checked by the test-suite, here the peak SNR of each
+        # injection's template is compared with the FP32 path's
+        paths = {}
+        for prec, tag in ((ci.SPLIT_BF16, "split_bf16"), (ci.SPLIT_FP16, "split_fp16")):
+            tms, kts, found, pks = timed(prec, tag)
+            v = n_t * args.steps / (tms / 1e3)
+            dev = max(abs(math.sqrt(pks["rho2"][i.tmpl]) - math.sqrt(pk32["rho2"][i.tmpl]))
+                      / math.sqrt(pk32["rho2"][i.tmpl]) for i in injs if i.tmpl >= 0) \
+                if any(i.tmpl >= 0 for i in injs) else None
+            paths[tag] = {"value": round(v, 1), "ms_per_step": round(tms / args.steps, 4),
+                          "speedup_vs_fp32": round(v / value, 3),
+                          "path_hbm_frac": round(16.0 * wl.n * n_t / (tms / args.steps / 1e3)
+                                                 / 1e9 / HBM_PEAK_GBS, 4),
+                          "kernels_ms_per_step": {k: round(x[2] / args.steps, 4)
+                                                  for k, x in kts.items()},
+                          "injection_peak_rho_rel_dev_vs_fp32": dev,
+                          "merged_windows": found}
+        out["precision_paths"] = paths
     if not args.no_copy_probe:
         out["copy_probe_gbs"] = round(copy_probe_gbs(), 1)
     if not args.no_cpu_baseline:

@@ -55,9 +55,11 @@ extern "C" {
 #define CI_EUNSUPPORTED (-5)  /* valid request this build does not handle  */
 
 /* arithmetic of the inverse transform */
-#define CI_FP32 0        /* FP32 VALU butterflies, FP32 intermediate       */
-#define CI_SPLIT_BF16 1  /* reserved: split-BF16 DFT-matrix stages (MFMA)  */
-#define CI_SPLIT_FP16 2  /* reserved: split-FP16 DFT-matrix stages (MFMA)  */
+#define CI_FP32 0        /* FP32 VALU butterflies, FP32 intermediate        */
+#define CI_SPLIT_BF16 1  /* radix-16 stages as DFT-matrix products on MFMA,
+                            hi/lo BF16 operands, 3 products, FP32 accumulate */
+#define CI_SPLIT_FP16 2  /* the same with hi/lo FP16 operands (inputs scaled
+                            by 2^6; |z| up to ~1e3 in SNR units)            */
 
 /* bank kinds for ci_make_bank */
 #define CI_BANK_GRID 0
@@ -184,8 +186,8 @@ int ci_gen_templates(ci_ctx* ctx, const ci_segment* seg,
  *   z_j = sum_{k=k_low}^{k_high} 4 df x~_k conj(h~_k) / S_k exp(2 pi i jk/n),
  * i.e. both quadrature correlators at every lag (eq. (matchedfilter)) in
  * SNR units: |z_j|^2 / sigma^2 is the quadrature sum c_+^2 + c_x^2.
- * d_z: complex64[n][n_seg] (device).  precision: CI_FP32
- * (CI_EUNSUPPORTED otherwise).  An empty template yields zeros. */
+ * d_z: complex64[n][n_seg] (device).  precision: CI_FP32, CI_SPLIT_BF16 or
+ * CI_SPLIT_FP16 (the matrix-core stages).  An empty template yields zeros. */
 int ci_matched_filter(ci_ctx* ctx, const ci_segment* seg,
                       const ci_tparams* d_params, int64_t n, int32_t precision,
                       void* d_z, void* stream);
@@ -209,7 +211,8 @@ int ci_matched_filter(ci_ctx* ctx, const ci_segment* seg,
  * exceeds `cap`, only the first `cap` in the stated order are written.
  * rho2 of a trigger is the value that decided it; re/im are recomputed at
  * that index from the same transform's intermediate with FP64 accumulation.
- * window: W >= 1.  j_hi <= 0 means n_seg.  precision: CI_FP32. */
+ * window: W >= 1.  j_hi <= 0 means n_seg.  precision as for
+ * ci_matched_filter. */
 int ci_find_triggers(ci_ctx* ctx, const ci_segment* seg,
                      const ci_tparams* d_params, int64_t n, int32_t precision,
                      float snr_threshold, int64_t window, int64_t j_lo,

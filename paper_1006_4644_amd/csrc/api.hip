@@ -185,11 +185,8 @@ int check_filter_args(Ctx* ctx, const ci_segment* seg, const ci_tparams* d_param
   if (!seg) return fail(ctx, CI_EINVAL, "null segment");
   if (n < 0) return fail(ctx, CI_EINVAL, "negative template count %lld", (long long)n);
   if (n > 0 && !d_params) return fail(ctx, CI_EINVAL, "null d_params");
-  if (precision != CI_FP32) {
-    if (precision == CI_SPLIT_BF16 || precision == CI_SPLIT_FP16)
-      return fail(ctx, CI_EUNSUPPORTED, "split-precision transform is not built");
+  if (precision != CI_FP32 && precision != CI_SPLIT_BF16 && precision != CI_SPLIT_FP16)
     return fail(ctx, CI_EINVAL, "unknown precision %d", precision);
-  }
   return CI_OK;
 }
 
@@ -550,6 +547,7 @@ int ci_matched_filter(ci_ctx* ctx, const ci_segment* seg, const ci_tparams* d_pa
   memset(&a, 0, sizeof a);
   a.seg = seg;
   a.bmax = (int)B;
+  a.precision = precision;
   for (int64_t b = 0, t0 = 0; t0 < n; ++b, t0 += B) {
     a.t0 = t0;
     a.nb = (int)((n - t0) < B ? (n - t0) : B);
@@ -616,6 +614,7 @@ int ci_find_triggers(ci_ctx* ctx, const ci_segment* seg, const ci_tparams* d_par
   a.cap = cap;
   a.d_count = d_count;
   a.merge = merge_across_templates ? 1 : 0;
+  a.precision = precision;
   {
     // resident pass-2 workgroups per CU: 2 leaves room for the other
     // stream's pass 1 (environment override for tuning runs)

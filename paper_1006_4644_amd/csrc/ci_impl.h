@@ -129,6 +129,7 @@ struct BatchArgs {
   // series mode
   float2* d_z;                // first template's series
   int p2_per_cu;              // pass-2 workgroups per CU (0: as many as fit)
+  int precision;              // CI_FP32 | CI_SPLIT_BF16 | CI_SPLIT_FP16
 };
 
 hipError_t launch_pass1(const BatchArgs& a, bool zero_trig, hipStream_t st);

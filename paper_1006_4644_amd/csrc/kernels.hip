@@ -15,6 +15,7 @@
 
 #include "ci_impl.h"
 #include "fft_device.h"
+#include "mfma_device.h"
 
 namespace ci {
 
@@ -222,6 +223,7 @@ struct P1Args {
   const float2* tw;        // exp(2 pi i e / 2048)
   const float2* twa;       // exp(2 pi i e / n), e < 2048
   const float2* twb;       // exp(2 pi i 2048 e / n)
+  const double2* tw64;     // exp(2 pi i e / 2048) in FP64
   float2* y;               // intermediate, [nb][n] in tile layout
   // per-batch trigger state to clear (null when not searching)
   u64* wkeys;
@@ -593,6 +595,10 @@ __device__ __forceinline__ void load_item(float2 (&x)[16], const P2Args& a, int 
   load_pass2<N1, N2, C, J>(x, a.y + (size_t)b * N, tile * J + cc, t);
 }
 
+template <int N1, int N2, int C, int J>
+__device__ __forceinline__ void pass2_post(const float2 (&x)[16], const P2Args& a, int b, int tile,
+                                           u64* s_best, unsigned tid, unsigned cc, unsigned t);
+
 // Second four-step pass and post-pass of one tile (J columns j2).
 template <int N1, int N2, int C, int J>
 __device__ __forceinline__ void pass2_tile(float2 (&x)[16], const P2Args& a, int item,
@@ -601,9 +607,18 @@ __device__ __forceinline__ void pass2_tile(float2 (&x)[16], const P2Args& a, int
   constexpr int TILES = N2 / J;
   using K = Col<N1, J>;
   const int b = item / TILES, tile = item % TILES;
-  const unsigned j2 = tile * J + cc;
   fft_col<N1, J, 1>(x, lds, t, cc, twl);
+  pass2_post<N1, N2, C, J>(x, a, b, tile, s_best, tid, cc, t);
+}
 
+// Post-pass of one pass-2 tile: x holds z for j1 = Col::out(t, r) of column
+// j2 = tile J + cc.
+template <int N1, int N2, int C, int J>
+__device__ __forceinline__ void pass2_post(const float2 (&x)[16], const P2Args& a, int b, int tile,
+                                           u64* s_best, unsigned tid, unsigned cc, unsigned t) {
+  constexpr int TILES = N2 / J;
+  using K = Col<N1, J>;
+  const unsigned j2 = tile * J + cc;
   // Post-pass: rho^2 = |z|^2 (already in SNR units).  Registers are
   // visited in increasing j, so a strict ">" keeps the smallest index
   // among equal values.
@@ -690,6 +705,300 @@ __global__ __launch_bounds__(J * N1 / 16, 4) void k_pass2_trig(P2Args a) {
     for (int r = 0; r < 16; ++r) x[r] = xn[r];
     if (item + G < total) load_item<N1, N2, C, J>(xn, a, item + G, cc, t);
     pass2_tile<N1, N2, C, J>(x, a, item, lds, twl, s_best, tid, cc, t);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// split-precision path: radix-16 stages as DFT-matrix products on MFMA
+// ---------------------------------------------------------------------------
+
+// Planar LDS rows for the matrix stages: plane p (0 re, 1 im), instance i,
+// element q at pl[(p * I + i) * kRow + q]; rows are padded to 20 floats so
+// the 32-byte operand reads of 16 consecutive instances hit distinct banks.
+constexpr int kRow = 20;
+
+// Exchange-2 slot of stage-2 output (row d, position s) in the interleaved
+// layout Col::stage3 reads (R3 == 1: row d alone).
+template <int R3>
+__device__ __forceinline__ unsigned x2_slot(unsigned d, unsigned s) {
+  if constexpr (R3 == 1) return d;
+  else if constexpr (R3 == 2) return d * 2 + ((s + (d >> 1)) & 1u);
+  else return d * R3 + ((s + d) & (R3 - 1));
+}
+
+// Load the 8 operand values of instance `inst` for this lane from planar rows.
+__device__ __forceinline__ void pl_load8(const float* pl, int I, unsigned inst, unsigned g,
+                                         float (&v)[8]) {
+  const float4* p = reinterpret_cast<const float4*>(pl + ((g >> 1) * I + inst) * kRow + 8 * (g & 1));
+  const float4 a = p[0], b = p[1];
+  v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+  v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+}
+
+// Stage-2 outputs (rows d = a0 + 16 a2 at position s2) of one column,
+// written in the exchange-2 layout; for R3 == 1 these are final.
+template <int L, int NC>
+__device__ __forceinline__ void mx_store_stage2(float2* xl, const float2 (&y)[16], unsigned lane,
+                                                unsigned wave) {
+  constexpr int R3 = L / 256;
+  const unsigned g = lane / 16;
+#pragma unroll
+  for (int bk = 0; bk < 4; ++bk) {
+    const unsigned inst = 16 * (4 * wave + bk) + (lane & 15);
+    const unsigned c = inst % NC, r = inst / NC;
+    const unsigned s2 = r % R3, a0 = r / R3;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const unsigned d = a0 + 16 * (4 * g + e);
+      xl[x2_slot<R3>(d, s2) * NC + c] = y[4 * bk + e];
+    }
+  }
+}
+
+// Final register layout after the matrix stages: lane (c, t) holds the
+// outputs Col::out(t, r) of its column.
+template <int L, int NC>
+__device__ __forceinline__ void mx_gather_out(float2 (&x)[16], const float2* xl, unsigned t,
+                                              unsigned c) {
+  constexpr int R3 = L / 256;
+  if constexpr (R3 == 1) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) x[r] = xl[(t + 16 * r) * NC + c];
+  } else {
+    constexpr int Lp = L / 16;
+#pragma unroll
+    for (int s = 0; s < R3; ++s) {
+      const unsigned rr = R3 == 2 ? ((s + (t >> 1)) & 1u) : ((s + t) & (R3 - 1));
+      const float2* pr = xl + (t * R3 + rr) * NC + c;
+#pragma unroll
+      for (int i = 0; i < 16 / R3; ++i) x[i * R3 + s] = pr[i * Lp * R3 * NC];
+    }
+    idft_groups<R3>(x);
+  }
+}
+
+// Stage-1 outputs x[a] of lane (c, t) written as stage-2 operand rows:
+// instance (a, t % R3, c), element q = t / R3.
+template <int L, int NC>
+__device__ __forceinline__ void mx_store_stage1(float* pl, const float2 (&x)[16], unsigned t,
+                                                unsigned c) {
+  constexpr int R3 = L / 256;
+  constexpr int I = NC * (L / 16);
+  const unsigned q = t / R3, s2 = t % R3;
+#pragma unroll
+  for (int a = 0; a < 16; ++a) {
+    const unsigned inst = (a * R3 + s2) * NC + c;
+    pl[inst * kRow + q] = x[a].x;
+    pl[(I + inst) * kRow + q] = x[a].y;
+  }
+}
+
+template <int N1, int N2, int C, int PREC>
+__device__ __forceinline__ void pass1_tile_mx(const P1Args& a, const ci_tparams& P, int b,
+                                              int tile, float2* lds, unsigned t, unsigned c,
+                                              const DftA<PREC>& A, int qsel) {
+  using K = Col<N2, C>;
+  constexpr int N = N1 * N2;
+  constexpr int Lp = K::Lp;
+  constexpr int R3 = K::R3;
+  constexpr int I = C * Lp;
+  const unsigned tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane / 16;
+  float* pl = reinterpret_cast<float*>(lds);
+  const unsigned k1 = tile * C + c;
+
+  float2 x[16];
+#pragma unroll
+  for (int m = 0; m < 8; ++m) {
+    float2 v = make_float2(0.f, 0.f);
+    if (m < qsel) {
+      const int k = (int)(k1 + N1 * (t + Lp * m));
+      if (k >= P.k_low && k <= P.k_high) {
+        const float2 e = chirp_phasor(P, k);
+        v = cmul(a.w[k], make_float2(e.x * P.scale, e.y * P.scale));
+      }
+    }
+    x[m] = v;
+  }
+  // stage 1 on the vector units (half the inputs are zero), twiddle w_L^{a t}
+  idft16<8>(x);
+  {
+    const char* twb = reinterpret_cast<const char*>(a.tw);
+    const unsigned step = t * (2048u / N2) * (unsigned)sizeof(float2);
+    unsigned off = 0;
+#pragma unroll
+    for (int aa = 1; aa < 16; ++aa) {
+      off += step;
+      x[aa] = cmul(x[aa], *reinterpret_cast<const float2*>(twb + off));
+    }
+  }
+  mx_store_stage1<N2, C>(pl, x, t, c);
+  __syncthreads();
+
+  // stage 2 on the matrix cores, four blocks of 16 instances per wave, with
+  // the stage twiddle and the four-step twiddle w_N^{k1 j2} merged:
+  // output a2 of instance (a0, s2, c) gets base w^{a2}.
+  float2 y[16];
+#pragma unroll
+  for (int bk = 0; bk < 4; ++bk) {
+    const unsigned inst = 16 * (4 * wave + bk) + (lane & 15);
+    float v[8];
+    pl_load8(pl, I, inst, g, v);
+    f32x4 yr, yi;
+    mx_dft16<PREC>(A, v, yr, yi);
+    const unsigned cb = inst % C, r = inst / C;
+    const unsigned s2 = r % R3, a0 = r / R3;
+    const unsigned kb = tile * C + cb;
+    const float2 base = tw_n(a.twa, a.twb, (int)(kb * a0));
+    float2 w = tw_n(a.twa, a.twb, (int)(16 * kb));
+    if constexpr (R3 > 1) w = cmul(a.tw[s2 * (2048 / (16 * R3))], w);
+    const float2 w2 = cmul(w, w), w4 = cmul(w2, w2), w8 = cmul(w4, w4);
+    float2 p = base;
+    if (g & 1) p = cmul(p, w4);
+    if (g & 2) p = cmul(p, w8);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      y[4 * bk + e] = cmul(make_float2(yr[e], yi[e]), p);
+      p = cmul(p, w);
+    }
+  }
+  __syncthreads();
+  float2* xl = lds;
+  mx_store_stage2<N2, C>(xl, y, lane, wave);
+  __syncthreads();
+  mx_gather_out<N2, C>(x, xl, t, c);
+  if constexpr (R3 > 1) {
+    const float2 v = tw_n(a.twa, a.twb, (int)(256 * k1));
+    float2 vb = v;
+#pragma unroll
+    for (int bb = 1; bb < R3; ++bb) {
+#pragma unroll
+      for (int i = 0; i < 16 / R3; ++i) x[i * R3 + bb] = cmul(x[i * R3 + bb], vb);
+      vb = cmul(vb, v);
+    }
+  }
+  float2* yt = a.y + (size_t)b * N + (size_t)tile * N2 * C;
+  const unsigned o = t * C + c;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) yt[o + K::off(r) * C] = x[r];
+}
+
+template <int N1, int N2, int C, int PREC>
+__global__ __launch_bounds__(C * N2 / 16) void k_pass1_mx(P1Args a) {
+  constexpr int Lp = N2 / 16;
+  constexpr int TILES = N1 / C;
+  extern __shared__ float2 lds[];
+  const unsigned tid = threadIdx.x;
+  const unsigned c = tid % C, t = tid / C;
+  if (a.wkeys) {
+    const int64_t gid = blockIdx.x * (int64_t)blockDim.x + tid;
+    const int64_t gsz = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = gid; i < a.nzero_w; i += gsz) a.wkeys[i] = 0ull;
+    if (gid == 0) a.bdone[0] = 0u;
+  }
+  const DftA<PREC> A = make_dft_a<PREC>(a.tw64, tid & 63);
+  const int bid = xcd_remap(blockIdx.x, gridDim.x);
+  const int b = bid / TILES, tile = bid % TILES;
+  const ci_tparams P = a.prm[b];
+  const int mneed = P.k_high >= P.k_low ? (P.k_high / N1) / Lp + 1 : 1;
+  pass1_tile_mx<N1, N2, C, PREC>(a, P, b, tile, lds, t, c, A, mneed);
+}
+
+// Pass 2 with both radix-16 stages on the matrix cores (one tile per
+// workgroup).
+template <int N1, int N2, int C, int J, int PREC, int MODE>
+__global__ __launch_bounds__(J * N1 / 16) void k_pass2_mx(P2Args a) {
+  constexpr int N = N1 * N2;
+  constexpr int TILES = N2 / J;
+  constexpr int L = N1;
+  constexpr int Lp = L / 16;
+  constexpr int R3 = L / 256;
+  constexpr int I = J * Lp;
+  extern __shared__ float2 lds[];
+  __shared__ u64 s_best[16];
+  const unsigned tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane / 16;
+  const unsigned cc = tid % J, t = tid / J;
+  float* pl = reinterpret_cast<float*>(lds);
+  const int bid = xcd_remap(blockIdx.x, gridDim.x);
+  const int b = bid / TILES, tile = bid % TILES;
+  const unsigned j2 = tile * J + cc;
+  const float2* yb = a.y + (size_t)b * N;
+  const DftA<PREC> A = make_dft_a<PREC>(a.tw64, lane);
+
+  float2 x[16];
+  load_pass2<N1, N2, C, J>(x, yb, j2, t);
+  {
+    // stage-1 operand rows: instance (t, cc), elements q = 0..15
+    const unsigned inst = t * J + cc;
+    float4* pr = reinterpret_cast<float4*>(pl + inst * kRow);
+    float4* pi = reinterpret_cast<float4*>(pl + (I + inst) * kRow);
+#pragma unroll
+    for (int q4 = 0; q4 < 4; ++q4) {
+      pr[q4] = make_float4(x[4 * q4].x, x[4 * q4 + 1].x, x[4 * q4 + 2].x, x[4 * q4 + 3].x);
+      pi[q4] = make_float4(x[4 * q4].y, x[4 * q4 + 1].y, x[4 * q4 + 2].y, x[4 * q4 + 3].y);
+    }
+  }
+  __syncthreads();
+  // stage 1: outputs a = 4g + e of instance (t1, c1), twiddle w_L^{a t1}
+  float2 y[16];
+#pragma unroll
+  for (int bk = 0; bk < 4; ++bk) {
+    const unsigned inst = 16 * (4 * wave + bk) + (lane & 15);
+    float v[8];
+    pl_load8(pl, I, inst, g, v);
+    f32x4 yr, yi;
+    mx_dft16<PREC>(A, v, yr, yi);
+    const unsigned t1 = inst / J;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const unsigned aa = 4 * g + e;
+      y[4 * bk + e] = cmul(make_float2(yr[e], yi[e]), a.tw[(aa * t1) * (2048 / L)]);
+    }
+  }
+  __syncthreads();
+  // stage-2 operand rows: instance (a, t1 % R3, c1), element q = t1 / R3
+#pragma unroll
+  for (int bk = 0; bk < 4; ++bk) {
+    const unsigned inst = 16 * (4 * wave + bk) + (lane & 15);
+    const unsigned t1 = inst / J, c1 = inst % J;
+    const unsigned q = t1 / R3, s2 = t1 % R3;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const unsigned aa = 4 * g + e;
+      const unsigned i2 = (aa * R3 + s2) * J + c1;
+      pl[i2 * kRow + q] = y[4 * bk + e].x;
+      pl[(I + i2) * kRow + q] = y[4 * bk + e].y;
+    }
+  }
+  __syncthreads();
+  // stage 2: outputs a2 = 4g + e of instance (a0, s2, c), twiddle
+  // w_{16 R3}^{a2 s2}
+#pragma unroll
+  for (int bk = 0; bk < 4; ++bk) {
+    const unsigned inst = 16 * (4 * wave + bk) + (lane & 15);
+    float v[8];
+    pl_load8(pl, I, inst, g, v);
+    f32x4 yr, yi;
+    mx_dft16<PREC>(A, v, yr, yi);
+    const unsigned s2 = (inst / J) % R3;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const unsigned a2 = 4 * g + e;
+      float2 z = make_float2(yr[e], yi[e]);
+      if constexpr (R3 > 1) z = cmul(z, a.tw[(16 * a2 * s2) * (2048 / L)]);
+      y[4 * bk + e] = z;
+    }
+  }
+  __syncthreads();
+  float2* xl = lds;
+  mx_store_stage2<L, J>(xl, y, lane, wave);
+  __syncthreads();
+  mx_gather_out<L, J>(x, xl, t, cc);
+  if constexpr (MODE == 0) {
+    pass2_post<N1, N2, C, J>(x, a, b, tile, s_best, tid, cc, t);
+  } else {
+    float2* zt = a.z + (size_t)b * N;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) zt[j2 + N2 * Col<N1, J>::out((int)t, r)] = x[r];
   }
 }
 
@@ -833,6 +1142,7 @@ P1Args make_p1(const BatchArgs& a, bool zero_trig) {
   p.tw = a.seg->tw2048;
   p.twa = a.seg->twa;
   p.twb = a.seg->twb;
+  p.tw64 = a.seg->tw64;
   p.y = a.y;
   p.nb = a.nb;
   if (zero_trig) {
@@ -919,6 +1229,26 @@ struct Inst {
     hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(J * N1 / 16), lds, st, make_p2(a));
     return hipGetLastError();
   }
+  template <int PREC>
+  static hipError_t p1mx(const BatchArgs& a, bool zero, hipStream_t st) {
+    const size_t lds = (size_t)10 * C * N2;
+    auto kern = k_pass1_mx<N1, N2, C, PREC>;
+    hipError_t e = set_lds(kern, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(kern, dim3((unsigned)(a.nb * (N1 / C))), dim3(C * N2 / 16), lds, st,
+                       make_p1(a, zero));
+    return hipGetLastError();
+  }
+  template <int PREC, int MODE>
+  static hipError_t p2mx(const BatchArgs& a, hipStream_t st) {
+    const size_t lds = (size_t)10 * J * N1;
+    auto kern = k_pass2_mx<N1, N2, C, J, PREC, MODE>;
+    hipError_t e = set_lds(kern, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(kern, dim3((unsigned)(a.nb * (N2 / J))), dim3(J * N1 / 16), lds, st,
+                       make_p2(a));
+    return hipGetLastError();
+  }
   static hipError_t fin(const BatchArgs& a, hipStream_t st) {
     hipLaunchKernelGGL((k_fin<N1, N2, C>), dim3((unsigned)a.nb), dim3(256), kFinLds, st,
                        make_p2(a));
@@ -962,16 +1292,31 @@ hipError_t dispatch(const Plan& p, F f) {
 }  // namespace
 
 hipError_t launch_pass1(const BatchArgs& a, bool zero_trig, hipStream_t st) {
-  return dispatch(a.seg->plan, [&](auto inst) { return decltype(inst)::p1(a, zero_trig, st); });
+  return dispatch(a.seg->plan, [&](auto inst) {
+    typedef decltype(inst) I;
+    if (a.precision == CI_SPLIT_BF16) return I::template p1mx<kBF16>(a, zero_trig, st);
+    if (a.precision == CI_SPLIT_FP16) return I::template p1mx<kFP16>(a, zero_trig, st);
+    return I::p1(a, zero_trig, st);
+  });
 }
 hipError_t launch_pass2_trig(const BatchArgs& a, hipStream_t st) {
-  return dispatch(a.seg->plan, [&](auto inst) { return decltype(inst)::p2t(a, st); });
+  return dispatch(a.seg->plan, [&](auto inst) {
+    typedef decltype(inst) I;
+    if (a.precision == CI_SPLIT_BF16) return I::template p2mx<kBF16, 0>(a, st);
+    if (a.precision == CI_SPLIT_FP16) return I::template p2mx<kFP16, 0>(a, st);
+    return I::p2t(a, st);
+  });
 }
 hipError_t launch_fin(const BatchArgs& a, hipStream_t st) {
   return dispatch(a.seg->plan, [&](auto inst) { return decltype(inst)::fin(a, st); });
 }
 hipError_t launch_pass2_series(const BatchArgs& a, hipStream_t st) {
-  return dispatch(a.seg->plan, [&](auto inst) { return decltype(inst)::p2s(a, st); });
+  return dispatch(a.seg->plan, [&](auto inst) {
+    typedef decltype(inst) I;
+    if (a.precision == CI_SPLIT_BF16) return I::template p2mx<kBF16, 1>(a, st);
+    if (a.precision == CI_SPLIT_FP16) return I::template p2mx<kFP16, 1>(a, st);
+    return I::p2s(a, st);
+  });
 }
 
 }  // namespace ci

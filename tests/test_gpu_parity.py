@@ -210,8 +210,8 @@ def test_argument_errors(ctx, tiny):
         ctx.find_triggers(tiny["seg"], tiny["params"], 6.0, 4096, j_lo=10, j_hi=5)
     assert ei.value.code == ci.EINVAL
     with pytest.raises(ci.CiError) as ei:
-        ctx.matched_filter(tiny["seg"], tiny["params"], precision=ci.SPLIT_BF16)
-    assert ei.value.code == ci.EUNSUPPORTED
+        ctx.matched_filter(tiny["seg"], tiny["params"], precision=7)
+    assert ei.value.code == ci.EINVAL
     import torch
     bad = torch.zeros(2**15 + 1, dtype=torch.complex64, device="cuda")
     badp = torch.ones(2**15 + 1, dtype=torch.float64, device="cuda")
@@ -280,3 +280,62 @@ def test_tile_shapes(ctx, tc, tj, log2n, monkeypatch):
         C.check_peak(P[i], zo)
         C.check_triggers(T[T["tmpl"] == i], zo, 4096, 5.5)
     seg.close()
+
+
+# --------------------------------------------------------------------------
+# split-precision path: radix-16 stages on the matrix cores (bar: 1e-3)
+# --------------------------------------------------------------------------
+
+TOL_SPLIT = 1e-3
+
+
+@pytest.mark.parametrize("prec", [ci.SPLIT_BF16, ci.SPLIT_FP16])
+@pytest.mark.parametrize("log2n", [16, 17, 18, 19, 20, 21])
+def test_split_precision_series(ctx, prec, log2n):
+    n, fs, fl = 1 << log2n, 4096.0, 20.0
+    bank = synth.draw_masses(2, 1.0, 12.0, "loguniform", 700 + log2n)
+    inj = synth.InjectionSpec(float(bank[0, 0]), float(bank[0, 1]), 14.0,
+                              n // 3 + 5, 2.2, 0)
+    x64, psd, x128 = C.make_case(n, fs, fl, bank, [inj], 3000 + log2n)
+    seg = _segment(ctx, x64, psd, n, fs, fl)
+    params = ctx.gen_templates(seg, bank)
+    z = ctx.matched_filter(seg, params, precision=prec)
+    peaks, trig, cnt = ctx.find_triggers(seg, params, 6.0, 4096, cap=256,
+                                         precision=prec)
+    _sync()
+    zg = z.cpu().numpy()
+    P = ci.triggers_to_numpy(peaks)
+    T = ci.triggers_to_numpy(trig, int(cnt.cpu()[0]))
+    for i, (m1, m2) in enumerate(bank):
+        zo, _ = C.oracle_series(x128, psd, n, fs, fl, m1, m2)
+        e = C.series_error(zg[i], zo)
+        print(f"precision {prec} n 2^{log2n} template {i}: series error {e:.2e}")
+        assert e <= TOL_SPLIT, e
+        C.check_peak(P[i], zo, tol=TOL_SPLIT)
+        C.check_triggers(T[T["tmpl"] == i], zo, 4096, 6.0, tol=TOL_SPLIT)
+    assert abs(int(P[0]["index"]) - inj.j0) <= 2
+    seg.close()
+
+
+@pytest.mark.parametrize("prec", [ci.SPLIT_BF16, ci.SPLIT_FP16])
+def test_split_precision_full_size_sampled(ctx, prec):
+    """The 2^20 x 1024-template workload on the matrix-core path; errors
+    per injection against the FP64 oracle stay below 1e-3."""
+    wl, bank, injs, x64, psd, x128 = C.workload_case("fp32-2^20")
+    seg = _segment(ctx, x64, psd, wl.n, wl.fs, wl.f_low)
+    params = ctx.gen_templates(seg, bank)
+    peaks, trig, cnt = ctx.find_triggers(seg, params, wl.snr_threshold,
+                                         wl.window, cap=1 << 20, precision=prec)
+    _sync()
+    P = ci.triggers_to_numpy(peaks)
+    T = ci.triggers_to_numpy(trig, int(cnt.cpu()[0]))
+    for inj in injs:
+        i = inj.tmpl
+        zo, _ = C.oracle_series(x128, psd, wl.n, wl.fs, wl.f_low, *bank[i])
+        C.check_peak(P[i], zo, tol=TOL_SPLIT)
+        C.check_triggers(T[T["tmpl"] == i], zo, wl.window, wl.snr_threshold,
+                         tol=TOL_SPLIT)
+        rho_o = np.abs(zo[int(P[i]["index"])])
+        err = abs(np.sqrt(P[i]["rho2"]) - rho_o) / rho_o
+        print(f"precision {prec} injection snr {inj.snr}: peak rho error {err:.2e}")
+        assert err <= TOL_SPLIT
