@@ -32,9 +32,12 @@ if ROOT not in sys.path:
 
 METRIC = "templates/sec (N=2^20 SNR series) FP32 vs split-BF16 MFMA; % HBM roofline"
 HBM_PEAK_GBS = 8000.0
+# name -> (library precision code, dtype tag of the arithmetic)
+PRECISIONS = {"fp32": (0, "f32"), "split-bf16": (1, "bf16x3"), "split-fp16": (2, "f16x3")}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_fp32-2^20.json")
 KERNEL_SOURCES = ["paper_1006_4644_amd/csrc/kernels.hip",
-                  "paper_1006_4644_amd/csrc/fft_device.h"]
+                  "paper_1006_4644_amd/csrc/fft_device.h",
+                  "paper_1006_4644_amd/csrc/mfma_device.h"]
 
 
 def log(msg):
@@ -60,8 +63,10 @@ def parse():
                    help="time budget of the CPU oracle baseline")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-copy-probe", action="store_true")
+    p.add_argument("--precision", default="fp32", choices=sorted(PRECISIONS),
+                   help="arithmetic of the headline run")
     p.add_argument("--no-split", action="store_true",
-                   help="skip the split-precision (matrix-core) comparison runs")
+                   help="skip the comparison runs at the other precisions")
     return p.parse_args()
 
 
@@ -117,7 +122,7 @@ def cpu_baseline(xt_host, psd, wl, bank, budget_s):
     thr2 = wl.snr_threshold ** 2
     t0 = time.perf_counter()
     done = 0
-    for i in order[:256]:
+    for i in order:
         zs, s2 = O.snr_series(x, psd, wl.n, wl.fs, wl.f_low, *bank[i])
         r2 = zs.real ** 2 + zs.imag ** 2
         O.peak(r2)
@@ -159,11 +164,11 @@ def main():
     ctx.segment_update(seg, xt, psd_d)
     n_t = len(bank)
     cap = 1 << 20
-    dev = torch.device("cuda", 0)
-    params = torch.empty((n_t, 96), dtype=torch.uint8, device=dev)
-    peaks = torch.empty((n_t, 4), dtype=torch.int64, device=dev)
-    trig = torch.empty((cap, 4), dtype=torch.int64, device=dev)
-    count = torch.zeros(1, dtype=torch.int64, device=dev)
+    device = torch.device("cuda", 0)
+    params = torch.empty((n_t, 96), dtype=torch.uint8, device=device)
+    peaks = torch.empty((n_t, 4), dtype=torch.int64, device=device)
+    trig = torch.empty((cap, 4), dtype=torch.int64, device=device)
+    count = torch.zeros(1, dtype=torch.int64, device=device)
     log(f"[bench] workload {wl.name}: n={wl.n}, {n_t} templates, {len(injs)} injections")
 
     def step(precision):
@@ -195,7 +200,8 @@ def main():
             f"{n_t * args.steps / (total_ms / 1e3):.0f} templates/s, {found} merged windows")
         return total_ms, kt, found, pk
 
-    total_ms, kt, nwin_found, pk32 = timed(ci.FP32, "fp32")
+    prec_code, dtype = PRECISIONS[args.precision]
+    total_ms, kt, nwin_found, pk32 = timed(prec_code, args.precision)
     ms_step = total_ms / args.steps
     value = n_t * args.steps / (total_ms / 1e3)
 
@@ -209,8 +215,9 @@ def main():
     if os.path.exists(TRAFFIC_FILE):
         with open(TRAFFIC_FILE) as fh:
             tr = json.load(fh)
-        if tr.get("source_hash") == kernel_source_hash() and name in tr.get("kernels", {}):
-            k = tr["kernels"][name]
+        tp = tr.get("paths", {}).get(args.precision, {})
+        if tp.get("source_hash") == kernel_source_hash() and name in tp.get("kernels", {}):
+            k = tp["kernels"][name]
             traffic = k["bytes_per_template"] * (tmpls / launches)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
@@ -222,11 +229,11 @@ def main():
         "metric": METRIC, "value": round(value, 1), "unit": "templates/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(ms_step, 4), "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "vs_baseline": None, "dtype": dtype, "data": "synthetic",
         "config": {"workload": wl.name, "n": wl.n, "fs": wl.fs, "f_low": wl.f_low,
                    "templates": n_t, "masses": f"{wl.dist} [{wl.m_min}, {wl.m_max}]",
                    "injections": len(injs), "snr_threshold": wl.snr_threshold,
-                   "window": wl.window, "merge": True, "precision": "fp32"},
+                   "window": wl.window, "merge": True, "precision": args.precision},
         "roofline": roofline,
         "path_hbm": {"algorithmic_bytes_per_template": 16 * wl.n,
                      "achieved_gbs": round(path_gbs, 1),
@@ -235,23 +242,25 @@ def main():
         "merged_windows": nwin_found,
     }
     if not args.no_split:
-        # the matrix-core paths on the same workload; accuracy against the
-        # FP64 oracle is checked by the test-suite, here the peak SNR of each
-        # injection's template is compared with the FP32 path's
+        # the other arithmetic paths on the same workload; accuracy against
+        # the FP64 oracle is checked by the test-suite, here the peak SNR of
+        # each injection's template is compared with the headline run's
         paths = {}
-        for prec, tag in ((ci.SPLIT_BF16, "split_bf16"), (ci.SPLIT_FP16, "split_fp16")):
+        for tag, (prec, _) in PRECISIONS.items():
+            if tag == args.precision:
+                continue
             tms, kts, found, pks = timed(prec, tag)
             v = n_t * args.steps / (tms / 1e3)
             dev = max(abs(math.sqrt(pks["rho2"][i.tmpl]) - math.sqrt(pk32["rho2"][i.tmpl]))
                       / math.sqrt(pk32["rho2"][i.tmpl]) for i in injs if i.tmpl >= 0) \
                 if any(i.tmpl >= 0 for i in injs) else None
             paths[tag] = {"value": round(v, 1), "ms_per_step": round(tms / args.steps, 4),
-                          "speedup_vs_fp32": round(v / value, 3),
+                          "speedup_vs_headline": round(v / value, 3),
                           "path_hbm_frac": round(16.0 * wl.n * n_t / (tms / args.steps / 1e3)
                                                  / 1e9 / HBM_PEAK_GBS, 4),
                           "kernels_ms_per_step": {k: round(x[2] / args.steps, 4)
                                                   for k, x in kts.items()},
-                          "injection_peak_rho_rel_dev_vs_fp32": dev,
+                          "injection_peak_rho_rel_dev_vs_headline": dev,
                           "merged_windows": found}
         out["precision_paths"] = paths
     if not args.no_copy_probe:
