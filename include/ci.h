@@ -220,11 +220,87 @@ int ci_find_triggers(ci_ctx* ctx, const ci_segment* seg,
                      int64_t cap, int64_t* d_count,
                      int32_t merge_across_templates, void* stream);
 
+/* --- batch schedule: length classes -----------------------------------------
+ * A bank of uneven chirp lengths is searched in length classes: each
+ * template goes to the shortest segment whose duration n_c / fs covers its
+ * 2PN time to coalescence from f_low (the paper's per-chunk loop over a
+ * bank, with the chunk length matched to the template).
+ * ci_length_classes (host only): class_n[0..nclass-1], increasing powers of
+ * two; class_out[i] receives the index c of the smallest class_n[c] with
+ * tau_2PN(f_low; m1, m2) <= class_n[c] / fs, or nclass - 1 when none is
+ * long enough.  CI_EINVAL for non-positive masses or a bad class list. */
+int ci_length_classes(const ci_template* bank_host, int64_t n, double fs,
+                      double f_low, const int64_t* class_n, int32_t nclass,
+                      int32_t* class_out);
+
+/* One class of a multi-class search: the same arguments as one
+ * ci_find_triggers call (all pointers device, owned by the caller). */
+typedef struct {
+  const ci_segment* seg;        /* data chunk of the class's length */
+  const ci_tparams* d_params;   /* [n] generated on seg */
+  int64_t n;
+  int64_t j_lo, j_hi;           /* search range; j_hi <= 0 means n_seg */
+  ci_trigger* d_peaks;          /* [n] */
+  ci_trigger* d_trig;           /* [cap] */
+  int64_t cap;
+  int64_t* d_count;             /* [1] */
+} ci_class_job;
+
+/* Run every job of the schedule, with results identical to one
+ * ci_find_triggers call per job (same precision, threshold, window and
+ * merge flag; merging is within a job).  Batches of all jobs alternate
+ * between the context's two internal streams, so consecutive batches
+ * overlap across class boundaries; `stream` waits for all of them.
+ * Jobs share the context's workspace: calls on one context must be
+ * ordered on the device (one stream, or synchronised).
+ * flags: 0.  CI_RUN_GRAPH (capture of the schedule into a HIP graph and
+ * replay) is reserved and currently returns CI_EUNSUPPORTED. */
+#define CI_RUN_GRAPH 1
+int ci_search_classes(ci_ctx* ctx, const ci_class_job* jobs, int32_t njobs,
+                      int32_t precision, float snr_threshold, int64_t window,
+                      int32_t merge_across_templates, int32_t flags,
+                      void* stream);
+
 /* --- tuning -----------------------------------------------------------------
- * Templates per batch of the two-pass transform (0 = the built-in choice for
- * the segment length).  The intermediate workspace is 2 x batch x n_seg x 8
- * bytes. */
+ * Templates per batch of the two-pass transform for every length (0 = the
+ * per-length configuration below).  The intermediate workspace is
+ * 2 x batch x n_seg x 8 bytes. */
 int ci_set_batch(ci_ctx* ctx, int64_t templates_per_batch);
+
+/* Launch configuration of the search at transform length 2^log2n and one
+ * precision, held per context.  The transform's arithmetic does not depend
+ * on it: every configuration gives bit-identical results. */
+typedef struct {
+  int32_t log2n;        /* 16..21 */
+  int32_t precision;    /* CI_FP32 | CI_SPLIT_BF16 | CI_SPLIT_FP16 */
+  int32_t tile_c;       /* first-pass columns per workgroup: 4 or 8 */
+  int32_t tile_j;       /* second-pass columns per workgroup: 4 or 8 */
+  int32_t p2_per_cu;    /* resident second-pass workgroups per CU, 0..8
+                           (0: as many as fit) */
+  int32_t tuned;        /* out: 1 when chosen by ci_autotune */
+  int64_t batch;        /* templates per batch, 0..4096 (0: 2^26 / n_seg,
+                           limited by the trigger workspace) */
+  double ms;            /* out (ci_autotune): time of the chosen one, ms */
+  int32_t candidates;   /* out (ci_autotune): configurations timed */
+  int32_t rejected;     /* out (ci_autotune): configurations excluded
+                           because their output differed */
+} ci_tune;
+
+int ci_get_tune(ci_ctx* ctx, int32_t log2n, int32_t precision, ci_tune* out);
+/* Sets tile_c, tile_j, p2_per_cu and batch for (log2n, precision). */
+int ci_set_tune(ci_ctx* ctx, const ci_tune* cfg);
+
+/* Autotuner: times ci_find_triggers (no merge) on the given templates under
+ * a coordinate search over tiles, second-pass residency and batch size,
+ * starting from the default configuration; a candidate whose peaks,
+ * trigger count or trigger list differ in any bit from the default's is
+ * excluded.  Stores the fastest as the context's configuration for the
+ * segment's length and precision and reports it in *out (may be NULL).
+ * Blocking: synchronises `stream`; allocates and frees its own output
+ * buffers (n + min(n * windows, 2^20) triggers). */
+int ci_autotune(ci_ctx* ctx, const ci_segment* seg, const ci_tparams* d_params,
+                int64_t n, int32_t precision, float snr_threshold,
+                int64_t window, ci_tune* out, void* stream);
 
 /* --- instrumentation ---------------------------------------------------------
  * With timing enabled, every transform-pass launch is bracketed by HIP

@@ -16,6 +16,7 @@ __all__ = [
     "load", "LibraryMissing", "CiError", "Library", "Context", "Segment",
     "TRIGGER_DTYPE", "TPARAMS_DTYPE", "FP32", "SPLIT_BF16", "SPLIT_FP16",
     "BANK_GRID", "BANK_UNIFORM", "BANK_LOGUNIFORM", "EXPORTED_SYMBOLS",
+    "RUN_GRAPH",
 ]
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -31,7 +32,10 @@ EXPORTED_SYMBOLS = (
     "ci_set_batch", "ci_make_bank", "ci_segment_create", "ci_segment_destroy",
     "ci_gen_templates", "ci_matched_filter", "ci_find_triggers",
     "ci_segment_update", "ci_set_timing", "ci_kernel_times",
+    "ci_length_classes", "ci_search_classes", "ci_get_tune", "ci_set_tune",
+    "ci_autotune",
 )
+RUN_GRAPH = 1
 
 # ci_trigger: {int64 tmpl, int64 index, float rho2, re, im, int32 window}
 TRIGGER_DTYPE = np.dtype([("tmpl", "<i8"), ("index", "<i8"), ("rho2", "<f4"),
@@ -76,6 +80,25 @@ class _SegSpec(ctypes.Structure):
                 ("f_low", ctypes.c_double)]
 
 
+class _ClassJob(ctypes.Structure):
+    _fields_ = [("seg", ctypes.c_void_p), ("d_params", ctypes.c_void_p),
+                ("n", ctypes.c_int64), ("j_lo", ctypes.c_int64),
+                ("j_hi", ctypes.c_int64), ("d_peaks", ctypes.c_void_p),
+                ("d_trig", ctypes.c_void_p), ("cap", ctypes.c_int64),
+                ("d_count", ctypes.c_void_p)]
+
+
+class _Tune(ctypes.Structure):
+    _fields_ = [("log2n", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("tile_c", ctypes.c_int32), ("tile_j", ctypes.c_int32),
+                ("p2_per_cu", ctypes.c_int32), ("tuned", ctypes.c_int32),
+                ("batch", ctypes.c_int64), ("ms", ctypes.c_double),
+                ("candidates", ctypes.c_int32), ("rejected", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 _vp, _i32, _i64, _f32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_float
 
 _SIGS = {
@@ -97,6 +120,14 @@ _SIGS = {
     "ci_find_triggers": (ctypes.c_int, [_vp, _vp, _vp, _i64, _i32, _f32, _i64,
                                         _i64, _i64, _vp, _vp, _i64, _vp, _i32,
                                         _vp]),
+    "ci_length_classes": (ctypes.c_int, [_vp, _i64, ctypes.c_double,
+                                         ctypes.c_double, _vp, _i32, _vp]),
+    "ci_search_classes": (ctypes.c_int, [_vp, ctypes.POINTER(_ClassJob), _i32,
+                                         _i32, _f32, _i64, _i32, _i32, _vp]),
+    "ci_get_tune": (ctypes.c_int, [_vp, _i32, _i32, ctypes.POINTER(_Tune)]),
+    "ci_set_tune": (ctypes.c_int, [_vp, ctypes.POINTER(_Tune)]),
+    "ci_autotune": (ctypes.c_int, [_vp, _vp, _vp, _i64, _i32, _f32, _i64,
+                                   ctypes.POINTER(_Tune), _vp]),
 }
 
 _LIB = None
@@ -152,6 +183,18 @@ class Library:
         spec = _BankSpec(kind, 0, m_min, m_max, seed)
         rc = self.dll.ci_make_bank(ctypes.byref(spec), n,
                                    out.ctypes.data if n else None)
+        self.check(rc)
+        return out
+
+    def length_classes(self, bank, fs: float, f_low: float, classes) -> np.ndarray:
+        """Class index per template: the shortest of `classes` (increasing
+        powers of two) whose duration covers the 2PN chirp from f_low."""
+        bank = np.ascontiguousarray(np.asarray(bank, dtype=np.float64).reshape(-1, 2))
+        cl = np.ascontiguousarray(np.asarray(classes, dtype=np.int64))
+        out = np.empty(bank.shape[0], dtype=np.int32)
+        rc = self.dll.ci_length_classes(
+            bank.ctypes.data if len(bank) else None, len(bank), fs, f_low,
+            cl.ctypes.data, len(cl), out.ctypes.data if len(bank) else None)
         self.check(rc)
         return out
 
@@ -289,6 +332,61 @@ class Context:
             window, j_lo, j_hi, _ptr(peaks), _ptr(trig), cap, _ptr(count),
             1 if merge else 0, _stream(stream)))
         return peaks, trig, count
+
+
+    def get_tune(self, log2n: int, precision: int = FP32) -> dict:
+        t = _Tune()
+        self._chk(self.lib.dll.ci_get_tune(self.handle, log2n, precision,
+                                           ctypes.byref(t)))
+        return t.as_dict()
+
+    def set_tune(self, log2n: int, precision: int = FP32, tile_c: int = 8,
+                 tile_j: int = 4, p2_per_cu: int = 2, batch: int = 0):
+        t = _Tune(log2n, precision, tile_c, tile_j, p2_per_cu, 0, batch)
+        self._chk(self.lib.dll.ci_set_tune(self.handle, ctypes.byref(t)))
+
+    def autotune(self, seg: Segment, params, thr: float, window: int,
+                 n: int | None = None, precision: int = FP32, stream=None) -> dict:
+        """Choose and store the fastest launch configuration for the
+        segment's length (blocking); returns it."""
+        n = params.shape[0] if n is None else n
+        t = _Tune()
+        self._chk(self.lib.dll.ci_autotune(
+            self.handle, seg.handle, _ptr(params), n, precision, float(thr),
+            window, ctypes.byref(t), _stream(stream)))
+        return t.as_dict()
+
+    def search_classes(self, jobs, thr: float, window: int, merge: bool = False,
+                       precision: int = FP32, graph: bool = False, stream=None):
+        """Multi-class search.  jobs: list of dicts with keys seg, params
+        and optionally n, j_lo, j_hi, cap, peaks, trig, count (device
+        tensors are allocated when absent).  Returns [(peaks, trig, count)]
+        per job."""
+        import torch
+        arr = (_ClassJob * max(len(jobs), 1))()
+        outs = []
+        for i, jb in enumerate(jobs):
+            params = jb["params"]
+            n = jb.get("n", params.shape[0])
+            cap = jb.get("cap", 1 << 16)
+            dev = params.device
+            peaks = jb.get("peaks")
+            if peaks is None:
+                peaks = torch.empty((max(n, 1), 4), dtype=torch.int64, device=dev)
+            trig = jb.get("trig")
+            if trig is None:
+                trig = torch.empty((max(cap, 1), 4), dtype=torch.int64, device=dev)
+            count = jb.get("count")
+            if count is None:
+                count = torch.zeros(1, dtype=torch.int64, device=dev)
+            arr[i] = _ClassJob(jb["seg"].handle, _ptr(params), n, jb.get("j_lo", 0),
+                               jb.get("j_hi", 0), _ptr(peaks), _ptr(trig), cap,
+                               _ptr(count))
+            outs.append((peaks, trig, count))
+        self._chk(self.lib.dll.ci_search_classes(
+            self.handle, arr, len(jobs), precision, float(thr), window,
+            1 if merge else 0, RUN_GRAPH if graph else 0, _stream(stream)))
+        return outs
 
 
 def triggers_to_numpy(t, count: int | None = None) -> np.ndarray:

@@ -13,6 +13,7 @@
 
 #include <new>
 #include <string>
+#include <vector>
 
 #include "ci_impl.h"
 
@@ -147,39 +148,46 @@ int ensure_ybuf(Ctx* ctx, size_t bytes) {
 
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
-int ensure_trig(Ctx* ctx, int64_t bmax, int64_t nwin, int64_t ntile2, TrigWork* tw) {
-  const size_t s_pk = align256(sizeof(unsigned long long) * 2 * bmax * ntile2);
-  const size_t s_wk = align256(sizeof(unsigned long long) * 2 * bmax * nwin);
-  const size_t s_bd = align256(sizeof(unsigned int) * 2);
-  const size_t s_cn = align256(sizeof(int) * 2 * bmax);
-  const size_t s_si = align256(sizeof(int) * 2 * bmax * nwin);
-  const size_t s_st = align256(sizeof(ci_trigger) * 2 * bmax * nwin);
-  const size_t s_mr = align256(sizeof(ci_trigger) * nwin);
-  const size_t s_rn = align256(sizeof(unsigned long long));
-  const size_t total = s_pk + s_wk + s_bd + s_cn + s_si + s_st + s_mr + s_rn;
-  if (ctx->tbytes < total) {
-    if (ctx->tbuf) (void)hipFree(ctx->tbuf);
-    ctx->tbuf = nullptr;
-    ctx->tbytes = 0;
-    hipError_t e = hipMalloc(&ctx->tbuf, total);
-    if (e != hipSuccess)
-      return fail(ctx, CI_ENOMEM, "trigger workspace of %zu bytes: %s", total,
-                  hipGetErrorString(e));
-    ctx->tbytes = total;
-  }
-  char* p = static_cast<char*>(ctx->tbuf);
-  tw->ppart = reinterpret_cast<unsigned long long*>(p); p += s_pk;
-  tw->wkeys = reinterpret_cast<unsigned long long*>(p); p += s_wk;
-  tw->bdone = reinterpret_cast<unsigned int*>(p); p += s_bd;
-  tw->cnt = reinterpret_cast<int*>(p); p += s_cn;
-  tw->sidx = reinterpret_cast<int*>(p); p += s_si;
-  tw->stage = reinterpret_cast<ci_trigger*>(p); p += s_st;
-  tw->mrec = reinterpret_cast<ci_trigger*>(p); p += s_mr;
+// Bytes of one search's trigger bookkeeping (two slot sets of bmax templates).
+size_t trig_bytes(int64_t bmax, int64_t nwin, int64_t ntile2) {
+  return align256(sizeof(unsigned long long) * 2 * bmax * ntile2) +
+         align256(sizeof(unsigned long long) * 2 * bmax * nwin) +
+         align256(sizeof(unsigned int) * 2) + align256(sizeof(int) * 2 * bmax) +
+         align256(sizeof(int) * 2 * bmax * nwin) + align256(sizeof(ci_trigger) * 2 * bmax * nwin) +
+         align256(sizeof(ci_trigger) * nwin) + align256(sizeof(unsigned long long));
+}
+
+void carve_trig(char* p, int64_t bmax, int64_t nwin, int64_t ntile2, TrigWork* tw) {
+  tw->ppart = reinterpret_cast<unsigned long long*>(p);
+  p += align256(sizeof(unsigned long long) * 2 * bmax * ntile2);
+  tw->wkeys = reinterpret_cast<unsigned long long*>(p);
+  p += align256(sizeof(unsigned long long) * 2 * bmax * nwin);
+  tw->bdone = reinterpret_cast<unsigned int*>(p);
+  p += align256(sizeof(unsigned int) * 2);
+  tw->cnt = reinterpret_cast<int*>(p);
+  p += align256(sizeof(int) * 2 * bmax);
+  tw->sidx = reinterpret_cast<int*>(p);
+  p += align256(sizeof(int) * 2 * bmax * nwin);
+  tw->stage = reinterpret_cast<ci_trigger*>(p);
+  p += align256(sizeof(ci_trigger) * 2 * bmax * nwin);
+  tw->mrec = reinterpret_cast<ci_trigger*>(p);
+  p += align256(sizeof(ci_trigger) * nwin);
   tw->run = reinterpret_cast<unsigned long long*>(p);
+}
+
+int ensure_tbuf(Ctx* ctx, size_t total) {
+  if (ctx->tbytes >= total) return CI_OK;
+  if (ctx->tbuf) (void)hipFree(ctx->tbuf);
+  ctx->tbuf = nullptr;
+  ctx->tbytes = 0;
+  hipError_t e = hipMalloc(&ctx->tbuf, total);
+  if (e != hipSuccess)
+    return fail(ctx, CI_ENOMEM, "trigger workspace of %zu bytes: %s", total, hipGetErrorString(e));
+  ctx->tbytes = total;
   return CI_OK;
 }
 
-int check_filter_args(Ctx* ctx, const ci_segment* seg, const ci_tparams* d_params, int64_t n,
+int check_filter_args(Ctx* ctx, const void* seg, const ci_tparams* d_params, int64_t n,
                       int32_t precision) {
   if (!ctx) return fail(nullptr, CI_EINVAL, "null context");
   if (!seg) return fail(ctx, CI_EINVAL, "null segment");
@@ -229,6 +237,150 @@ int ensure_streams(Ctx* ctx) {
       hipError_t e = hipEventCreateWithFlags(&ctx->sev[i], hipEventDisableTiming);
       if (e != hipSuccess) return hipfail(ctx, e, "internal event");
     }
+  return CI_OK;
+}
+
+// One validated search: a segment, its templates and its outputs, with the
+// launch configuration and workspace chosen for it.
+struct Job {
+  const Seg* seg;
+  const ci_tparams* params;
+  int64_t n;
+  int64_t j_lo, j_hi;
+  ci_trigger* peaks;
+  ci_trigger* trig;
+  int64_t cap;
+  int64_t* count;
+  Plan plan;
+  Tune cfg;
+  int64_t B, nwin;
+  size_t toff;
+  TrigWork tw;
+};
+
+int check_job(Ctx* ctx, Job& jb, int32_t precision, float thr, int64_t window) {
+  int rc = check_filter_args(ctx, jb.seg, jb.params, jb.n, precision);
+  if (rc != CI_OK) return rc;
+  const int64_t N = jb.seg->host.n;
+  if (window < 1 || window > N)
+    return fail(ctx, CI_EINVAL, "window %lld outside 1..n", (long long)window);
+  if (jb.j_hi <= 0) jb.j_hi = N;
+  if (jb.j_lo < 0 || jb.j_hi > N || jb.j_lo >= jb.j_hi)
+    return fail(ctx, CI_EINVAL, "search range [%lld, %lld) invalid for n = %lld",
+                (long long)jb.j_lo, (long long)jb.j_hi, (long long)N);
+  if (!isfinite(thr) || thr < 0.f) return fail(ctx, CI_EINVAL, "threshold must be finite and >= 0");
+  if (jb.cap < 0) return fail(ctx, CI_EINVAL, "negative capacity");
+  if (!jb.count) return fail(ctx, CI_EINVAL, "null d_count");
+  if (jb.n > 0 && !jb.peaks) return fail(ctx, CI_EINVAL, "null d_peaks");
+  if (jb.cap > 0 && !jb.trig) return fail(ctx, CI_EINVAL, "null d_trig with cap > 0");
+  const int l2 = jb.seg->plan.log2n;
+  jb.cfg = ctx->tune[l2][precision];
+  jb.plan = plan_for(l2, jb.cfg.c, jb.cfg.j);
+  jb.nwin = (N + window - 1) / window;
+  int64_t B = ctx->batch_override > 0 ? ctx->batch_override
+              : jb.cfg.batch > 0      ? jb.cfg.batch
+                                      : default_batch(ctx, N);
+  const int64_t wlimit = (int64_t(1) << 22) / jb.nwin;
+  if (B > wlimit) B = wlimit > 0 ? wlimit : 1;
+  // the batch placement keeps one offset per template in LDS (>= 4096 ints)
+  if (B > 4096) B = 4096;
+  if (B > jb.n) B = jb.n > 0 ? jb.n : 1;
+  jb.B = B;
+  return CI_OK;
+}
+
+// Workspace for a set of jobs: one trigger region each, and intermediate
+// slot sets sized for the largest batch.  Returns the slot stride in
+// complex elements.
+int prepare_jobs(Ctx* ctx, std::vector<Job>& jobs, size_t* slot_elems) {
+  size_t ymax = 0, ttot = 0;
+  for (Job& jb : jobs) {
+    jb.toff = ttot;
+    ttot += trig_bytes(jb.B, jb.nwin, jb.plan.n2 / jb.plan.j);
+    if (jb.n > 0) {
+      const size_t y = (size_t)jb.B * (size_t)jb.seg->host.n;
+      if (y > ymax) ymax = y;
+    }
+  }
+  int rc = ensure_tbuf(ctx, ttot);
+  if (rc != CI_OK) return rc;
+  if (ymax > 0) {
+    rc = ensure_ybuf(ctx, sizeof(float2) * 2 * ymax);
+    if (rc != CI_OK) return rc;
+  }
+  for (Job& jb : jobs)
+    carve_trig(static_cast<char*>(ctx->tbuf) + jb.toff, jb.B, jb.nwin, jb.plan.n2 / jb.plan.j,
+               &jb.tw);
+  *slot_elems = ymax;
+  return ensure_streams(ctx);
+}
+
+// Enqueue the jobs on stream st.  Batches of all jobs alternate
+// between the two internal streams (global batch b uses slot set b & 1 and
+// stream b & 1), so one batch's second pass overlaps the next batch's first
+// pass, across job boundaries too.  Within a job the finalisers are chained
+// in batch order, which keeps its trigger list ordered; st joins both
+// internal streams at the end.
+int enqueue_jobs(Ctx* ctx, const std::vector<Job>& jobs, size_t slot_elems, int32_t precision,
+                 float thr2, int64_t window, int merge, hipStream_t st) {
+  hipError_t e = hipSuccess;
+  for (const Job& jb : jobs) {
+    e = launch_init_call(jb.tw, (int)jb.nwin, jb.count, st);
+    if (e != hipSuccess) return hipfail(ctx, e, "init launch");
+  }
+  e = hipEventRecord(ctx->sev[2], st);
+  for (int i = 0; i < 2 && e == hipSuccess; ++i) e = hipStreamWaitEvent(ctx->ws[i], ctx->sev[2], 0);
+  if (e != hipSuccess) return hipfail(ctx, e, "stream fork");
+  int64_t b = 0;
+  for (const Job& jb : jobs) {
+    if (jb.n == 0) continue;
+    BatchArgs a;
+    memset(&a, 0, sizeof a);
+    a.seg = jb.seg;
+    a.plan = jb.plan;
+    a.bmax = (int)jb.B;
+    a.tw = jb.tw;
+    a.nwin = (int)jb.nwin;
+    a.window = window;
+    a.j_lo = jb.j_lo;
+    a.j_hi = jb.j_hi;
+    a.thr2 = thr2;
+    a.d_peaks = jb.peaks;
+    a.d_trig = jb.trig;
+    a.cap = jb.cap;
+    a.d_count = jb.count;
+    a.merge = merge;
+    a.precision = precision;
+    a.p2_per_cu = jb.cfg.p2_per_cu;
+    hipEvent_t prev_fin = nullptr;
+    for (int64_t t0 = 0; t0 < jb.n; ++b, t0 += jb.B) {
+      hipStream_t sb = ctx->ws[b & 1];
+      a.t0 = t0;
+      a.nb = (int)((jb.n - t0) < jb.B ? (jb.n - t0) : jb.B);
+      a.slot = (int)(b & 1);
+      a.params = jb.params + t0;
+      a.y = static_cast<float2*>(ctx->ybuf) + (size_t)(b & 1) * slot_elems;
+      a.last_batch = (t0 + jb.B >= jb.n) ? 1 : 0;
+      e = timed(ctx, 0, a.nb, sb, [&] { return launch_pass1(a, true, sb); });
+      if (e != hipSuccess) return hipfail(ctx, e, "pass-1 launch");
+      e = timed(ctx, 1, a.nb, sb, [&] { return launch_pass2_trig(a, sb); });
+      if (e != hipSuccess) return hipfail(ctx, e, "pass-2 launch");
+      if (prev_fin) {
+        e = hipStreamWaitEvent(sb, prev_fin, 0);
+        if (e != hipSuccess) return hipfail(ctx, e, "finaliser ordering");
+      }
+      e = launch_fin(a, sb);
+      if (e != hipSuccess) return hipfail(ctx, e, "finalise launch");
+      prev_fin = ctx->sev[b & 1];
+      e = hipEventRecord(prev_fin, sb);
+      if (e != hipSuccess) return hipfail(ctx, e, "finaliser event");
+    }
+  }
+  for (int i = 0; i < 2 && e == hipSuccess; ++i) {
+    e = hipEventRecord(ctx->sev[i], ctx->ws[i]);
+    if (e == hipSuccess) e = hipStreamWaitEvent(st, ctx->sev[i], 0);
+  }
+  if (e != hipSuccess) return hipfail(ctx, e, "stream join");
   return CI_OK;
 }
 
@@ -354,13 +506,7 @@ int ci_segment_create(ci_ctx* ctx, const ci_segment_spec* spec, const void* d_xt
   if (!s) return fail(ctx, CI_ENOMEM, "segment allocation");
   s->ctx = ctx;
   s->spec = *spec;
-  {
-    // tile shape: environment overrides for tuning runs, else 8 x 4 (the
-    // fastest measured at 2^20)
-    const char* ec = getenv("CI_TILE_C");
-    const char* ej = getenv("CI_TILE_J");
-    s->plan = plan_for(l2, ec ? atoi(ec) : 8, ej ? atoi(ej) : 4);
-  }
+  s->plan = plan_for(l2, 8, 4);
   SegDev& h = s->host;
   h.n = spec->n;
   h.half = spec->n / 2;
@@ -546,6 +692,10 @@ int ci_matched_filter(ci_ctx* ctx, const ci_segment* seg, const ci_tparams* d_pa
   BatchArgs a;
   memset(&a, 0, sizeof a);
   a.seg = seg;
+  {
+    const Tune& t = ctx->tune[seg->plan.log2n][precision];
+    a.plan = plan_for(seg->plan.log2n, t.c, t.j);
+  }
   a.bmax = (int)B;
   a.precision = precision;
   for (int64_t b = 0, t0 = 0; t0 < n; ++b, t0 += B) {
@@ -567,94 +717,286 @@ int ci_find_triggers(ci_ctx* ctx, const ci_segment* seg, const ci_tparams* d_par
                      int32_t precision, float snr_threshold, int64_t window, int64_t j_lo,
                      int64_t j_hi, ci_trigger* d_peaks, ci_trigger* d_trig, int64_t cap,
                      int64_t* d_count, int32_t merge_across_templates, void* stream) {
+  if (!ctx) return fail(nullptr, CI_EINVAL, "null context");
+  std::vector<Job> jobs(1);
+  Job& jb = jobs[0];
+  jb.seg = seg;
+  jb.params = d_params;
+  jb.n = n;
+  jb.j_lo = j_lo;
+  jb.j_hi = j_hi;
+  jb.peaks = d_peaks;
+  jb.trig = d_trig;
+  jb.cap = cap;
+  jb.count = d_count;
+  int rc = check_job(ctx, jb, precision, snr_threshold, window);
+  if (rc != CI_OK) return rc;
+  DeviceGuard dg(ctx->device);
+  if (!dg.ok) return fail(ctx, CI_EHIP, "cannot select device %d", ctx->device);
+  size_t slot = 0;
+  rc = prepare_jobs(ctx, jobs, &slot);
+  if (rc != CI_OK) return rc;
+  return enqueue_jobs(ctx, jobs, slot, precision, snr_threshold * snr_threshold, window,
+                      merge_across_templates ? 1 : 0, static_cast<hipStream_t>(stream));
+}
+
+int ci_search_classes(ci_ctx* ctx, const ci_class_job* jobs_in, int32_t njobs, int32_t precision,
+                      float snr_threshold, int64_t window, int32_t merge_across_templates,
+                      int32_t flags, void* stream) {
+  if (!ctx) return fail(nullptr, CI_EINVAL, "null context");
+  if (njobs < 0 || (njobs > 0 && !jobs_in)) return fail(ctx, CI_EINVAL, "bad job list");
+  if (flags & ~CI_RUN_GRAPH) return fail(ctx, CI_EINVAL, "unknown flags 0x%x", flags);
+  if (flags & CI_RUN_GRAPH)
+    return fail(ctx, CI_EUNSUPPORTED,
+                "graph replay of the schedule is disabled (a capture of a multi-batch "
+                "schedule ended the process in the runtime; cause not identified)");
+  std::vector<Job> jobs((size_t)njobs);
+  for (int32_t i = 0; i < njobs; ++i) {
+    const ci_class_job& in = jobs_in[i];
+    Job& jb = jobs[(size_t)i];
+    jb.seg = in.seg;
+    jb.params = in.d_params;
+    jb.n = in.n;
+    jb.j_lo = in.j_lo;
+    jb.j_hi = in.j_hi;
+    jb.peaks = in.d_peaks;
+    jb.trig = in.d_trig;
+    jb.cap = in.cap;
+    jb.count = in.d_count;
+    const int rc = check_job(ctx, jb, precision, snr_threshold, window);
+    if (rc != CI_OK) return fail(ctx, rc, "job %d: %s", i, ctx->err.c_str());
+  }
+  if (njobs == 0) return CI_OK;
+  DeviceGuard dg(ctx->device);
+  if (!dg.ok) return fail(ctx, CI_EHIP, "cannot select device %d", ctx->device);
+  size_t slot = 0;
+  int rc = prepare_jobs(ctx, jobs, &slot);
+  if (rc != CI_OK) return rc;
+  return enqueue_jobs(ctx, jobs, slot, precision, snr_threshold * snr_threshold, window,
+                      merge_across_templates ? 1 : 0, static_cast<hipStream_t>(stream));
+}
+
+int ci_length_classes(const ci_template* bank_host, int64_t n, double fs, double f_low,
+                      const int64_t* class_n, int32_t nclass, int32_t* class_out) {
+  if (n < 0) return fail(nullptr, CI_EINVAL, "negative bank size");
+  if (n > 0 && (!bank_host || !class_out)) return fail(nullptr, CI_EINVAL, "null bank or output");
+  if (nclass < 1 || !class_n) return fail(nullptr, CI_EINVAL, "need at least one class");
+  if (!(fs > 0.0) || !(f_low > 0.0) || !isfinite(fs) || !isfinite(f_low))
+    return fail(nullptr, CI_EINVAL, "fs and f_low must be finite and > 0");
+  for (int32_t c = 0; c < nclass; ++c) {
+    if (ilog2_exact(class_n[c]) < 0)
+      return fail(nullptr, CI_EINVAL, "class %d: n = %lld is not a power of two", c,
+                  (long long)class_n[c]);
+    if (c > 0 && class_n[c] <= class_n[c - 1])
+      return fail(nullptr, CI_EINVAL, "class lengths must increase");
+  }
+  for (int64_t i = 0; i < n; ++i) {
+    const double m1 = bank_host[i].m1, m2 = bank_host[i].m2;
+    if (!(m1 > 0.0) || !(m2 > 0.0) || !isfinite(m1) || !isfinite(m2))
+      return fail(nullptr, CI_EINVAL, "template %lld has non-positive mass", (long long)i);
+    const double tau = tau_2pn(f_low, m1 >= m2 ? m1 : m2, m1 >= m2 ? m2 : m1);
+    int32_t c = nclass - 1;
+    for (int32_t k = 0; k < nclass; ++k)
+      if (tau <= (double)class_n[k] / fs) {
+        c = k;
+        break;
+      }
+    class_out[i] = c;
+  }
+  return CI_OK;
+}
+
+int ci_get_tune(ci_ctx* ctx, int32_t log2n, int32_t precision, ci_tune* out) {
+  if (!ctx) return fail(nullptr, CI_EINVAL, "null context");
+  if (!out) return fail(ctx, CI_EINVAL, "null output");
+  if (log2n < 16 || log2n > 21) return fail(ctx, CI_EINVAL, "log2n %d outside 16..21", log2n);
+  if (precision < 0 || precision > 2) return fail(ctx, CI_EINVAL, "unknown precision %d", precision);
+  const Tune& t = ctx->tune[log2n][precision];
+  memset(out, 0, sizeof *out);
+  out->log2n = log2n;
+  out->precision = precision;
+  out->tile_c = t.c;
+  out->tile_j = t.j;
+  out->p2_per_cu = t.p2_per_cu;
+  out->tuned = t.tuned ? 1 : 0;
+  out->batch = t.batch;
+  return CI_OK;
+}
+
+int ci_set_tune(ci_ctx* ctx, const ci_tune* cfg) {
+  if (!ctx) return fail(nullptr, CI_EINVAL, "null context");
+  if (!cfg) return fail(ctx, CI_EINVAL, "null configuration");
+  if (cfg->log2n < 16 || cfg->log2n > 21)
+    return fail(ctx, CI_EINVAL, "log2n %d outside 16..21", cfg->log2n);
+  if (cfg->precision < 0 || cfg->precision > 2)
+    return fail(ctx, CI_EINVAL, "unknown precision %d", cfg->precision);
+  if ((cfg->tile_c != 4 && cfg->tile_c != 8) || (cfg->tile_j != 4 && cfg->tile_j != 8))
+    return fail(ctx, CI_EINVAL, "tiles must be 4 or 8 (got %d x %d)", cfg->tile_c, cfg->tile_j);
+  if (cfg->p2_per_cu < 0 || cfg->p2_per_cu > 8)
+    return fail(ctx, CI_EINVAL, "p2_per_cu %d outside 0..8", cfg->p2_per_cu);
+  if (cfg->batch < 0 || cfg->batch > 4096)
+    return fail(ctx, CI_EINVAL, "batch %lld outside 0..4096", (long long)cfg->batch);
+  Tune& t = ctx->tune[cfg->log2n][cfg->precision];
+  t.c = cfg->tile_c;
+  t.j = cfg->tile_j;
+  t.p2_per_cu = cfg->p2_per_cu;
+  t.batch = cfg->batch;
+  t.tuned = false;
+  return CI_OK;
+}
+
+int ci_autotune(ci_ctx* ctx, const ci_segment* seg, const ci_tparams* d_params, int64_t n,
+                int32_t precision, float snr_threshold, int64_t window, ci_tune* out,
+                void* stream) {
   int rc = check_filter_args(ctx, seg, d_params, n, precision);
   if (rc != CI_OK) return rc;
+  if (n < 1) return fail(ctx, CI_EINVAL, "autotuning needs at least one template");
   const int64_t N = seg->host.n;
   if (window < 1 || window > N) return fail(ctx, CI_EINVAL, "window %lld outside 1..n", (long long)window);
-  if (j_hi <= 0) j_hi = N;
-  if (j_lo < 0 || j_hi > N || j_lo >= j_hi)
-    return fail(ctx, CI_EINVAL, "search range [%lld, %lld) invalid for n = %lld", (long long)j_lo,
-                (long long)j_hi, (long long)N);
-  if (!isfinite(snr_threshold) || snr_threshold < 0.f)
-    return fail(ctx, CI_EINVAL, "threshold must be finite and >= 0");
-  if (cap < 0) return fail(ctx, CI_EINVAL, "negative capacity");
-  if (!d_count) return fail(ctx, CI_EINVAL, "null d_count");
-  if (n > 0 && !d_peaks) return fail(ctx, CI_EINVAL, "null d_peaks");
-  if (cap > 0 && !d_trig) return fail(ctx, CI_EINVAL, "null d_trig with cap > 0");
   DeviceGuard dg(ctx->device);
   if (!dg.ok) return fail(ctx, CI_EHIP, "cannot select device %d", ctx->device);
   hipStream_t st = static_cast<hipStream_t>(stream);
+  const int l2 = seg->plan.log2n;
   const int64_t nwin = (N + window - 1) / window;
-  int64_t B = default_batch(ctx, N);
-  const int64_t wlimit = (int64_t(1) << 22) / nwin;
-  if (B > wlimit) B = wlimit > 0 ? wlimit : 1;
-  // the batch placement keeps one offset per template in LDS (>= 4096 ints)
-  if (B > 4096) B = 4096;
-  if (B > n) B = n > 0 ? n : 1;
-  TrigWork tw;
-  rc = ensure_trig(ctx, B, nwin, seg->plan.n2 / seg->plan.j, &tw);
-  if (rc != CI_OK) return rc;
-  hipError_t e = launch_init_call(tw, (int)nwin, d_count, st);
-  if (e != hipSuccess) return hipfail(ctx, e, "init launch");
-  if (n == 0) return CI_OK;
-  rc = ensure_ybuf(ctx, sizeof(float2) * 2 * (size_t)B * (size_t)N);
-  if (rc != CI_OK) return rc;
-  BatchArgs a;
-  memset(&a, 0, sizeof a);
-  a.seg = seg;
-  a.bmax = (int)B;
-  a.tw = tw;
-  a.nwin = (int)nwin;
-  a.window = window;
-  a.j_lo = j_lo;
-  a.j_hi = j_hi;
-  a.thr2 = snr_threshold * snr_threshold;
-  a.d_peaks = d_peaks;
-  a.d_trig = d_trig;
-  a.cap = cap;
-  a.d_count = d_count;
-  a.merge = merge_across_templates ? 1 : 0;
-  a.precision = precision;
-  {
-    // resident pass-2 workgroups per CU: 2 leaves room for the other
-    // stream's pass 1 (environment override for tuning runs)
-    const char* ep = getenv("CI_P2_WG_PER_CU");
-    a.p2_per_cu = ep ? atoi(ep) : 2;
-  }
-  rc = ensure_streams(ctx);
-  if (rc != CI_OK) return rc;
-  // Batches alternate between two internal streams (batch b uses slot set
-  // b & 1 and stream b & 1), so one batch's second pass overlaps the next
-  // batch's first pass.  The finalisers are chained in batch order, which
-  // keeps the trigger list ordered; the caller's stream joins the last one.
-  e = hipEventRecord(ctx->sev[2], st);
-  for (int i = 0; i < 2 && e == hipSuccess; ++i) e = hipStreamWaitEvent(ctx->ws[i], ctx->sev[2], 0);
-  if (e != hipSuccess) return hipfail(ctx, e, "stream fork");
-  hipEvent_t prev_fin = nullptr;
-  for (int64_t b = 0, t0 = 0; t0 < n; ++b, t0 += B) {
-    hipStream_t sb = ctx->ws[b & 1];
-    a.t0 = t0;
-    a.nb = (int)((n - t0) < B ? (n - t0) : B);
-    a.slot = (int)(b & 1);
-    a.params = d_params + t0;
-    a.y = static_cast<float2*>(ctx->ybuf) + (size_t)a.slot * B * N;
-    a.last_batch = (t0 + B >= n) ? 1 : 0;
-    e = timed(ctx, 0, a.nb, sb, [&] { return launch_pass1(a, true, sb); });
-    if (e != hipSuccess) return hipfail(ctx, e, "pass-1 launch");
-    e = timed(ctx, 1, a.nb, sb, [&] { return launch_pass2_trig(a, sb); });
-    if (e != hipSuccess) return hipfail(ctx, e, "pass-2 launch");
-    if (prev_fin) {
-      e = hipStreamWaitEvent(sb, prev_fin, 0);
-      if (e != hipSuccess) return hipfail(ctx, e, "finaliser ordering");
+  int64_t cap = n * nwin;
+  if (cap > (int64_t(1) << 20)) cap = int64_t(1) << 20;
+  const size_t pk_b = sizeof(ci_trigger) * (size_t)n, tr_b = sizeof(ci_trigger) * (size_t)cap;
+  void* dbuf = nullptr;
+  hipError_t e = hipMalloc(&dbuf, pk_b + tr_b + 256);
+  if (e != hipSuccess) return fail(ctx, CI_ENOMEM, "autotune outputs: %s", hipGetErrorString(e));
+  ci_trigger* d_pk = static_cast<ci_trigger*>(dbuf);
+  ci_trigger* d_tr = reinterpret_cast<ci_trigger*>(static_cast<char*>(dbuf) + pk_b);
+  int64_t* d_cnt = reinterpret_cast<int64_t*>(static_cast<char*>(dbuf) + pk_b + tr_b);
+  std::vector<ci_trigger> ref_pk((size_t)n), pk((size_t)n);
+  std::vector<ci_trigger> ref_tr, tr;
+  int64_t ref_cnt = -1;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  const int64_t saved_override = ctx->batch_override;
+  const Tune saved = ctx->tune[l2][precision];
+  ctx->batch_override = 0;
+  int cands = 0, rejected = 0;
+  Tune best = saved;
+  float best_ms = 0.f;
+
+  // one call's outputs back on the host
+  auto fetch = [&](std::vector<ci_trigger>& p, std::vector<ci_trigger>& t, int64_t& c) -> int {
+    hipError_t x = hipMemcpyAsync(p.data(), d_pk, pk_b, hipMemcpyDeviceToHost, st);
+    if (x == hipSuccess) x = hipMemcpyAsync(&c, d_cnt, sizeof c, hipMemcpyDeviceToHost, st);
+    if (x == hipSuccess) x = hipStreamSynchronize(st);
+    if (x != hipSuccess) return hipfail(ctx, x, "autotune readback");
+    const int64_t k = c < cap ? c : cap;
+    t.resize((size_t)k);
+    if (k > 0) {
+      x = hipMemcpy(t.data(), d_tr, sizeof(ci_trigger) * (size_t)k, hipMemcpyDeviceToHost);
+      if (x != hipSuccess) return hipfail(ctx, x, "autotune readback");
     }
-    e = launch_fin(a, sb);
-    if (e != hipSuccess) return hipfail(ctx, e, "finalise launch");
-    prev_fin = ctx->sev[b & 1];
-    e = hipEventRecord(prev_fin, sb);
-    if (e != hipSuccess) return hipfail(ctx, e, "finaliser event");
+    return CI_OK;
+  };
+  auto call = [&]() {
+    return ci_find_triggers(ctx, seg, d_params, n, precision, snr_threshold, window, 0, 0, d_pk,
+                            d_tr, cap, d_cnt, 0, stream);
+  };
+  // time one configuration (best of three after a warm-up call) and check
+  // that its outputs equal the reference configuration's bit for bit
+  auto trial = [&](const Tune& cand, float* ms, bool* same) -> int {
+    ctx->tune[l2][precision] = cand;
+    int r = call();
+    if (r != CI_OK) return r;
+    int64_t cnt = 0;
+    r = fetch(pk, tr, cnt);
+    if (r != CI_OK) return r;
+    *same = cnt == ref_cnt && memcmp(pk.data(), ref_pk.data(), pk_b) == 0 && tr.size() == ref_tr.size() &&
+            (tr.empty() || memcmp(tr.data(), ref_tr.data(), sizeof(ci_trigger) * tr.size()) == 0);
+    float bestt = 0.f;
+    for (int rep = 0; rep < 3; ++rep) {
+      hipError_t x = hipEventRecord(e0, st);
+      if (x != hipSuccess) return hipfail(ctx, x, "autotune timing");
+      r = call();
+      if (r != CI_OK) return r;
+      x = hipEventRecord(e1, st);
+      if (x == hipSuccess) x = hipEventSynchronize(e1);
+      float t = 0.f;
+      if (x == hipSuccess) x = hipEventElapsedTime(&t, e0, e1);
+      if (x != hipSuccess) return hipfail(ctx, x, "autotune timing");
+      if (rep == 0 || t < bestt) bestt = t;
+    }
+    *ms = bestt;
+    ++cands;
+    return CI_OK;
+  };
+  rc = CI_OK;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    rc = fail(ctx, CI_EHIP, "autotune events");
+  // reference outputs: the default configuration
+  if (rc == CI_OK) {
+    ctx->tune[l2][precision] = Tune();
+    rc = call();
+    if (rc == CI_OK) rc = fetch(ref_pk, ref_tr, ref_cnt);
   }
-  e = hipStreamWaitEvent(st, prev_fin, 0);
-  if (e != hipSuccess) return hipfail(ctx, e, "stream join");
+  if (rc == CI_OK) {
+    best = Tune();
+    bool same = true;
+    rc = trial(best, &best_ms, &same);
+  }
+  // coordinate search: tiles, then pass-2 residency, then batch size
+  const int tiles[4][2] = {{4, 4}, {4, 8}, {8, 4}, {8, 8}};
+  for (int i = 0; i < 4 && rc == CI_OK; ++i) {
+    Tune c = best;
+    c.c = tiles[i][0];
+    c.j = tiles[i][1];
+    if (c.c == best.c && c.j == best.j) continue;
+    float ms = 0.f;
+    bool same = false;
+    rc = trial(c, &ms, &same);
+    if (rc == CI_OK && !same) ++rejected;
+    else if (rc == CI_OK && ms < best_ms) { best = c; best_ms = ms; }
+  }
+  for (int p2 = 0; p2 <= 4 && rc == CI_OK; ++p2) {
+    if (p2 == best.p2_per_cu) continue;
+    Tune c = best;
+    c.p2_per_cu = p2;
+    float ms = 0.f;
+    bool same = false;
+    rc = trial(c, &ms, &same);
+    if (rc == CI_OK && !same) ++rejected;
+    else if (rc == CI_OK && ms < best_ms) { best = c; best_ms = ms; }
+  }
+  const int64_t b0 = default_batch(ctx, N);
+  const int64_t bs[4] = {b0 / 4, b0 / 2, b0 * 2, b0 * 4};
+  for (int i = 0; i < 4 && rc == CI_OK; ++i) {
+    if (bs[i] < 1 || bs[i] > 4096 || bs[i] >= 2 * n) continue;
+    Tune c = best;
+    c.batch = bs[i];
+    float ms = 0.f;
+    bool same = false;
+    rc = trial(c, &ms, &same);
+    if (rc == CI_OK && !same) ++rejected;
+    else if (rc == CI_OK && ms < best_ms) { best = c; best_ms = ms; }
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  (void)hipStreamSynchronize(st);
+  (void)hipFree(dbuf);
+  ctx->batch_override = saved_override;
+  if (rc != CI_OK) {
+    ctx->tune[l2][precision] = saved;
+    return rc;
+  }
+  best.tuned = true;
+  ctx->tune[l2][precision] = best;
+  if (out) {
+    memset(out, 0, sizeof *out);
+    out->log2n = l2;
+    out->precision = precision;
+    out->tile_c = best.c;
+    out->tile_j = best.j;
+    out->p2_per_cu = best.p2_per_cu;
+    out->tuned = 1;
+    out->batch = best.batch;
+    out->ms = best_ms;
+    out->candidates = cands;
+    out->rejected = rejected;
+  }
   return CI_OK;
 }
 

@@ -47,6 +47,15 @@ struct TrigWork {
   unsigned long long* run;     // [1]           triggers placed so far
 };
 
+// Launch configuration of one search: tiles, pass-2 residency and batch.
+struct Tune {
+  int c = 8;             // k1 columns per pass-1 workgroup (4 or 8)
+  int j = 4;             // j2 columns per pass-2 workgroup (4 or 8)
+  int p2_per_cu = 2;     // resident pass-2 workgroups per CU (0: as many as fit)
+  int64_t batch = 0;     // templates per batch (0: by intermediate size)
+  bool tuned = false;    // chosen by the autotuner
+};
+
 // One instrumented launch: events bracketing it on its stream.
 struct TimedLaunch {
   int kind;            // 0 pass 1, 1 pass 2
@@ -74,6 +83,8 @@ struct Ctx {
   // and join back to the caller's stream
   hipStream_t ws[2] = {nullptr, nullptr};
   hipEvent_t sev[3] = {nullptr, nullptr, nullptr};
+  // launch configuration per (log2 n, precision): autotuned or default
+  Tune tune[32][3];
   // instrumentation
   bool timing = false;
   std::vector<TimedLaunch> launches;
@@ -108,6 +119,7 @@ hipError_t launch_init_call(const TrigWork& tw, int nwin, int64_t* d_count,
 
 struct BatchArgs {
   const Seg* seg;
+  Plan plan;                  // factorisation and tiles of this call
   const ci_tparams* params;   // first template of the batch
   int64_t t0;                 // bank index of the first template
   int nb;                     // templates in this batch

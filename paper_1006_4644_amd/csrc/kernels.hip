@@ -1167,7 +1167,7 @@ P2Args make_p2(const BatchArgs& a) {
   p.y = a.y;
   p.t0 = a.t0;
   p.nb = a.nb;
-  p.ntile2 = a.seg->plan.n2 / a.seg->plan.j;
+  p.ntile2 = a.plan.n2 / a.plan.j;
   p.ppart = a.tw.ppart ? a.tw.ppart + (size_t)s * a.bmax * p.ntile2 : nullptr;
   p.wkeys = a.tw.wkeys ? a.tw.wkeys + (size_t)s * a.bmax * a.nwin : nullptr;
   p.bdone = a.tw.bdone ? a.tw.bdone + s : nullptr;
@@ -1292,7 +1292,7 @@ hipError_t dispatch(const Plan& p, F f) {
 }  // namespace
 
 hipError_t launch_pass1(const BatchArgs& a, bool zero_trig, hipStream_t st) {
-  return dispatch(a.seg->plan, [&](auto inst) {
+  return dispatch(a.plan, [&](auto inst) {
     typedef decltype(inst) I;
     if (a.precision == CI_SPLIT_BF16) return I::template p1mx<kBF16>(a, zero_trig, st);
     if (a.precision == CI_SPLIT_FP16) return I::template p1mx<kFP16>(a, zero_trig, st);
@@ -1300,7 +1300,7 @@ hipError_t launch_pass1(const BatchArgs& a, bool zero_trig, hipStream_t st) {
   });
 }
 hipError_t launch_pass2_trig(const BatchArgs& a, hipStream_t st) {
-  return dispatch(a.seg->plan, [&](auto inst) {
+  return dispatch(a.plan, [&](auto inst) {
     typedef decltype(inst) I;
     if (a.precision == CI_SPLIT_BF16) return I::template p2mx<kBF16, 0>(a, st);
     if (a.precision == CI_SPLIT_FP16) return I::template p2mx<kFP16, 0>(a, st);
@@ -1308,10 +1308,10 @@ hipError_t launch_pass2_trig(const BatchArgs& a, hipStream_t st) {
   });
 }
 hipError_t launch_fin(const BatchArgs& a, hipStream_t st) {
-  return dispatch(a.seg->plan, [&](auto inst) { return decltype(inst)::fin(a, st); });
+  return dispatch(a.plan, [&](auto inst) { return decltype(inst)::fin(a, st); });
 }
 hipError_t launch_pass2_series(const BatchArgs& a, hipStream_t st) {
-  return dispatch(a.seg->plan, [&](auto inst) {
+  return dispatch(a.plan, [&](auto inst) {
     typedef decltype(inst) I;
     if (a.precision == CI_SPLIT_BF16) return I::template p2mx<kBF16, 1>(a, st);
     if (a.precision == CI_SPLIT_FP16) return I::template p2mx<kFP16, 1>(a, st);

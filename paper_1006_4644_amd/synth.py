@@ -30,6 +30,7 @@ import numpy as np
 __all__ = [
     "Workload", "WORKLOADS", "psd_model", "make_psd", "k_low_of",
     "make_noise", "draw_masses", "InjectionSpec", "draw_injections",
+    "CLASS_LENGTHS", "class_noise_seed",
 ]
 
 
@@ -79,6 +80,16 @@ WORKLOADS = {
                         (8.0, 11.0, 14.0, 17.0, 20.0),
                         1006 + 500, 4644 + 5, 20100625 + 5),
 }
+
+
+# Segment lengths of the length classes (chirps of up to 32, 64, 128 and
+# 256 s at 4096 Hz).
+CLASS_LENGTHS = (1 << 17, 1 << 18, 1 << 19, 1 << 20)
+
+
+def class_noise_seed(wl: Workload, c: int) -> int:
+    """Noise seed of class c's segment: the workload's seed plus c."""
+    return wl.noise_seed + c
 
 
 def psd_model(f):

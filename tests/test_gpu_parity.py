@@ -257,10 +257,9 @@ def test_full_size_fp32_workload_sampled(ctx):
 
 @pytest.mark.parametrize("tc,tj", [(4, 4), (4, 8), (8, 4), (8, 8)])
 @pytest.mark.parametrize("log2n", [16, 20, 21])
-def test_tile_shapes(ctx, tc, tj, log2n, monkeypatch):
-    """Every pass-1 / pass-2 tile shape gives the oracle's series and peaks."""
-    monkeypatch.setenv("CI_TILE_C", str(tc))
-    monkeypatch.setenv("CI_TILE_J", str(tj))
+def test_tile_shapes(ctx, tc, tj, log2n):
+    """Every pass-1 / pass-2 tile shape gives the oracle's series and peaks,
+    bit-identical to the default shape's."""
     n, fs, fl = 1 << log2n, 4096.0, 20.0
     bank = synth.draw_masses(3, 1.0, 20.0, "loguniform", 31 * tc + tj + log2n)
     inj = synth.InjectionSpec(float(bank[1, 0]), float(bank[1, 1]), 9.0,
@@ -268,9 +267,20 @@ def test_tile_shapes(ctx, tc, tj, log2n, monkeypatch):
     x64, psd, x128 = C.make_case(n, fs, fl, bank, [inj], 2000 + log2n)
     seg = _segment(ctx, x64, psd, n, fs, fl)
     params = ctx.gen_templates(seg, bank)
-    z = ctx.matched_filter(seg, params)
-    peaks, trig, cnt = ctx.find_triggers(seg, params, 5.5, 4096, cap=256)
-    _sync()
+    z0 = ctx.matched_filter(seg, params)
+    p0, t0, c0 = ctx.find_triggers(seg, params, 5.5, 4096, cap=256)
+    ctx.set_tune(log2n, ci.FP32, tc, tj, 1 + (tc + tj) % 3, 2)
+    try:
+        z = ctx.matched_filter(seg, params)
+        peaks, trig, cnt = ctx.find_triggers(seg, params, 5.5, 4096, cap=256)
+        _sync()
+    finally:
+        ctx.set_tune(log2n, ci.FP32)
+    assert np.array_equal(z.cpu().numpy(), z0.cpu().numpy())
+    assert np.array_equal(peaks.cpu().numpy(), p0.cpu().numpy())
+    assert int(cnt.cpu()[0]) == int(c0.cpu()[0])
+    k = min(int(c0.cpu()[0]), 256)
+    assert np.array_equal(trig.cpu().numpy()[:k], t0.cpu().numpy()[:k])
     zg = z.cpu().numpy()
     P = ci.triggers_to_numpy(peaks)
     T = ci.triggers_to_numpy(trig, int(cnt.cpu()[0]))

@@ -1,0 +1,225 @@
+"""Batch schedule on the GPU: length classes in one multi-class search and
+the autotuner (needs an MI355X).
+
+A multi-class search must give, per class, exactly what one search call per
+class gives (bit for bit), and every autotuner candidate it keeps must agree
+bit for bit with the default launch configuration; spot checks against the
+FP64 oracle cover the arithmetic itself.
+"""
+import numpy as np
+import pytest
+
+from paper_1006_4644_amd import ci, synth
+from tests import mfcase as C
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx(gpu_lib):
+    c = gpu_lib.context(0)
+    yield c
+    c.close()
+
+
+def _dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _sync():
+    import torch
+    torch.cuda.synchronize()
+
+
+def _np(t):
+    return t.cpu().numpy().copy()
+
+
+def _class_setup(ctx, lib, bank, classes, fs, fl, seed):
+    """Segments and generated templates per class (pure noise data)."""
+    cls = lib.length_classes(bank, fs, fl, classes)
+    out = []
+    for c, n in enumerate(classes):
+        idx = np.nonzero(cls == c)[0]
+        psd = synth.make_psd(n, fs)
+        x = synth.make_noise(n, fs, fl, psd, seed + c).astype(np.complex64)
+        seg = ctx.segment(_dev(x), _dev(psd), n, fs, fl)
+        params = ctx.gen_templates(seg, bank[idx]) if len(idx) else None
+        out.append(dict(n=n, idx=idx, seg=seg, params=params, psd=psd,
+                        x128=x.astype(np.complex128)))
+    return cls, out
+
+
+def _jobs(setup, cap):
+    return [dict(seg=s["seg"], params=s["params"], n=len(s["idx"]), cap=cap)
+            for s in setup if s["params"] is not None]
+
+
+def _per_class(ctx, setup, thr, window, cap, merge):
+    res = []
+    for s in setup:
+        if s["params"] is None:
+            continue
+        p, t, c = ctx.find_triggers(s["seg"], s["params"], thr, window, cap=cap,
+                                    merge=merge)
+        res.append((p, t, c))
+    _sync()
+    return [(_np(p), _np(t)[:min(int(c.cpu()[0]), cap)], int(c.cpu()[0]))
+            for p, t, c in res]
+
+
+def _same(a, b):
+    assert len(a) == len(b)
+    for (p0, t0, c0), (p1, t1, c1) in zip(a, b):
+        assert c0 == c1
+        assert np.array_equal(p0, p1)
+        assert np.array_equal(t0, t1)
+
+
+def _collect(outs, cap):
+    _sync()
+    return [(_np(p), _np(t)[:min(int(c.cpu()[0]), cap)], int(c.cpu()[0]))
+            for p, t, c in outs]
+
+
+@pytest.mark.parametrize("merge", [False, True])
+def test_classes_match_per_class_calls(ctx, gpu_lib, merge):
+    fs, fl, thr, W, cap = 4096.0, 20.0, 5.0, 4096, 4096
+    classes = (1 << 16, 1 << 17, 1 << 18)
+    bank = synth.draw_masses(40, 1.0, 12.0, "loguniform", 515)
+    cls, setup = _class_setup(ctx, gpu_lib, bank, classes, fs, fl, 9100)
+    assert len(set(cls.tolist())) >= 2
+    ref = _per_class(ctx, setup, thr, W, cap, merge)
+    jobs = _jobs(setup, cap)
+    _same(ref, _collect(ctx.search_classes(jobs, thr, W, merge=merge), cap))
+    # again into the same buffers, after other work on the context
+    outs = ctx.search_classes(jobs, thr, W, merge=merge)
+    ctx.find_triggers(jobs[0]["seg"], jobs[0]["params"], thr + 1.0, 1024, cap=8)
+    for p, t, c in outs:
+        p.fill_(-7)
+        t.fill_(-7)
+        c.fill_(-7)
+    again = ctx.search_classes([dict(j, peaks=o[0], trig=o[1], count=o[2])
+                                for j, o in zip(jobs, outs)], thr, W, merge=merge)
+    _same(ref, _collect(again, cap))
+    for s in setup:
+        s["seg"].close()
+
+
+@pytest.mark.skip(reason="graph replay of the schedule is disabled: a graph-captured "
+                  "run of the 16384-template class schedule ended the process with a "
+                  "host segmentation fault inside the library call; cause not "
+                  "identified, the library returns CI_EUNSUPPORTED for CI_RUN_GRAPH")
+def test_classes_graph_replay(ctx, gpu_lib):
+    fs, fl, thr, W, cap = 4096.0, 20.0, 5.0, 4096, 4096
+    classes = (1 << 16, 1 << 17, 1 << 18)
+    bank = synth.draw_masses(40, 1.0, 12.0, "loguniform", 515)
+    cls, setup = _class_setup(ctx, gpu_lib, bank, classes, fs, fl, 9100)
+    ref = _per_class(ctx, setup, thr, W, cap, False)
+    jobs = _jobs(setup, cap)
+    for rep in range(3):
+        _same(ref, _collect(ctx.search_classes(jobs, thr, W, graph=True), cap))
+    for s in setup:
+        s["seg"].close()
+
+
+def test_classes_against_oracle(ctx, gpu_lib):
+    """Two templates per class, peaks and triggers against the oracle."""
+    fs, fl, thr, W, cap = 4096.0, 20.0, 4.5, 4096, 1 << 14
+    classes = (1 << 16, 1 << 17, 1 << 18)
+    bank = synth.draw_masses(24, 1.0, 12.0, "loguniform", 616)
+    cls, setup = _class_setup(ctx, gpu_lib, bank, classes, fs, fl, 9200)
+    outs = _collect(ctx.search_classes(_jobs(setup, cap), thr, W), cap)
+    k = 0
+    for s in setup:
+        if s["params"] is None:
+            continue
+        P = outs[k][0].view(ci.TRIGGER_DTYPE).reshape(-1)
+        T = outs[k][1].view(ci.TRIGGER_DTYPE).reshape(-1)
+        k += 1
+        for i in range(min(2, len(s["idx"]))):
+            m1, m2 = bank[s["idx"][i]]
+            zo, _ = C.oracle_series(s["x128"], s["psd"], s["n"], fs, fl, m1, m2)
+            C.check_peak(P[i], zo)
+            C.check_triggers(T[T["tmpl"] == i], zo, W, thr)
+    for s in setup:
+        s["seg"].close()
+
+
+def test_empty_class_and_bad_jobs(ctx, gpu_lib):
+    import torch
+    fs, fl = 4096.0, 20.0
+    n = 1 << 16
+    psd = synth.make_psd(n, fs)
+    x = synth.make_noise(n, fs, fl, psd, 77).astype(np.complex64)
+    seg = ctx.segment(_dev(x), _dev(psd), n, fs, fl)
+    params = ctx.gen_templates(seg, synth.draw_masses(3, 1.0, 3.0, "uniform", 5))
+    cnt = torch.full((1,), 99, dtype=torch.int64, device="cuda")
+    outs = ctx.search_classes([dict(seg=seg, params=params, n=0, count=cnt),
+                               dict(seg=seg, params=params, n=3)], 5.0, 4096)
+    _sync()
+    assert int(cnt.cpu()[0]) == 0
+    assert int(outs[1][2].cpu()[0]) >= 0
+    with pytest.raises(ci.CiError) as e:
+        ctx.search_classes([dict(seg=seg, params=params, n=3, j_lo=5, j_hi=3)], 5.0, 4096)
+    assert e.value.code == ci.EINVAL and "job 0" in str(e.value)
+    with pytest.raises(ci.CiError):
+        ctx.search_classes([dict(seg=seg, params=params, n=3)], 5.0, 0)
+    # graph replay is reserved: an error before any work is enqueued
+    with pytest.raises(ci.CiError) as e:
+        ctx.search_classes([dict(seg=seg, params=params, n=3)], 5.0, 4096, graph=True)
+    assert e.value.code == ci.EUNSUPPORTED
+    seg.close()
+
+
+def test_autotune_keeps_results(ctx):
+    import torch
+    fs, fl, W = 4096.0, 20.0, 4096
+    n = 1 << 18
+    bank = synth.draw_masses(48, 1.0, 10.0, "loguniform", 818)
+    psd = synth.make_psd(n, fs)
+    x = synth.make_noise(n, fs, fl, psd, 818).astype(np.complex64)
+    seg = ctx.segment(_dev(x), _dev(psd), n, fs, fl)
+    params = ctx.gen_templates(seg, bank)
+    p0, t0, c0 = ctx.find_triggers(seg, params, 5.0, W, cap=4096)
+    ref = (_np(p0), _np(t0)[:min(int(c0.cpu()[0]), 4096)], int(c0.cpu()[0]))
+    cfg = ctx.autotune(seg, params, 5.0, W)
+    print("autotune 2^18:", cfg)
+    assert cfg["tuned"] == 1 and cfg["candidates"] >= 8 and cfg["rejected"] == 0
+    assert cfg["tile_c"] in (4, 8) and cfg["tile_j"] in (4, 8) and cfg["ms"] > 0
+    got = ctx.get_tune(18)
+    assert (got["tile_c"], got["tile_j"], got["p2_per_cu"], got["batch"], got["tuned"]) == \
+        (cfg["tile_c"], cfg["tile_j"], cfg["p2_per_cu"], cfg["batch"], 1)
+    p1, t1, c1 = ctx.find_triggers(seg, params, 5.0, W, cap=4096)
+    _same([ref], [(_np(p1), _np(t1)[:min(int(c1.cpu()[0]), 4096)], int(c1.cpu()[0]))])
+    ctx.set_tune(18, ci.FP32)
+    assert ctx.get_tune(18)["tuned"] == 0
+    seg.close()
+
+
+def test_batched_classes_workload(ctx, gpu_lib):
+    """The 16384-template uneven bank (log-U[1, 30], classes 2^17..2^20) in
+    one multi-class search: identical to per-class calls, merged per class,
+    and spot-checked against the oracle."""
+    wl = synth.WORKLOADS["batched-classes"]
+    bank = synth.draw_masses(wl.n_templates, wl.m_min, wl.m_max, wl.dist, wl.bank_seed)
+    cls, setup = _class_setup(ctx, gpu_lib, bank, synth.CLASS_LENGTHS, wl.fs, wl.f_low,
+                              wl.noise_seed)
+    counts = np.bincount(cls, minlength=len(synth.CLASS_LENGTHS))
+    print("class sizes:", counts.tolist())
+    assert counts.sum() == wl.n_templates and (counts > 0).all()
+    cap = 1 << 20
+    ref = _per_class(ctx, setup, wl.snr_threshold, wl.window, cap, True)
+    outs = _collect(ctx.search_classes(_jobs(setup, cap), wl.snr_threshold, wl.window,
+                                       merge=True), cap)
+    _same(ref, outs)
+    rng = np.random.default_rng(3)
+    for k, s in enumerate(setup):
+        P = outs[k][0].view(ci.TRIGGER_DTYPE).reshape(-1)
+        for i in rng.choice(len(s["idx"]), size=2, replace=False):
+            m1, m2 = bank[s["idx"][i]]
+            zo, _ = C.oracle_series(s["x128"], s["psd"], s["n"], wl.fs, wl.f_low, m1, m2)
+            C.check_peak(P[i], zo)
+    for s in setup:
+        s["seg"].close()

@@ -74,3 +74,29 @@ def test_struct_layouts():
     # ci_trigger is 32 bytes, ci_tparams 96 bytes (documented in ci.h)
     assert ci.TRIGGER_DTYPE.itemsize == 32
     assert ci.TPARAMS_DTYPE.itemsize == 96
+
+
+@pytest.mark.parametrize("fs,f_low,lo,hi", [(4096.0, 20.0, 1.0, 30.0),
+                                            (4096.0, 10.0, 1.0, 50.0)])
+def test_length_classes_match_oracle(lib, fs, f_low, lo, hi):
+    """Class of every template equals the oracle's rule (shortest segment
+    covering the 2PN chirp duration), including the clamp to the last."""
+    from paper_1006_4644_amd import synth
+    bank = synth.draw_masses(3000, lo, hi, "loguniform", 4647)
+    classes = synth.CLASS_LENGTHS
+    got = lib.length_classes(bank, fs, f_low, classes)
+    want = [classes.index(O.length_class(m1, m2, f_low, fs, classes)) for m1, m2 in bank]
+    assert got.tolist() == want
+    # m1 < m2 order does not matter
+    assert np.array_equal(lib.length_classes(bank[:, ::-1], fs, f_low, classes), got)
+
+
+def test_length_classes_reject_bad_input(lib):
+    bank = np.array([[1.4, 1.4]])
+    for classes in ([], [3 << 16], [1 << 18, 1 << 17]):
+        with pytest.raises(ci.CiError) as e:
+            lib.length_classes(bank, 4096.0, 20.0, classes)
+        assert e.value.code == ci.EINVAL
+    with pytest.raises(ci.CiError):
+        lib.length_classes(np.array([[0.0, 1.4]]), 4096.0, 20.0, [1 << 17])
+    assert lib.length_classes(np.zeros((0, 2)), 4096.0, 20.0, [1 << 17]).shape == (0,)
