@@ -67,7 +67,33 @@ def parse():
                    help="arithmetic of the headline run")
     p.add_argument("--no-split", action="store_true",
                    help="skip the comparison runs at the other precisions")
+    p.add_argument("--no-autotune", action="store_true",
+                   help="keep the default launch configuration")
+    p.add_argument("--tune", default="",
+                   help="explicit launch configuration C,J,P2,BATCH (skips the autotuner)")
     return p.parse_args()
+
+
+def configure(ctx, ci, args, tune_calls):
+    """Launch configuration per (length, precision): explicit, autotuned
+    (tune_calls: [(seg, params, n, thr, window, log2n)]), or the default."""
+    out = {}
+    for prec_name, (prec, _) in PRECISIONS.items():
+        if args.no_split and prec_name != args.precision:
+            continue
+        for seg, params, n, thr, window, l2 in tune_calls:
+            if args.tune:
+                c, j, p2, b = (int(v) for v in args.tune.split(","))
+                ctx.set_tune(l2, prec, c, j, p2, b)
+                cfg = ctx.get_tune(l2, prec)
+            elif args.no_autotune:
+                cfg = ctx.get_tune(l2, prec)
+            else:
+                cfg = ctx.autotune(seg, params, thr, window, n=n, precision=prec)
+            out[f"{prec_name}/2^{l2}"] = {k: cfg[k] for k in
+                                          ("tile_c", "tile_j", "p2_per_cu", "batch", "tuned")}
+            log(f"[bench] launch configuration {prec_name} 2^{l2}: {out[f'{prec_name}/2^{l2}']}")
+    return out
 
 
 def inject_on_gpu(ctx, seg, xt, wl, injs):
@@ -137,6 +163,95 @@ def cpu_baseline(xt_host, psd, wl, bank, budget_s):
                       f"FP64 numpy, one thread, {el:.1f} s"}
 
 
+def run_classes(args, lib, ctx, wl):
+    """The uneven bank in length classes: one segment per class, the whole
+    schedule in one multi-class search per step."""
+    import torch
+    from paper_1006_4644_amd import ci, synth
+    bank = synth.draw_masses(wl.n_templates, wl.m_min, wl.m_max, wl.dist, wl.bank_seed)
+    classes = synth.CLASS_LENGTHS
+    cls = lib.length_classes(bank, wl.fs, wl.f_low, classes)
+    dev = torch.device("cuda", 0)
+    cap = 1 << 16
+    inputs, jobs, tune_calls, sizes = [], [], [], {}
+    for c, n in enumerate(classes):
+        idx = np.nonzero(cls == c)[0]
+        if len(idx) == 0:
+            continue
+        psd = synth.make_psd(n, wl.fs)
+        x = synth.make_noise(n, wl.fs, wl.f_low, psd, synth.class_noise_seed(wl, c))
+        psd_d = torch.from_numpy(psd).cuda()
+        xt = torch.from_numpy(x.astype(np.complex64)).cuda()
+        seg = ctx.segment(xt, psd_d, n, wl.fs, wl.f_low)
+        params = torch.empty((len(idx), 96), dtype=torch.uint8, device=dev)
+        ctx.gen_templates(seg, bank[idx], out=params)
+        jobs.append(dict(seg=seg, params=params, n=len(idx), cap=cap,
+                         peaks=torch.empty((len(idx), 4), dtype=torch.int64, device=dev),
+                         trig=torch.empty((cap, 4), dtype=torch.int64, device=dev),
+                         count=torch.zeros(1, dtype=torch.int64, device=dev)))
+        inputs.append((seg, xt, psd_d, bank[idx], params))
+        tune_calls.append((seg, params, min(len(idx), 2048), wl.snr_threshold, wl.window,
+                           n.bit_length() - 1))
+        sizes[f"2^{n.bit_length() - 1}"] = int(len(idx))
+    log(f"[bench] workload {wl.name}: classes {sizes}")
+    tune_cfg = configure(ctx, ci, args, tune_calls)
+    alg_bytes = sum(16.0 * jb["seg"].n * jb["n"] for jb in jobs)
+
+    def step(prec):
+        for seg, xt, psd_d, b, params in inputs:
+            ctx.segment_update(seg, xt, psd_d)
+            ctx.gen_templates(seg, b, out=params)
+        ctx.search_classes(jobs, wl.snr_threshold, wl.window, merge=True, precision=prec)
+
+    def timed(prec, tag):
+        for _ in range(args.warmup):
+            step(prec)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(args.steps):
+            step(prec)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / args.steps
+        v = wl.n_templates / (ms / 1e3)
+        gbs = alg_bytes / (ms / 1e3) / 1e9
+        log(f"[bench] {tag}: {ms:.3f} ms/step, {v:.0f} templates/s, {gbs:.0f} GB/s")
+        return ms, v, gbs
+
+    prec_code, dtype = PRECISIONS[args.precision]
+    ms, value, gbs = timed(prec_code, args.precision)
+    out = {
+        "metric": METRIC, "value": round(value, 1), "unit": "templates/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": dtype, "data": "synthetic",
+        "config": {"workload": wl.name, "classes": sizes, "fs": wl.fs, "f_low": wl.f_low,
+                   "templates": wl.n_templates,
+                   "masses": f"{wl.dist} [{wl.m_min}, {wl.m_max}]",
+                   "snr_threshold": wl.snr_threshold, "window": wl.window, "merge": True,
+                   "precision": args.precision},
+        "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "whole schedule (sum of 16 n_c bytes per template)"},
+        "launch_config": tune_cfg,
+    }
+    if not args.no_split:
+        paths = {}
+        for tag, (prec, _) in PRECISIONS.items():
+            if tag == args.precision:
+                continue
+            ms2, v2, gbs2 = timed(prec, tag)
+            paths[tag] = {"value": round(v2, 1), "ms_per_step": round(ms2, 4),
+                          "speedup_vs_headline": round(v2 / value, 3),
+                          "path_hbm_frac": round(gbs2 / HBM_PEAK_GBS, 4)}
+        out["precision_paths"] = paths
+    for seg, *_ in inputs:
+        seg.close()
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -153,6 +268,8 @@ def main():
     if args.batch:
         ctx.set_batch(args.batch)
     wl = synth.WORKLOADS[args.workload]
+    if wl.name == "batched-classes":
+        return run_classes(args, lib, ctx, wl)
     bank = synth.draw_masses(wl.n_templates, wl.m_min, wl.m_max, wl.dist, wl.bank_seed)
     injs = synth.draw_injections(wl, bank)
     psd = synth.make_psd(wl.n, wl.fs)
@@ -170,6 +287,10 @@ def main():
     trig = torch.empty((cap, 4), dtype=torch.int64, device=device)
     count = torch.zeros(1, dtype=torch.int64, device=device)
     log(f"[bench] workload {wl.name}: n={wl.n}, {n_t} templates, {len(injs)} injections")
+    ctx.gen_templates(seg, bank, out=params)
+    n_tune = min(n_t, 2048)
+    tune_cfg = configure(ctx, ci, args, [(seg, params, n_tune, wl.snr_threshold, wl.window,
+                                          wl.n.bit_length() - 1)])
 
     def step(precision):
         ctx.segment_update(seg, xt, psd_d)
@@ -240,6 +361,7 @@ def main():
                      "frac": round(path_gbs / HBM_PEAK_GBS, 4)},
         "kernels_ms_per_step": {k: round(v[2] / args.steps, 4) for k, v in kt.items()},
         "merged_windows": nwin_found,
+        "launch_config": tune_cfg,
     }
     if not args.no_split:
         # the other arithmetic paths on the same workload; accuracy against

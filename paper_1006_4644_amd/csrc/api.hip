@@ -198,6 +198,16 @@ int check_filter_args(Ctx* ctx, const void* seg, const ci_tparams* d_params, int
   return CI_OK;
 }
 
+// CI_EUNSUPPORTED when the tiles of `p` do not fit the LDS at `precision`.
+int check_plan(Ctx* ctx, const Plan& p, int32_t precision) {
+  const hipError_t e = plan_fits(p, precision);
+  if (e == hipErrorInvalidConfiguration)
+    return fail(ctx, CI_EUNSUPPORTED, "tiles %d x %d at n = 2^%d exceed the LDS at precision %d",
+                p.c, p.j, p.log2n, precision);
+  if (e != hipSuccess) return hipfail(ctx, e, "kernel attributes");
+  return CI_OK;
+}
+
 hipEvent_t pool_event(Ctx* ctx) {
   if (!ctx->ev_pool.empty()) {
     hipEvent_t e = ctx->ev_pool.back();
@@ -276,6 +286,8 @@ int check_job(Ctx* ctx, Job& jb, int32_t precision, float thr, int64_t window) {
   const int l2 = jb.seg->plan.log2n;
   jb.cfg = ctx->tune[l2][precision];
   jb.plan = plan_for(l2, jb.cfg.c, jb.cfg.j);
+  rc = check_plan(ctx, jb.plan, precision);
+  if (rc != CI_OK) return rc;
   jb.nwin = (N + window - 1) / window;
   int64_t B = ctx->batch_override > 0 ? ctx->batch_override
               : jb.cfg.batch > 0      ? jb.cfg.batch
@@ -696,6 +708,8 @@ int ci_matched_filter(ci_ctx* ctx, const ci_segment* seg, const ci_tparams* d_pa
     const Tune& t = ctx->tune[seg->plan.log2n][precision];
     a.plan = plan_for(seg->plan.log2n, t.c, t.j);
   }
+  rc = check_plan(ctx, a.plan, precision);
+  if (rc != CI_OK) return rc;
   a.bmax = (int)B;
   a.precision = precision;
   for (int64_t b = 0, t0 = 0; t0 < n; ++b, t0 += B) {
@@ -718,6 +732,8 @@ int ci_find_triggers(ci_ctx* ctx, const ci_segment* seg, const ci_tparams* d_par
                      int64_t j_hi, ci_trigger* d_peaks, ci_trigger* d_trig, int64_t cap,
                      int64_t* d_count, int32_t merge_across_templates, void* stream) {
   if (!ctx) return fail(nullptr, CI_EINVAL, "null context");
+  DeviceGuard dg(ctx->device);
+  if (!dg.ok) return fail(ctx, CI_EHIP, "cannot select device %d", ctx->device);
   std::vector<Job> jobs(1);
   Job& jb = jobs[0];
   jb.seg = seg;
@@ -731,8 +747,6 @@ int ci_find_triggers(ci_ctx* ctx, const ci_segment* seg, const ci_tparams* d_par
   jb.count = d_count;
   int rc = check_job(ctx, jb, precision, snr_threshold, window);
   if (rc != CI_OK) return rc;
-  DeviceGuard dg(ctx->device);
-  if (!dg.ok) return fail(ctx, CI_EHIP, "cannot select device %d", ctx->device);
   size_t slot = 0;
   rc = prepare_jobs(ctx, jobs, &slot);
   if (rc != CI_OK) return rc;
@@ -750,6 +764,8 @@ int ci_search_classes(ci_ctx* ctx, const ci_class_job* jobs_in, int32_t njobs, i
     return fail(ctx, CI_EUNSUPPORTED,
                 "graph replay of the schedule is disabled (a capture of a multi-batch "
                 "schedule ended the process in the runtime; cause not identified)");
+  DeviceGuard dg(ctx->device);
+  if (!dg.ok) return fail(ctx, CI_EHIP, "cannot select device %d", ctx->device);
   std::vector<Job> jobs((size_t)njobs);
   for (int32_t i = 0; i < njobs; ++i) {
     const ci_class_job& in = jobs_in[i];
@@ -767,8 +783,6 @@ int ci_search_classes(ci_ctx* ctx, const ci_class_job* jobs_in, int32_t njobs, i
     if (rc != CI_OK) return fail(ctx, rc, "job %d: %s", i, ctx->err.c_str());
   }
   if (njobs == 0) return CI_OK;
-  DeviceGuard dg(ctx->device);
-  if (!dg.ok) return fail(ctx, CI_EHIP, "cannot select device %d", ctx->device);
   size_t slot = 0;
   int rc = prepare_jobs(ctx, jobs, &slot);
   if (rc != CI_OK) return rc;
@@ -836,6 +850,12 @@ int ci_set_tune(ci_ctx* ctx, const ci_tune* cfg) {
     return fail(ctx, CI_EINVAL, "p2_per_cu %d outside 0..8", cfg->p2_per_cu);
   if (cfg->batch < 0 || cfg->batch > 4096)
     return fail(ctx, CI_EINVAL, "batch %lld outside 0..4096", (long long)cfg->batch);
+  {
+    DeviceGuard dg(ctx->device);
+    if (!dg.ok) return fail(ctx, CI_EHIP, "cannot select device %d", ctx->device);
+    const int rc = check_plan(ctx, plan_for(cfg->log2n, cfg->tile_c, cfg->tile_j), cfg->precision);
+    if (rc != CI_OK) return rc;
+  }
   Tune& t = ctx->tune[cfg->log2n][cfg->precision];
   t.c = cfg->tile_c;
   t.j = cfg->tile_j;
@@ -945,6 +965,7 @@ int ci_autotune(ci_ctx* ctx, const ci_segment* seg, const ci_tparams* d_params, 
     c.c = tiles[i][0];
     c.j = tiles[i][1];
     if (c.c == best.c && c.j == best.j) continue;
+    if (plan_fits(plan_for(l2, c.c, c.j), precision) != hipSuccess) continue;
     float ms = 0.f;
     bool same = false;
     rc = trial(c, &ms, &same);

@@ -148,5 +148,8 @@ hipError_t launch_pass1(const BatchArgs& a, bool zero_trig, hipStream_t st);
 hipError_t launch_pass2_trig(const BatchArgs& a, hipStream_t st);
 hipError_t launch_pass2_series(const BatchArgs& a, hipStream_t st);
 hipError_t launch_fin(const BatchArgs& a, hipStream_t st);
+// hipSuccess when every kernel of a search with this plan and precision
+// fits the per-workgroup LDS limit, hipErrorInvalidConfiguration when not.
+hipError_t plan_fits(const Plan& p, int precision);
 
 }  // namespace ci

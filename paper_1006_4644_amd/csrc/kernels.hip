@@ -1195,8 +1195,52 @@ P2Args make_p2(const BatchArgs& a) {
   return p;
 }
 
+// Whether a kernel's dynamic plus static LDS fits one workgroup's limit.
+template <typename K>
+hipError_t lds_fits(K kern, size_t dyn) {
+  hipFuncAttributes fa;
+  hipError_t e = hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(kern));
+  if (e != hipSuccess) return e;
+  int dev = 0, lim = 0;
+  e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&lim, hipDeviceAttributeSharedMemPerBlockOptin, dev);
+  if (e != hipSuccess) return e;
+  return dyn + fa.sharedSizeBytes <= (size_t)lim ? hipSuccess : hipErrorInvalidConfiguration;
+}
+
 template <int N1, int N2, int C, int J>
 struct Inst {
+  // every kernel a search (trigger or series mode) launches fits
+  static hipError_t fits(int precision) {
+    // per instantiation and precision: 0 unknown, else the cached answer
+    static hipError_t known[3] = {hipSuccess, hipSuccess, hipSuccess};
+    static bool have[3] = {false, false, false};
+    if (precision < 0 || precision > 2) return hipErrorInvalidValue;
+    if (have[precision]) return known[precision];
+    hipError_t e;
+    if (precision == CI_FP32) {
+      e = lds_fits(k_pass1<N1, N2, C>, (size_t)Col<N2, C>::LDS_ELEMS * sizeof(float2));
+      if (e == hipSuccess)
+        e = lds_fits(k_pass2_trig<N1, N2, C, J>,
+                     (size_t)(Col<N1, J>::LDS_ELEMS + N1) * sizeof(float2));
+      if (e == hipSuccess)
+        e = lds_fits(k_pass2_series<N1, N2, C, J>, (size_t)Col<N1, J>::LDS_ELEMS * sizeof(float2));
+    } else if (precision == CI_SPLIT_BF16) {
+      e = lds_fits(k_pass1_mx<N1, N2, C, kBF16>, (size_t)10 * C * N2);
+      if (e == hipSuccess) e = lds_fits(k_pass2_mx<N1, N2, C, J, kBF16, 0>, (size_t)10 * J * N1);
+      if (e == hipSuccess) e = lds_fits(k_pass2_mx<N1, N2, C, J, kBF16, 1>, (size_t)10 * J * N1);
+    } else {
+      e = lds_fits(k_pass1_mx<N1, N2, C, kFP16>, (size_t)10 * C * N2);
+      if (e == hipSuccess) e = lds_fits(k_pass2_mx<N1, N2, C, J, kFP16, 0>, (size_t)10 * J * N1);
+      if (e == hipSuccess) e = lds_fits(k_pass2_mx<N1, N2, C, J, kFP16, 1>, (size_t)10 * J * N1);
+    }
+    if (e == hipSuccess) e = lds_fits(k_fin<N1, N2, C>, kFinLds);
+    if (e == hipSuccess || e == hipErrorInvalidConfiguration) {
+      known[precision] = e;
+      have[precision] = true;
+    }
+    return e;
+  }
   static hipError_t p1(const BatchArgs& a, bool zero, hipStream_t st) {
     const size_t lds = (size_t)Col<N2, C>::LDS_ELEMS * sizeof(float2);
     auto kern = k_pass1<N1, N2, C>;
@@ -1306,6 +1350,9 @@ hipError_t launch_pass2_trig(const BatchArgs& a, hipStream_t st) {
     if (a.precision == CI_SPLIT_FP16) return I::template p2mx<kFP16, 0>(a, st);
     return I::p2t(a, st);
   });
+}
+hipError_t plan_fits(const Plan& p, int precision) {
+  return dispatch(p, [&](auto inst) { return decltype(inst)::fits(precision); });
 }
 hipError_t launch_fin(const BatchArgs& a, hipStream_t st) {
   return dispatch(a.plan, [&](auto inst) { return decltype(inst)::fin(a, st); });

@@ -223,3 +223,24 @@ def test_batched_classes_workload(ctx, gpu_lib):
             C.check_peak(P[i], zo)
     for s in setup:
         s["seg"].close()
+
+
+def test_tiles_beyond_lds_are_refused(ctx):
+    """At 2^21 the matrix-core second pass with 8 columns per workgroup needs
+    more LDS than a workgroup has: refused, and skipped by the autotuner."""
+    with pytest.raises(ci.CiError) as e:
+        ctx.set_tune(21, ci.SPLIT_BF16, 4, 8)
+    assert e.value.code == ci.EUNSUPPORTED
+    assert ctx.get_tune(21, ci.SPLIT_BF16)["tile_j"] == 4
+    ctx.set_tune(21, ci.FP32, 8, 8)          # the FP32 kernels fit
+    ctx.set_tune(21, ci.FP32)
+    fs, fl, n = 4096.0, 20.0, 1 << 21
+    psd = synth.make_psd(n, fs)
+    x = synth.make_noise(n, fs, fl, psd, 2121).astype(np.complex64)
+    seg = ctx.segment(_dev(x), _dev(psd), n, fs, fl)
+    params = ctx.gen_templates(seg, synth.draw_masses(6, 1.0, 10.0, "loguniform", 21))
+    cfg = ctx.autotune(seg, params, 6.0, 4096, precision=ci.SPLIT_BF16)
+    print("autotune 2^21 split-bf16:", cfg)
+    assert cfg["rejected"] == 0 and not (cfg["tile_j"] == 8)
+    ctx.set_tune(21, ci.SPLIT_BF16)
+    seg.close()
