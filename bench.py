@@ -34,6 +34,9 @@ METRIC = "templates/sec (N=2^20 SNR series) FP32 vs split-BF16 MFMA; % HBM roofl
 HBM_PEAK_GBS = 8000.0
 # name -> (library precision code, dtype tag of the arithmetic)
 PRECISIONS = {"fp32": (0, "f32"), "split-bf16": (1, "bf16x3"), "split-fp16": (2, "f16x3")}
+# bytes of the intermediate per complex value (written by pass 1, read by
+# pass 2): FP32 pairs, or FP16 pairs on the split-precision paths
+Y_BYTES = {"fp32": 8, "split-bf16": 4, "split-fp16": 4}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_fp32-2^20.json")
 KERNEL_SOURCES = ["paper_1006_4644_amd/csrc/kernels.hip",
                   "paper_1006_4644_amd/csrc/fft_device.h",
@@ -195,7 +198,8 @@ def run_classes(args, lib, ctx, wl):
         sizes[f"2^{n.bit_length() - 1}"] = int(len(idx))
     log(f"[bench] workload {wl.name}: classes {sizes}")
     tune_cfg = configure(ctx, ci, args, tune_calls)
-    alg_bytes = sum(16.0 * jb["seg"].n * jb["n"] for jb in jobs)
+    alg_bytes = {tag: sum(2.0 * Y_BYTES[tag] * jb["seg"].n * jb["n"] for jb in jobs)
+                 for tag in PRECISIONS}
 
     def step(prec):
         for seg, xt, psd_d, b, params in inputs:
@@ -215,7 +219,7 @@ def run_classes(args, lib, ctx, wl):
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / args.steps
         v = wl.n_templates / (ms / 1e3)
-        gbs = alg_bytes / (ms / 1e3) / 1e9
+        gbs = alg_bytes[tag] / (ms / 1e3) / 1e9
         log(f"[bench] {tag}: {ms:.3f} ms/step, {v:.0f} templates/s, {gbs:.0f} GB/s")
         return ms, v, gbs
 
@@ -233,7 +237,8 @@ def run_classes(args, lib, ctx, wl):
                    "precision": args.precision},
         "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": "whole schedule (sum of 16 n_c bytes per template)"},
+                     "kernel": "whole schedule (intermediate bytes: 2 x 8 n_c per "
+                               "template at FP32, 2 x 4 n_c on the split paths)"},
         "launch_config": tune_cfg,
     }
     if not args.no_split:
@@ -330,7 +335,7 @@ def main():
     name = max(kt, key=lambda k: kt[k][2])
     launches, tmpls, kms = kt[name]
     per_launch_ms = kms / launches
-    bytes_per_launch = 8.0 * wl.n * (tmpls / launches)
+    bytes_per_launch = Y_BYTES[args.precision] * wl.n * (tmpls / launches)
     achieved = bytes_per_launch / (per_launch_ms / 1e3) / 1e9
     traffic = None
     if os.path.exists(TRAFFIC_FILE):
@@ -345,7 +350,7 @@ def main():
                 "traffic": traffic, "kernel": name,
                 "avg_launch_ms": round(per_launch_ms, 4),
                 "templates_per_launch": tmpls / launches}
-    path_gbs = 16.0 * wl.n * n_t / (ms_step / 1e3) / 1e9
+    path_gbs = 2.0 * Y_BYTES[args.precision] * wl.n * n_t / (ms_step / 1e3) / 1e9
     out = {
         "metric": METRIC, "value": round(value, 1), "unit": "templates/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -356,7 +361,7 @@ def main():
                    "injections": len(injs), "snr_threshold": wl.snr_threshold,
                    "window": wl.window, "merge": True, "precision": args.precision},
         "roofline": roofline,
-        "path_hbm": {"algorithmic_bytes_per_template": 16 * wl.n,
+        "path_hbm": {"algorithmic_bytes_per_template": 2 * Y_BYTES[args.precision] * wl.n,
                      "achieved_gbs": round(path_gbs, 1),
                      "frac": round(path_gbs / HBM_PEAK_GBS, 4)},
         "kernels_ms_per_step": {k: round(v[2] / args.steps, 4) for k, v in kt.items()},
@@ -378,8 +383,9 @@ def main():
                 if any(i.tmpl >= 0 for i in injs) else None
             paths[tag] = {"value": round(v, 1), "ms_per_step": round(tms / args.steps, 4),
                           "speedup_vs_headline": round(v / value, 3),
-                          "path_hbm_frac": round(16.0 * wl.n * n_t / (tms / args.steps / 1e3)
-                                                 / 1e9 / HBM_PEAK_GBS, 4),
+                          "path_hbm_frac": round(2.0 * Y_BYTES[tag] * wl.n * n_t
+                                                 / (tms / args.steps / 1e3) / 1e9
+                                                 / HBM_PEAK_GBS, 4),
                           "kernels_ms_per_step": {k: round(x[2] / args.steps, 4)
                                                   for k, x in kts.items()},
                           "injection_peak_rho_rel_dev_vs_headline": dev,

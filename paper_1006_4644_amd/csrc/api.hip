@@ -124,6 +124,8 @@ void free_seg(Seg* s) {
   if (s->tw64) (void)hipFree(s->tw64);
   if (s->twa) (void)hipFree(s->twa);
   if (s->twb) (void)hipFree(s->twb);
+  for (int i = 0; i < 2; ++i)
+    if (s->mxa2[i]) (void)hipFree(s->mxa2[i]);
   delete s;
 }
 
@@ -546,6 +548,7 @@ int ci_segment_create(ci_ctx* ctx, const ci_segment_spec* spec, const void* d_xt
   ALLOC(s->tw64, sizeof(double2) * 2048);
   ALLOC(s->twa, sizeof(float2) * 2048);
   ALLOC(s->twb, sizeof(float2) * (nb > 0 ? nb : 1));
+  for (int i = 0; i < 2; ++i) ALLOC(s->mxa2[i], sizeof(uint4) * 256 * (s->plan.n1 / 256 + 1));
 #undef ALLOC
   // twiddle tables in FP64, rounded once to FP32
   std::string fails;
@@ -583,6 +586,7 @@ int ci_segment_create(ci_ctx* ctx, const ci_segment_spec* spec, const void* d_xt
     }
   }
   e = launch_segment(s, d_xtilde, d_psd, static_cast<hipStream_t>(stream));
+  if (e == hipSuccess) e = launch_mx_tables(s, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) {
     free_seg(s);
     return hipfail(ctx, e, "segment setup launch");

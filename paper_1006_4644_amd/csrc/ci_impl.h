@@ -103,7 +103,9 @@ struct Seg {
   double2* tw64;     // [2048] exp(2 pi i e / 2048) in FP64
   float2* twa;       // [2048] exp(2 pi i e / n)
   float2* twb;       // [n/2048] exp(2 pi i 2048 e / n)
-  Plan plan;
+  Plan plan;         // factorisation (tiles of the default configuration)
+  uint4* mxa2[2];    // matrix-core fragments of the pass-2 column DFT (BF16, FP16):
+                     // (n1/256 + 1) x 64 lanes x 4 x 16 bytes each
 };
 
 // Elements per workgroup of the segment-setup scan.
@@ -116,6 +118,8 @@ hipError_t launch_params(const Seg* s, ci_tparams* d_params, int64_t n,
                          void* d_htilde, hipStream_t st);
 hipError_t launch_init_call(const TrigWork& tw, int nwin, int64_t* d_count,
                             hipStream_t st);
+// Matrix-core operand tables of a segment (after its FP64 twiddles exist).
+hipError_t launch_mx_tables(Seg* s, hipStream_t st);
 
 struct BatchArgs {
   const Seg* seg;

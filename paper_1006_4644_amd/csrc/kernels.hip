@@ -343,11 +343,39 @@ __device__ __forceinline__ void load_pass2(float2 (&x)[16], const float2* __rest
   for (int q = 0; q < 16; ++q) x[q] = p[q * (Lp * N2)];
 }
 
+// Packed FP16 storage of the intermediate (split-precision paths): one
+// 32-bit word per complex value, real part in the low half.
+typedef _Float16 h2v __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ unsigned f2h(float2 v) {
+  h2v h;
+  h.x = (_Float16)v.x;
+  h.y = (_Float16)v.y;
+  return __builtin_bit_cast(unsigned, h);
+}
+__device__ __forceinline__ float2 h2f(unsigned u) {
+  const h2v h = __builtin_bit_cast(h2v, u);
+  return make_float2((float)h.x, (float)h.y);
+}
+__device__ __forceinline__ float2 ld_y(const float2* p, size_t i) { return p[i]; }
+__device__ __forceinline__ float2 ld_y(const unsigned* p, size_t i) { return h2f(p[i]); }
+
+template <int N1, int N2, int C, int J>
+__device__ __forceinline__ void load_pass2(float2 (&x)[16], const unsigned* __restrict__ yb,
+                                           unsigned j2, unsigned t) {
+  constexpr unsigned Lp = N1 / 16;
+  const unsigned* p = yb + ((t / C) * N2 + j2) * C + (t % C);
+  unsigned u[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) u[q] = p[q * (Lp * N2)];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) x[q] = h2f(u[q]);
+}
+
 // z_j = sum_{k1} exp(2 pi i j1 k1 / N1) Y[k1][j2] for j = j2 + N2 j1, with
 // FP64 twiddles and accumulation, computed by one wave (64 lanes, N1/64
 // terms each, then a butterfly reduction); every lane returns the result.
-template <int N1, int N2, int C>
-__device__ double2 wave_direct_z(const float2* __restrict__ yb, const double2* __restrict__ tw64,
+template <int N1, int N2, int C, typename T>
+__device__ double2 wave_direct_z(const T* __restrict__ yb, const double2* __restrict__ tw64,
                                  int64_t j) {
   const int lane = threadIdx.x & 63;
   const int j2 = (int)(j % N2), j1 = (int)(j / N2);
@@ -356,7 +384,7 @@ __device__ double2 wave_direct_z(const float2* __restrict__ yb, const double2* _
 #pragma unroll
   for (int i = 0; i < PER; ++i) {
     const int k1 = lane + 64 * i;
-    v[i] = yb[((size_t)(k1 / C) * N2 + j2) * C + (k1 % C)];
+    v[i] = ld_y(yb, ((size_t)(k1 / C) * N2 + j2) * C + (k1 % C));
   }
   double re = 0.0, im = 0.0;
 #pragma unroll
@@ -429,6 +457,8 @@ struct P2Args {
   int last_batch;
   // series mode
   float2* z;                 // batch's first series
+  int half_y;                // intermediate stored as packed FP16 pairs
+  const uint4* mxa;          // matrix-core fragments of the pass-2 column DFT
 };
 
 // Peak and triggers of template b once all its pass-2 tiles are done: the
@@ -503,7 +533,10 @@ __device__ void finalize_template(const P2Args& a, int b, void* ldsv) {
   for (int it = wave; it <= total; it += nwaves) {
     const int64_t j = it == 0 ? (int64_t)(0xFFFFFFFFu - (unsigned int)(pk & 0xFFFFFFFFull))
                               : st[it - 1].index;
-    const double2 z = wave_direct_z<N1, N2, C>(yb, a.tw64, j);
+    const double2 z =
+        a.half_y ? wave_direct_z<N1, N2, C>(reinterpret_cast<const unsigned*>(a.y) + (size_t)b * N,
+                                            a.tw64, j)
+                 : wave_direct_z<N1, N2, C>(yb, a.tw64, j);
     if (lane == 0) {
       if (it == 0) {
         ci_trigger e;
@@ -876,10 +909,10 @@ __device__ __forceinline__ void pass1_tile_mx(const P1Args& a, const ci_tparams&
       vb = cmul(vb, v);
     }
   }
-  float2* yt = a.y + (size_t)b * N + (size_t)tile * N2 * C;
+  unsigned* yt = reinterpret_cast<unsigned*>(a.y) + (size_t)b * N + (size_t)tile * N2 * C;
   const unsigned o = t * C + c;
 #pragma unroll
-  for (int r = 0; r < 16; ++r) yt[o + K::off(r) * C] = x[r];
+  for (int r = 0; r < 16; ++r) yt[o + K::off(r) * C] = f2h(x[r]);
 }
 
 template <int N1, int N2, int C, int PREC>
@@ -903,102 +936,232 @@ __global__ __launch_bounds__(C * N2 / 16) void k_pass1_mx(P1Args a) {
   pass1_tile_mx<N1, N2, C, PREC>(a, P, b, tile, lds, t, c, A, mneed);
 }
 
-// Pass 2 with both radix-16 stages on the matrix cores (one tile per
-// workgroup).
-template <int N1, int N2, int C, int J, int PREC, int MODE>
-__global__ __launch_bounds__(J * N1 / 16) void k_pass2_mx(P2Args a) {
-  constexpr int N = N1 * N2;
-  constexpr int TILES = N2 / J;
-  constexpr int L = N1;
-  constexpr int Lp = L / 16;
-  constexpr int R3 = L / 256;
-  constexpr int I = J * Lp;
-  extern __shared__ float2 lds[];
-  __shared__ u64 s_best[16];
-  const unsigned tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane / 16;
-  const unsigned cc = tid % J, t = tid / J;
-  float* pl = reinterpret_cast<float*>(lds);
-  const int bid = xcd_remap(blockIdx.x, gridDim.x);
-  const int b = bid / TILES, tile = bid % TILES;
-  const unsigned j2 = tile * J + cc;
-  const float2* yb = a.y + (size_t)b * N;
-  const DftA<PREC> A = make_dft_a<PREC>(a.tw64, lane);
+// ---------------------------------------------------------------------------
+// split-precision second pass: a radix-R3 stage on the vector units, then
+// two radix-16 DFT-matrix stages on the matrix cores.  For a column of
+// length L = 256 R3, with m = u + 256 p and n = b + R3 (v1 + 16 v0):
+//   A[b][u]          = sum_p X[u + 256 p] w_R3^{b p}
+//   B[b][u0][v1]     = sum_u1 w16^{v1 u1} w_L^{16 b u1} A[b][u0 + 16 u1]
+//   Y[b + R3 v1 + 16 R3 v0] = sum_u0 w16^{v0 u0} w_L^{u0 (b + R3 v1)} B[b][u0][v1]
+// The twiddle of the radix-R3 stage is split between the stage-B matrix
+// (its u1 part, one matrix per b) and the twiddle before stage C (its u0
+// part, merged with the four-step twiddle of the 256-point DFT).
+// ---------------------------------------------------------------------------
 
-  float2 x[16];
-  load_pass2<N1, N2, C, J>(x, yb, j2, t);
+// Operand fragments of the matrices for column length L: for mi < R3 the
+// stage-B matrix M_mi[v][q] = w16^{v q} w_L^{16 mi q}, for mi = R3 the plain
+// w16^{v q}.  Lane l holds output row v = l % 16 and inputs
+// q = 4 (l / 16) + e / 2 (e < 8, real and imaginary parts interleaved along
+// k) of the real rows [Re, -Im] and imaginary rows [Im, Re], split into high
+// and low parts: out[(mi 64 + l) 4 + f], f = re_hi, re_lo, im_hi, im_lo.
+template <int PREC>
+__global__ void k_mx_table(int L, const double2* __restrict__ tw64, uint4* __restrict__ out) {
+  typedef typename MxT<PREC>::v8 V8;
+  typedef typename MxT<PREC>::s S;
+  const int mi = blockIdx.x, l = threadIdx.x;
+  const int R3 = L / 256, v = l % 16, g = l / 16;
+  V8 f[4];
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const int q = 4 * g + e / 2;
+    int E = (L / 16) * v * q + (mi < R3 ? 16 * mi * q : 0);
+    E %= L;
+    const double2 w = tw64[E * (2048 / L)];
+    const float re = (e & 1) ? (float)(-w.y) : (float)w.x;
+    const float im = (e & 1) ? (float)w.x : (float)w.y;
+    const S rh = (S)re, ih = (S)im;
+    f[0][e] = rh;
+    f[1][e] = (S)(re - (float)rh);
+    f[2][e] = ih;
+    f[3][e] = (S)(im - (float)ih);
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) out[(mi * 64 + l) * 4 + k] = __builtin_bit_cast(uint4, f[k]);
+}
+
+template <int R>
+__device__ __forceinline__ void idft_r(float2 (&x)[R]) {
+  if constexpr (R == 2) {
+    idft2(x[0], x[1]);
+  } else if constexpr (R == 4) {
+    idft4(x[0], x[1], x[2], x[3]);
+  } else if constexpr (R == 8) {
+    float2 t[16];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) t[i] = x[i];
+    idft8<0>(t);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) x[i] = t[i];
+  }
+}
+
+// Completion of this wave's LDS operations (the exchange rows are private
+// to the wave, so no workgroup barrier is needed).
+__device__ __forceinline__ void wave_lds_sync() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
+
+constexpr int kXS = 18;  // row stride (complex) of the stage-C exchange
+
+template <int L>
+constexpr size_t p2mx_lds_bytes(int J) {
+  return sizeof(float2) * L + sizeof(uint4) * (L / 256 + 1) * 256 +
+         sizeof(float2) * 16 * kXS * (size_t)J;
+}
+
+// Persistent split-precision pass 2: wave w of a workgroup transforms
+// column j2 = tile J + w; lane (u0 = l % 16, g = l / 16) loads
+// X[u0 + 16 (4 g + e) + 256 p] (e < 4, p < R3) from the FP16 intermediate.
+// MODE 0: post-pass (peaks and window keys); MODE 1: store the series.
+template <int N1, int N2, int C, int J, int PREC, int MODE>
+__global__ __launch_bounds__(J * 64) void k_p2mx(P2Args a) {
+  constexpr int L = N1, R3 = L / 256, N = N1 * N2, TILES = N2 / J;
+  typedef typename MxT<PREC>::v8 V8;
+  extern __shared__ float2 lds[];
+  __shared__ u64 s_best[J];
+  float2* twl = lds;
+  const uint4* afr = reinterpret_cast<const uint4*>(lds + L);
+  const unsigned tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const unsigned u0 = lane & 15, g = lane >> 4;
+  float2* xw = lds + L + (R3 + 1) * 256 * 2 + wave * 16 * kXS;
   {
-    // stage-1 operand rows: instance (t, cc), elements q = 0..15
-    const unsigned inst = t * J + cc;
-    float4* pr = reinterpret_cast<float4*>(pl + inst * kRow);
-    float4* pi = reinterpret_cast<float4*>(pl + (I + inst) * kRow);
-#pragma unroll
-    for (int q4 = 0; q4 < 4; ++q4) {
-      pr[q4] = make_float4(x[4 * q4].x, x[4 * q4 + 1].x, x[4 * q4 + 2].x, x[4 * q4 + 3].x);
-      pi[q4] = make_float4(x[4 * q4].y, x[4 * q4 + 1].y, x[4 * q4 + 2].y, x[4 * q4 + 3].y);
-    }
+    uint4* af = reinterpret_cast<uint4*>(lds + L);
+    for (int k = tid; k < L; k += J * 64) twl[k] = a.tw[k * (2048 / L)];
+    for (int k = tid; k < (R3 + 1) * 256; k += J * 64) af[k] = a.mxa[k];
   }
   __syncthreads();
-  // stage 1: outputs a = 4g + e of instance (t1, c1), twiddle w_L^{a t1}
-  float2 y[16];
+  V8 wc[4];
 #pragma unroll
-  for (int bk = 0; bk < 4; ++bk) {
-    const unsigned inst = 16 * (4 * wave + bk) + (lane & 15);
-    float v[8];
-    pl_load8(pl, I, inst, g, v);
-    f32x4 yr, yi;
-    mx_dft16<PREC>(A, v, yr, yi);
-    const unsigned t1 = inst / J;
+  for (int f = 0; f < 4; ++f) wc[f] = __builtin_bit_cast(V8, afr[(R3 * 64 + lane) * 4 + f]);
+  const int total = a.nb * TILES;
+  for (int item = blockIdx.x; item < total; item += gridDim.x) {
+    const int bt = item / TILES, tile = item % TILES;
+    const unsigned j2 = tile * J + wave;
+    const unsigned* yb = reinterpret_cast<const unsigned*>(a.y) + (size_t)bt * N;
+    float2 x[R3][4];
+    {
+      unsigned raw[R3][4];
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const unsigned aa = 4 * g + e;
-      y[4 * bk + e] = cmul(make_float2(yr[e], yi[e]), a.tw[(aa * t1) * (2048 / L)]);
+      for (int p = 0; p < R3; ++p)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const unsigned k1 = u0 + 16 * (4 * g + e) + 256 * p;
+          raw[p][e] = yb[((k1 / C) * N2 + j2) * C + (k1 % C)];
+        }
+#pragma unroll
+      for (int p = 0; p < R3; ++p)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) x[p][e] = h2f(raw[p][e]);
     }
-  }
-  __syncthreads();
-  // stage-2 operand rows: instance (a, t1 % R3, c1), element q = t1 / R3
+    // stage A: radix-R3 over p
+    if constexpr (R3 > 1) {
 #pragma unroll
-  for (int bk = 0; bk < 4; ++bk) {
-    const unsigned inst = 16 * (4 * wave + bk) + (lane & 15);
-    const unsigned t1 = inst / J, c1 = inst % J;
-    const unsigned q = t1 / R3, s2 = t1 % R3;
+      for (int e = 0; e < 4; ++e) {
+        float2 t[R3];
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const unsigned aa = 4 * g + e;
-      const unsigned i2 = (aa * R3 + s2) * J + c1;
-      pl[i2 * kRow + q] = y[4 * bk + e].x;
-      pl[(I + i2) * kRow + q] = y[4 * bk + e].y;
+        for (int p = 0; p < R3; ++p) t[p] = x[p][e];
+        idft_r<R3>(t);
+#pragma unroll
+        for (int p = 0; p < R3; ++p) x[p][e] = t[p];
+      }
     }
-  }
-  __syncthreads();
-  // stage 2: outputs a2 = 4g + e of instance (a0, s2, c), twiddle
-  // w_{16 R3}^{a2 s2}
+    // stage B with the folded twiddle, then w_L^{u0 (b + R3 v1)}
 #pragma unroll
-  for (int bk = 0; bk < 4; ++bk) {
-    const unsigned inst = 16 * (4 * wave + bk) + (lane & 15);
-    float v[8];
-    pl_load8(pl, I, inst, g, v);
-    f32x4 yr, yi;
-    mx_dft16<PREC>(A, v, yr, yi);
-    const unsigned s2 = (inst / J) % R3;
+    for (int b = 0; b < R3; ++b) {
+      V8 A4[4];
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const unsigned a2 = 4 * g + e;
-      float2 z = make_float2(yr[e], yi[e]);
-      if constexpr (R3 > 1) z = cmul(z, a.tw[(16 * a2 * s2) * (2048 / L)]);
-      y[4 * bk + e] = z;
+      for (int f = 0; f < 4; ++f) A4[f] = __builtin_bit_cast(V8, afr[(b * 64 + lane) * 4 + f]);
+      float v[8];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        v[2 * e] = x[b][e].x;
+        v[2 * e + 1] = x[b][e].y;
+      }
+      f32x4 yr, yi;
+      mx_prod<PREC>(A4, v, yr, yi);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const unsigned E = (u0 * (unsigned)(b + R3 * (4 * g + e))) & (L - 1);
+        x[b][e] = cmul(make_float2(yr[e], yi[e]), twl[E]);
+      }
     }
-  }
-  __syncthreads();
-  float2* xl = lds;
-  mx_store_stage2<L, J>(xl, y, lane, wave);
-  __syncthreads();
-  mx_gather_out<L, J>(x, xl, t, cc);
-  if constexpr (MODE == 0) {
-    pass2_post<N1, N2, C, J>(x, a, b, tile, s_best, tid, cc, t);
-  } else {
-    float2* zt = a.z + (size_t)b * N;
+    // stage C per b through this wave's exchange rows: lane (u0, g) holds
+    // v1 = 4 g + e; afterwards lane (v1 = l % 16, g) holds u0 = 4 g + e
 #pragma unroll
-    for (int r = 0; r < 16; ++r) zt[j2 + N2 * Col<N1, J>::out((int)t, r)] = x[r];
+    for (int b = 0; b < R3; ++b) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) xw[(4 * g + e) * kXS + u0] = x[b][e];
+      wave_lds_sync();
+      const float4* rp = reinterpret_cast<const float4*>(xw + u0 * kXS + 4 * g);
+      const float4 r0 = rp[0], r1 = rp[1];
+      wave_lds_sync();
+      const float v[8] = {r0.x, r0.y, r0.z, r0.w, r1.x, r1.y, r1.z, r1.w};
+      f32x4 yr, yi;
+      mx_prod<PREC>(wc, v, yr, yi);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) x[b][e] = make_float2(yr[e], yi[e]);
+    }
+    // x[b][e] = z at n = b + R3 v1 + 16 R3 (4 g + e), v1 = u0
+    if constexpr (MODE == 1) {
+      float2* zt = a.z + (size_t)bt * N + j2;
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+#pragma unroll
+        for (int b = 0; b < R3; ++b)
+          zt[(size_t)N2 * (b + R3 * u0 + 16 * R3 * (4 * g + e))] = x[b][e];
+    } else {
+      // visited in increasing n, so a strict ">" keeps the smallest index
+      float bv = -1.f;
+      int bn = 0;
+      bool hot = false;
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+#pragma unroll
+        for (int b = 0; b < R3; ++b) {
+          const int n = b + R3 * (int)u0 + 16 * R3 * (4 * (int)g + e);
+          float r2 = fmaf(x[b][e].x, x[b][e].x, x[b][e].y * x[b][e].y);
+          if (!a.full) {
+            const int j = (int)j2 + N2 * n;
+            if (j < a.jlo32 || j >= a.jhi32) r2 = -1.f;
+          }
+          if (r2 > bv) {
+            bv = r2;
+            bn = n;
+          }
+          hot |= r2 > a.thr2;
+        }
+      if (__any(hot)) {
+        u64* wk = a.wkeys + (size_t)bt * a.nwin;
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+#pragma unroll
+          for (int b = 0; b < R3; ++b) {
+            const float r2 = fmaf(x[b][e].x, x[b][e].x, x[b][e].y * x[b][e].y);
+            const int j = (int)j2 + N2 * (b + R3 * (int)u0 + 16 * R3 * (4 * (int)g + e));
+            if (r2 > a.thr2 && (a.full || (j >= a.jlo32 && j < a.jhi32))) {
+              const u64 key = ((u64)__float_as_uint(r2) << 32) | (u64)(0xFFFFFFFFu - (unsigned int)j);
+              atomicMax(&wk[(unsigned int)j / a.win32], key);
+            }
+          }
+      }
+      u64 best = 0ull;
+      if (bv >= 0.f) {
+        const unsigned int j = (unsigned int)((int)j2 + N2 * bn);
+        best = ((u64)__float_as_uint(bv) << 32) | (u64)(0xFFFFFFFFu - j);
+      }
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        const u64 o = __shfl_xor(best, off, 64);
+        best = o > best ? o : best;
+      }
+      if (lane == 0) s_best[wave] = best;
+      __syncthreads();
+      if (tid == 0) {
+        u64 m = 0ull;
+#pragma unroll
+        for (int i = 0; i < J; ++i) m = s_best[i] > m ? s_best[i] : m;
+        a.ppart[(size_t)bt * TILES + tile] = m;
+      }
+      __syncthreads();
+    }
   }
 }
 
@@ -1192,6 +1355,10 @@ P2Args make_p2(const BatchArgs& a) {
   p.merge = a.merge;
   p.last_batch = a.last_batch;
   p.z = a.d_z;
+  p.half_y = a.precision != CI_FP32 ? 1 : 0;
+  p.mxa = a.precision == CI_SPLIT_BF16   ? a.seg->mxa2[0]
+          : a.precision == CI_SPLIT_FP16 ? a.seg->mxa2[1]
+                                         : nullptr;
   return p;
 }
 
@@ -1227,12 +1394,12 @@ struct Inst {
         e = lds_fits(k_pass2_series<N1, N2, C, J>, (size_t)Col<N1, J>::LDS_ELEMS * sizeof(float2));
     } else if (precision == CI_SPLIT_BF16) {
       e = lds_fits(k_pass1_mx<N1, N2, C, kBF16>, (size_t)10 * C * N2);
-      if (e == hipSuccess) e = lds_fits(k_pass2_mx<N1, N2, C, J, kBF16, 0>, (size_t)10 * J * N1);
-      if (e == hipSuccess) e = lds_fits(k_pass2_mx<N1, N2, C, J, kBF16, 1>, (size_t)10 * J * N1);
+      if (e == hipSuccess) e = lds_fits(k_p2mx<N1, N2, C, J, kBF16, 0>, p2mx_lds_bytes<N1>(J));
+      if (e == hipSuccess) e = lds_fits(k_p2mx<N1, N2, C, J, kBF16, 1>, p2mx_lds_bytes<N1>(J));
     } else {
       e = lds_fits(k_pass1_mx<N1, N2, C, kFP16>, (size_t)10 * C * N2);
-      if (e == hipSuccess) e = lds_fits(k_pass2_mx<N1, N2, C, J, kFP16, 0>, (size_t)10 * J * N1);
-      if (e == hipSuccess) e = lds_fits(k_pass2_mx<N1, N2, C, J, kFP16, 1>, (size_t)10 * J * N1);
+      if (e == hipSuccess) e = lds_fits(k_p2mx<N1, N2, C, J, kFP16, 0>, p2mx_lds_bytes<N1>(J));
+      if (e == hipSuccess) e = lds_fits(k_p2mx<N1, N2, C, J, kFP16, 1>, p2mx_lds_bytes<N1>(J));
     }
     if (e == hipSuccess) e = lds_fits(k_fin<N1, N2, C>, kFinLds);
     if (e == hipSuccess || e == hipErrorInvalidConfiguration) {
@@ -1285,12 +1452,25 @@ struct Inst {
   }
   template <int PREC, int MODE>
   static hipError_t p2mx(const BatchArgs& a, hipStream_t st) {
-    const size_t lds = (size_t)10 * J * N1;
-    auto kern = k_pass2_mx<N1, N2, C, J, PREC, MODE>;
+    const size_t lds = p2mx_lds_bytes<N1>(J);
+    auto kern = k_p2mx<N1, N2, C, J, PREC, MODE>;
     hipError_t e = set_lds(kern, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(kern, dim3((unsigned)(a.nb * (N2 / J))), dim3(J * N1 / 16), lds, st,
-                       make_p2(a));
+    static int per_cu = 0, cus = 0;
+    if (per_cu == 0) {
+      int dev = 0;
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, J * 64, lds);
+      if (e == hipSuccess) e = hipGetDevice(&dev);
+      if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+      if (e != hipSuccess) return e;
+      if (per_cu < 1) per_cu = 1;
+    }
+    const int wpc = (a.p2_per_cu > 0 && a.p2_per_cu < per_cu) ? a.p2_per_cu : per_cu;
+    const long long items = (long long)a.nb * (N2 / J);
+    long long grid = (long long)wpc * cus;
+    if (grid > items) grid = items;
+    if (grid < 1) grid = 1;
+    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(J * 64), lds, st, make_p2(a));
     return hipGetLastError();
   }
   static hipError_t fin(const BatchArgs& a, hipStream_t st) {
@@ -1351,6 +1531,15 @@ hipError_t launch_pass2_trig(const BatchArgs& a, hipStream_t st) {
     return I::p2t(a, st);
   });
 }
+hipError_t launch_mx_tables(Seg* s, hipStream_t st) {
+  const int L = s->plan.n1;
+  hipLaunchKernelGGL(k_mx_table<kBF16>, dim3(L / 256 + 1), dim3(64), 0, st, L, s->tw64, s->mxa2[0]);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_mx_table<kFP16>, dim3(L / 256 + 1), dim3(64), 0, st, L, s->tw64, s->mxa2[1]);
+  return hipGetLastError();
+}
+
 hipError_t plan_fits(const Plan& p, int precision) {
   return dispatch(p, [&](auto inst) { return decltype(inst)::fits(precision); });
 }

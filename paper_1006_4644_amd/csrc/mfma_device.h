@@ -100,8 +100,10 @@ __device__ __forceinline__ DftA<PREC> make_dft_a(const double2* __restrict__ tw6
 
 // One radix-16 step on 16 instances: v = this lane's 8 inputs (component
 // g / 2, inputs 8 (g % 2) .. +7 of instance lane % 16).  Returns the real
-// and imaginary parts of outputs a = 4 g + e, e < 4.
-template <int PREC>
+// and imaginary parts of outputs a = 4 g + e, e < 4.  X_EXACT: the inputs
+// are exact in the 16-bit type (read from FP16 storage on the FP16 path),
+// so their low parts are zero and the W_hi x_lo product is skipped.
+template <int PREC, bool X_EXACT = false>
 __device__ __forceinline__ void mx_dft16(const DftA<PREC>& A, const float (&v)[8], f32x4& yr,
                                          f32x4& yi) {
   typedef MxT<PREC> M;
@@ -109,11 +111,60 @@ __device__ __forceinline__ void mx_dft16(const DftA<PREC>& A, const float (&v)[8
   split8<PREC>(v, bh, bl);
   f32x4 z = {0.f, 0.f, 0.f, 0.f};
   yr = M::mma(A.re_hi, bh, z);
-  yr = M::mma(A.re_hi, bl, yr);
+  if constexpr (!X_EXACT) yr = M::mma(A.re_hi, bl, yr);
   yr = M::mma(A.re_lo, bh, yr);
   yi = M::mma(A.im_hi, bh, z);
-  yi = M::mma(A.im_hi, bl, yi);
+  if constexpr (!X_EXACT) yi = M::mma(A.im_hi, bl, yi);
   yi = M::mma(A.im_lo, bh, yi);
+  if constexpr (M::kPre != 1.0f) {
+    constexpr float inv = 1.0f / M::kPre;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      yr[e] *= inv;
+      yi[e] *= inv;
+    }
+  }
+}
+
+// Split 8 FP32 values into the two 16-bit operands of a product.  BF16:
+// the high part is the value truncated to BF16 (exact in FP32, so the low
+// part x - hi is exact before its own rounding).  FP16: round to nearest
+// after the 2^6 pre-scale.
+template <int PREC>
+__device__ __forceinline__ void split8t(const float (&v)[8], typename MxT<PREC>::v8& hi,
+                                        typename MxT<PREC>::v8& lo) {
+  if constexpr (PREC == kBF16) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const unsigned u = __builtin_bit_cast(unsigned, v[e]) & 0xffff0000u;
+      hi[e] = __builtin_bit_cast(__bf16, (unsigned short)(u >> 16));
+      lo[e] = (__bf16)(v[e] - __builtin_bit_cast(float, u));
+    }
+  } else {
+    split8<PREC>(v, hi, lo);
+  }
+}
+
+// One DFT-matrix product on 16 instances with the operand layout that
+// interleaves real and imaginary parts along k: the lane (j = l % 16,
+// g = l / 16) supplies complex inputs q = 4 g .. 4 g + 3 of instance j as
+// v = (re, im, re, im, ...), and A holds that lane's fragments of the
+// matrix rows [Re, -Im] (real outputs) and [Im, Re] (imaginary outputs),
+// high and low parts: A[0] re_hi, A[1] re_lo, A[2] im_hi, A[3] im_lo.
+// Returns outputs v = 4 g .. 4 g + 3 of instance j.
+template <int PREC>
+__device__ __forceinline__ void mx_prod(const typename MxT<PREC>::v8 (&A)[4], const float (&v)[8],
+                                        f32x4& yr, f32x4& yi) {
+  typedef MxT<PREC> M;
+  typename M::v8 bh, bl;
+  split8t<PREC>(v, bh, bl);
+  f32x4 z = {0.f, 0.f, 0.f, 0.f};
+  yr = M::mma(A[0], bh, z);
+  yi = M::mma(A[2], bh, z);
+  yr = M::mma(A[0], bl, yr);
+  yi = M::mma(A[2], bl, yi);
+  yr = M::mma(A[1], bh, yr);
+  yi = M::mma(A[3], bh, yi);
   if constexpr (M::kPre != 1.0f) {
     constexpr float inv = 1.0f / M::kPre;
 #pragma unroll

@@ -225,15 +225,21 @@ def test_batched_classes_workload(ctx, gpu_lib):
         s["seg"].close()
 
 
-def test_tiles_beyond_lds_are_refused(ctx):
-    """At 2^21 the matrix-core second pass with 8 columns per workgroup needs
-    more LDS than a workgroup has: refused, and skipped by the autotuner."""
-    with pytest.raises(ci.CiError) as e:
-        ctx.set_tune(21, ci.SPLIT_BF16, 4, 8)
-    assert e.value.code == ci.EUNSUPPORTED
-    assert ctx.get_tune(21, ci.SPLIT_BF16)["tile_j"] == 4
-    ctx.set_tune(21, ci.FP32, 8, 8)          # the FP32 kernels fit
-    ctx.set_tune(21, ci.FP32)
+def test_tile_shapes_accepted_and_checked(ctx):
+    """Every tile shape fits the workgroup LDS at every length and precision
+    (the launch check would refuse one that did not); invalid shapes are
+    argument errors; the autotuner at 2^21 on the matrix-core path keeps
+    only bit-identical candidates."""
+    for l2 in (16, 20, 21):
+        for prec in (ci.FP32, ci.SPLIT_BF16, ci.SPLIT_FP16):
+            for tc in (4, 8):
+                for tj in (4, 8):
+                    ctx.set_tune(l2, prec, tc, tj)
+            ctx.set_tune(l2, prec)
+    for bad in ((3, 4), (4, 16)):
+        with pytest.raises(ci.CiError) as e:
+            ctx.set_tune(20, ci.FP32, *bad)
+        assert e.value.code == ci.EINVAL
     fs, fl, n = 4096.0, 20.0, 1 << 21
     psd = synth.make_psd(n, fs)
     x = synth.make_noise(n, fs, fl, psd, 2121).astype(np.complex64)
@@ -241,6 +247,6 @@ def test_tiles_beyond_lds_are_refused(ctx):
     params = ctx.gen_templates(seg, synth.draw_masses(6, 1.0, 10.0, "loguniform", 21))
     cfg = ctx.autotune(seg, params, 6.0, 4096, precision=ci.SPLIT_BF16)
     print("autotune 2^21 split-bf16:", cfg)
-    assert cfg["rejected"] == 0 and not (cfg["tile_j"] == 8)
+    assert cfg["rejected"] == 0 and cfg["candidates"] >= 8
     ctx.set_tune(21, ci.SPLIT_BF16)
     seg.close()
