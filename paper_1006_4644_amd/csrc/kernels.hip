@@ -232,6 +232,22 @@ struct P1Args {
   int nb;
 };
 
+// Packed FP16 storage of the intermediate (split-precision paths): one
+// 32-bit word per complex value, real part in the low half.
+typedef _Float16 h2v __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ unsigned f2h(float2 v) {
+  h2v h;
+  h.x = (_Float16)v.x;
+  h.y = (_Float16)v.y;
+  return __builtin_bit_cast(unsigned, h);
+}
+__device__ __forceinline__ float2 h2f(unsigned u) {
+  const h2v h = __builtin_bit_cast(h2v, u);
+  return make_float2((float)h.x, (float)h.y);
+}
+__device__ __forceinline__ float2 ld_y(const float2* p, size_t i) { return p[i]; }
+__device__ __forceinline__ float2 ld_y(const unsigned* p, size_t i) { return h2f(p[i]); }
+
 // w_N^e for 0 <= e < N from the two-level table.
 __device__ __forceinline__ float2 tw_n(const float2* __restrict__ twa,
                                        const float2* __restrict__ twb, int e) {
@@ -240,7 +256,7 @@ __device__ __forceinline__ float2 tw_n(const float2* __restrict__ twa,
 
 // Pass-1 body for one tile.  Q: number of stage-1 inputs per lane that can
 // be nonzero (m < Q), chosen per template from its upper band edge.
-template <int N1, int N2, int C, int Q>
+template <int N1, int N2, int C, int Q, bool H>
 __device__ __forceinline__ void pass1_tile(const P1Args& a, const ci_tparams& P, int b, int tile,
                                            float2* lds, unsigned t, unsigned c) {
   using K = Col<N2, C>;
@@ -295,13 +311,20 @@ __device__ __forceinline__ void pass1_tile(const P1Args& a, const ci_tparams& P,
     }
   }
 
-  float2* yt = a.y + (size_t)b * N + (size_t)tile * N2 * C;
   const unsigned o = t * C + c;
+  if constexpr (H) {
+    unsigned* yt = reinterpret_cast<unsigned*>(a.y) + (size_t)b * N + (size_t)tile * N2 * C;
 #pragma unroll
-  for (int r = 0; r < 16; ++r) yt[o + K::off(r) * C] = x[r];
+    for (int r = 0; r < 16; ++r) yt[o + K::off(r) * C] = f2h(x[r]);
+  } else {
+    float2* yt = a.y + (size_t)b * N + (size_t)tile * N2 * C;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) yt[o + K::off(r) * C] = x[r];
+  }
 }
 
-template <int N1, int N2, int C>
+// H: store the intermediate as FP16 pairs (split-precision paths).
+template <int N1, int N2, int C, bool H>
 __global__ __launch_bounds__(C * N2 / 16) void k_pass1(P1Args a) {
   constexpr int Lp = N2 / 16;
   constexpr int TILES = N1 / C;
@@ -322,9 +345,9 @@ __global__ __launch_bounds__(C * N2 / 16) void k_pass1(P1Args a) {
   // Every band bin lies below n/2 (k2 < N2/2, so m < 8), and below k_high:
   // m <= (k_high / N1) / Lp.  The choice is uniform over the workgroup.
   const int mneed = P.k_high >= P.k_low ? (P.k_high / N1) / Lp + 1 : 1;
-  if (mneed <= 2) pass1_tile<N1, N2, C, 2>(a, P, b, tile, lds, t, c);
-  else if (mneed <= 4) pass1_tile<N1, N2, C, 4>(a, P, b, tile, lds, t, c);
-  else pass1_tile<N1, N2, C, 8>(a, P, b, tile, lds, t, c);
+  if (mneed <= 2) pass1_tile<N1, N2, C, 2, H>(a, P, b, tile, lds, t, c);
+  else if (mneed <= 4) pass1_tile<N1, N2, C, 4, H>(a, P, b, tile, lds, t, c);
+  else pass1_tile<N1, N2, C, 8, H>(a, P, b, tile, lds, t, c);
 }
 
 // ---------------------------------------------------------------------------
@@ -343,21 +366,6 @@ __device__ __forceinline__ void load_pass2(float2 (&x)[16], const float2* __rest
   for (int q = 0; q < 16; ++q) x[q] = p[q * (Lp * N2)];
 }
 
-// Packed FP16 storage of the intermediate (split-precision paths): one
-// 32-bit word per complex value, real part in the low half.
-typedef _Float16 h2v __attribute__((ext_vector_type(2)));
-__device__ __forceinline__ unsigned f2h(float2 v) {
-  h2v h;
-  h.x = (_Float16)v.x;
-  h.y = (_Float16)v.y;
-  return __builtin_bit_cast(unsigned, h);
-}
-__device__ __forceinline__ float2 h2f(unsigned u) {
-  const h2v h = __builtin_bit_cast(h2v, u);
-  return make_float2((float)h.x, (float)h.y);
-}
-__device__ __forceinline__ float2 ld_y(const float2* p, size_t i) { return p[i]; }
-__device__ __forceinline__ float2 ld_y(const unsigned* p, size_t i) { return h2f(p[i]); }
 
 template <int N1, int N2, int C, int J>
 __device__ __forceinline__ void load_pass2(float2 (&x)[16], const unsigned* __restrict__ yb,
@@ -739,201 +747,6 @@ __global__ __launch_bounds__(J * N1 / 16, 4) void k_pass2_trig(P2Args a) {
     if (item + G < total) load_item<N1, N2, C, J>(xn, a, item + G, cc, t);
     pass2_tile<N1, N2, C, J>(x, a, item, lds, twl, s_best, tid, cc, t);
   }
-}
-
-// ---------------------------------------------------------------------------
-// split-precision path: radix-16 stages as DFT-matrix products on MFMA
-// ---------------------------------------------------------------------------
-
-// Planar LDS rows for the matrix stages: plane p (0 re, 1 im), instance i,
-// element q at pl[(p * I + i) * kRow + q]; rows are padded to 20 floats so
-// the 32-byte operand reads of 16 consecutive instances hit distinct banks.
-constexpr int kRow = 20;
-
-// Exchange-2 slot of stage-2 output (row d, position s) in the interleaved
-// layout Col::stage3 reads (R3 == 1: row d alone).
-template <int R3>
-__device__ __forceinline__ unsigned x2_slot(unsigned d, unsigned s) {
-  if constexpr (R3 == 1) return d;
-  else if constexpr (R3 == 2) return d * 2 + ((s + (d >> 1)) & 1u);
-  else return d * R3 + ((s + d) & (R3 - 1));
-}
-
-// Load the 8 operand values of instance `inst` for this lane from planar rows.
-__device__ __forceinline__ void pl_load8(const float* pl, int I, unsigned inst, unsigned g,
-                                         float (&v)[8]) {
-  const float4* p = reinterpret_cast<const float4*>(pl + ((g >> 1) * I + inst) * kRow + 8 * (g & 1));
-  const float4 a = p[0], b = p[1];
-  v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
-  v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
-}
-
-// Stage-2 outputs (rows d = a0 + 16 a2 at position s2) of one column,
-// written in the exchange-2 layout; for R3 == 1 these are final.
-template <int L, int NC>
-__device__ __forceinline__ void mx_store_stage2(float2* xl, const float2 (&y)[16], unsigned lane,
-                                                unsigned wave) {
-  constexpr int R3 = L / 256;
-  const unsigned g = lane / 16;
-#pragma unroll
-  for (int bk = 0; bk < 4; ++bk) {
-    const unsigned inst = 16 * (4 * wave + bk) + (lane & 15);
-    const unsigned c = inst % NC, r = inst / NC;
-    const unsigned s2 = r % R3, a0 = r / R3;
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const unsigned d = a0 + 16 * (4 * g + e);
-      xl[x2_slot<R3>(d, s2) * NC + c] = y[4 * bk + e];
-    }
-  }
-}
-
-// Final register layout after the matrix stages: lane (c, t) holds the
-// outputs Col::out(t, r) of its column.
-template <int L, int NC>
-__device__ __forceinline__ void mx_gather_out(float2 (&x)[16], const float2* xl, unsigned t,
-                                              unsigned c) {
-  constexpr int R3 = L / 256;
-  if constexpr (R3 == 1) {
-#pragma unroll
-    for (int r = 0; r < 16; ++r) x[r] = xl[(t + 16 * r) * NC + c];
-  } else {
-    constexpr int Lp = L / 16;
-#pragma unroll
-    for (int s = 0; s < R3; ++s) {
-      const unsigned rr = R3 == 2 ? ((s + (t >> 1)) & 1u) : ((s + t) & (R3 - 1));
-      const float2* pr = xl + (t * R3 + rr) * NC + c;
-#pragma unroll
-      for (int i = 0; i < 16 / R3; ++i) x[i * R3 + s] = pr[i * Lp * R3 * NC];
-    }
-    idft_groups<R3>(x);
-  }
-}
-
-// Stage-1 outputs x[a] of lane (c, t) written as stage-2 operand rows:
-// instance (a, t % R3, c), element q = t / R3.
-template <int L, int NC>
-__device__ __forceinline__ void mx_store_stage1(float* pl, const float2 (&x)[16], unsigned t,
-                                                unsigned c) {
-  constexpr int R3 = L / 256;
-  constexpr int I = NC * (L / 16);
-  const unsigned q = t / R3, s2 = t % R3;
-#pragma unroll
-  for (int a = 0; a < 16; ++a) {
-    const unsigned inst = (a * R3 + s2) * NC + c;
-    pl[inst * kRow + q] = x[a].x;
-    pl[(I + inst) * kRow + q] = x[a].y;
-  }
-}
-
-template <int N1, int N2, int C, int PREC>
-__device__ __forceinline__ void pass1_tile_mx(const P1Args& a, const ci_tparams& P, int b,
-                                              int tile, float2* lds, unsigned t, unsigned c,
-                                              const DftA<PREC>& A, int qsel) {
-  using K = Col<N2, C>;
-  constexpr int N = N1 * N2;
-  constexpr int Lp = K::Lp;
-  constexpr int R3 = K::R3;
-  constexpr int I = C * Lp;
-  const unsigned tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane / 16;
-  float* pl = reinterpret_cast<float*>(lds);
-  const unsigned k1 = tile * C + c;
-
-  float2 x[16];
-#pragma unroll
-  for (int m = 0; m < 8; ++m) {
-    float2 v = make_float2(0.f, 0.f);
-    if (m < qsel) {
-      const int k = (int)(k1 + N1 * (t + Lp * m));
-      if (k >= P.k_low && k <= P.k_high) {
-        const float2 e = chirp_phasor(P, k);
-        v = cmul(a.w[k], make_float2(e.x * P.scale, e.y * P.scale));
-      }
-    }
-    x[m] = v;
-  }
-  // stage 1 on the vector units (half the inputs are zero), twiddle w_L^{a t}
-  idft16<8>(x);
-  {
-    const char* twb = reinterpret_cast<const char*>(a.tw);
-    const unsigned step = t * (2048u / N2) * (unsigned)sizeof(float2);
-    unsigned off = 0;
-#pragma unroll
-    for (int aa = 1; aa < 16; ++aa) {
-      off += step;
-      x[aa] = cmul(x[aa], *reinterpret_cast<const float2*>(twb + off));
-    }
-  }
-  mx_store_stage1<N2, C>(pl, x, t, c);
-  __syncthreads();
-
-  // stage 2 on the matrix cores, four blocks of 16 instances per wave, with
-  // the stage twiddle and the four-step twiddle w_N^{k1 j2} merged:
-  // output a2 of instance (a0, s2, c) gets base w^{a2}.
-  float2 y[16];
-#pragma unroll
-  for (int bk = 0; bk < 4; ++bk) {
-    const unsigned inst = 16 * (4 * wave + bk) + (lane & 15);
-    float v[8];
-    pl_load8(pl, I, inst, g, v);
-    f32x4 yr, yi;
-    mx_dft16<PREC>(A, v, yr, yi);
-    const unsigned cb = inst % C, r = inst / C;
-    const unsigned s2 = r % R3, a0 = r / R3;
-    const unsigned kb = tile * C + cb;
-    const float2 base = tw_n(a.twa, a.twb, (int)(kb * a0));
-    float2 w = tw_n(a.twa, a.twb, (int)(16 * kb));
-    if constexpr (R3 > 1) w = cmul(a.tw[s2 * (2048 / (16 * R3))], w);
-    const float2 w2 = cmul(w, w), w4 = cmul(w2, w2), w8 = cmul(w4, w4);
-    float2 p = base;
-    if (g & 1) p = cmul(p, w4);
-    if (g & 2) p = cmul(p, w8);
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      y[4 * bk + e] = cmul(make_float2(yr[e], yi[e]), p);
-      p = cmul(p, w);
-    }
-  }
-  __syncthreads();
-  float2* xl = lds;
-  mx_store_stage2<N2, C>(xl, y, lane, wave);
-  __syncthreads();
-  mx_gather_out<N2, C>(x, xl, t, c);
-  if constexpr (R3 > 1) {
-    const float2 v = tw_n(a.twa, a.twb, (int)(256 * k1));
-    float2 vb = v;
-#pragma unroll
-    for (int bb = 1; bb < R3; ++bb) {
-#pragma unroll
-      for (int i = 0; i < 16 / R3; ++i) x[i * R3 + bb] = cmul(x[i * R3 + bb], vb);
-      vb = cmul(vb, v);
-    }
-  }
-  unsigned* yt = reinterpret_cast<unsigned*>(a.y) + (size_t)b * N + (size_t)tile * N2 * C;
-  const unsigned o = t * C + c;
-#pragma unroll
-  for (int r = 0; r < 16; ++r) yt[o + K::off(r) * C] = f2h(x[r]);
-}
-
-template <int N1, int N2, int C, int PREC>
-__global__ __launch_bounds__(C * N2 / 16) void k_pass1_mx(P1Args a) {
-  constexpr int Lp = N2 / 16;
-  constexpr int TILES = N1 / C;
-  extern __shared__ float2 lds[];
-  const unsigned tid = threadIdx.x;
-  const unsigned c = tid % C, t = tid / C;
-  if (a.wkeys) {
-    const int64_t gid = blockIdx.x * (int64_t)blockDim.x + tid;
-    const int64_t gsz = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = gid; i < a.nzero_w; i += gsz) a.wkeys[i] = 0ull;
-    if (gid == 0) a.bdone[0] = 0u;
-  }
-  const DftA<PREC> A = make_dft_a<PREC>(a.tw64, tid & 63);
-  const int bid = xcd_remap(blockIdx.x, gridDim.x);
-  const int b = bid / TILES, tile = bid % TILES;
-  const ci_tparams P = a.prm[b];
-  const int mneed = P.k_high >= P.k_low ? (P.k_high / N1) / Lp + 1 : 1;
-  pass1_tile_mx<N1, N2, C, PREC>(a, P, b, tile, lds, t, c, A, mneed);
 }
 
 // ---------------------------------------------------------------------------
@@ -1386,18 +1199,18 @@ struct Inst {
     if (have[precision]) return known[precision];
     hipError_t e;
     if (precision == CI_FP32) {
-      e = lds_fits(k_pass1<N1, N2, C>, (size_t)Col<N2, C>::LDS_ELEMS * sizeof(float2));
+      e = lds_fits(k_pass1<N1, N2, C, false>, (size_t)Col<N2, C>::LDS_ELEMS * sizeof(float2));
       if (e == hipSuccess)
         e = lds_fits(k_pass2_trig<N1, N2, C, J>,
                      (size_t)(Col<N1, J>::LDS_ELEMS + N1) * sizeof(float2));
       if (e == hipSuccess)
         e = lds_fits(k_pass2_series<N1, N2, C, J>, (size_t)Col<N1, J>::LDS_ELEMS * sizeof(float2));
     } else if (precision == CI_SPLIT_BF16) {
-      e = lds_fits(k_pass1_mx<N1, N2, C, kBF16>, (size_t)10 * C * N2);
+      e = lds_fits(k_pass1<N1, N2, C, true>, (size_t)Col<N2, C>::LDS_ELEMS * sizeof(float2));
       if (e == hipSuccess) e = lds_fits(k_p2mx<N1, N2, C, J, kBF16, 0>, p2mx_lds_bytes<N1>(J));
       if (e == hipSuccess) e = lds_fits(k_p2mx<N1, N2, C, J, kBF16, 1>, p2mx_lds_bytes<N1>(J));
     } else {
-      e = lds_fits(k_pass1_mx<N1, N2, C, kFP16>, (size_t)10 * C * N2);
+      e = lds_fits(k_pass1<N1, N2, C, true>, (size_t)Col<N2, C>::LDS_ELEMS * sizeof(float2));
       if (e == hipSuccess) e = lds_fits(k_p2mx<N1, N2, C, J, kFP16, 0>, p2mx_lds_bytes<N1>(J));
       if (e == hipSuccess) e = lds_fits(k_p2mx<N1, N2, C, J, kFP16, 1>, p2mx_lds_bytes<N1>(J));
     }
@@ -1408,9 +1221,10 @@ struct Inst {
     }
     return e;
   }
+  template <bool H>
   static hipError_t p1(const BatchArgs& a, bool zero, hipStream_t st) {
     const size_t lds = (size_t)Col<N2, C>::LDS_ELEMS * sizeof(float2);
-    auto kern = k_pass1<N1, N2, C>;
+    auto kern = k_pass1<N1, N2, C, H>;
     hipError_t e = set_lds(kern, lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(kern, dim3((unsigned)(a.nb * (N1 / C))), dim3(C * N2 / 16), lds, st,
@@ -1438,16 +1252,6 @@ struct Inst {
     if (grid > items) grid = items;
     if (grid < 1) grid = 1;
     hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(J * N1 / 16), lds, st, make_p2(a));
-    return hipGetLastError();
-  }
-  template <int PREC>
-  static hipError_t p1mx(const BatchArgs& a, bool zero, hipStream_t st) {
-    const size_t lds = (size_t)10 * C * N2;
-    auto kern = k_pass1_mx<N1, N2, C, PREC>;
-    hipError_t e = set_lds(kern, lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(kern, dim3((unsigned)(a.nb * (N1 / C))), dim3(C * N2 / 16), lds, st,
-                       make_p1(a, zero));
     return hipGetLastError();
   }
   template <int PREC, int MODE>
@@ -1518,9 +1322,10 @@ hipError_t dispatch(const Plan& p, F f) {
 hipError_t launch_pass1(const BatchArgs& a, bool zero_trig, hipStream_t st) {
   return dispatch(a.plan, [&](auto inst) {
     typedef decltype(inst) I;
-    if (a.precision == CI_SPLIT_BF16) return I::template p1mx<kBF16>(a, zero_trig, st);
-    if (a.precision == CI_SPLIT_FP16) return I::template p1mx<kFP16>(a, zero_trig, st);
-    return I::p1(a, zero_trig, st);
+    // the split-precision paths keep the first pass on the vector units and
+    // store its output as FP16 pairs
+    if (a.precision != CI_FP32) return I::template p1<true>(a, zero_trig, st);
+    return I::template p1<false>(a, zero_trig, st);
   });
 }
 hipError_t launch_pass2_trig(const BatchArgs& a, hipStream_t st) {

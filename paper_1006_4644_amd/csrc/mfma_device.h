@@ -1,13 +1,14 @@
-// mfma_device.h -- radix-16 DFT-matrix stages on the gfx950 matrix cores.
+// mfma_device.h -- radix-16 DFT-matrix products on the gfx950 matrix cores.
 //
-// A radix-16 step Y_a = sum_q X_q w16^{aq} (w16 = exp(2 pi i/16)) over 16
-// independent instances is the real product
-//   [Yr]   [ C  -S ] [Xr]        C_aq = cos(2 pi aq/16),
-//   [Yi] = [ S   C ] [Xi]        S_aq = sin(2 pi aq/16),
-// a 32 x 32 matrix times a 32 x 16 block, i.e. one 16x16x32 MFMA per output
-// half.  Operands are split into a high and a low part in the 16-bit type
-// (x = x_hi + x_lo, W = W_hi + W_lo) and three products
-//   W_hi x_hi + W_hi x_lo + W_lo x_hi
+// A radix-16 step Y_a = sum_q M_aq X_q over 16 independent instances is a
+// real product of a 32 x 32 matrix and a 32 x 16 block, one 16x16x32 MFMA
+// per output half, with the real and imaginary parts of the inputs
+// interleaved along k (k = 2 q + part):
+//   real outputs:      row a = [Re M_a0, -Im M_a0, Re M_a1, -Im M_a1, ...]
+//   imaginary outputs: row a = [Im M_a0,  Re M_a0, Im M_a1,  Re M_a1, ...]
+// Operands are split into a high and a low part in the 16-bit type
+// (x = x_hi + x_lo, M = M_hi + M_lo) and three products
+//   M_hi x_hi + M_hi x_lo + M_lo x_hi
 // accumulate in FP32, which keeps ~2^-16 (BF16) or ~2^-21 (FP16) relative
 // error per stage.  FP16 inputs are pre-scaled by 2^6 to stay clear of its
 // subnormal range and the outputs scaled back exactly.
@@ -16,9 +17,9 @@
 //   A[i][k]: i = l % 16, k = 8 g + e (e < 8)
 //   B[k][j]: j = l % 16, k = 8 g + e
 //   D[i][j]: j = l % 16, i = 4 g + e (e < 4)
-// so with B rows 0..15 = Xr and 16..31 = Xi, lane l supplies component
-// g / 2 (re, im) of inputs 8 (g % 2) .. +7 of instance l % 16, and receives
-// outputs a = 4 g .. 4 g + 3 of that instance.
+// so lane l supplies complex inputs q = 4 g .. 4 g + 3 of instance l % 16
+// as (re, im, re, im, ...) and receives outputs a = 4 g .. 4 g + 3 of that
+// instance: the same four-per-lane shape on both sides.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -65,64 +66,6 @@ __device__ __forceinline__ void split8(const float (&v)[8], typename MxT<PREC>::
     const S h = (S)x;
     hi[e] = h;
     lo[e] = (S)(x - (float)h);
-  }
-}
-
-// The lane's slice of the DFT-16 matrix rows for both output halves,
-// split into high and low parts.  tw64: exp(2 pi i e / 2048) in FP64.
-template <int PREC>
-struct DftA {
-  typename MxT<PREC>::v8 re_hi, re_lo, im_hi, im_lo;
-};
-
-template <int PREC>
-__device__ __forceinline__ DftA<PREC> make_dft_a(const double2* __restrict__ tw64,
-                                                 unsigned lane) {
-  typedef typename MxT<PREC>::s S;
-  DftA<PREC> A;
-  const int i = lane % 16, g = lane / 16;
-#pragma unroll
-  for (int e = 0; e < 8; ++e) {
-    const int k = 8 * g + e;
-    const int q = k & 15;
-    const double2 w = tw64[((i * q) & 15) * 128];  // w16^{iq} = (C, S)
-    // rows 0..15 (Yr): [C, -S]; rows 16..31 (Yi): [S, C]
-    const float ar = k < 16 ? (float)w.x : (float)(-w.y);
-    const float ai = k < 16 ? (float)w.y : (float)w.x;
-    const S rh = (S)ar, ih = (S)ai;
-    A.re_hi[e] = rh;
-    A.re_lo[e] = (S)(ar - (float)rh);
-    A.im_hi[e] = ih;
-    A.im_lo[e] = (S)(ai - (float)ih);
-  }
-  return A;
-}
-
-// One radix-16 step on 16 instances: v = this lane's 8 inputs (component
-// g / 2, inputs 8 (g % 2) .. +7 of instance lane % 16).  Returns the real
-// and imaginary parts of outputs a = 4 g + e, e < 4.  X_EXACT: the inputs
-// are exact in the 16-bit type (read from FP16 storage on the FP16 path),
-// so their low parts are zero and the W_hi x_lo product is skipped.
-template <int PREC, bool X_EXACT = false>
-__device__ __forceinline__ void mx_dft16(const DftA<PREC>& A, const float (&v)[8], f32x4& yr,
-                                         f32x4& yi) {
-  typedef MxT<PREC> M;
-  typename M::v8 bh, bl;
-  split8<PREC>(v, bh, bl);
-  f32x4 z = {0.f, 0.f, 0.f, 0.f};
-  yr = M::mma(A.re_hi, bh, z);
-  if constexpr (!X_EXACT) yr = M::mma(A.re_hi, bl, yr);
-  yr = M::mma(A.re_lo, bh, yr);
-  yi = M::mma(A.im_hi, bh, z);
-  if constexpr (!X_EXACT) yi = M::mma(A.im_hi, bl, yi);
-  yi = M::mma(A.im_lo, bh, yi);
-  if constexpr (M::kPre != 1.0f) {
-    constexpr float inv = 1.0f / M::kPre;
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      yr[e] *= inv;
-      yi[e] *= inv;
-    }
   }
 }
 
