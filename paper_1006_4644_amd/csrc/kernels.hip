@@ -636,6 +636,61 @@ __device__ __forceinline__ void load_item(float2 (&x)[16], const P2Args& a, int 
   load_pass2<N1, N2, C, J>(x, a.y + (size_t)b * N, tile * J + cc, t);
 }
 
+// Post-pass of one pass-2 tile (workgroup of NW waves).  r2[i], i < K, are
+// this lane's |z|^2 values (-1 outside the search range) in increasing
+// sample index j = jof(i).  Samples above the threshold raise their
+// window's key; the tile's peak key (rho^2 bits over the complemented
+// smallest index with that value) goes to a.ppart[pidx].  The lane maximum
+// decides both the threshold test and the peak; only lanes holding the
+// workgroup maximum search for its index.
+template <int K, int NW, typename JF>
+__device__ __forceinline__ void tile_post(const float (&r2)[K], JF jof, const P2Args& a, int bt,
+                                          size_t pidx, float* s_m, unsigned* s_j,
+                                          unsigned tid) {
+  const unsigned lane = tid & 63, wave = tid >> 6;
+  float m = r2[0];
+#pragma unroll
+  for (int i = 1; i < K; ++i) m = fmaxf(m, r2[i]);
+  if (__any(m > a.thr2)) {
+    // rare: samples above threshold update their window's key
+    u64* wk = a.wkeys + (size_t)bt * a.nwin;
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+      if (r2[i] > a.thr2) {
+        const unsigned j = jof(i);
+        const u64 key = ((u64)__float_as_uint(r2[i]) << 32) | (u64)(0xFFFFFFFFu - j);
+        atomicMax(&wk[j / a.win32], key);
+      }
+    }
+  }
+  float wm = m;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) wm = fmaxf(wm, __shfl_xor(wm, off, 64));
+  if (lane == 0) s_m[wave] = wm;
+  __syncthreads();
+  float M = s_m[0];
+#pragma unroll
+  for (int w = 1; w < NW; ++w) M = fmaxf(M, s_m[w]);
+  unsigned jm = 0xFFFFFFFFu;
+  if (M >= 0.f && __any(m == M)) {
+    if (m == M) {
+#pragma unroll
+      for (int i = K - 1; i >= 0; --i)
+        if (r2[i] == M) jm = jof(i);
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) jm = min(jm, (unsigned)__shfl_xor((int)jm, off, 64));
+  }
+  if (lane == 0) s_j[wave] = jm;
+  __syncthreads();
+  if (tid == 0) {
+    unsigned j = s_j[0];
+#pragma unroll
+    for (int w = 1; w < NW; ++w) j = min(j, s_j[w]);
+    a.ppart[pidx] = M >= 0.f ? (((u64)__float_as_uint(M) << 32) | (u64)(0xFFFFFFFFu - j)) : 0ull;
+  }
+}
+
 template <int N1, int N2, int C, int J>
 __device__ __forceinline__ void pass2_post(const float2 (&x)[16], const P2Args& a, int b, int tile,
                                            u64* s_best, unsigned tid, unsigned cc, unsigned t);
@@ -660,58 +715,23 @@ __device__ __forceinline__ void pass2_post(const float2 (&x)[16], const P2Args& 
   constexpr int TILES = N2 / J;
   using K = Col<N1, J>;
   const unsigned j2 = tile * J + cc;
-  // Post-pass: rho^2 = |z|^2 (already in SNR units).  Registers are
-  // visited in increasing j, so a strict ">" keeps the smallest index
-  // among equal values.
-  float bv = -1.f;
-  int br = 0;
-  bool hot = false;
+  auto jof = [&](int kk) { return j2 + (unsigned)N2 * (unsigned)K::out((int)t, K::reg_by_order(kk)); };
+  float r2[16];
 #pragma unroll
   for (int kk = 0; kk < 16; ++kk) {
-    const int r = K::reg_by_order(kk);
-    float r2 = fmaf(x[r].x, x[r].x, x[r].y * x[r].y);
-    if (!a.full) {
-      const int j = (int)j2 + N2 * K::out((int)t, r);
-      if (j < a.jlo32 || j >= a.jhi32) r2 = -1.f;
-    }
-    if (r2 > bv) {
-      bv = r2;
-      br = r;
-    }
-    hot |= r2 > a.thr2;
+    const float2 z = x[K::reg_by_order(kk)];
+    r2[kk] = fmaf(z.x, z.x, z.y * z.y);
   }
-  if (__any(hot)) {
-    // rare: samples above threshold update their window's key
-    u64* wk = a.wkeys + (size_t)b * a.nwin;
+  if (!a.full) {
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      const float r2 = fmaf(x[r].x, x[r].x, x[r].y * x[r].y);
-      const int j = (int)j2 + N2 * K::out((int)t, r);
-      if (r2 > a.thr2 && (a.full || (j >= a.jlo32 && j < a.jhi32))) {
-        const u64 key = ((u64)__float_as_uint(r2) << 32) | (u64)(0xFFFFFFFFu - (unsigned int)j);
-        atomicMax(&wk[(unsigned int)j / a.win32], key);
-      }
+    for (int kk = 0; kk < 16; ++kk) {
+      const int j = (int)jof(kk);
+      if (j < a.jlo32 || j >= a.jhi32) r2[kk] = -1.f;
     }
   }
-  u64 best = 0ull;
-  if (bv >= 0.f) {
-    const unsigned int j = (unsigned int)((int)j2 + N2 * K::out((int)t, br));
-    best = ((u64)__float_as_uint(bv) << 32) | (u64)(0xFFFFFFFFu - j);
-  }
-  // workgroup max of the peak key, stored as this tile's partial
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    const u64 o = __shfl_xor(best, off, 64);
-    best = o > best ? o : best;
-  }
-  if ((tid & 63) == 0) s_best[tid >> 6] = best;
-  __syncthreads();
-  if (tid == 0) {
-    u64 m = 0ull;
-    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) m = s_best[i] > m ? s_best[i] : m;
-    a.ppart[(size_t)b * TILES + tile] = m;
-  }
-  __syncthreads();
+  float* s_m = reinterpret_cast<float*>(s_best);
+  unsigned* s_j = reinterpret_cast<unsigned*>(s_best) + 16;
+  tile_post<16, J * N1 / 16 / 64>(r2, jof, a, b, (size_t)b * TILES + tile, s_m, s_j, tid);
 }
 
 // Persistent pass 2: each workgroup walks tiles item = blockIdx.x + k G
@@ -829,7 +849,8 @@ __global__ __launch_bounds__(J * 64) void k_p2mx(P2Args a) {
   constexpr int L = N1, R3 = L / 256, N = N1 * N2, TILES = N2 / J;
   typedef typename MxT<PREC>::v8 V8;
   extern __shared__ float2 lds[];
-  __shared__ u64 s_best[J];
+  __shared__ float s_m[J];
+  __shared__ unsigned s_j[J];
   float2* twl = lds;
   const uint4* afr = reinterpret_cast<const uint4*>(lds + L);
   const unsigned tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -921,59 +942,24 @@ __global__ __launch_bounds__(J * 64) void k_p2mx(P2Args a) {
         for (int b = 0; b < R3; ++b)
           zt[(size_t)N2 * (b + R3 * u0 + 16 * R3 * (4 * g + e))] = x[b][e];
     } else {
-      // visited in increasing n, so a strict ">" keeps the smallest index
-      float bv = -1.f;
-      int bn = 0;
-      bool hot = false;
+      // visited in increasing n = b + R3 v1 + 16 R3 (4 g + e)
+      auto jof = [&](int i) {
+        const int e = i / R3, b = i % R3;
+        return j2 + (unsigned)N2 * (unsigned)(b + R3 * (int)u0 + 16 * R3 * (4 * (int)g + e));
+      };
+      float r2[4 * R3];
 #pragma unroll
       for (int e = 0; e < 4; ++e)
 #pragma unroll
-        for (int b = 0; b < R3; ++b) {
-          const int n = b + R3 * (int)u0 + 16 * R3 * (4 * (int)g + e);
-          float r2 = fmaf(x[b][e].x, x[b][e].x, x[b][e].y * x[b][e].y);
-          if (!a.full) {
-            const int j = (int)j2 + N2 * n;
-            if (j < a.jlo32 || j >= a.jhi32) r2 = -1.f;
-          }
-          if (r2 > bv) {
-            bv = r2;
-            bn = n;
-          }
-          hot |= r2 > a.thr2;
+        for (int b = 0; b < R3; ++b) r2[e * R3 + b] = fmaf(x[b][e].x, x[b][e].x, x[b][e].y * x[b][e].y);
+      if (!a.full) {
+#pragma unroll
+        for (int i = 0; i < 4 * R3; ++i) {
+          const int j = (int)jof(i);
+          if (j < a.jlo32 || j >= a.jhi32) r2[i] = -1.f;
         }
-      if (__any(hot)) {
-        u64* wk = a.wkeys + (size_t)bt * a.nwin;
-#pragma unroll
-        for (int e = 0; e < 4; ++e)
-#pragma unroll
-          for (int b = 0; b < R3; ++b) {
-            const float r2 = fmaf(x[b][e].x, x[b][e].x, x[b][e].y * x[b][e].y);
-            const int j = (int)j2 + N2 * (b + R3 * (int)u0 + 16 * R3 * (4 * (int)g + e));
-            if (r2 > a.thr2 && (a.full || (j >= a.jlo32 && j < a.jhi32))) {
-              const u64 key = ((u64)__float_as_uint(r2) << 32) | (u64)(0xFFFFFFFFu - (unsigned int)j);
-              atomicMax(&wk[(unsigned int)j / a.win32], key);
-            }
-          }
       }
-      u64 best = 0ull;
-      if (bv >= 0.f) {
-        const unsigned int j = (unsigned int)((int)j2 + N2 * bn);
-        best = ((u64)__float_as_uint(bv) << 32) | (u64)(0xFFFFFFFFu - j);
-      }
-#pragma unroll
-      for (int off = 32; off > 0; off >>= 1) {
-        const u64 o = __shfl_xor(best, off, 64);
-        best = o > best ? o : best;
-      }
-      if (lane == 0) s_best[wave] = best;
-      __syncthreads();
-      if (tid == 0) {
-        u64 m = 0ull;
-#pragma unroll
-        for (int i = 0; i < J; ++i) m = s_best[i] > m ? s_best[i] : m;
-        a.ppart[(size_t)bt * TILES + tile] = m;
-      }
-      __syncthreads();
+      tile_post<4 * R3, J>(r2, jof, a, bt, (size_t)bt * TILES + tile, s_m, s_j, tid);
     }
   }
 }
