@@ -786,7 +786,8 @@ __global__ __launch_bounds__(J * N1 / 16, 4) void k_pass2_trig(P2Args a) {
 // w16^{v q}.  Lane l holds output row v = l % 16 and inputs
 // q = 4 (l / 16) + e / 2 (e < 8, real and imaginary parts interleaved along
 // k) of the real rows [Re, -Im] and imaginary rows [Im, Re], split into high
-// and low parts: out[(mi 64 + l) 4 + f], f = re_hi, re_lo, im_hi, im_lo.
+// and low parts: out[(mi 4 + f) 64 + l], f = re_hi, re_lo, im_hi, im_lo
+// (fragment-major, so the lanes of one read hit consecutive 16-byte words).
 template <int PREC>
 __global__ void k_mx_table(int L, const double2* __restrict__ tw64, uint4* __restrict__ out) {
   typedef typename MxT<PREC>::v8 V8;
@@ -809,7 +810,7 @@ __global__ void k_mx_table(int L, const double2* __restrict__ tw64, uint4* __res
     f[3][e] = (S)(im - (float)ih);
   }
 #pragma unroll
-  for (int k = 0; k < 4; ++k) out[(mi * 64 + l) * 4 + k] = __builtin_bit_cast(uint4, f[k]);
+  for (int k = 0; k < 4; ++k) out[(mi * 4 + k) * 64 + l] = __builtin_bit_cast(uint4, f[k]);
 }
 
 template <int R>
@@ -864,7 +865,7 @@ __global__ __launch_bounds__(J * 64) void k_p2mx(P2Args a) {
   __syncthreads();
   V8 wc[4];
 #pragma unroll
-  for (int f = 0; f < 4; ++f) wc[f] = __builtin_bit_cast(V8, afr[(R3 * 64 + lane) * 4 + f]);
+  for (int f = 0; f < 4; ++f) wc[f] = __builtin_bit_cast(V8, afr[(R3 * 4 + f) * 64 + lane]);
   const int total = a.nb * TILES;
   for (int item = blockIdx.x; item < total; item += gridDim.x) {
     const int bt = item / TILES, tile = item % TILES;
@@ -902,7 +903,7 @@ __global__ __launch_bounds__(J * 64) void k_p2mx(P2Args a) {
     for (int b = 0; b < R3; ++b) {
       V8 A4[4];
 #pragma unroll
-      for (int f = 0; f < 4; ++f) A4[f] = __builtin_bit_cast(V8, afr[(b * 64 + lane) * 4 + f]);
+      for (int f = 0; f < 4; ++f) A4[f] = __builtin_bit_cast(V8, afr[(b * 4 + f) * 64 + lane]);
       float v[8];
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
