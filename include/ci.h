@@ -56,10 +56,13 @@ extern "C" {
 
 /* arithmetic of the inverse transform */
 #define CI_FP32 0        /* FP32 VALU butterflies, FP32 intermediate        */
-#define CI_SPLIT_BF16 1  /* radix-16 stages as DFT-matrix products on MFMA,
-                            hi/lo BF16 operands, 3 products, FP32 accumulate;
-                            intermediate stored as FP16 pairs (4 bytes per
-                            complex value: half the transform's HBM bytes) */
+#define CI_SPLIT_BF16 1  /* the radix-16 stages of the second transform
+                            pass as DFT-matrix products on MFMA, hi/lo BF16
+                            operands, 3 products, FP32 accumulate; the first
+                            pass in FP32 on the vector units; intermediate
+                            stored as FP16 pairs (4 bytes per complex value:
+                            half the transform's HBM bytes).  SNR error
+                            below 1e-3 of the series maximum.             */
 #define CI_SPLIT_FP16 2  /* the same with hi/lo FP16 operands (inputs scaled
                             by 2^6; |z| up to ~1e3 in SNR units)            */
 
