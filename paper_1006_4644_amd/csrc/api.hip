@@ -150,28 +150,31 @@ int ensure_ybuf(Ctx* ctx, size_t bytes) {
 
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
-// Bytes of one search's trigger bookkeeping (two slot sets of bmax templates).
+// Bytes of one search's trigger bookkeeping (kSlots slot sets of bmax
+// templates).
 size_t trig_bytes(int64_t bmax, int64_t nwin, int64_t ntile2) {
-  return align256(sizeof(unsigned long long) * 2 * bmax * ntile2) +
-         align256(sizeof(unsigned long long) * 2 * bmax * nwin) +
-         align256(sizeof(unsigned int) * 2) + align256(sizeof(int) * 2 * bmax) +
-         align256(sizeof(int) * 2 * bmax * nwin) + align256(sizeof(ci_trigger) * 2 * bmax * nwin) +
+  const int64_t S = kSlots;
+  return align256(sizeof(unsigned long long) * S * bmax * ntile2) +
+         align256(sizeof(unsigned long long) * S * bmax * nwin) +
+         align256(sizeof(unsigned int) * S) + align256(sizeof(int) * S * bmax) +
+         align256(sizeof(int) * S * bmax * nwin) + align256(sizeof(ci_trigger) * S * bmax * nwin) +
          align256(sizeof(ci_trigger) * nwin) + align256(sizeof(unsigned long long));
 }
 
 void carve_trig(char* p, int64_t bmax, int64_t nwin, int64_t ntile2, TrigWork* tw) {
+  const int64_t S = kSlots;
   tw->ppart = reinterpret_cast<unsigned long long*>(p);
-  p += align256(sizeof(unsigned long long) * 2 * bmax * ntile2);
+  p += align256(sizeof(unsigned long long) * S * bmax * ntile2);
   tw->wkeys = reinterpret_cast<unsigned long long*>(p);
-  p += align256(sizeof(unsigned long long) * 2 * bmax * nwin);
+  p += align256(sizeof(unsigned long long) * S * bmax * nwin);
   tw->bdone = reinterpret_cast<unsigned int*>(p);
-  p += align256(sizeof(unsigned int) * 2);
+  p += align256(sizeof(unsigned int) * S);
   tw->cnt = reinterpret_cast<int*>(p);
-  p += align256(sizeof(int) * 2 * bmax);
+  p += align256(sizeof(int) * S * bmax);
   tw->sidx = reinterpret_cast<int*>(p);
-  p += align256(sizeof(int) * 2 * bmax * nwin);
+  p += align256(sizeof(int) * S * bmax * nwin);
   tw->stage = reinterpret_cast<ci_trigger*>(p);
-  p += align256(sizeof(ci_trigger) * 2 * bmax * nwin);
+  p += align256(sizeof(ci_trigger) * S * bmax * nwin);
   tw->mrec = reinterpret_cast<ci_trigger*>(p);
   p += align256(sizeof(ci_trigger) * nwin);
   tw->run = reinterpret_cast<unsigned long long*>(p);
@@ -237,16 +240,24 @@ hipError_t timed(Ctx* ctx, int kind, int64_t templates, hipStream_t st, F launch
   return hipSuccess;
 }
 
-// Internal streams and fork/join events (created on first use).
+// Internal streams and ordering events (created on first use).
 int ensure_streams(Ctx* ctx) {
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < 3; ++i)
     if (!ctx->ws[i]) {
       hipError_t e = hipStreamCreateWithFlags(&ctx->ws[i], hipStreamNonBlocking);
       if (e != hipSuccess) return hipfail(ctx, e, "internal stream");
     }
-  for (int i = 0; i < 3; ++i)
-    if (!ctx->sev[i]) {
-      hipError_t e = hipEventCreateWithFlags(&ctx->sev[i], hipEventDisableTiming);
+  hipEvent_t* evs[1 + 3 + 2 * kSlots];
+  int ne = 0;
+  evs[ne++] = &ctx->fork_ev;
+  for (int i = 0; i < 3; ++i) evs[ne++] = &ctx->join_ev[i];
+  for (int i = 0; i < kSlots; ++i) {
+    evs[ne++] = &ctx->p2_done[i];
+    evs[ne++] = &ctx->fin_done[i];
+  }
+  for (int i = 0; i < ne; ++i)
+    if (!*evs[i]) {
+      hipError_t e = hipEventCreateWithFlags(evs[i], hipEventDisableTiming);
       if (e != hipSuccess) return hipfail(ctx, e, "internal event");
     }
   return CI_OK;
@@ -319,7 +330,7 @@ int prepare_jobs(Ctx* ctx, std::vector<Job>& jobs, size_t* slot_elems) {
   int rc = ensure_tbuf(ctx, ttot);
   if (rc != CI_OK) return rc;
   if (ymax > 0) {
-    rc = ensure_ybuf(ctx, sizeof(float2) * 2 * ymax);
+    rc = ensure_ybuf(ctx, sizeof(float2) * kSlots * ymax);
     if (rc != CI_OK) return rc;
   }
   for (Job& jb : jobs)
@@ -329,12 +340,14 @@ int prepare_jobs(Ctx* ctx, std::vector<Job>& jobs, size_t* slot_elems) {
   return ensure_streams(ctx);
 }
 
-// Enqueue the jobs on stream st.  Batches of all jobs alternate
-// between the two internal streams (global batch b uses slot set b & 1 and
-// stream b & 1), so one batch's second pass overlaps the next batch's first
-// pass, across job boundaries too.  Within a job the finalisers are chained
-// in batch order, which keeps its trigger list ordered; st joins both
-// internal streams at the end.
+// Enqueue the jobs on stream st.  The batches of all jobs (global batch
+// counter b) alternate their two passes between the internal streams
+// ws[b & 1], so one batch's second pass overlaps the next batch's first
+// pass, across job boundaries too; the finalisers run on ws[2] in batch
+// order, which keeps each job's trigger list ordered.  Batch b uses slot
+// set b % kSlots: its first pass waits for the finaliser of batch
+// b - kSlots (the slot's previous user), its finaliser for its own second
+// pass.  st joins all three streams at the end.
 int enqueue_jobs(Ctx* ctx, const std::vector<Job>& jobs, size_t slot_elems, int32_t precision,
                  float thr2, int64_t window, int merge, hipStream_t st) {
   hipError_t e = hipSuccess;
@@ -342,9 +355,10 @@ int enqueue_jobs(Ctx* ctx, const std::vector<Job>& jobs, size_t slot_elems, int3
     e = launch_init_call(jb.tw, (int)jb.nwin, jb.count, st);
     if (e != hipSuccess) return hipfail(ctx, e, "init launch");
   }
-  e = hipEventRecord(ctx->sev[2], st);
-  for (int i = 0; i < 2 && e == hipSuccess; ++i) e = hipStreamWaitEvent(ctx->ws[i], ctx->sev[2], 0);
+  e = hipEventRecord(ctx->fork_ev, st);
+  for (int i = 0; i < 3 && e == hipSuccess; ++i) e = hipStreamWaitEvent(ctx->ws[i], ctx->fork_ev, 0);
   if (e != hipSuccess) return hipfail(ctx, e, "stream fork");
+  hipStream_t sf = ctx->ws[2];
   int64_t b = 0;
   for (const Job& jb : jobs) {
     if (jb.n == 0) continue;
@@ -366,33 +380,35 @@ int enqueue_jobs(Ctx* ctx, const std::vector<Job>& jobs, size_t slot_elems, int3
     a.merge = merge;
     a.precision = precision;
     a.p2_per_cu = jb.cfg.p2_per_cu;
-    hipEvent_t prev_fin = nullptr;
     for (int64_t t0 = 0; t0 < jb.n; ++b, t0 += jb.B) {
       hipStream_t sb = ctx->ws[b & 1];
+      const int slot = (int)(b % kSlots);
       a.t0 = t0;
       a.nb = (int)((jb.n - t0) < jb.B ? (jb.n - t0) : jb.B);
-      a.slot = (int)(b & 1);
+      a.slot = slot;
       a.params = jb.params + t0;
-      a.y = static_cast<float2*>(ctx->ybuf) + (size_t)(b & 1) * slot_elems;
+      a.y = static_cast<float2*>(ctx->ybuf) + (size_t)slot * slot_elems;
       a.last_batch = (t0 + jb.B >= jb.n) ? 1 : 0;
+      if (b >= kSlots) {
+        e = hipStreamWaitEvent(sb, ctx->fin_done[slot], 0);
+        if (e != hipSuccess) return hipfail(ctx, e, "slot reuse ordering");
+      }
       e = timed(ctx, 0, a.nb, sb, [&] { return launch_pass1(a, true, sb); });
       if (e != hipSuccess) return hipfail(ctx, e, "pass-1 launch");
       e = timed(ctx, 1, a.nb, sb, [&] { return launch_pass2_trig(a, sb); });
       if (e != hipSuccess) return hipfail(ctx, e, "pass-2 launch");
-      if (prev_fin) {
-        e = hipStreamWaitEvent(sb, prev_fin, 0);
-        if (e != hipSuccess) return hipfail(ctx, e, "finaliser ordering");
-      }
-      e = launch_fin(a, sb);
+      e = hipEventRecord(ctx->p2_done[slot], sb);
+      if (e == hipSuccess) e = hipStreamWaitEvent(sf, ctx->p2_done[slot], 0);
+      if (e != hipSuccess) return hipfail(ctx, e, "finaliser ordering");
+      e = launch_fin(a, sf);
       if (e != hipSuccess) return hipfail(ctx, e, "finalise launch");
-      prev_fin = ctx->sev[b & 1];
-      e = hipEventRecord(prev_fin, sb);
+      e = hipEventRecord(ctx->fin_done[slot], sf);
       if (e != hipSuccess) return hipfail(ctx, e, "finaliser event");
     }
   }
-  for (int i = 0; i < 2 && e == hipSuccess; ++i) {
-    e = hipEventRecord(ctx->sev[i], ctx->ws[i]);
-    if (e == hipSuccess) e = hipStreamWaitEvent(st, ctx->sev[i], 0);
+  for (int i = 0; i < 3 && e == hipSuccess; ++i) {
+    e = hipEventRecord(ctx->join_ev[i], ctx->ws[i]);
+    if (e == hipSuccess) e = hipStreamWaitEvent(st, ctx->join_ev[i], 0);
   }
   if (e != hipSuccess) return hipfail(ctx, e, "stream join");
   return CI_OK;
@@ -439,13 +455,18 @@ int ci_ctx_destroy(ci_ctx* ctx) {
     ctx->ev_pool.push_back(t.e1);
   }
   for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < 3; ++i)
     if (ctx->ws[i]) {
       (void)hipStreamSynchronize(ctx->ws[i]);
       (void)hipStreamDestroy(ctx->ws[i]);
     }
+  if (ctx->fork_ev) (void)hipEventDestroy(ctx->fork_ev);
   for (int i = 0; i < 3; ++i)
-    if (ctx->sev[i]) (void)hipEventDestroy(ctx->sev[i]);
+    if (ctx->join_ev[i]) (void)hipEventDestroy(ctx->join_ev[i]);
+  for (int i = 0; i < kSlots; ++i) {
+    if (ctx->p2_done[i]) (void)hipEventDestroy(ctx->p2_done[i]);
+    if (ctx->fin_done[i]) (void)hipEventDestroy(ctx->fin_done[i]);
+  }
   if (ctx->ybuf) (void)hipFree(ctx->ybuf);
   if (ctx->tbuf) (void)hipFree(ctx->tbuf);
   delete ctx;

@@ -33,18 +33,21 @@ struct Plan {
 
 Plan plan_for(int log2n, int c, int j);
 
-// Per-call trigger bookkeeping (device).  Two slot sets alternate between
-// consecutive batches so that batch b+1's first pass can clear its keys
-// while batch b's second pass still reads its own.
+// Slot sets of the intermediate and of the trigger bookkeeping in flight:
+// batch b uses slot b % kSlots, so a batch's first pass can start while the
+// finalisers of the previous kSlots - 1 batches still read their slots.
+constexpr int kSlots = 3;
+
+// Per-call trigger bookkeeping (device), kSlots slot sets.
 struct TrigWork {
-  unsigned long long* ppart;   // [2][B][n2/j]  peak key per pass-2 workgroup
-  unsigned long long* wkeys;   // [2][B][nwin]  window key per template
-  unsigned int* bdone;         // [2]           finished templates
-  int* cnt;                    // [2][B]        triggers per template
-  int* sidx;                   // [2][B][nwin]  staging slot of window w
-  ci_trigger* stage;           // [2][B][nwin]  compacted triggers
-  ci_trigger* mrec;            // [nwin]        merged record per window
-  unsigned long long* run;     // [1]           triggers placed so far
+  unsigned long long* ppart;   // [kSlots][B][n2/j]  peak key per pass-2 workgroup
+  unsigned long long* wkeys;   // [kSlots][B][nwin]  window key per template
+  unsigned int* bdone;         // [kSlots]           finished templates
+  int* cnt;                    // [kSlots][B]        triggers per template
+  int* sidx;                   // [kSlots][B][nwin]  staging slot of window w
+  ci_trigger* stage;           // [kSlots][B][nwin]  compacted triggers
+  ci_trigger* mrec;            // [nwin]             merged record per window
+  unsigned long long* run;     // [1]                triggers placed so far
 };
 
 // Launch configuration of one search: tiles, pass-2 residency and batch.
@@ -68,7 +71,7 @@ struct Ctx {
   int device = 0;
   std::string err;
   int64_t batch_override = 0;
-  // intermediate workspace (2 slot sets)
+  // intermediate workspace (kSlots slot sets)
   void* ybuf = nullptr;
   size_t ybytes = 0;
   // trigger workspace
@@ -79,10 +82,14 @@ struct Ctx {
   size_t pinbytes = 0;
   hipEvent_t pin_ev = nullptr;
   bool pin_ev_armed = false;
-  // two internal streams that alternate batches, and events to fork from
-  // and join back to the caller's stream
-  hipStream_t ws[2] = {nullptr, nullptr};
-  hipEvent_t sev[3] = {nullptr, nullptr, nullptr};
+  // internal streams: ws[0], ws[1] alternate the batches' two passes, ws[2]
+  // runs the finalisers in batch order; events fork from and join back to
+  // the caller's stream and order the slots
+  hipStream_t ws[3] = {nullptr, nullptr, nullptr};
+  hipEvent_t fork_ev = nullptr;
+  hipEvent_t join_ev[3] = {nullptr, nullptr, nullptr};
+  hipEvent_t p2_done[kSlots] = {};   // second pass of the slot's batch done
+  hipEvent_t fin_done[kSlots] = {};  // finaliser of the slot's batch done
   // launch configuration per (log2 n, precision): autotuned or default
   Tune tune[32][3];
   // instrumentation
