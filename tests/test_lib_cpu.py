@@ -100,3 +100,33 @@ def test_length_classes_reject_bad_input(lib):
     with pytest.raises(ci.CiError):
         lib.length_classes(np.array([[0.0, 1.4]]), 4096.0, 20.0, [1 << 17])
     assert lib.length_classes(np.zeros((0, 2)), 4096.0, 20.0, [1 << 17]).shape == (0,)
+
+
+def test_ctypes_structs_match_header(tmp_path):
+    """Sizes and field offsets of the binding's ctypes structures equal the C
+    compiler's for include/ci.h (compiled with gcc, no GPU)."""
+    import ctypes
+    import shutil
+    import subprocess
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("no gcc")
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    structs = {"ci_tune": ci._Tune, "ci_class_job": ci._ClassJob, "ci_bank_spec": ci._BankSpec,
+               "ci_segment_spec": ci._SegSpec, "ci_kernel_time": ci._KernelTime}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "ci.h"', "int main(void) {"]
+    for cname, cls in structs.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in cls._fields_:
+            lines.append(f'  printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([gcc, "-I", inc, str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout
+    got = {tuple(l.split()[:-1]): int(l.split()[-1]) for l in out.splitlines()}
+    for cname, cls in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(cls), cname
+        for fname, _ in cls._fields_:
+            assert got[(cname, fname)] == getattr(cls, fname).offset, (cname, fname)
