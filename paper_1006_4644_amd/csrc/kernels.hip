@@ -258,12 +258,30 @@ __device__ __forceinline__ float2 tw_n(const float2* __restrict__ twa,
 // be nonzero (m < Q), chosen per template from its upper band edge.
 template <int N1, int N2, int C, int Q, bool H>
 __device__ __forceinline__ void pass1_tile(const P1Args& a, const ci_tparams& P, int b, int tile,
-                                           float2* lds, unsigned t, unsigned c) {
+                                           float2* lds, const float2* twl, unsigned t,
+                                           unsigned c) {
   using K = Col<N2, C>;
   constexpr int N = N1 * N2;
   constexpr int Lp = K::Lp;
   constexpr int R3 = K::R3;
   const unsigned k1 = tile * C + c;
+
+  // Per-lane twiddle constants, read first so that their latency overlaps
+  // the generation: the stage-2 twiddle merged with the four-step twiddle
+  // w_N^{k1 j2} is base * w^{a2} (a geometric sequence in the stage-2
+  // output a2), the radix-R3 outputs b add v^b.
+  float2 base, w, v3 = make_float2(1.f, 0.f);
+  if constexpr (R3 == 1) {
+    // j2 = t + 16 a2 is final after stage 2
+    base = tw_n(a.twa, a.twb, (int)(k1 * t));
+    w = tw_n(a.twa, a.twb, (int)(16 * k1));
+  } else {
+    // rows d = a0 + 16 a2 of the radix-R3 step; output b adds 256 b to j2
+    const unsigned a0 = t / R3, s2 = t % R3;
+    base = tw_n(a.twa, a.twb, (int)(k1 * a0));
+    w = cmul(twl[s2 * (N2 / (16 * R3))], tw_n(a.twa, a.twb, (int)(16 * k1)));
+    v3 = tw_n(a.twa, a.twb, (int)(256 * k1));
+  }
 
   // Z_k for k = k1 + N1 k2, k2 = t + Lp m (zero outside the band).
   float2 x[16];
@@ -278,21 +296,8 @@ __device__ __forceinline__ void pass1_tile(const P1Args& a, const ci_tparams& P,
     x[m] = v;
   }
 
-  K::template stage1<Q>(x, lds, t, c, a.tw);
+  K::template stage1<Q, 1>(x, lds, t, c, twl);
   K::stage2(x, lds, t, c);
-  // Stage-2 twiddle merged with the four-step twiddle w_N^{k1 j2}: the
-  // factor of output a2 is base * w^{a2} (a geometric sequence).
-  float2 base, w;
-  if constexpr (R3 == 1) {
-    // j2 = t + 16 a2 is final here
-    base = tw_n(a.twa, a.twb, (int)(k1 * t));
-    w = tw_n(a.twa, a.twb, (int)(16 * k1));
-  } else {
-    // rows d = a0 + 16 a2 of the radix-R3 step; output b adds 256 b to j2
-    const unsigned a0 = t / R3, s2 = t % R3;
-    base = tw_n(a.twa, a.twb, (int)(k1 * a0));
-    w = cmul(a.tw[s2 * (2048 / (16 * R3))], tw_n(a.twa, a.twb, (int)(16 * k1)));
-  }
   x[0] = cmul(x[0], base);
 #pragma unroll
   for (int a2 = 1; a2 < 16; ++a2) {
@@ -301,7 +306,7 @@ __device__ __forceinline__ void pass1_tile(const P1Args& a, const ci_tparams& P,
   }
   K::stage3(x, lds, t, c);
   if constexpr (R3 > 1) {
-    const float2 v = tw_n(a.twa, a.twb, (int)(256 * k1));
+    const float2 v = v3;
     float2 vb = v;
 #pragma unroll
     for (int bb = 1; bb < R3; ++bb) {
@@ -339,15 +344,21 @@ __global__ __launch_bounds__(C * N2 / 16) void k_pass1(P1Args a) {
     if (gid == 0) a.bdone[0] = 0u;
   }
 
+  // w_{N2}^e, e < N2, in LDS after the exchange buffer (stage-1 and
+  // stage-2 twiddles)
+  float2* twl = lds + Col<N2, C>::LDS_ELEMS;
+  for (int k = (int)tid; k < N2; k += (int)blockDim.x) twl[k] = a.tw[k * (2048 / N2)];
+  __syncthreads();
+
   const int bid = xcd_remap(blockIdx.x, gridDim.x);
   const int b = bid / TILES, tile = bid % TILES;
   const ci_tparams P = a.prm[b];
   // Every band bin lies below n/2 (k2 < N2/2, so m < 8), and below k_high:
   // m <= (k_high / N1) / Lp.  The choice is uniform over the workgroup.
   const int mneed = P.k_high >= P.k_low ? (P.k_high / N1) / Lp + 1 : 1;
-  if (mneed <= 2) pass1_tile<N1, N2, C, 2, H>(a, P, b, tile, lds, t, c);
-  else if (mneed <= 4) pass1_tile<N1, N2, C, 4, H>(a, P, b, tile, lds, t, c);
-  else pass1_tile<N1, N2, C, 8, H>(a, P, b, tile, lds, t, c);
+  if (mneed <= 2) pass1_tile<N1, N2, C, 2, H>(a, P, b, tile, lds, twl, t, c);
+  else if (mneed <= 4) pass1_tile<N1, N2, C, 4, H>(a, P, b, tile, lds, twl, t, c);
+  else pass1_tile<N1, N2, C, 8, H>(a, P, b, tile, lds, twl, t, c);
 }
 
 // ---------------------------------------------------------------------------
@@ -1186,18 +1197,18 @@ struct Inst {
     if (have[precision]) return known[precision];
     hipError_t e;
     if (precision == CI_FP32) {
-      e = lds_fits(k_pass1<N1, N2, C, false>, (size_t)Col<N2, C>::LDS_ELEMS * sizeof(float2));
+      e = lds_fits(k_pass1<N1, N2, C, false>, (size_t)(Col<N2, C>::LDS_ELEMS + N2) * sizeof(float2));
       if (e == hipSuccess)
         e = lds_fits(k_pass2_trig<N1, N2, C, J>,
                      (size_t)(Col<N1, J>::LDS_ELEMS + N1) * sizeof(float2));
       if (e == hipSuccess)
         e = lds_fits(k_pass2_series<N1, N2, C, J>, (size_t)Col<N1, J>::LDS_ELEMS * sizeof(float2));
     } else if (precision == CI_SPLIT_BF16) {
-      e = lds_fits(k_pass1<N1, N2, C, true>, (size_t)Col<N2, C>::LDS_ELEMS * sizeof(float2));
+      e = lds_fits(k_pass1<N1, N2, C, true>, (size_t)(Col<N2, C>::LDS_ELEMS + N2) * sizeof(float2));
       if (e == hipSuccess) e = lds_fits(k_p2mx<N1, N2, C, J, kBF16, 0>, p2mx_lds_bytes<N1>(J));
       if (e == hipSuccess) e = lds_fits(k_p2mx<N1, N2, C, J, kBF16, 1>, p2mx_lds_bytes<N1>(J));
     } else {
-      e = lds_fits(k_pass1<N1, N2, C, true>, (size_t)Col<N2, C>::LDS_ELEMS * sizeof(float2));
+      e = lds_fits(k_pass1<N1, N2, C, true>, (size_t)(Col<N2, C>::LDS_ELEMS + N2) * sizeof(float2));
       if (e == hipSuccess) e = lds_fits(k_p2mx<N1, N2, C, J, kFP16, 0>, p2mx_lds_bytes<N1>(J));
       if (e == hipSuccess) e = lds_fits(k_p2mx<N1, N2, C, J, kFP16, 1>, p2mx_lds_bytes<N1>(J));
     }
@@ -1210,7 +1221,7 @@ struct Inst {
   }
   template <bool H>
   static hipError_t p1(const BatchArgs& a, bool zero, hipStream_t st) {
-    const size_t lds = (size_t)Col<N2, C>::LDS_ELEMS * sizeof(float2);
+    const size_t lds = (size_t)(Col<N2, C>::LDS_ELEMS + N2) * sizeof(float2);
     auto kern = k_pass1<N1, N2, C, H>;
     hipError_t e = set_lds(kern, lds);
     if (e != hipSuccess) return e;
