@@ -254,8 +254,9 @@ typedef struct {
 /* Run every job of the schedule, with results identical to one
  * ci_find_triggers call per job (same precision, threshold, window and
  * merge flag; merging is within a job).  Batches of all jobs alternate
- * between the context's two internal streams, so consecutive batches
- * overlap across class boundaries; `stream` waits for all of them.
+ * between the context's two internal compute streams (their finalisers
+ * run in order on a third), so consecutive batches overlap across class
+ * boundaries; `stream` waits for all of them.
  * Jobs share the context's workspace: calls on one context must be
  * ordered on the device (one stream, or synchronised).
  * flags: 0.  CI_RUN_GRAPH (capture of the schedule into a HIP graph and
