@@ -71,8 +71,10 @@ __device__ __forceinline__ void split8(const float (&v)[8], typename MxT<PREC>::
 
 // Split 8 FP32 values into the two 16-bit operands of a product.  BF16:
 // the high part is the value truncated to BF16 (exact in FP32, so the low
-// part x - hi is exact before its own rounding).  FP16: round to nearest
-// after the 2^6 pre-scale.
+// part x - hi is exact before its own rounding).  FP16: after the 2^6
+// pre-scale, the high parts are rounded to nearest two at a time, and each
+// low part x - hi comes from one mixed-precision FMA that reads the high
+// part as FP16 and writes its FP16 result into its half of the packed word.
 template <int PREC>
 __device__ __forceinline__ void split8t(const float (&v)[8], typename MxT<PREC>::v8& hi,
                                         typename MxT<PREC>::v8& lo) {
@@ -84,7 +86,24 @@ __device__ __forceinline__ void split8t(const float (&v)[8], typename MxT<PREC>:
       lo[e] = (__bf16)(v[e] - __builtin_bit_cast(float, u));
     }
   } else {
-    split8<PREC>(v, hi, lo);
+    typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+    unsigned hw[4], lw[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const float a = v[2 * i] * MxT<PREC>::kPre, b = v[2 * i + 1] * MxT<PREC>::kPre;
+      h2 h;
+      h.x = (_Float16)a;
+      h.y = (_Float16)b;
+      const unsigned hp = __builtin_bit_cast(unsigned, h);
+      unsigned lp = 0u;
+      asm("v_fma_mixlo_f16 %0, %1, -1.0, %2 op_sel_hi:[1,0,0]" : "+v"(lp) : "v"(hp), "v"(a));
+      asm("v_fma_mixhi_f16 %0, %1, -1.0, %2 op_sel:[1,0,0] op_sel_hi:[1,0,0]"
+          : "+v"(lp) : "v"(hp), "v"(b));
+      hw[i] = hp;
+      lw[i] = lp;
+    }
+    hi = __builtin_bit_cast(typename MxT<PREC>::v8, make_uint4(hw[0], hw[1], hw[2], hw[3]));
+    lo = __builtin_bit_cast(typename MxT<PREC>::v8, make_uint4(lw[0], lw[1], lw[2], lw[3]));
   }
 }
 
