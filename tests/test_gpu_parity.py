@@ -395,3 +395,63 @@ def test_large_banks_sampled(ctx, name):
         if w not in {int(x["window"]) for x in M16}:
             assert float(m["rho2"]) <= wl.snr_threshold ** 2 * (1 + 4 * TOL_SPLIT)
     seg.close()
+
+
+@pytest.mark.parametrize("prec", [ci.SPLIT_BF16, ci.SPLIT_FP16])
+def test_split_range_window_merge_and_overflow(ctx, tiny, prec):
+    """The matrix-core second pass's own post-pass: a search range, an odd
+    window, the merged list and a capacity overflow, against the oracle at
+    the split bar, and the merged list against its per-template list."""
+    j_lo, j_hi, W = 1234, 60001, 3000
+    peaks, trig, cnt = ctx.find_triggers(tiny["seg"], tiny["params"], 4.0, W, j_lo=j_lo,
+                                         j_hi=j_hi, cap=4096, precision=prec)
+    _, mtrig, mcnt = ctx.find_triggers(tiny["seg"], tiny["params"], 4.0, W, j_lo=j_lo,
+                                       j_hi=j_hi, cap=4096, merge=True, precision=prec)
+    _, t3, c3 = ctx.find_triggers(tiny["seg"], tiny["params"], 4.0, W, j_lo=j_lo,
+                                  j_hi=j_hi, cap=3, precision=prec)
+    _sync()
+    P = ci.triggers_to_numpy(peaks)
+    total = int(cnt.cpu()[0])
+    T = ci.triggers_to_numpy(trig, total)
+    for i, zo in enumerate(tiny["zo"]):
+        C.check_peak(P[i], zo, tol=TOL_SPLIT, j_lo=j_lo, j_hi=j_hi)
+        C.check_triggers(T[T["tmpl"] == i], zo, W, 4.0, tol=TOL_SPLIT, j_lo=j_lo, j_hi=j_hi)
+    assert np.all((T["index"] >= j_lo) & (T["index"] < j_hi))
+    M = ci.triggers_to_numpy(mtrig, int(mcnt.cpu()[0]))
+    assert sorted(set(T["window"].tolist())) == M["window"].tolist()
+    for m in M:
+        same = T[T["window"] == m["window"]]
+        best = same[np.lexsort((same["tmpl"], -same["rho2"]))][0]
+        assert (m["tmpl"], m["index"], m["rho2"]) == (best["tmpl"], best["index"], best["rho2"])
+    assert total > 3 and int(c3.cpu()[0]) == total
+    assert np.array_equal(ci.triggers_to_numpy(t3, 3), T[:3])
+
+
+def test_segment_update_equals_fresh_segment(ctx):
+    """ci_segment_update with new data and PSD gives bit for bit what a
+    segment created from that data gives (parameters and search)."""
+    n, fs, fl = 1 << 17, 4096.0, 20.0
+    bank = synth.draw_masses(5, 1.0, 8.0, "loguniform", 31)
+    psd_a = synth.make_psd(n, fs)
+    psd_b = psd_a * (1.0 + 0.3 * np.sin(np.arange(n // 2 + 1) / 500.0) ** 2)
+    xa = synth.make_noise(n, fs, fl, psd_a, 41).astype(np.complex64)
+    xb = synth.make_noise(n, fs, fl, psd_b, 42).astype(np.complex64)
+    seg = _segment(ctx, xa, psd_a, n, fs, fl)
+    ctx.segment_update(seg, _dev(xb), _dev(psd_b))
+    fresh = _segment(ctx, xb, psd_b, n, fs, fl)
+    pu, pf = ctx.gen_templates(seg, bank), ctx.gen_templates(fresh, bank)
+    ru = ctx.find_triggers(seg, pu, 4.0, 4096, cap=4096)
+    rf = ctx.find_triggers(fresh, pf, 4.0, 4096, cap=4096)
+    _sync()
+    assert np.array_equal(pu.cpu().numpy(), pf.cpu().numpy())
+    assert np.array_equal(ru[0].cpu().numpy(), rf[0].cpu().numpy())
+    cu, cf = int(ru[2].cpu()[0]), int(rf[2].cpu()[0])
+    assert cu == cf
+    assert np.array_equal(ru[1].cpu().numpy()[:cu], rf[1].cpu().numpy()[:cf])
+    # and against the oracle on the new data
+    P = ci.triggers_to_numpy(ru[0])
+    for i, (m1, m2) in enumerate(bank):
+        zo, _ = C.oracle_series(xb.astype(np.complex128), psd_b, n, fs, fl, m1, m2)
+        C.check_peak(P[i], zo)
+    seg.close()
+    fresh.close()
