@@ -38,13 +38,17 @@ as follows (the full list of readings lives with the design notes):
 * threshold: strict ">" (the pipeline's "c(t) > lambda");
 * local maxima: aligned windows of W samples, argmax per window, ties to the
   smallest index; across templates, max per window, ties to the smaller
-  template id.
+  template id;
+* chi-squared veto (the test the Conclusions plan, ref. Chi2): p contiguous
+  bands of equal sigma^2 share, chi2 = p sum_l |z_l - z/p|^2.
 
 Every function below is pinned by tests that do not re-type its formula:
 brute-force DFT, Parseval, the stationary-phase identity against an
 independently written 2PN time-to-coalescence, the f^{-7/6} amplitude law,
 the white-noise closed form of sigma^2, noise-free recovery of injections,
-chi^2_2 statistics in noise, and brute force on tiny planted series.
+chi^2_2 statistics in noise, and brute force on tiny planted series; the
+veto by its sum rule, its closed form for an exactly matching signal and
+its chi^2_{2p-2} statistics in noise.
 """
 from __future__ import annotations
 
@@ -289,6 +293,57 @@ def length_class(m1: float, m2: float, f_low: float, fs: float,
         if tau <= nc / fs:
             return nc
     return classes[-1]
+
+
+def chisq_edges(m1: float, m2: float, n: int, fs: float, f_low: float, psd,
+                bands: int):
+    """Bin edges e_0 .. e_p of the chi-squared veto's frequency bands.
+
+    The planned chi-squared test of the Conclusions (their ref. Chi2; the
+    time-frequency discriminator of B. Allen, PRD 71, 062001 (2005)) splits
+    the template band [k_low, k_high] into p contiguous bands carrying equal
+    shares of sigma^2.  Reading: with the inclusive running sum
+    c_k = sum_{k_low <= k' <= k} |h~_k'|^2 / S_k', edge e_l (0 < l < p) is the
+    first bin with c_k >= (l / p) c_{k_high}; e_0 = k_low, e_p = k_high + 1;
+    band l is [e_l, e_{l+1}).
+    """
+    df = fs / n
+    _, _, _, kl, kh = band(m1, m2, n, fs, f_low)
+    if kh < kl:
+        return None
+    h = spa_htilde(n, fs, f_low, m1, m2)
+    c = np.cumsum(np.abs(h[kl:kh + 1]) ** 2 / psd[kl:kh + 1])
+    edges = [kl]
+    for l in range(1, bands):
+        edges.append(kl + int(np.searchsorted(c, (l / bands) * c[-1], side="left")))
+    edges.append(kh + 1)
+    return edges
+
+
+def chisq(xtilde, psd, n: int, fs: float, f_low: float, m1: float, m2: float,
+          j: int, bands: int):
+    """Chi-squared veto value at sample j: p sum_l |z_l(j) - z(j)/p|^2, where
+    z_l is the SNR series (same normalisation as snr_series) of the
+    correlation restricted to band l, so that z = sum_l z_l.  Returns
+    (chi2, z(j), [z_l(j)]); None for an empty template.  In Gaussian noise
+    chi2 has 2p - 2 degrees of freedom (each quadrature of z has unit
+    variance); for a signal exactly matching the template it vanishes up to
+    the discreteness of the band edges."""
+    df = fs / n
+    _, _, _, kl, kh = band(m1, m2, n, fs, f_low)
+    edges = chisq_edges(m1, m2, n, fs, f_low, psd, bands)
+    if edges is None:
+        return None
+    h = spa_htilde(n, fs, f_low, m1, m2)
+    s = math.sqrt(sigma2(h, psd, df, kl, kh))
+    k = np.arange(n, dtype=np.int64)
+    ph = np.exp(2j * np.pi * ((k * j) % n) / n)
+    Z = corr_spectrum(xtilde, h, psd, n, df, kl, kh) / s
+    zl = [complex(np.sum(Z[edges[l]:edges[l + 1]] * ph[edges[l]:edges[l + 1]]))
+          for l in range(bands)]
+    z = sum(zl)
+    chi2 = bands * sum(abs(v - z / bands) ** 2 for v in zl)
+    return chi2, z, zl
 
 
 def search(xtilde, psd, n: int, fs: float, f_low: float, bank, thr: float,

@@ -392,3 +392,106 @@ def test_length_class_rule():
         assert tau <= nc / fs or nc == 1 << 20
         if nc > 1 << 17:
             assert tau > (nc // 2) / fs
+
+
+# ---------------------------------------------------------------------------
+# chi-squared veto (the chi-squared test routine the Conclusions plan)
+# ---------------------------------------------------------------------------
+
+def _chisq_case(n, m1, m2, seed, inj=None):
+    from paper_1006_4644_amd import synth
+    fs, fl = 4096.0, 20.0
+    psd = synth.make_psd(n, fs)
+    x = synth.make_noise(n, fs, fl, psd, seed) if seed is not None else np.zeros(n // 2 + 1, complex)
+    if inj is not None:
+        (im1, im2, snr, j0) = inj
+        h = O.spa_htilde(n, fs, fl, im1, im2, tc=j0 / fs, phic=0.3)
+        _, _, _, kl, kh = O.band(im1, im2, n, fs, fl)
+        x = x + h * (snr / np.sqrt(O.sigma2(h, psd, fs / n, kl, kh)))
+    return x, psd, fs, fl
+
+
+@pytest.mark.parametrize("bands", [2, 8, 16])
+def test_chisq_bands_carry_equal_sigma2(bands):
+    n, fs, fl = 1 << 16, 4096.0, 20.0
+    from paper_1006_4644_amd import synth
+    psd = synth.make_psd(n, fs)
+    m1, m2 = 1.6, 1.2
+    e = O.chisq_edges(m1, m2, n, fs, fl, psd, bands)
+    _, _, _, kl, kh = O.band(m1, m2, n, fs, fl)
+    h = O.spa_htilde(n, fs, fl, m1, m2)
+    w = np.abs(h) ** 2 / psd
+    tot = w[kl:kh + 1].sum()
+    assert e[0] == kl and e[-1] == kh + 1 and all(a < b for a, b in zip(e, e[1:]))
+    big = w[kl:kh + 1].max() / tot
+    for l in range(bands):
+        share = w[e[l]:e[l + 1]].sum() / tot
+        assert abs(share - 1.0 / bands) <= big + 1e-12
+
+
+def test_chisq_sum_rule_matches_series():
+    """The band-limited series, summed directly per band, add up to the SNR
+    series computed through the FFT."""
+    n = 1 << 14
+    x, psd, fs, fl = _chisq_case(n, 2.0, 1.5, 11, inj=(2.0, 1.5, 9.0, 5000))
+    zs, _ = O.snr_series(x, psd, n, fs, fl, 2.0, 1.5)
+    for j in (0, 17, 5000, n - 1):
+        chi2, z, zl = O.chisq(x, psd, n, fs, fl, 2.0, 1.5, j, 8)
+        assert abs(z - zs[j]) <= 1e-10 * np.max(np.abs(zs))
+        assert abs(sum(zl) - z) <= 1e-12 * max(1.0, abs(z))
+
+
+@pytest.mark.parametrize("bands", [4, 16])
+def test_chisq_closed_form_for_matching_signal(bands):
+    """Noise-free, exactly matching signal of SNR rho at j0: z_l(j0) =
+    z(j0) s_l with s_l the band's sigma^2 share, so chi2 = p rho^2 sum_l
+    (s_l - 1/p)^2 exactly (and tiny)."""
+    n, fs, fl = 1 << 15, 4096.0, 20.0
+    m1, m2, rho, j0 = 1.7, 1.3, 12.0, 9000
+    x, psd, fs, fl = _chisq_case(n, m1, m2, None, inj=(m1, m2, rho, j0))
+    chi2, z, zl = O.chisq(x, psd, n, fs, fl, m1, m2, j0, bands)
+    e = O.chisq_edges(m1, m2, n, fs, fl, psd, bands)
+    h = O.spa_htilde(n, fs, fl, m1, m2)
+    w = np.abs(h) ** 2 / psd
+    tot = w[e[0]:e[-1]].sum()
+    shares = [w[e[l]:e[l + 1]].sum() / tot for l in range(bands)]
+    want = bands * abs(z) ** 2 * sum((s - 1.0 / bands) ** 2 for s in shares)
+    assert abs(abs(z) - rho) < 1e-9 * rho
+    assert abs(chi2 - want) <= 1e-9 * max(want, 1e-12) + 1e-20
+    # each share is within one bin's share of 1/p
+    big = w[e[0]:e[-1]].max() / tot
+    assert chi2 <= bands * bands * rho * rho * big * big * (1 + 1e-9)
+
+
+def test_chisq_noise_statistics():
+    """Gaussian noise: chi2 at well-separated samples follows chi^2 with
+    2p - 2 degrees of freedom."""
+    from scipy import stats
+    n, bands = 1 << 14, 6
+    vals = []
+    for seed in (101, 102, 103):
+        x, psd, fs, fl = _chisq_case(n, 2.2, 1.4, seed)
+        for j in range(0, n, 64):
+            vals.append(O.chisq(x, psd, n, fs, fl, 2.2, 1.4, j, bands)[0])
+    vals = np.array(vals)
+    dof = 2 * bands - 2
+    assert abs(vals.mean() - dof) < 5 * np.sqrt(2 * dof / len(vals)) * 1.5
+    # unit-variance quadratures: chi2 / 1 ~ chi^2_{dof}
+    assert stats.kstest(vals, stats.chi2(dof).cdf).pvalue > 1e-3
+
+
+def test_chisq_flags_mismatched_signal():
+    """A loud chirp of another chirp mass: the template's peak carries SNR
+    but its power is unevenly spread over the bands, so chi2 far exceeds
+    its noise mean, while the matching template's chi2 stays near it."""
+    n, bands = 1 << 16, 8
+    x, psd, fs, fl = _chisq_case(n, 1.4, 1.4, 7, inj=(1.6, 1.3, 40.0, 30000))
+    zs, _ = O.snr_series(x, psd, n, fs, fl, 1.4, 1.4)
+    j = int(np.argmax(np.abs(zs)))
+    chi2_bad = O.chisq(x, psd, n, fs, fl, 1.4, 1.4, j, bands)[0]
+    zs2, _ = O.snr_series(x, psd, n, fs, fl, 1.6, 1.3)
+    j2 = int(np.argmax(np.abs(zs2)))
+    chi2_ok = O.chisq(x, psd, n, fs, fl, 1.6, 1.3, j2, bands)[0]
+    assert abs(zs[j]) > 8.0
+    assert chi2_bad > 10 * (2 * bands - 2)
+    assert chi2_ok < 4 * (2 * bands - 2)
