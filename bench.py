@@ -66,6 +66,9 @@ def parse():
                    help="time budget of the CPU oracle baseline")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-copy-probe", action="store_true")
+    p.add_argument("--no-chisq", action="store_true",
+                   help="skip timing the chi-squared veto at the per-template peaks")
+    p.add_argument("--chisq-bands", type=int, default=16)
     p.add_argument("--precision", default="fp32", choices=sorted(PRECISIONS),
                    help="arithmetic of the headline run")
     p.add_argument("--no-split", action="store_true",
@@ -164,6 +167,33 @@ def cpu_baseline(xt_host, psd, wl, bank, budget_s):
             "sample": f"{done} seeded-random templates of the {wl.name} bank, "
                       f"full per-template search (series, peak, window triggers), "
                       f"FP64 numpy, one thread, {el:.1f} s"}
+
+
+def chisq_timing(ctx, ci, seg, params, peaks, n_t, bands, reps=10):
+    """Time the chi-squared veto at every template's peak (one entry per
+    template) on torch's current stream, where the call is enqueued."""
+    import torch
+    out = torch.empty(n_t, dtype=torch.float64, device=peaks.device)
+    for _ in range(2):
+        ctx.chisq(seg, params, peaks, n_t, bands=bands, out=out)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        ctx.chisq(seg, params, peaks, n_t, bands=bands, out=out)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    P = ci.params_to_numpy(params)
+    bins = int(np.sum(np.maximum(P["k_high"].astype(np.int64) - P["k_low"] + 1, 0)))
+    c = out.cpu().numpy()
+    fin = c[np.isfinite(c)]
+    log(f"[bench] chi-squared veto: {n_t} peaks, {bands} bands, {ms:.3f} ms")
+    return {"entries": n_t, "bands": bands, "ms_per_call": round(ms, 4),
+            "entries_per_s": round(n_t / (ms / 1e3), 1),
+            "bins_per_s": round(bins / (ms / 1e3), 1),
+            "median_chi2_per_dof": round(float(np.median(fin)) / (2 * bands - 2), 3)
+            if len(fin) else None}
 
 
 def run_classes(args, lib, ctx, wl):
@@ -391,6 +421,8 @@ def main():
                           "injection_peak_rho_rel_dev_vs_headline": dev,
                           "merged_windows": found}
         out["precision_paths"] = paths
+    if not args.no_chisq:
+        out["chisq_veto"] = chisq_timing(ctx, ci, seg, params, peaks, n_t, args.chisq_bands)
     if not args.no_copy_probe:
         out["copy_probe_gbs"] = round(copy_probe_gbs(), 1)
     if not args.no_cpu_baseline:

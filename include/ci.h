@@ -13,6 +13,7 @@
  *   ci_gen_templates    device_template_init + device_template_proc
  *   ci_matched_filter   device_complex_mf + device_cufft_C2R + device_madd2
  *   ci_find_triggers    device_maxfind + the clusterization step
+ *   ci_chisq            the chi-squared veto planned in the Conclusions
  *
  * Conventions shared by every call
  * --------------------------------
@@ -224,6 +225,31 @@ int ci_find_triggers(ci_ctx* ctx, const ci_segment* seg,
                      int64_t j_hi, ci_trigger* d_peaks, ci_trigger* d_trig,
                      int64_t cap, int64_t* d_count,
                      int32_t merge_across_templates, void* stream);
+
+/* --- chi-squared veto ---------------------------------------------------------
+ * The signal-consistency test the Conclusions plan as the next stage of the
+ * pipeline (their ref. [Chi2], B. Allen, Phys. Rev. D 71, 062001 (2005)),
+ * evaluated at trigger samples.  For trigger i with template t = tmpl and
+ * sample j = index:
+ *  - the band [k_low, k_high] of t splits into p = `bands` contiguous bands
+ *    of equal sigma^2 share: with c_k the running sum of 4 df f^{-7/3}/S
+ *    over [k_low, k], edge e_l (0 < l < p) is the first k with
+ *    c_k >= (l / p) c_{k_high}; e_0 = k_low, e_p = k_high + 1;
+ *  - z_l is the series value z(j)/sigma of ci_matched_filter restricted to
+ *    band l (so z = sum_l z_l), accumulated in FP64 from the segment's
+ *    weighted spectrum and the chirp phase at each bin;
+ *  - d_chisq[i] = p sum_l |z_l - z/p|^2, which in Gaussian noise follows a
+ *    chi-squared law with 2p - 2 degrees of freedom and stays small for a
+ *    signal that matches the template.
+ * d_params: [n] generated on seg (device).  d_trig: [n_trig] device, e.g.
+ * the d_trig or d_peaks output of ci_find_triggers; d_chisq: [n_trig]
+ * doubles, device, owned by the caller.  A trigger whose tmpl is outside
+ * [0, n) or whose index is outside [0, n_seg), and one of an empty
+ * template, gets NaN.  bands: 2..64, else CI_EINVAL.  Asynchronous on
+ * `stream`; no workspace. */
+int ci_chisq(ci_ctx* ctx, const ci_segment* seg, const ci_tparams* d_params,
+             int64_t n, const ci_trigger* d_trig, int64_t n_trig,
+             int32_t bands, double* d_chisq, void* stream);
 
 /* --- batch schedule: length classes -----------------------------------------
  * A bank of uneven chirp lengths is searched in length classes: each

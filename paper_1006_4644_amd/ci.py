@@ -33,7 +33,7 @@ EXPORTED_SYMBOLS = (
     "ci_gen_templates", "ci_matched_filter", "ci_find_triggers",
     "ci_segment_update", "ci_set_timing", "ci_kernel_times",
     "ci_length_classes", "ci_search_classes", "ci_get_tune", "ci_set_tune",
-    "ci_autotune",
+    "ci_autotune", "ci_chisq",
 )
 RUN_GRAPH = 1
 
@@ -128,6 +128,7 @@ _SIGS = {
     "ci_set_tune": (ctypes.c_int, [_vp, ctypes.POINTER(_Tune)]),
     "ci_autotune": (ctypes.c_int, [_vp, _vp, _vp, _i64, _i32, _f32, _i64,
                                    ctypes.POINTER(_Tune), _vp]),
+    "ci_chisq": (ctypes.c_int, [_vp, _vp, _vp, _i64, _vp, _i64, _i32, _vp, _vp]),
 }
 
 _LIB = None
@@ -355,6 +356,21 @@ class Context:
             self.handle, seg.handle, _ptr(params), n, precision, float(thr),
             window, ctypes.byref(t), _stream(stream)))
         return t.as_dict()
+
+    def chisq(self, seg: Segment, params, trig, n_trig: int | None = None,
+              bands: int = 16, n: int | None = None, out=None, stream=None):
+        """Chi-squared veto at trigger samples: trig is a (m, 4) int64 device
+        tensor of ci_trigger rows; returns float64 [n_trig] (NaN for an
+        invalid or empty entry)."""
+        import torch
+        n = params.shape[0] if n is None else n
+        n_trig = trig.shape[0] if n_trig is None else n_trig
+        if out is None:
+            out = torch.empty(max(n_trig, 1), dtype=torch.float64, device=trig.device)
+        self._chk(self.lib.dll.ci_chisq(
+            self.handle, seg.handle, _ptr(params), n, _ptr(trig), n_trig, bands,
+            _ptr(out), _stream(stream)))
+        return out[:n_trig]
 
     def search_classes(self, jobs, thr: float, window: int, merge: bool = False,
                        precision: int = FP32, graph: bool = False, stream=None):

@@ -779,6 +779,24 @@ int ci_find_triggers(ci_ctx* ctx, const ci_segment* seg, const ci_tparams* d_par
                       merge_across_templates ? 1 : 0, static_cast<hipStream_t>(stream));
 }
 
+int ci_chisq(ci_ctx* ctx, const ci_segment* seg, const ci_tparams* d_params, int64_t n,
+             const ci_trigger* d_trig, int64_t n_trig, int32_t bands, double* d_chisq,
+             void* stream) {
+  if (!ctx) return fail(nullptr, CI_EINVAL, "null context");
+  if (!seg) return fail(ctx, CI_EINVAL, "null segment");
+  if (n < 0 || n_trig < 0) return fail(ctx, CI_EINVAL, "negative count");
+  if (bands < 2 || bands > 64) return fail(ctx, CI_EINVAL, "bands %d outside 2..64", bands);
+  if (n_trig == 0) return CI_OK;
+  if (!d_trig || !d_chisq) return fail(ctx, CI_EINVAL, "null trigger or output pointer");
+  if (n > 0 && !d_params) return fail(ctx, CI_EINVAL, "null d_params");
+  DeviceGuard dg(ctx->device);
+  if (!dg.ok) return fail(ctx, CI_EHIP, "cannot select device %d", ctx->device);
+  const hipError_t e = launch_chisq(seg, d_params, n, d_trig, n_trig, bands, d_chisq,
+                                    static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hipfail(ctx, e, "chi-squared launch");
+  return CI_OK;
+}
+
 int ci_search_classes(ci_ctx* ctx, const ci_class_job* jobs_in, int32_t njobs, int32_t precision,
                       float snr_threshold, int64_t window, int32_t merge_across_templates,
                       int32_t flags, void* stream) {

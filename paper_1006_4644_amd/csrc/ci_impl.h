@@ -125,6 +125,10 @@ hipError_t launch_params(const Seg* s, ci_tparams* d_params, int64_t n,
                          void* d_htilde, hipStream_t st);
 hipError_t launch_init_call(const TrigWork& tw, int nwin, int64_t* d_count,
                             hipStream_t st);
+// Chi-squared veto of ntrig triggers (bands 2..64).
+hipError_t launch_chisq(const Seg* s, const ci_tparams* d_params, int64_t ntmpl,
+                        const ci_trigger* d_trig, int64_t ntrig, int bands, double* d_out,
+                        hipStream_t st);
 // Matrix-core operand tables of a segment (after its FP64 twiddles exist).
 hipError_t launch_mx_tables(Seg* s, hipStream_t st);
 

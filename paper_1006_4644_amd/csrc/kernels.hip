@@ -712,7 +712,6 @@ __device__ __forceinline__ void pass2_tile(float2 (&x)[16], const P2Args& a, int
                                            float2* lds, const float2* twl, u64* s_best,
                                            unsigned tid, unsigned cc, unsigned t) {
   constexpr int TILES = N2 / J;
-  using K = Col<N1, J>;
   const int b = item / TILES, tile = item % TILES;
   fft_col<N1, J, 1>(x, lds, t, cc, twl);
   pass2_post<N1, N2, C, J>(x, a, b, tile, s_best, tid, cc, t);
@@ -751,7 +750,6 @@ __device__ __forceinline__ void pass2_post(const float2 (&x)[16], const P2Args& 
 // its butterflies.
 template <int N1, int N2, int C, int J>
 __global__ __launch_bounds__(J * N1 / 16, 4) void k_pass2_trig(P2Args a) {
-  constexpr int N = N1 * N2;
   constexpr int TILES = N2 / J;
   using K = Col<N1, J>;
   extern __shared__ float2 lds[];
@@ -1035,6 +1033,112 @@ __global__ void k_init_call(ci_trigger* mrec, int nwin, u64* run, int64_t* d_cou
 }
 
 // ---------------------------------------------------------------------------
+// chi-squared veto at trigger samples
+// ---------------------------------------------------------------------------
+
+constexpr int kChiThreads = 256;
+constexpr int kChiMaxBands = 64;
+
+// Sum of a double2 over the workgroup (every thread gets the result).
+__device__ __forceinline__ double2 block_sum_d2(double2 v, double2* sh) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    v.x += __shfl_xor(v.x, off, 64);
+    v.y += __shfl_xor(v.y, off, 64);
+  }
+  __syncthreads();
+  if (lane == 0) sh[wave] = v;
+  __syncthreads();
+  double2 t = make_double2(0.0, 0.0);
+  for (int w = 0; w < kChiThreads / 64; ++w) {
+    t.x += sh[w].x;
+    t.y += sh[w].y;
+  }
+  return t;
+}
+
+// One workgroup per trigger: band edges by binary search of the FP64
+// running sum of 4 df f^{-7/3} / S (the template's sigma^2 up to bin k),
+// band-limited SNR z_l at the trigger's sample j with
+//   Z_k exp(2 pi i j k / n) = scale w_k exp(2 pi i (Psi_k / 2 pi + j k / n)),
+// the phase fraction formed in FP64 and the terms accumulated in FP64, and
+// chi2 = p sum_l |z_l - z / p|^2 with z = sum_l z_l.
+__global__ __launch_bounds__(kChiThreads) void k_chisq(const SegDev* __restrict__ sd,
+                                                       const ci_tparams* __restrict__ prm,
+                                                       int64_t ntmpl,
+                                                       const float2* __restrict__ w,
+                                                       const double* __restrict__ psum,
+                                                       const ci_trigger* __restrict__ trig,
+                                                       int bands, double* __restrict__ out) {
+  __shared__ int s_edge[kChiMaxBands + 1];
+  __shared__ double2 s_red[kChiThreads / 64];
+  __shared__ double2 s_zl[kChiMaxBands];
+  const int64_t i = blockIdx.x;
+  const int tid = threadIdx.x;
+  const ci_trigger tr = trig[i];
+  const int64_t n = sd->n;
+  const bool valid_idx = tr.tmpl >= 0 && tr.tmpl < ntmpl && tr.index >= 0 && tr.index < n;
+  ci_tparams P;
+  if (valid_idx) P = prm[tr.tmpl];
+  if (!valid_idx || P.k_high < P.k_low || (P.flags & CI_TMPL_EMPTY)) {
+    if (tid == 0) out[i] = __builtin_nan("");
+    return;
+  }
+  const int kl = P.k_low, kh = P.k_high;
+  const double total = psum[kh];
+  if (tid == 0) {
+    s_edge[0] = kl;
+    s_edge[bands] = kh + 1;
+  }
+  if (tid >= 1 && tid < bands) {
+    // first k in [kl, kh] with psum[k] >= (tid / bands) total
+    const double thr = total * (double)tid / (double)bands;
+    int lo = kl, hi = kh;
+    while (lo < hi) {
+      const int mid = lo + (hi - lo) / 2;
+      if (psum[mid] >= thr) hi = mid;
+      else lo = mid + 1;
+    }
+    s_edge[tid] = lo;
+  }
+  __syncthreads();
+  // n is a power of two: (j k) mod n is a mask
+  const uint64_t j = (uint64_t)tr.index, nmask = (uint64_t)n - 1;
+  const double inv_n = 1.0 / (double)n;
+  for (int l = 0; l < bands; ++l) {
+    double2 acc = make_double2(0.0, 0.0);
+    for (int k = s_edge[l] + tid; k < s_edge[l + 1]; k += kChiThreads) {
+      double f = (double)phase_frac(P, k) + (double)((j * (uint64_t)k) & nmask) * inv_n;
+      f -= rint(f);
+      const float fr = (float)f;
+      const float2 e = make_float2(__builtin_amdgcn_cosf(fr) * P.scale,
+                                   __builtin_amdgcn_sinf(fr) * P.scale);
+      const float2 t = cmul(w[k], e);
+      acc.x += (double)t.x;
+      acc.y += (double)t.y;
+    }
+    const double2 zl = block_sum_d2(acc, s_red);
+    if (tid == 0) s_zl[l] = zl;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double zr = 0.0, zi = 0.0;
+    for (int l = 0; l < bands; ++l) {
+      zr += s_zl[l].x;
+      zi += s_zl[l].y;
+    }
+    const double pr = zr / bands, pi = zi / bands;
+    double c = 0.0;
+    for (int l = 0; l < bands; ++l) {
+      const double dr = s_zl[l].x - pr, di = s_zl[l].y - pi;
+      c += dr * dr + di * di;
+    }
+    out[i] = bands * c;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // host launchers
 // ---------------------------------------------------------------------------
 
@@ -1084,6 +1188,19 @@ hipError_t launch_params(const Seg* s, ci_tparams* d_params, int64_t n, void* d_
     hipLaunchKernelGGL(k_htilde, dim3(bx, (unsigned)cnt), dim3(256), 0, st, s->dev,
                        d_params + t0, reinterpret_cast<float2*>(d_htilde) + t0 * m);
     e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_chisq(const Seg* s, const ci_tparams* d_params, int64_t ntmpl,
+                        const ci_trigger* d_trig, int64_t ntrig, int bands, double* d_out,
+                        hipStream_t st) {
+  for (int64_t t0 = 0; t0 < ntrig; t0 += 65535 * 64) {
+    const int64_t cnt = (ntrig - t0 < 65535 * 64) ? ntrig - t0 : 65535 * 64;
+    hipLaunchKernelGGL(k_chisq, dim3((unsigned)cnt), dim3(kChiThreads), 0, st, s->dev, d_params,
+                       ntmpl, s->w, s->psum, d_trig + t0, bands, d_out + t0);
+    const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
