@@ -31,6 +31,8 @@
  * - "d_" arguments are device pointers (hipMalloc'd or torch CUDA tensors);
  *   "host" arguments are host pointers.
  * - One ci_ctx per host thread.  Calls that share a ctx must not overlap.
+ *   A segment passed with a ctx must have been created on that ctx
+ *   (CI_EINVAL otherwise).
  * - Frequencies f_k = k fs/n, k = 0..n/2; df = fs/n; T = n/fs.
  * - Spectra are one-sided.  The inner product is
  *   <a, b> = 4 Re sum_k df a_k conj(b_k) / S_k (eq. (matchedfilter) taken at
@@ -129,6 +131,9 @@ typedef struct ci_tparams {
 
 /* Create a context bound to HIP device `device`.  *out receives the handle. */
 int ci_ctx_create(int device, ci_ctx** out);
+/* Frees the context's workspaces.  Segments created on it that are still
+ * alive are detached: their buffers stay valid until ci_segment_destroy,
+ * the only call that accepts them afterwards (others return CI_EINVAL). */
 int ci_ctx_destroy(ci_ctx* ctx);
 
 /* Message of the last failed call on `ctx` (or, with ctx == NULL, of the

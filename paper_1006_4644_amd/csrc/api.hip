@@ -196,6 +196,8 @@ int check_filter_args(Ctx* ctx, const void* seg, const ci_tparams* d_params, int
                       int32_t precision) {
   if (!ctx) return fail(nullptr, CI_EINVAL, "null context");
   if (!seg) return fail(ctx, CI_EINVAL, "null segment");
+  if (static_cast<const Seg*>(seg)->ctx != ctx)
+    return fail(ctx, CI_EINVAL, "segment belongs to another (or a destroyed) context");
   if (n < 0) return fail(ctx, CI_EINVAL, "negative template count %lld", (long long)n);
   if (n > 0 && !d_params) return fail(ctx, CI_EINVAL, "null d_params");
   if (precision != CI_FP32 && precision != CI_SPLIT_BF16 && precision != CI_SPLIT_FP16)
@@ -469,6 +471,8 @@ int ci_ctx_destroy(ci_ctx* ctx) {
   }
   if (ctx->ybuf) (void)hipFree(ctx->ybuf);
   if (ctx->tbuf) (void)hipFree(ctx->tbuf);
+  // segments still alive keep their buffers until ci_segment_destroy
+  for (Seg* sg : ctx->segs) sg->ctx = nullptr;
   delete ctx;
   return CI_OK;
 }
@@ -540,6 +544,7 @@ int ci_segment_create(ci_ctx* ctx, const ci_segment_spec* spec, const void* d_xt
   ci_segment* s = new (std::nothrow) ci_segment();
   if (!s) return fail(ctx, CI_ENOMEM, "segment allocation");
   s->ctx = ctx;
+  s->device = ctx->device;
   s->spec = *spec;
   s->plan = plan_for(l2, 8, 4);
   SegDev& h = s->host;
@@ -612,13 +617,23 @@ int ci_segment_create(ci_ctx* ctx, const ci_segment_spec* spec, const void* d_xt
     free_seg(s);
     return hipfail(ctx, e, "segment setup launch");
   }
+  ctx->segs.push_back(s);
   *out = s;
   return CI_OK;
 }
 
 int ci_segment_destroy(ci_segment* seg) {
   if (!seg) return CI_OK;
-  DeviceGuard g(seg->ctx->device);
+  if (seg->ctx) {
+    auto& v = seg->ctx->segs;
+    for (size_t i = 0; i < v.size(); ++i)
+      if (v[i] == seg) {
+        v[i] = v.back();
+        v.pop_back();
+        break;
+      }
+  }
+  DeviceGuard g(seg->device);
   // buffers may still be read by enqueued work: wait for the device
   (void)hipDeviceSynchronize();
   free_seg(seg);
@@ -628,6 +643,7 @@ int ci_segment_destroy(ci_segment* seg) {
 int ci_segment_update(ci_segment* seg, const void* d_xtilde, const double* d_psd, void* stream) {
   if (!seg) return fail(nullptr, CI_EINVAL, "null segment");
   Ctx* ctx = seg->ctx;
+  if (!ctx) return fail(nullptr, CI_EINVAL, "the segment's context was destroyed");
   if (!d_xtilde || !d_psd) return fail(ctx, CI_EINVAL, "null data or PSD pointer");
   DeviceGuard dg(ctx->device);
   if (!dg.ok) return fail(ctx, CI_EHIP, "cannot select device %d", ctx->device);
@@ -669,6 +685,8 @@ int ci_gen_templates(ci_ctx* ctx, const ci_segment* seg, const ci_template* bank
                      ci_tparams* d_params, void* d_htilde_opt, void* stream) {
   if (!ctx) return fail(nullptr, CI_EINVAL, "null context");
   if (!seg) return fail(ctx, CI_EINVAL, "null segment");
+  if (seg->ctx != ctx)
+    return fail(ctx, CI_EINVAL, "segment belongs to another (or a destroyed) context");
   if (n < 0) return fail(ctx, CI_EINVAL, "negative template count");
   if (n == 0) return CI_OK;
   if (!bank_host || !d_params) return fail(ctx, CI_EINVAL, "null bank or d_params");
@@ -784,6 +802,8 @@ int ci_chisq(ci_ctx* ctx, const ci_segment* seg, const ci_tparams* d_params, int
              void* stream) {
   if (!ctx) return fail(nullptr, CI_EINVAL, "null context");
   if (!seg) return fail(ctx, CI_EINVAL, "null segment");
+  if (seg->ctx != ctx)
+    return fail(ctx, CI_EINVAL, "segment belongs to another (or a destroyed) context");
   if (n < 0 || n_trig < 0) return fail(ctx, CI_EINVAL, "negative count");
   if (bands < 2 || bands > 64) return fail(ctx, CI_EINVAL, "bands %d outside 2..64", bands);
   if (n_trig == 0) return CI_OK;

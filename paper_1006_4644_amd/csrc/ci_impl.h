@@ -66,6 +66,8 @@ struct TimedLaunch {
   hipEvent_t e0, e1;
 };
 
+struct Seg;
+
 // Host-side state.
 struct Ctx {
   int device = 0;
@@ -92,6 +94,8 @@ struct Ctx {
   hipEvent_t fin_done[kSlots] = {};  // finaliser of the slot's batch done
   // launch configuration per (log2 n, precision): autotuned or default
   Tune tune[32][3];
+  // live segments created on this context (detached when it is destroyed)
+  std::vector<Seg*> segs;
   // instrumentation
   bool timing = false;
   std::vector<TimedLaunch> launches;
@@ -99,7 +103,8 @@ struct Ctx {
 };
 
 struct Seg {
-  Ctx* ctx;
+  Ctx* ctx;          // owning context; null once that context is destroyed
+  int device;        // HIP device of the segment's buffers
   ci_segment_spec spec;
   SegDev host;       // host copy (g and p_total are only valid on device)
   SegDev* dev;       // device copy

@@ -49,7 +49,7 @@ def tiny(ctx):
     zo = [C.oracle_series(x128, psd, wl.n, wl.fs, wl.f_low, m1, m2)[0]
           for m1, m2 in bank]
     return dict(wl=wl, bank=bank, injs=injs, x64=x64, psd=psd, x128=x128,
-                seg=seg, params=params, zo=zo)
+                seg=seg, params=params, zo=zo, ctx=ctx)
 
 
 def test_gen_templates_params_and_htilde(ctx, tiny):
@@ -218,6 +218,35 @@ def test_argument_errors(ctx, tiny):
     with pytest.raises(ci.CiError) as ei:
         ctx.segment(bad, badp, 2**16, 4096.0, 3000.0)
     assert ei.value.code == ci.EINVAL
+
+
+def test_segment_outlives_its_context(gpu_lib, tiny):
+    """A segment still alive when its context is destroyed is detached: it
+    can only be destroyed, other calls reject it, and nothing the library
+    does afterwards sees a stale device error."""
+    wl = tiny["wl"]
+    x = _dev(tiny["x64"])
+    p = _dev(tiny["psd"])
+    a = gpu_lib.context(0)
+    sa = a.segment(x, p, wl.n, wl.fs, wl.f_low)
+    a.close()
+    b = gpu_lib.context(0)
+    with pytest.raises(ci.CiError) as ei:
+        b.gen_templates(sa, tiny["bank"])
+    assert ei.value.code == ci.EINVAL
+    with pytest.raises(ci.CiError) as ei:
+        b.segment_update(sa, x, p)
+    assert ei.value.code == ci.EINVAL
+    sa.close()
+    sb = b.segment(x, p, wl.n, wl.fs, wl.f_low)
+    params = b.gen_templates(sb, tiny["bank"])
+    z = b.matched_filter(sb, params)
+    _sync()
+    assert np.array_equal(z.cpu().numpy()[0],
+                          tiny["ctx"].matched_filter(tiny["seg"], tiny["params"])
+                          .cpu().numpy()[0])
+    sb.close()
+    b.close()
 
 
 def test_full_size_fp32_workload_sampled(ctx):
