@@ -14,6 +14,8 @@
  *   ci_matched_filter   device_complex_mf + device_cufft_C2R + device_madd2
  *   ci_find_triggers    device_maxfind + the clusterization step
  *   ci_chisq            the chi-squared veto planned in the Conclusions
+ *   ci_td_*             the paper's own template form: time-domain
+ *                       generator, two polarizations, two C2R + madd2
  *
  * Conventions shared by every call
  * --------------------------------
@@ -127,6 +129,32 @@ typedef struct ci_tparams {
   int32_t reserved[2];
 } ci_tparams;
 
+/* Constants of one two-polarization time-domain template (the paper's own
+ * generator: phase of post-Newtonian order 2.5, Newtonian amplitude), made
+ * by ci_td_params, device-resident, 176 bytes.  TaylorT2 from energy
+ * balance with the published 2PN binding energy and 2.5PN flux, t_c = 0:
+ *   t(v)   = -K v^-8 (1 + tau_2 v^2 + tau_3 v^3 + tau_4 v^4 + tau_5 v^5),
+ *   dt/dv  = 8 K v^-9 (1 + r_2 v^2 + r_3 v^3 + r_4 v^4 + r_5 v^5),
+ *   phi(v) = -P (v^-5 (1 + p_2 v^2 + p_3 v^3 + p_4 v^4) + p_5 ln v),
+ * K = 5M/(256 eta), P = 1/(32 eta), phi the orbital phase.  Sample m >= 1
+ * before coalescence (time -m/fs, index n - m of the circular grid) holds
+ * h_+ + i h_x = v^2 exp(2 i phi(v)) with t(v) = -m/fs, for m_lo <= m <= m_hi
+ * (v from v_low = (pi M f_low)^{1/3} to the ISCO v_end = 6^{-1/2}); the
+ * statistic's band is k_low <= k <= n/2 - 1. */
+typedef struct ci_tdparams {
+  double m1, m2;          /* canonical masses, m1 >= m2 */
+  double K;               /* 5 M / (256 eta), seconds */
+  double tau[4];          /* tau_2 .. tau_5 */
+  double r[4];            /* r_2 .. r_5 */
+  double P;               /* 1 / (32 eta) */
+  double p[4];            /* p_2 .. p_5 */
+  double v_low, v_end;
+  int64_t m_lo, m_hi;     /* chirp samples; m_hi < m_lo for an empty template */
+  int32_t k_low, k_high;  /* band of the statistic */
+  int32_t flags;          /* CI_TMPL_EMPTY */
+  int32_t reserved;
+} ci_tdparams;
+
 /* --- context ------------------------------------------------------------ */
 
 /* Create a context bound to HIP device `device`.  *out receives the handle. */
@@ -230,6 +258,48 @@ int ci_find_triggers(ci_ctx* ctx, const ci_segment* seg,
                      int64_t j_hi, ci_trigger* d_peaks, ci_trigger* d_trig,
                      int64_t cap, int64_t* d_count,
                      int32_t merge_across_templates, void* stream);
+
+/* --- the paper's two-polarization form ----------------------------------------
+ * The template form of "Template generation" and of the per-template loop
+ * of "Matched filtering": both polarizations generated in the time domain,
+ * Fourier transformed, each normalised to unit norm (sigma_+^2 = <h_+, h_+>,
+ * sigma_x^2 = <h_x, h_x>), correlated with the data through
+ * eq. (matchedfilter), taken back to the time domain by two real inverse
+ * transforms (the paper's two device_cufft_C2R) and combined in quadrature
+ * (device_madd2):
+ *   c_+(t_j) = 4 Re sum_{k_low <= k <= n/2-1} df x~_k conj(H~+_k) e^{2 pi i jk/n}
+ *              / S_k / sigma_+,   likewise c_x,   rho^2 = c_+^2 + c_x^2,
+ * with H~_k = dt sum_j h_j e^{-2 pi i jk/n}.  On the device the two real
+ * transforms are one complex transform of the Hermitian-packed spectrum
+ * (its real part is c_+, its imaginary part c_x), and the two forward
+ * transforms are one complex transform of u = h_+ + i h_x.  FP32 arithmetic
+ * (FP64 for v(t), the phase and sigma^2); no split-precision variant.
+ *
+ * ci_td_params (bank on the host, outputs on the device): d_tdparams[n],
+ * asynchronous on `stream`; CI_EINVAL for a non-positive mass. */
+int ci_td_params(ci_ctx* ctx, const ci_segment* seg, const ci_template* bank_host,
+                 int64_t n, ci_tdparams* d_tdparams, void* stream);
+
+/* Materialise templates (tests, inspection).  Any output may be NULL:
+ *   d_u      complex64 [n][n_seg]: h_+ + i h_x on the circular grid;
+ *   d_hf     complex64 [n][2][n_seg/2 + 1]: H~+_k then H~x_k, k = 0..n_seg/2;
+ *   d_sigma2 double [n][2]: sigma_+^2, sigma_x^2 (0 for an empty template).
+ * Uses the context's workspace. */
+int ci_td_templates(ci_ctx* ctx, const ci_segment* seg, const ci_tdparams* d_tdparams,
+                    int64_t n, void* d_u, void* d_hf, double* d_sigma2, void* stream);
+
+/* Series: d_z complex64 [n][n_seg] receives c_+ + i c_x (zero for an empty
+ * template). */
+int ci_td_matched_filter(ci_ctx* ctx, const ci_segment* seg, const ci_tdparams* d_tdparams,
+                         int64_t n, void* d_z, void* stream);
+
+/* Search with the two-polarization statistic: arguments, outputs, ordering,
+ * merge and error behaviour as ci_find_triggers (FP32); re/im of a trigger
+ * are c_+ and c_x at its sample. */
+int ci_td_find_triggers(ci_ctx* ctx, const ci_segment* seg, const ci_tdparams* d_tdparams,
+                        int64_t n, float snr_threshold, int64_t window, int64_t j_lo,
+                        int64_t j_hi, ci_trigger* d_peaks, ci_trigger* d_trig, int64_t cap,
+                        int64_t* d_count, int32_t merge_across_templates, void* stream);
 
 /* --- chi-squared veto ---------------------------------------------------------
  * The signal-consistency test the Conclusions plan as the next stage of the

@@ -33,7 +33,8 @@ EXPORTED_SYMBOLS = (
     "ci_gen_templates", "ci_matched_filter", "ci_find_triggers",
     "ci_segment_update", "ci_set_timing", "ci_kernel_times",
     "ci_length_classes", "ci_search_classes", "ci_get_tune", "ci_set_tune",
-    "ci_autotune", "ci_chisq",
+    "ci_autotune", "ci_chisq", "ci_td_params", "ci_td_templates",
+    "ci_td_matched_filter", "ci_td_find_triggers",
 )
 RUN_GRAPH = 1
 
@@ -47,7 +48,14 @@ TPARAMS_DTYPE = np.dtype([("m1", "<f8"), ("m2", "<f8"), ("x0", "<f8"),
                           ("scale", "<f4"), ("k_low", "<i4"),
                           ("k_high", "<i4"), ("flags", "<i4"),
                           ("reserved", "<i4", (2,))])
+# ci_tdparams (176 bytes)
+TDPARAMS_DTYPE = np.dtype([("m1", "<f8"), ("m2", "<f8"), ("K", "<f8"),
+                           ("tau", "<f8", (4,)), ("r", "<f8", (4,)), ("P", "<f8"),
+                           ("p", "<f8", (4,)), ("v_low", "<f8"), ("v_end", "<f8"),
+                           ("m_lo", "<i8"), ("m_hi", "<i8"), ("k_low", "<i4"),
+                           ("k_high", "<i4"), ("flags", "<i4"), ("reserved", "<i4")])
 assert TRIGGER_DTYPE.itemsize == 32 and TPARAMS_DTYPE.itemsize == 96
+assert TDPARAMS_DTYPE.itemsize == 176
 
 
 class LibraryMissing(RuntimeError):
@@ -129,6 +137,11 @@ _SIGS = {
     "ci_autotune": (ctypes.c_int, [_vp, _vp, _vp, _i64, _i32, _f32, _i64,
                                    ctypes.POINTER(_Tune), _vp]),
     "ci_chisq": (ctypes.c_int, [_vp, _vp, _vp, _i64, _vp, _i64, _i32, _vp, _vp]),
+    "ci_td_params": (ctypes.c_int, [_vp, _vp, _vp, _i64, _vp, _vp]),
+    "ci_td_templates": (ctypes.c_int, [_vp, _vp, _vp, _i64, _vp, _vp, _vp, _vp]),
+    "ci_td_matched_filter": (ctypes.c_int, [_vp, _vp, _vp, _i64, _vp, _vp]),
+    "ci_td_find_triggers": (ctypes.c_int, [_vp, _vp, _vp, _i64, _f32, _i64, _i64, _i64,
+                                           _vp, _vp, _i64, _vp, _i32, _vp]),
 }
 
 _LIB = None
@@ -372,6 +385,69 @@ class Context:
             _ptr(out), _stream(stream)))
         return out[:n_trig]
 
+    # --- the paper's two-polarization (time-domain) template form ---------
+
+    def td_params(self, seg: Segment, bank, stream=None, out=None):
+        """Time-domain template constants (uint8 CUDA tensor [n, 176]) for a
+        (n, 2) bank."""
+        import torch
+        bank = np.ascontiguousarray(np.asarray(bank, dtype=np.float64).reshape(-1, 2))
+        n = bank.shape[0]
+        dev = torch.device("cuda", self.device)
+        tdp = out if out is not None else torch.empty(
+            (max(n, 1), TDPARAMS_DTYPE.itemsize), dtype=torch.uint8, device=dev)
+        self._chk(self.lib.dll.ci_td_params(
+            self.handle, seg.handle, bank.ctypes.data, n, _ptr(tdp), _stream(stream)))
+        return tdp
+
+    def td_templates(self, seg: Segment, tdp, n: int | None = None, u: bool = True,
+                     hf: bool = True, sigma2: bool = True, stream=None):
+        """(u [n, N] complex64 or None, hf [n, 2, N/2+1] complex64 or None,
+        sigma2 [n, 2] float64 or None)."""
+        import torch
+        n = tdp.shape[0] if n is None else n
+        dev = tdp.device
+        N = seg.n
+        ou = torch.empty((max(n, 1), N), dtype=torch.complex64, device=dev) if u else None
+        oh = torch.empty((max(n, 1), 2, N // 2 + 1), dtype=torch.complex64,
+                         device=dev) if hf else None
+        os_ = torch.empty((max(n, 1), 2), dtype=torch.float64, device=dev) if sigma2 else None
+        self._chk(self.lib.dll.ci_td_templates(
+            self.handle, seg.handle, _ptr(tdp), n, _ptr(ou) if u else None,
+            _ptr(oh) if hf else None, _ptr(os_) if sigma2 else None, _stream(stream)))
+        return ou, oh, os_
+
+    def td_matched_filter(self, seg: Segment, tdp, n: int | None = None, out=None,
+                          stream=None):
+        """c_+ + i c_x per template, complex64 [n, N]."""
+        import torch
+        n = tdp.shape[0] if n is None else n
+        if out is None:
+            out = torch.empty((max(n, 1), seg.n), dtype=torch.complex64, device=tdp.device)
+        self._chk(self.lib.dll.ci_td_matched_filter(
+            self.handle, seg.handle, _ptr(tdp), n, _ptr(out), _stream(stream)))
+        return out
+
+    def td_find_triggers(self, seg: Segment, tdp, thr: float, window: int,
+                         n: int | None = None, j_lo: int = 0, j_hi: int = 0,
+                         cap: int = 1 << 16, merge: bool = False, peaks=None, trig=None,
+                         count=None, stream=None):
+        """Search with the two-polarization statistic; returns (peaks, trig,
+        count) device tensors as find_triggers."""
+        import torch
+        n = tdp.shape[0] if n is None else n
+        dev = tdp.device
+        if peaks is None:
+            peaks = torch.empty((max(n, 1), 4), dtype=torch.int64, device=dev)
+        if trig is None:
+            trig = torch.empty((max(cap, 1), 4), dtype=torch.int64, device=dev)
+        if count is None:
+            count = torch.zeros(1, dtype=torch.int64, device=dev)
+        self._chk(self.lib.dll.ci_td_find_triggers(
+            self.handle, seg.handle, _ptr(tdp), n, float(thr), window, j_lo, j_hi,
+            _ptr(peaks), _ptr(trig), cap, _ptr(count), 1 if merge else 0, _stream(stream)))
+        return peaks, trig, count
+
     def search_classes(self, jobs, thr: float, window: int, merge: bool = False,
                        precision: int = FP32, graph: bool = False, stream=None):
         """Multi-class search.  jobs: list of dicts with keys seg, params
@@ -413,3 +489,7 @@ def triggers_to_numpy(t, count: int | None = None) -> np.ndarray:
 
 def params_to_numpy(p) -> np.ndarray:
     return p.detach().cpu().numpy().view(TPARAMS_DTYPE).reshape(-1)
+
+
+def tdparams_to_numpy(p) -> np.ndarray:
+    return p.detach().cpu().numpy().view(TDPARAMS_DTYPE).reshape(-1)

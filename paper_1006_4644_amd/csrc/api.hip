@@ -118,6 +118,8 @@ void free_seg(Seg* s) {
   if (!s) return;
   if (s->dev) (void)hipFree(s->dev);
   if (s->w) (void)hipFree(s->w);
+  if (s->w0) (void)hipFree(s->w0);
+  if (s->isp) (void)hipFree(s->isp);
   if (s->psum) (void)hipFree(s->psum);
   if (s->bsum) (void)hipFree(s->bsum);
   if (s->tw2048) (void)hipFree(s->tw2048);
@@ -136,6 +138,64 @@ int64_t default_batch(const Ctx* ctx, int64_t nseg) {
   return b < 1 ? 1 : b;
 }
 
+// Constants of one two-polarization time-domain template: TaylorT2 at
+// 2.5PN from energy balance, dt/dv = -E'(v)/F(v), with the published 2PN
+// binding energy and 2.5PN flux (Blanchet, Damour, Iyer, Will & Wiseman,
+// PRL 74, 3515 (1995); Blanchet, CQG 13, 619 (1996)).  The ratio
+// (E'/E'_N) / (F/F_N) is expanded to O(v^5) by power-series division and
+// integrated term by term (t_c = phi_c = 0).
+void host_td_params(const ci_template& tm, const SegDev& sd, ci_tdparams* T) {
+  const double m1 = tm.m1 >= tm.m2 ? tm.m1 : tm.m2;
+  const double m2 = tm.m1 >= tm.m2 ? tm.m2 : tm.m1;
+  memset(T, 0, sizeof *T);
+  T->m1 = m1;
+  T->m2 = m2;
+  const double M = (m1 + m2) * kTSun;
+  const double eta = m1 * m2 / ((m1 + m2) * (m1 + m2));
+  // E = -(M eta / 2) v^2 (1 + a v^2 + b v^4): E'/E'_N = 1 + 2a v^2 + 3b v^4
+  const double a2 = -(0.75 + eta / 12.0);
+  const double a4 = -(27.0 / 8.0 - 19.0 * eta / 8.0 + eta * eta / 24.0);
+  const double num[6] = {1.0, 0.0, 2.0 * a2, 0.0, 3.0 * a4, 0.0};
+  const double den[6] = {1.0,
+                         0.0,
+                         -(1247.0 / 336.0 + 35.0 * eta / 12.0),
+                         4.0 * kPi,
+                         -44711.0 / 9072.0 + 9271.0 * eta / 504.0 + 65.0 * eta * eta / 18.0,
+                         -(8191.0 / 672.0 + 583.0 * eta / 24.0) * kPi};
+  double r[6];
+  for (int k = 0; k < 6; ++k) {
+    double v = num[k];
+    for (int i = 0; i < k; ++i) v -= r[i] * den[k - i];
+    r[k] = v;
+  }
+  T->K = 5.0 * M / (256.0 * eta);
+  T->P = 1.0 / (32.0 * eta);
+  for (int k = 2; k < 6; ++k) {
+    T->tau[k - 2] = 8.0 * r[k] / (8.0 - k);
+    T->r[k - 2] = r[k];
+  }
+  for (int k = 2; k < 5; ++k) T->p[k - 2] = 5.0 * r[k] / (5.0 - k);
+  T->p[3] = -5.0 * r[5];
+  T->v_low = cbrt(kPi * M * sd.f_low);
+  T->v_end = 1.0 / sqrt(6.0);
+  T->k_low = (int32_t)sd.k_low;
+  T->k_high = (int32_t)(sd.half - 1);
+  auto t_of_v = [&](double v) {
+    const double s = 1.0 + v * v * (T->tau[0] + v * (T->tau[1] + v * (T->tau[2] + v * T->tau[3])));
+    return -T->K * pow(v, -8.0) * s;
+  };
+  int64_t m_lo = 1, m_hi = 0;
+  if (T->v_low < T->v_end) {
+    m_lo = (int64_t)ceil(-t_of_v(T->v_end) * sd.fs);
+    if (m_lo < 1) m_lo = 1;
+    const double hi = floor(-t_of_v(T->v_low) * sd.fs);
+    m_hi = hi < (double)(sd.n - 1) ? (int64_t)hi : sd.n - 1;
+  }
+  T->m_lo = m_lo;
+  T->m_hi = m_hi;
+  T->flags = m_lo > m_hi ? CI_TMPL_EMPTY : 0;
+}
+
 int ensure_ybuf(Ctx* ctx, size_t bytes) {
   if (ctx->ybytes >= bytes) return CI_OK;
   if (ctx->ybuf) (void)hipFree(ctx->ybuf);
@@ -146,6 +206,31 @@ int ensure_ybuf(Ctx* ctx, size_t bytes) {
                                    bytes, hipGetErrorString(e));
   ctx->ybytes = bytes;
   return CI_OK;
+}
+
+int ensure_tdbuf(Ctx* ctx, size_t bytes) {
+  if (ctx->tdbytes >= bytes) return CI_OK;
+  if (ctx->tdbuf) (void)hipFree(ctx->tdbuf);
+  ctx->tdbuf = nullptr;
+  ctx->tdbytes = 0;
+  hipError_t e = hipMalloc(&ctx->tdbuf, bytes);
+  if (e != hipSuccess) return fail(ctx, CI_ENOMEM, "template-transform workspace of %zu bytes: %s",
+                                   bytes, hipGetErrorString(e));
+  ctx->tdbytes = bytes;
+  return CI_OK;
+}
+
+// Bytes of one slot set of the two-polarization workspace.
+size_t td_slot_bytes(int64_t bmax, int64_t n) {
+  return sizeof(float2) * (size_t)bmax * (size_t)n +
+         sizeof(double) * 2 * kTdChunks * (size_t)bmax;
+}
+
+// The transform and sigma^2 partials of slot `slot` (slot stride `sb`).
+void td_slot(Ctx* ctx, int slot, size_t sb, int64_t bmax, int64_t n, BatchArgs* a) {
+  char* base = static_cast<char*>(ctx->tdbuf) + (size_t)slot * sb;
+  a->uv = reinterpret_cast<float2*>(base);
+  a->sig = reinterpret_cast<double*>(base + sizeof(float2) * (size_t)bmax * (size_t)n);
 }
 
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
@@ -192,7 +277,7 @@ int ensure_tbuf(Ctx* ctx, size_t total) {
   return CI_OK;
 }
 
-int check_filter_args(Ctx* ctx, const void* seg, const ci_tparams* d_params, int64_t n,
+int check_filter_args(Ctx* ctx, const void* seg, const void* d_params, int64_t n,
                       int32_t precision) {
   if (!ctx) return fail(nullptr, CI_EINVAL, "null context");
   if (!seg) return fail(ctx, CI_EINVAL, "null segment");
@@ -270,6 +355,7 @@ int ensure_streams(Ctx* ctx) {
 struct Job {
   const Seg* seg;
   const ci_tparams* params;
+  const ci_tdparams* td = nullptr;  // two-polarization templates instead of params
   int64_t n;
   int64_t j_lo, j_hi;
   ci_trigger* peaks;
@@ -284,7 +370,11 @@ struct Job {
 };
 
 int check_job(Ctx* ctx, Job& jb, int32_t precision, float thr, int64_t window) {
-  int rc = check_filter_args(ctx, jb.seg, jb.params, jb.n, precision);
+  if (jb.td && precision != CI_FP32)
+    return fail(ctx, CI_EUNSUPPORTED, "two-polarization templates run in FP32 only");
+  int rc = check_filter_args(ctx, jb.seg,
+                             jb.td ? static_cast<const void*>(jb.td) : jb.params, jb.n,
+                             precision);
   if (rc != CI_OK) return rc;
   const int64_t N = jb.seg->host.n;
   if (window < 1 || window > N)
@@ -320,17 +410,26 @@ int check_job(Ctx* ctx, Job& jb, int32_t precision, float thr, int64_t window) {
 // slot sets sized for the largest batch.  Returns the slot stride in
 // complex elements.
 int prepare_jobs(Ctx* ctx, std::vector<Job>& jobs, size_t* slot_elems) {
-  size_t ymax = 0, ttot = 0;
+  size_t ymax = 0, ttot = 0, tdmax = 0;
   for (Job& jb : jobs) {
     jb.toff = ttot;
     ttot += trig_bytes(jb.B, jb.nwin, jb.plan.n2 / jb.plan.j);
     if (jb.n > 0) {
       const size_t y = (size_t)jb.B * (size_t)jb.seg->host.n;
       if (y > ymax) ymax = y;
+      if (jb.td) {
+        const size_t tb = align256(td_slot_bytes(jb.B, jb.seg->host.n));
+        if (tb > tdmax) tdmax = tb;
+      }
     }
   }
   int rc = ensure_tbuf(ctx, ttot);
   if (rc != CI_OK) return rc;
+  ctx->td_slot = tdmax;
+  if (tdmax > 0) {
+    rc = ensure_tdbuf(ctx, kSlots * tdmax);
+    if (rc != CI_OK) return rc;
+  }
   if (ymax > 0) {
     rc = ensure_ybuf(ctx, sizeof(float2) * kSlots * ymax);
     if (rc != CI_OK) return rc;
@@ -388,14 +487,22 @@ int enqueue_jobs(Ctx* ctx, const std::vector<Job>& jobs, size_t slot_elems, int3
       a.t0 = t0;
       a.nb = (int)((jb.n - t0) < jb.B ? (jb.n - t0) : jb.B);
       a.slot = slot;
-      a.params = jb.params + t0;
+      a.params = jb.td ? nullptr : jb.params + t0;
+      a.td = jb.td ? jb.td + t0 : nullptr;
+      if (jb.td) td_slot(ctx, slot, ctx->td_slot, jb.B, jb.seg->host.n, &a);
       a.y = static_cast<float2*>(ctx->ybuf) + (size_t)slot * slot_elems;
       a.last_batch = (t0 + jb.B >= jb.n) ? 1 : 0;
       if (b >= kSlots) {
         e = hipStreamWaitEvent(sb, ctx->fin_done[slot], 0);
         if (e != hipSuccess) return hipfail(ctx, e, "slot reuse ordering");
       }
-      e = timed(ctx, 0, a.nb, sb, [&] { return launch_pass1(a, true, sb); });
+      e = timed(ctx, 0, a.nb, sb, [&] {
+        if (a.td) {
+          const hipError_t r = launch_td_prep(a, sb);
+          if (r != hipSuccess) return r;
+        }
+        return launch_pass1(a, true, sb);
+      });
       if (e != hipSuccess) return hipfail(ctx, e, "pass-1 launch");
       e = timed(ctx, 1, a.nb, sb, [&] { return launch_pass2_trig(a, sb); });
       if (e != hipSuccess) return hipfail(ctx, e, "pass-2 launch");
@@ -413,6 +520,83 @@ int enqueue_jobs(Ctx* ctx, const std::vector<Job>& jobs, size_t slot_elems, int3
     if (e == hipSuccess) e = hipStreamWaitEvent(st, ctx->join_ev[i], 0);
   }
   if (e != hipSuccess) return hipfail(ctx, e, "stream join");
+  return CI_OK;
+}
+
+// Fill `bytes` of pinned host staging with fill(ptr) and copy them to d_dst
+// on st.  The staging buffer is reused once the previous copy completed.
+template <typename F>
+int stage_upload(Ctx* ctx, size_t bytes, void* d_dst, hipStream_t st, F fill) {
+  hipError_t e;
+  if (!ctx->pin_ev) {
+    e = hipEventCreateWithFlags(&ctx->pin_ev, hipEventDisableTiming);
+    if (e != hipSuccess) return hipfail(ctx, e, "event create");
+  }
+  if (ctx->pin_ev_armed) {
+    e = hipEventSynchronize(ctx->pin_ev);
+    if (e != hipSuccess) return hipfail(ctx, e, "pinned staging wait");
+    ctx->pin_ev_armed = false;
+  }
+  if (ctx->pinbytes < bytes) {
+    if (ctx->pin) (void)hipHostFree(ctx->pin);
+    ctx->pin = nullptr;
+    ctx->pinbytes = 0;
+    e = hipHostMalloc(&ctx->pin, bytes, hipHostMallocDefault);
+    if (e != hipSuccess) return fail(ctx, CI_ENOMEM, "pinned staging: %s", hipGetErrorString(e));
+    ctx->pinbytes = bytes;
+  }
+  fill(ctx->pin);
+  e = hipMemcpyAsync(d_dst, ctx->pin, bytes, hipMemcpyHostToDevice, st);
+  if (e != hipSuccess) return hipfail(ctx, e, "parameter upload");
+  e = hipEventRecord(ctx->pin_ev, st);
+  if (e != hipSuccess) return hipfail(ctx, e, "event record");
+  ctx->pin_ev_armed = true;
+  return CI_OK;
+}
+
+int check_bank(Ctx* ctx, const ci_template* bank_host, int64_t n) {
+  for (int64_t i = 0; i < n; ++i) {
+    if (!(bank_host[i].m1 > 0.0) || !(bank_host[i].m2 > 0.0) || !isfinite(bank_host[i].m1) ||
+        !isfinite(bank_host[i].m2))
+      return fail(ctx, CI_EINVAL, "template %lld has non-positive mass", (long long)i);
+  }
+  return CI_OK;
+}
+
+// Batches of a series-type two-polarization call (templates or series) on
+// one stream: workspace for B templates, then f(a) per batch.
+template <typename F>
+int td_batches(Ctx* ctx, const Seg* seg, const ci_tdparams* d_tdp, int64_t n, hipStream_t st,
+               F f) {
+  const int64_t N = seg->host.n;
+  int64_t B = default_batch(ctx, N);
+  if (B > 4096) B = 4096;
+  if (B > n) B = n;
+  int rc = ensure_ybuf(ctx, sizeof(float2) * (size_t)B * (size_t)N);
+  if (rc != CI_OK) return rc;
+  const size_t sb = align256(td_slot_bytes(B, N));
+  rc = ensure_tdbuf(ctx, sb);
+  if (rc != CI_OK) return rc;
+  BatchArgs a;
+  memset(&a, 0, sizeof a);
+  a.seg = seg;
+  const Tune& t = ctx->tune[seg->plan.log2n][CI_FP32];
+  a.plan = plan_for(seg->plan.log2n, t.c, t.j);
+  rc = check_plan(ctx, a.plan, CI_FP32);
+  if (rc != CI_OK) return rc;
+  a.bmax = (int)B;
+  a.precision = CI_FP32;
+  a.y = static_cast<float2*>(ctx->ybuf);
+  td_slot(ctx, 0, sb, B, N, &a);
+  for (int64_t t0 = 0; t0 < n; t0 += B) {
+    a.t0 = t0;
+    a.nb = (int)((n - t0) < B ? (n - t0) : B);
+    a.td = d_tdp + t0;
+    hipError_t e = launch_td_prep(a, st);
+    if (e != hipSuccess) return hipfail(ctx, e, "template transform launch");
+    rc = f(a);
+    if (rc != CI_OK) return rc;
+  }
   return CI_OK;
 }
 
@@ -471,6 +655,7 @@ int ci_ctx_destroy(ci_ctx* ctx) {
   }
   if (ctx->ybuf) (void)hipFree(ctx->ybuf);
   if (ctx->tbuf) (void)hipFree(ctx->tbuf);
+  if (ctx->tdbuf) (void)hipFree(ctx->tdbuf);
   // segments still alive keep their buffers until ci_segment_destroy
   for (Seg* sg : ctx->segs) sg->ctx = nullptr;
   delete ctx;
@@ -568,6 +753,8 @@ int ci_segment_create(ci_ctx* ctx, const ci_segment_spec* spec, const void* d_xt
   }
   ALLOC(s->dev, sizeof(SegDev));
   ALLOC(s->w, sizeof(float2) * half);
+  ALLOC(s->w0, sizeof(float2) * half);
+  ALLOC(s->isp, sizeof(double) * half);
   ALLOC(s->psum, sizeof(double) * half);
   ALLOC(s->bsum, sizeof(double) * (half / kSegBlock));
   ALLOC(s->tw2048, sizeof(float2) * 2048);
@@ -690,42 +877,16 @@ int ci_gen_templates(ci_ctx* ctx, const ci_segment* seg, const ci_template* bank
   if (n < 0) return fail(ctx, CI_EINVAL, "negative template count");
   if (n == 0) return CI_OK;
   if (!bank_host || !d_params) return fail(ctx, CI_EINVAL, "null bank or d_params");
-  for (int64_t i = 0; i < n; ++i) {
-    if (!(bank_host[i].m1 > 0.0) || !(bank_host[i].m2 > 0.0) || !isfinite(bank_host[i].m1) ||
-        !isfinite(bank_host[i].m2))
-      return fail(ctx, CI_EINVAL, "template %lld has non-positive mass", (long long)i);
-  }
+  if (check_bank(ctx, bank_host, n) != CI_OK) return CI_EINVAL;
   DeviceGuard dg(ctx->device);
   if (!dg.ok) return fail(ctx, CI_EHIP, "cannot select device %d", ctx->device);
   hipStream_t st = static_cast<hipStream_t>(stream);
-  const size_t bytes = sizeof(ci_tparams) * (size_t)n;
-  hipError_t e;
-  if (!ctx->pin_ev) {
-    e = hipEventCreateWithFlags(&ctx->pin_ev, hipEventDisableTiming);
-    if (e != hipSuccess) return hipfail(ctx, e, "event create");
-  }
-  // the previous upload from the pinned buffer must have completed
-  if (ctx->pin_ev_armed) {
-    e = hipEventSynchronize(ctx->pin_ev);
-    if (e != hipSuccess) return hipfail(ctx, e, "pinned staging wait");
-    ctx->pin_ev_armed = false;
-  }
-  if (ctx->pinbytes < bytes) {
-    if (ctx->pin) (void)hipHostFree(ctx->pin);
-    ctx->pin = nullptr;
-    ctx->pinbytes = 0;
-    e = hipHostMalloc(&ctx->pin, bytes, hipHostMallocDefault);
-    if (e != hipSuccess) return fail(ctx, CI_ENOMEM, "pinned staging: %s", hipGetErrorString(e));
-    ctx->pinbytes = bytes;
-  }
-  ci_tparams* hp = static_cast<ci_tparams*>(ctx->pin);
-  for (int64_t i = 0; i < n; ++i) host_params(bank_host[i], seg->host, &hp[i]);
-  e = hipMemcpyAsync(d_params, hp, bytes, hipMemcpyHostToDevice, st);
-  if (e != hipSuccess) return hipfail(ctx, e, "parameter upload");
-  e = hipEventRecord(ctx->pin_ev, st);
-  if (e != hipSuccess) return hipfail(ctx, e, "event record");
-  ctx->pin_ev_armed = true;
-  e = launch_params(seg, d_params, n, d_htilde_opt, st);
+  int rc = stage_upload(ctx, sizeof(ci_tparams) * (size_t)n, d_params, st, [&](void* hp) {
+    for (int64_t i = 0; i < n; ++i)
+      host_params(bank_host[i], seg->host, static_cast<ci_tparams*>(hp) + i);
+  });
+  if (rc != CI_OK) return rc;
+  const hipError_t e = launch_params(seg, d_params, n, d_htilde_opt, st);
   if (e != hipSuccess) return hipfail(ctx, e, "parameter kernel launch");
   return CI_OK;
 }
@@ -794,6 +955,107 @@ int ci_find_triggers(ci_ctx* ctx, const ci_segment* seg, const ci_tparams* d_par
   rc = prepare_jobs(ctx, jobs, &slot);
   if (rc != CI_OK) return rc;
   return enqueue_jobs(ctx, jobs, slot, precision, snr_threshold * snr_threshold, window,
+                      merge_across_templates ? 1 : 0, static_cast<hipStream_t>(stream));
+}
+
+// --- the two-polarization (time-domain) template form ---------------------
+
+int ci_td_params(ci_ctx* ctx, const ci_segment* seg, const ci_template* bank_host, int64_t n,
+                 ci_tdparams* d_tdparams, void* stream) {
+  if (!ctx) return fail(nullptr, CI_EINVAL, "null context");
+  if (!seg) return fail(ctx, CI_EINVAL, "null segment");
+  if (seg->ctx != ctx)
+    return fail(ctx, CI_EINVAL, "segment belongs to another (or a destroyed) context");
+  if (n < 0) return fail(ctx, CI_EINVAL, "negative template count");
+  if (n == 0) return CI_OK;
+  if (!bank_host || !d_tdparams) return fail(ctx, CI_EINVAL, "null bank or d_tdparams");
+  if (check_bank(ctx, bank_host, n) != CI_OK) return CI_EINVAL;
+  DeviceGuard dg(ctx->device);
+  if (!dg.ok) return fail(ctx, CI_EHIP, "cannot select device %d", ctx->device);
+  return stage_upload(ctx, sizeof(ci_tdparams) * (size_t)n, d_tdparams,
+                      static_cast<hipStream_t>(stream), [&](void* hp) {
+                        for (int64_t i = 0; i < n; ++i)
+                          host_td_params(bank_host[i], seg->host,
+                                         static_cast<ci_tdparams*>(hp) + i);
+                      });
+}
+
+
+int ci_td_templates(ci_ctx* ctx, const ci_segment* seg, const ci_tdparams* d_tdparams, int64_t n,
+                    void* d_u, void* d_hf, double* d_sigma2, void* stream) {
+  int rc = check_filter_args(ctx, seg, d_tdparams, n, CI_FP32);
+  if (rc != CI_OK) return rc;
+  if (n == 0 || (!d_u && !d_hf && !d_sigma2)) return CI_OK;
+  DeviceGuard dg(ctx->device);
+  if (!dg.ok) return fail(ctx, CI_EHIP, "cannot select device %d", ctx->device);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int64_t N = seg->host.n;
+  // d_u needs the generated signal before the transform replaces it: run
+  // the generation again per batch into the caller's buffer
+  return td_batches(ctx, seg, d_tdparams, n, st, [&](const BatchArgs& a) {
+    hipError_t e = hipSuccess;
+    if (d_u) {
+      BatchArgs c = a;
+      c.uv = static_cast<float2*>(d_u) + (size_t)a.t0 * N;
+      e = launch_td_gen(c, st);
+      if (e != hipSuccess) return hipfail(ctx, e, "template generation launch");
+    }
+    if (d_hf || d_sigma2) {
+      e = launch_td_export(
+          a, d_hf ? static_cast<float2*>(d_hf) + (size_t)a.t0 * 2 * (N / 2 + 1) : nullptr,
+          d_sigma2 ? d_sigma2 + (size_t)a.t0 * 2 : nullptr, st);
+      if (e != hipSuccess) return hipfail(ctx, e, "template export launch");
+    }
+    return (int)CI_OK;
+  });
+}
+
+int ci_td_matched_filter(ci_ctx* ctx, const ci_segment* seg, const ci_tdparams* d_tdparams,
+                         int64_t n, void* d_z, void* stream) {
+  int rc = check_filter_args(ctx, seg, d_tdparams, n, CI_FP32);
+  if (rc != CI_OK) return rc;
+  if (n == 0) return CI_OK;
+  if (!d_z) return fail(ctx, CI_EINVAL, "null d_z");
+  DeviceGuard dg(ctx->device);
+  if (!dg.ok) return fail(ctx, CI_EHIP, "cannot select device %d", ctx->device);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int64_t N = seg->host.n;
+  return td_batches(ctx, seg, d_tdparams, n, st, [&](const BatchArgs& a0) {
+    BatchArgs a = a0;
+    a.d_z = static_cast<float2*>(d_z) + (size_t)a.t0 * N;
+    hipError_t e = launch_pass1(a, false, st);
+    if (e != hipSuccess) return hipfail(ctx, e, "pass-1 launch");
+    e = launch_pass2_series(a, st);
+    if (e != hipSuccess) return hipfail(ctx, e, "pass-2 launch");
+    return (int)CI_OK;
+  });
+}
+
+int ci_td_find_triggers(ci_ctx* ctx, const ci_segment* seg, const ci_tdparams* d_tdparams,
+                        int64_t n, float snr_threshold, int64_t window, int64_t j_lo,
+                        int64_t j_hi, ci_trigger* d_peaks, ci_trigger* d_trig, int64_t cap,
+                        int64_t* d_count, int32_t merge_across_templates, void* stream) {
+  if (!ctx) return fail(nullptr, CI_EINVAL, "null context");
+  DeviceGuard dg(ctx->device);
+  if (!dg.ok) return fail(ctx, CI_EHIP, "cannot select device %d", ctx->device);
+  std::vector<Job> jobs(1);
+  Job& jb = jobs[0];
+  jb.seg = seg;
+  jb.params = nullptr;
+  jb.td = d_tdparams;
+  jb.n = n;
+  jb.j_lo = j_lo;
+  jb.j_hi = j_hi;
+  jb.peaks = d_peaks;
+  jb.trig = d_trig;
+  jb.cap = cap;
+  jb.count = d_count;
+  int rc = check_job(ctx, jb, CI_FP32, snr_threshold, window);
+  if (rc != CI_OK) return rc;
+  size_t slot = 0;
+  rc = prepare_jobs(ctx, jobs, &slot);
+  if (rc != CI_OK) return rc;
+  return enqueue_jobs(ctx, jobs, slot, CI_FP32, snr_threshold * snr_threshold, window,
                       merge_across_templates ? 1 : 0, static_cast<hipStream_t>(stream));
 }
 

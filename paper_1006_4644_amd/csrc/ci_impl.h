@@ -79,6 +79,11 @@ struct Ctx {
   // trigger workspace
   void* tbuf = nullptr;
   size_t tbytes = 0;
+  // two-polarization templates: per slot set the template transform
+  // [B][n] complex64, then the sigma^2 partials [B][kTdChunks][2] doubles
+  void* tdbuf = nullptr;
+  size_t tdbytes = 0;
+  size_t td_slot = 0;          // bytes per slot set of the current call
   // pinned staging for parameter upload
   void* pin = nullptr;
   size_t pinbytes = 0;
@@ -109,6 +114,8 @@ struct Seg {
   SegDev host;       // host copy (g and p_total are only valid on device)
   SegDev* dev;       // device copy
   float2* w;         // [n/2]  PSD-weighted, scaled data spectrum
+  float2* w0;        // [n/2]  g x~ / S (two-polarization templates)
+  double* isp;       // [n/2]  1 / S on the band, 0 below it
   double* psum;      // [n/2]  running sum of 4 df f^-7/3 / S from k_low
   double* bsum;      // [n/2 / kSegBlock] block sums, then block offsets
   float2* tw2048;    // [2048] exp(2 pi i e / 2048)
@@ -162,9 +169,23 @@ struct BatchArgs {
   float2* d_z;                // first template's series
   int p2_per_cu;              // pass-2 workgroups per CU (0: as many as fit)
   int precision;              // CI_FP32 | CI_SPLIT_BF16 | CI_SPLIT_FP16
+  // two-polarization templates (null td: the frequency-domain chirp)
+  const ci_tdparams* td;      // batch's first template
+  float2* uv;                 // [bmax][n] template transform of this slot set
+  double* sig;                // [bmax][kTdChunks][2] sigma^2 partials
 };
 
 hipError_t launch_pass1(const BatchArgs& a, bool zero_trig, hipStream_t st);
+// Two-polarization templates of a batch: generate u = h_+ + i h_x into
+// a.uv, replace it by V = IDFT(u), and form the sigma^2 partials in a.sig.
+// launch_pass1 then reads V when a.td is set.
+hipError_t launch_td_prep(const BatchArgs& a, hipStream_t st);
+// The generation step alone (u into a.uv).
+hipError_t launch_td_gen(const BatchArgs& a, hipStream_t st);
+// Spectra H~+ / H~x and sigma^2 of a prepared batch (either may be null).
+hipError_t launch_td_export(const BatchArgs& a, void* d_hf, double* d_sigma2, hipStream_t st);
+// sigma^2 partial sums per two-polarization template
+constexpr int kTdChunks = 16;
 hipError_t launch_pass2_trig(const BatchArgs& a, hipStream_t st);
 hipError_t launch_pass2_series(const BatchArgs& a, hipStream_t st);
 hipError_t launch_fin(const BatchArgs& a, hipStream_t st);

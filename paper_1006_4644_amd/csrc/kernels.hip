@@ -135,7 +135,9 @@ __global__ __launch_bounds__(kSegThreads) void k_seg_final(const SegDev* __restr
                                                            const double* __restrict__ psd,
                                                            double* __restrict__ psum,
                                                            const double* __restrict__ boff,
-                                                           float2* __restrict__ w) {
+                                                           float2* __restrict__ w,
+                                                           float2* __restrict__ w0,
+                                                           double* __restrict__ isp) {
   __shared__ double sh[kSegThreads];
   const int64_t kl = sd->k_low;
   const double df = sd->df, g = sd->g;
@@ -154,13 +156,19 @@ __global__ __launch_bounds__(kSegThreads) void k_seg_final(const SegDev* __restr
     const int64_t k = base + i;
     run += v[i];
     psum[k] = k >= kl ? run : 0.0;
-    float2 o = make_float2(0.f, 0.f);
+    float2 o = make_float2(0.f, 0.f), o0 = o;
+    double is = 0.0;
     if (k >= kl) {
-      const double fac = g * pow((double)k * df, -7.0 / 6.0) / psd[k];
+      is = 1.0 / psd[k];
+      const double fac0 = g * is;
+      const double fac = fac0 * pow((double)k * df, -7.0 / 6.0);
       const float2 x = xt[k];
       o = make_float2((float)((double)x.x * fac), (float)((double)x.y * fac));
+      o0 = make_float2((float)((double)x.x * fac0), (float)((double)x.y * fac0));
     }
     w[k] = o;
+    w0[k] = o0;
+    isp[k] = is;
   }
 }
 
@@ -217,6 +225,132 @@ __device__ __forceinline__ int xcd_remap(int bid, int nblk) {
 // pass 1: generate + correlate + first four-step pass
 // ---------------------------------------------------------------------------
 
+// v with t(v) = t (t < 0) for a time-domain template: Newton's method in
+// FP64 from the Newtonian guess t = -K v^-8, kept inside [v_low, v_end],
+// until the step falls below 1e-15 v.
+__device__ __forceinline__ double td_solve_v(const ci_tdparams& T, double t) {
+  const float q = (float)(-t / T.K);
+  double v = (double)__builtin_amdgcn_exp2f(-0.125f * __builtin_amdgcn_logf(q));
+  v = fmin(fmax(v, T.v_low), T.v_end);
+  for (int it = 0; it < 40; ++it) {
+    const double iv = 1.0 / v;
+    const double iv2 = iv * iv, iv4 = iv2 * iv2, iv8 = iv4 * iv4;
+    const double s = fma(v * v, fma(v, fma(v, fma(v, T.tau[3], T.tau[2]), T.tau[1]), T.tau[0]), 1.0);
+    const double R = fma(v * v, fma(v, fma(v, fma(v, T.r[3], T.r[2]), T.r[1]), T.r[0]), 1.0);
+    const double f = fma(-T.K * iv8, s, -t);
+    const double d = 8.0 * T.K * iv8 * iv * R;
+    double vn = v - f / d;
+    vn = fmin(fmax(vn, T.v_low), T.v_end);
+    const bool done = fabs(vn - v) <= 1e-15 * v;
+    v = vn;
+    if (done) break;
+  }
+  return v;
+}
+
+// Gravitational-wave phase 2 phi(v) in revolutions, reduced to [-1/2, 1/2]
+// in FP64.
+__device__ __forceinline__ float td_phase_frac(const ci_tdparams& T, double v) {
+  const double iv = 1.0 / v;
+  const double iv2 = iv * iv, iv5 = iv2 * iv2 * iv;
+  const double s = fma(v * v, fma(v, fma(v, T.p[2], T.p[1]), T.p[0]), 1.0);
+  const double phi = -T.P * fma(iv5, s, T.p[3] * log(v));
+  const double r = phi * 0.31830988618379067;  // phi / pi
+  return (float)(r - rint(r));
+}
+
+// u = h_+ + i h_x = v^2 exp(2 i phi) on the circular grid: sample j holds
+// m = n - j samples before coalescence.  Grid (n / 256, templates).
+__global__ __launch_bounds__(256) void k_td_gen(const SegDev* __restrict__ sd,
+                                                const ci_tdparams* __restrict__ tdp,
+                                                float2* __restrict__ u) {
+  const int b = blockIdx.y;
+  const int64_t n = sd->n;
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const ci_tdparams& T = tdp[b];
+  const int64_t m = n - j;
+  float2 o = make_float2(0.f, 0.f);
+  if (!(T.flags & CI_TMPL_EMPTY) && m >= T.m_lo && m <= T.m_hi) {
+    const double v = td_solve_v(T, -(double)m / sd->fs);
+    const float fr = td_phase_frac(T, v);
+    const float a = (float)(v * v);
+    o = make_float2(a * __builtin_amdgcn_cosf(fr), a * __builtin_amdgcn_sinf(fr));
+  }
+  u[(size_t)b * n + j] = o;
+}
+
+// Split of the transform V = IDFT(h_+ + i h_x) of two real signals into
+// theirs: Vp_k = (V_k + conj V_{n-k}) / 2 = IDFT(h_+)_k and
+// Vc_k = (V_k - conj V_{n-k}) / (2i) = IDFT(h_x)_k.
+__device__ __forceinline__ void td_split(float2 va, float2 vb, float2& vp, float2& vc) {
+  vp = make_float2(0.5f * (va.x + vb.x), 0.5f * (va.y - vb.y));
+  vc = make_float2(0.5f * (va.y + vb.y), 0.5f * (vb.x - va.x));
+}
+
+// Partial sums of S_+ = sum_band |Vp_k|^2 / S_k and S_x (likewise) over
+// kTdChunks equal slices of the band, in FP64.  Grid (kTdChunks, templates).
+__global__ __launch_bounds__(256) void k_td_sigma(const SegDev* __restrict__ sd,
+                                                  const ci_tdparams* __restrict__ tdp,
+                                                  const float2* __restrict__ V,
+                                                  const double* __restrict__ isp,
+                                                  double* __restrict__ sig) {
+  __shared__ double sh[2][4];
+  const int b = blockIdx.y, ch = blockIdx.x, tid = threadIdx.x;
+  const int64_t n = sd->n, half = sd->half;
+  const int64_t kl = tdp[b].k_low;
+  const int64_t len = half > kl ? half - kl : 0;
+  const int64_t c0 = kl + len * ch / kTdChunks, c1 = kl + len * (ch + 1) / kTdChunks;
+  const float2* vb = V + (size_t)b * n;
+  double sp = 0.0, sc = 0.0;
+  for (int64_t k = c0 + tid; k < c1; k += 256) {
+    float2 vp, vc;
+    td_split(vb[k], vb[n - k], vp, vc);
+    const double w = isp[k];
+    sp += ((double)vp.x * vp.x + (double)vp.y * vp.y) * w;
+    sc += ((double)vc.x * vc.x + (double)vc.y * vc.y) * w;
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    sp += __shfl_xor(sp, off, 64);
+    sc += __shfl_xor(sc, off, 64);
+  }
+  if ((tid & 63) == 0) {
+    sh[0][tid >> 6] = sp;
+    sh[1][tid >> 6] = sc;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    sig[((size_t)b * kTdChunks + ch) * 2] = (sh[0][0] + sh[0][1]) + (sh[0][2] + sh[0][3]);
+    sig[((size_t)b * kTdChunks + ch) * 2 + 1] = (sh[1][0] + sh[1][1]) + (sh[1][2] + sh[1][3]);
+  }
+}
+
+// Spectra H~+_k = dt conj(Vp_k), H~x_k = dt conj(Vc_k) for k = 0..n/2 and
+// sigma^2 = 4 df dt^2 S.  Grid (ceil((n/2 + 1) / 256), templates).
+__global__ __launch_bounds__(256) void k_td_export(const SegDev* __restrict__ sd,
+                                                   const float2* __restrict__ V,
+                                                   const double* __restrict__ sig,
+                                                   float2* __restrict__ hf,
+                                                   double* __restrict__ sigma2) {
+  const int b = blockIdx.y;
+  const int64_t n = sd->n, m = sd->half + 1;
+  const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const double dt = 1.0 / sd->fs;
+  const float2* vb = V + (size_t)b * n;
+  if (hf && k < m) {
+    float2 vp, vc;
+    td_split(vb[k], vb[(n - k) & (n - 1)], vp, vc);
+    float2* o = hf + (size_t)b * 2 * m;
+    o[k] = make_float2((float)(dt * vp.x), (float)(-dt * vp.y));
+    o[m + k] = make_float2((float)(dt * vc.x), (float)(-dt * vc.y));
+  }
+  if (sigma2 && blockIdx.x == 0 && threadIdx.x < 2) {
+    double s = 0.0;
+    for (int i = 0; i < kTdChunks; ++i) s += sig[((size_t)b * kTdChunks + i) * 2 + threadIdx.x];
+    sigma2[(size_t)b * 2 + threadIdx.x] = 4.0 * sd->df * dt * dt * s;
+  }
+}
+
 struct P1Args {
   const ci_tparams* prm;   // batch's first template
   const float2* w;         // weighted data spectrum [n/2]
@@ -230,6 +364,12 @@ struct P1Args {
   unsigned int* bdone;
   int64_t nzero_w;         // entries of wkeys to clear
   int nb;
+  // two-polarization templates (k_pass1_mem)
+  const float2* uv;        // [nb][n] spectrum in memory, natural order
+  const ci_tdparams* tdp;  // batch's first template
+  const float2* w0;        // g x~_k / S_k  [n/2]
+  const double* sig;       // [nb][kTdChunks][2] sigma^2 partial sums
+  const SegDev* sd;        // df and the data scale g of w0
 };
 
 // Packed FP16 storage of the intermediate (split-precision paths): one
@@ -254,10 +394,26 @@ __device__ __forceinline__ float2 tw_n(const float2* __restrict__ twa,
   return cmul(twa[e & 2047], twb[e >> 11]);
 }
 
+// Inputs of pass 1: Z_k of the frequency-domain chirp, generated on chip
+// (zero outside the band).
+struct SrcSpa {
+  const ci_tparams& P;
+  const float2* __restrict__ w;
+  __device__ __forceinline__ float2 operator()(int k) const {
+    float2 v = make_float2(0.f, 0.f);
+    if (k >= P.k_low && k <= P.k_high) {
+      const float2 e = chirp_phasor(P, k);
+      v = cmul(w[k], make_float2(e.x * P.scale, e.y * P.scale));
+    }
+    return v;
+  }
+};
+
 // Pass-1 body for one tile.  Q: number of stage-1 inputs per lane that can
 // be nonzero (m < Q), chosen per template from its upper band edge.
-template <int N1, int N2, int C, int Q, bool H>
-__device__ __forceinline__ void pass1_tile(const P1Args& a, const ci_tparams& P, int b, int tile,
+// src(k) gives the input Z_k.
+template <int N1, int N2, int C, int Q, bool H, class Src>
+__device__ __forceinline__ void pass1_tile(const P1Args& a, const Src& src, int b, int tile,
                                            float2* lds, const float2* twl, unsigned t,
                                            unsigned c) {
   using K = Col<N2, C>;
@@ -283,18 +439,10 @@ __device__ __forceinline__ void pass1_tile(const P1Args& a, const ci_tparams& P,
     v3 = tw_n(a.twa, a.twb, (int)(256 * k1));
   }
 
-  // Z_k for k = k1 + N1 k2, k2 = t + Lp m (zero outside the band).
+  // Z_k for k = k1 + N1 k2, k2 = t + Lp m.
   float2 x[16];
 #pragma unroll
-  for (int m = 0; m < Q; ++m) {
-    const int k = (int)(k1 + N1 * (t + Lp * m));
-    float2 v = make_float2(0.f, 0.f);
-    if (k >= P.k_low && k <= P.k_high) {
-      const float2 e = chirp_phasor(P, k);
-      v = cmul(a.w[k], make_float2(e.x * P.scale, e.y * P.scale));
-    }
-    x[m] = v;
-  }
+  for (int m = 0; m < Q; ++m) x[m] = src((int)(k1 + N1 * (t + Lp * m)));
 
   K::template stage1<Q, 1>(x, lds, t, c, twl);
   K::stage2(x, lds, t, c);
@@ -356,9 +504,97 @@ __global__ __launch_bounds__(C * N2 / 16) void k_pass1(P1Args a) {
   // Every band bin lies below n/2 (k2 < N2/2, so m < 8), and below k_high:
   // m <= (k_high / N1) / Lp.  The choice is uniform over the workgroup.
   const int mneed = P.k_high >= P.k_low ? (P.k_high / N1) / Lp + 1 : 1;
-  if (mneed <= 2) pass1_tile<N1, N2, C, 2, H>(a, P, b, tile, lds, twl, t, c);
-  else if (mneed <= 4) pass1_tile<N1, N2, C, 4, H>(a, P, b, tile, lds, twl, t, c);
-  else pass1_tile<N1, N2, C, 8, H>(a, P, b, tile, lds, twl, t, c);
+  const SrcSpa src{P, a.w};
+  if (mneed <= 2) pass1_tile<N1, N2, C, 2, H>(a, src, b, tile, lds, twl, t, c);
+  else if (mneed <= 4) pass1_tile<N1, N2, C, 4, H>(a, src, b, tile, lds, twl, t, c);
+  else pass1_tile<N1, N2, C, 8, H>(a, src, b, tile, lds, twl, t, c);
+}
+
+// ---------------------------------------------------------------------------
+// two-polarization time-domain templates
+// ---------------------------------------------------------------------------
+
+// Input of the plain inverse DFT of a spectrum held in memory.
+struct SrcMem {
+  const float2* __restrict__ z;
+  __device__ __forceinline__ float2 operator()(int k) const { return z[k]; }
+};
+
+// Input of the two-polarization correlator transform.  For a real template
+// IDFT(h)_k = conj(H~_k) / dt, so with a_k = ap w0_k Vp_k and
+// b_k = ac w0_k Vc_k (ap = sqrt(4 df / S_+) / (2 g), S_+ = sum_band
+// |Vp_k|^2 / S_k, likewise ac) the band bins carry (a_k + i b_k) and their
+// mirrors n - k carry conj(a_k) + i conj(b_k): the inverse DFT of that
+// packed spectrum is c_+ + i c_x, the paper's two C2R outputs at once.
+struct SrcTd {
+  const float2* __restrict__ V;
+  const float2* __restrict__ w0;
+  float ap, ac;
+  int k_low, half, n;
+  __device__ __forceinline__ float2 operator()(int k) const {
+    int kk;
+    bool mir;
+    if (k >= k_low && k < half) {
+      kk = k;
+      mir = false;
+    } else if (k > half && n - k >= k_low) {
+      kk = n - k;
+      mir = true;
+    } else {
+      return make_float2(0.f, 0.f);
+    }
+    float2 vp, vc;
+    td_split(V[kk], V[n - kk], vp, vc);
+    const float2 x = w0[kk];
+    const float2 pa = cmul(x, vp), pb = cmul(x, vc);
+    const float2 av = make_float2(pa.x * ap, pa.y * ap);
+    const float2 bv = make_float2(pb.x * ac, pb.y * ac);
+    return mir ? make_float2(av.x + bv.y, bv.x - av.y) : make_float2(av.x - bv.y, av.y + bv.x);
+  }
+};
+
+// Pass 1 over a spectrum held in memory, every bin possibly nonzero.
+// MODE 0: the plain inverse DFT of a.uv.  MODE 1: the two-polarization
+// correlator built from a.uv = IDFT(h_+ + i h_x) and w0.
+template <int N1, int N2, int C, int MODE>
+__global__ __launch_bounds__(C * N2 / 16) void k_pass1_mem(P1Args a) {
+  constexpr int N = N1 * N2;
+  constexpr int TILES = N1 / C;
+  extern __shared__ float2 lds[];
+  const unsigned tid = threadIdx.x;
+  const unsigned c = tid % C, t = tid / C;
+
+  if (a.wkeys) {
+    const int64_t gid = blockIdx.x * (int64_t)blockDim.x + tid;
+    const int64_t gsz = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = gid; i < a.nzero_w; i += gsz) a.wkeys[i] = 0ull;
+    if (gid == 0) a.bdone[0] = 0u;
+  }
+  float2* twl = lds + Col<N2, C>::LDS_ELEMS;
+  for (int k = (int)tid; k < N2; k += (int)blockDim.x) twl[k] = a.tw[k * (2048 / N2)];
+  __syncthreads();
+
+  const int bid = xcd_remap(blockIdx.x, gridDim.x);
+  const int b = bid / TILES, tile = bid % TILES;
+  const float2* vb = a.uv + (size_t)b * N;
+  if constexpr (MODE == 0) {
+    pass1_tile<N1, N2, C, 16, false>(a, SrcMem{vb}, b, tile, lds, twl, t, c);
+  } else {
+    // sigma^2 sums in a fixed order
+    const double* sg = a.sig + (size_t)b * kTdChunks * 2;
+    double sp = 0.0, sc = 0.0;
+    for (int i = 0; i < kTdChunks; ++i) {
+      sp += sg[2 * i];
+      sc += sg[2 * i + 1];
+    }
+    const ci_tdparams& T = a.tdp[b];
+    const bool live = !(T.flags & CI_TMPL_EMPTY) && sp > 0.0 && sc > 0.0;
+    const double df = a.sd->df, g = a.sd->g;
+    const float ap = live ? (float)(0.5 * sqrt(4.0 * df / sp) / g) : 0.f;
+    const float ac = live ? (float)(0.5 * sqrt(4.0 * df / sc) / g) : 0.f;
+    const SrcTd src{vb, a.w0, ap, ac, T.k_low, N / 2, N};
+    pass1_tile<N1, N2, C, 16, false>(a, src, b, tile, lds, twl, t, c);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -446,7 +682,8 @@ __device__ int block_excl_scan(int v, int* sh, int* total) {
 }
 
 struct P2Args {
-  const ci_tparams* prm;     // batch's first template
+  const char* flagp;         // flags of the batch's first template ...
+  int flag_stride;           // ... and the byte stride to the next one
   const float2* tw;
   const double2* tw64;
   const float2* y;           // intermediate of this batch
@@ -490,7 +727,7 @@ __device__ void finalize_template(const P2Args& a, int b, void* ldsv) {
   const int tid = threadIdx.x, nt = blockDim.x;
   const int wave = tid >> 6, lane = tid & 63, nwaves = nt >> 6;
   int* iscr = reinterpret_cast<int*>(ldsv);
-  const ci_tparams P = a.prm[b];
+  const int32_t flags = *reinterpret_cast<const int32_t*>(a.flagp + (size_t)b * a.flag_stride);
   const int64_t tg = a.t0 + b;
   const float2* yb = a.y + (size_t)b * N;
   // peak key: max over the pass-2 workgroups' partials
@@ -511,7 +748,7 @@ __device__ void finalize_template(const P2Args& a, int b, void* ldsv) {
     pk = ush[0];
     __syncthreads();
   }
-  if ((P.flags & CI_TMPL_EMPTY) || pk == 0ull) {
+  if ((flags & CI_TMPL_EMPTY) || pk == 0ull) {
     if (tid == 0) {
       ci_trigger e;
       e.tmpl = tg; e.index = -1; e.rho2 = 0.f; e.re = 0.f; e.im = 0.f; e.window = -1;
@@ -1169,7 +1406,8 @@ hipError_t launch_segment(Seg* s, const void* d_xtilde, const double* d_psd, hip
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_seg_final, dim3(nblk), dim3(kSegThreads), 0, st, s->dev,
-                     reinterpret_cast<const float2*>(d_xtilde), d_psd, s->psum, s->bsum, s->w);
+                     reinterpret_cast<const float2*>(d_xtilde), d_psd, s->psum, s->bsum, s->w,
+                     s->w0, s->isp);
   return hipGetLastError();
 }
 
@@ -1236,6 +1474,11 @@ P1Args make_p1(const BatchArgs& a, bool zero_trig) {
   p.tw64 = a.seg->tw64;
   p.y = a.y;
   p.nb = a.nb;
+  p.uv = a.uv;
+  p.tdp = a.td;
+  p.w0 = a.seg->w0;
+  p.sig = a.sig;
+  p.sd = a.seg->dev;
   if (zero_trig) {
     const int s = a.slot;
     p.wkeys = a.tw.wkeys + (size_t)s * a.bmax * a.nwin;
@@ -1252,7 +1495,13 @@ P1Args make_p1(const BatchArgs& a, bool zero_trig) {
 P2Args make_p2(const BatchArgs& a) {
   P2Args p;
   const int s = a.slot;
-  p.prm = a.params;
+  if (a.td) {
+    p.flagp = reinterpret_cast<const char*>(&a.td->flags);
+    p.flag_stride = (int)sizeof(ci_tdparams);
+  } else {
+    p.flagp = reinterpret_cast<const char*>(&a.params->flags);
+    p.flag_stride = (int)sizeof(ci_tparams);
+  }
   p.tw = a.seg->tw2048;
   p.tw64 = a.seg->tw64;
   p.y = a.y;
@@ -1340,6 +1589,16 @@ struct Inst {
   static hipError_t p1(const BatchArgs& a, bool zero, hipStream_t st) {
     const size_t lds = (size_t)(Col<N2, C>::LDS_ELEMS + N2) * sizeof(float2);
     auto kern = k_pass1<N1, N2, C, H>;
+    hipError_t e = set_lds(kern, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(kern, dim3((unsigned)(a.nb * (N1 / C))), dim3(C * N2 / 16), lds, st,
+                       make_p1(a, zero));
+    return hipGetLastError();
+  }
+  template <int MODE>
+  static hipError_t p1mem(const BatchArgs& a, bool zero, hipStream_t st) {
+    const size_t lds = (size_t)(Col<N2, C>::LDS_ELEMS + N2) * sizeof(float2);
+    auto kern = k_pass1_mem<N1, N2, C, MODE>;
     hipError_t e = set_lds(kern, lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(kern, dim3((unsigned)(a.nb * (N1 / C))), dim3(C * N2 / 16), lds, st,
@@ -1434,7 +1693,41 @@ hipError_t dispatch(const Plan& p, F f) {
 
 }  // namespace
 
+hipError_t launch_td_gen(const BatchArgs& a, hipStream_t st) {
+  hipLaunchKernelGGL(k_td_gen, dim3((unsigned)(a.seg->host.n / 256), (unsigned)a.nb), dim3(256),
+                     0, st, a.seg->dev, a.td, a.uv);
+  return hipGetLastError();
+}
+
+hipError_t launch_td_prep(const BatchArgs& a, hipStream_t st) {
+  hipError_t e = launch_td_gen(a, st);
+  if (e != hipSuccess) return e;
+  // V = IDFT(u), through the intermediate, back into the same buffer
+  BatchArgs c = a;
+  c.d_z = a.uv;
+  e = dispatch(c.plan, [&](auto inst) {
+    typedef decltype(inst) I;
+    hipError_t r = I::template p1mem<0>(c, false, st);
+    return r == hipSuccess ? I::p2s(c, st) : r;
+  });
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_td_sigma, dim3(kTdChunks, (unsigned)a.nb), dim3(256), 0, st, a.seg->dev,
+                     a.td, a.uv, a.seg->isp, a.sig);
+  return hipGetLastError();
+}
+
+hipError_t launch_td_export(const BatchArgs& a, void* d_hf, double* d_sigma2, hipStream_t st) {
+  const int64_t m = a.seg->host.half + 1;
+  hipLaunchKernelGGL(k_td_export, dim3((unsigned)((m + 255) / 256), (unsigned)a.nb), dim3(256), 0,
+                     st, a.seg->dev, a.uv, a.sig, reinterpret_cast<float2*>(d_hf), d_sigma2);
+  return hipGetLastError();
+}
+
 hipError_t launch_pass1(const BatchArgs& a, bool zero_trig, hipStream_t st) {
+  if (a.td)
+    return dispatch(a.plan, [&](auto inst) {
+      return decltype(inst)::template p1mem<1>(a, zero_trig, st);
+    });
   return dispatch(a.plan, [&](auto inst) {
     typedef decltype(inst) I;
     // the split-precision paths keep the first pass on the vector units and

@@ -1,0 +1,211 @@
+"""GPU-vs-oracle parity of the paper's two-polarization template form
+(needs an MI355X): time-domain 2.5PN generator, per-polarization spectra and
+normalisation, c_+ + i c_x series, and the search built on it.
+
+Bars: FP32 series error <= 1e-5 of the series maximum, peaks and triggers as
+for the frequency-domain path (indices exact up to ties within tolerance);
+the generated signal within 2e-6 of its amplitude (FP64 phase rounded once
+to FP32, hardware sine/cosine); spectra within 2e-5 of their maximum
+(an FP32 transform of up to 2^20 points).
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import td_oracle as T
+from paper_1006_4644_amd import ci, synth
+from tests import mfcase as C
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx(gpu_lib):
+    c = gpu_lib.context(0)
+    yield c
+    c.close()
+
+
+def _dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _sync():
+    import torch
+    torch.cuda.synchronize()
+
+
+def _td_case(n, fs, fl, bank, inj, noise_seed):
+    """Data: Gaussian noise plus h_+ of the injected masses coalescing at j0,
+    scaled to optimal SNR snr over [k_low, n/2 - 1] (oracle generator)."""
+    psd = synth.make_psd(n, fs)
+    x = synth.make_noise(n, fs, fl, psd, noise_seed) if noise_seed is not None \
+        else np.zeros(n // 2 + 1, complex)
+    if inj is not None:
+        m1, m2, snr, j0 = inj
+        hp, _ = T.td_chirp(n, fs, fl, m1, m2)
+        H = np.fft.rfft(np.roll(hp, j0)) / fs
+        kl = int(math.ceil(fl * n / fs))
+        H[:kl] = 0
+        H[n // 2:] = 0
+        s = math.sqrt(4 * fs / n * np.sum(np.abs(H) ** 2 / psd))
+        x = x + H * (snr / s)
+    x64 = x.astype(np.complex64)
+    return x64, psd, x64.astype(np.complex128)
+
+
+@pytest.fixture(scope="module")
+def small(ctx):
+    n, fs, fl = 1 << 16, 4096.0, 20.0
+    bank = np.array([[3.0, 2.0], [1.6, 1.2], [8.0, 1.5], [12.0, 9.0], [2.5, 2.5],
+                     [150.0, 150.0]])
+    x64, psd, x128 = _td_case(n, fs, fl, bank, (3.0, 2.0, 11.0, 40000), 77)
+    seg = ctx.segment(_dev(x64), _dev(psd), n, fs, fl)
+    tdp = ctx.td_params(seg, bank)
+    zo = [T.td_series(x128, psd, n, fs, fl, m1, m2) for m1, m2 in bank]
+    return dict(n=n, fs=fs, fl=fl, bank=bank, psd=psd, x128=x128, seg=seg, tdp=tdp, zo=zo)
+
+
+def test_td_params_match_oracle(ctx, small):
+    _sync()
+    P = ci.tdparams_to_numpy(small["tdp"])
+    n, fs, fl = small["n"], small["fs"], small["fl"]
+    for i, (m1, m2) in enumerate(small["bank"]):
+        M = (m1 + m2) * 4.925490947641267e-6
+        eta = m1 * m2 / (m1 + m2) ** 2
+        tau, p = T.t2_coefficients(eta)
+        r = T.balance_series(eta)
+        assert np.allclose(P["tau"][i], tau[2:], rtol=1e-13, atol=1e-13)
+        assert np.allclose(P["r"][i], r[2:], rtol=1e-13, atol=1e-13)
+        assert np.allclose(P["p"][i], p[2:], rtol=1e-13, atol=1e-13)
+        assert abs(P["K"][i] / (5 * M / (256 * eta)) - 1) < 1e-14
+        v_low, v_end, m_lo, m_hi = T.td_layout(n, fs, fl, m1, m2)
+        if m_lo > m_hi:
+            assert P["flags"][i] == ci.TMPL_EMPTY
+            continue
+        assert (P["m_lo"][i], P["m_hi"][i]) == (m_lo, m_hi)
+        assert P["k_low"][i] == math.ceil(fl * n / fs) and P["k_high"][i] == n // 2 - 1
+
+
+def test_td_templates_match_oracle(ctx, small):
+    u, hf, s2 = ctx.td_templates(small["seg"], small["tdp"])
+    _sync()
+    u, hf, s2 = u.cpu().numpy(), hf.cpu().numpy(), s2.cpu().numpy()
+    n, fs, fl, psd = small["n"], small["fs"], small["fl"], small["psd"]
+    kl = int(math.ceil(fl * n / fs))
+    for i, (m1, m2) in enumerate(small["bank"]):
+        hp, hc = T.td_chirp(n, fs, fl, m1, m2)
+        uo = hp + 1j * hc
+        Hp, Hc = T.td_spectra(n, fs, fl, m1, m2)
+        if not np.any(uo):
+            assert not np.any(u[i]) and np.all(s2[i] == 0)
+            continue
+        eu = np.max(np.abs(u[i] - uo)) / np.max(np.abs(uo))
+        assert eu < 2e-6, (i, eu)
+        for H, g, s in ((Hp, hf[i, 0], s2[i, 0]), (Hc, hf[i, 1], s2[i, 1])):
+            eh = np.max(np.abs(g - H)) / np.max(np.abs(H))
+            assert eh < 2e-5, (i, eh)
+            so = 4 * fs / n * np.sum(np.abs(H[kl:n // 2]) ** 2 / psd[kl:n // 2])
+            assert abs(s / so - 1) < 1e-5, (i, s, so)
+        print(f"template {i}: signal error {eu:.1e}")
+
+
+def test_td_series_match_oracle(ctx, small):
+    z = ctx.td_matched_filter(small["seg"], small["tdp"])
+    _sync()
+    zg = z.cpu().numpy()
+    for i, (zo, sp, sc) in enumerate(small["zo"]):
+        if sp == 0:
+            assert not np.any(zg[i])
+            continue
+        e = C.series_error(zg[i], zo)
+        print(f"template {i}: series error {e:.2e}")
+        assert e <= C.TOL_FP32, (i, e)
+    # the injected template recovers the injection
+    r2 = np.abs(zg[0]) ** 2
+    assert abs(int(np.argmax(r2)) - 40000) <= 2
+
+
+def test_td_triggers_match_oracle(ctx, small):
+    peaks, trig, cnt = ctx.td_find_triggers(small["seg"], small["tdp"], 6.0, 4096, cap=4096)
+    _, mtrig, mcnt = ctx.td_find_triggers(small["seg"], small["tdp"], 6.0, 4096, cap=4096,
+                                          merge=True)
+    _sync()
+    P = ci.triggers_to_numpy(peaks)
+    count = int(cnt.cpu()[0])
+    Tr = ci.triggers_to_numpy(trig, count)
+    M = ci.triggers_to_numpy(mtrig, int(mcnt.cpu()[0]))
+    keys = [(int(t["tmpl"]), int(t["window"])) for t in Tr]
+    assert keys == sorted(keys)
+    for i, (zo, sp, sc) in enumerate(small["zo"]):
+        if sp == 0:
+            assert int(P[i]["index"]) == -1 and not np.any(Tr["tmpl"] == i)
+            continue
+        C.check_peak(P[i], zo)
+        C.check_triggers(Tr[Tr["tmpl"] == i], zo, 4096, 6.0)
+    assert sorted(set(Tr["window"].tolist())) == M["window"].tolist()
+    for m in M:
+        same = Tr[Tr["window"] == m["window"]]
+        best = same[np.lexsort((same["tmpl"], -same["rho2"]))][0]
+        assert (m["tmpl"], m["index"], m["rho2"]) == (best["tmpl"], best["index"], best["rho2"])
+    # restricted range and argument errors
+    p2, t2, c2 = ctx.td_find_triggers(small["seg"], small["tdp"], 6.0, 1000, j_lo=30000,
+                                      j_hi=50001, cap=4096)
+    _sync()
+    P2 = ci.triggers_to_numpy(p2)
+    for i, (zo, sp, sc) in enumerate(small["zo"]):
+        if sp > 0:
+            C.check_peak(P2[i], zo, j_lo=30000, j_hi=50001)
+            C.check_triggers(ci.triggers_to_numpy(t2, int(c2.cpu()[0]))[
+                ci.triggers_to_numpy(t2, int(c2.cpu()[0]))["tmpl"] == i], zo, 1000, 6.0,
+                j_lo=30000, j_hi=50001)
+    with pytest.raises(ci.CiError) as ei:
+        ctx.td_find_triggers(small["seg"], small["tdp"], 6.0, 0)
+    assert ei.value.code == ci.EINVAL
+
+
+def test_td_noise_free_injection_snr(ctx):
+    """Noise-free data holding one template's h_+ at SNR 10: c_+ at the
+    coalescence sample is 10 (c_x there nearly 0) on the GPU too."""
+    n, fs, fl = 1 << 17, 4096.0, 20.0
+    bank = np.array([[4.0, 3.0]])
+    x64, psd, x128 = _td_case(n, fs, fl, bank, (4.0, 3.0, 10.0, 70000), None)
+    seg = ctx.segment(_dev(x64), _dev(psd), n, fs, fl)
+    tdp = ctx.td_params(seg, bank)
+    z = ctx.td_matched_filter(seg, tdp)
+    peaks, _, _ = ctx.td_find_triggers(seg, tdp, 6.0, 4096)
+    _sync()
+    zg = z.cpu().numpy()[0]
+    assert abs(zg[70000].real - 10.0) < 1e-4 * 10
+    assert abs(zg[70000].imag) < 0.2
+    assert int(ci.triggers_to_numpy(peaks)[0]["index"]) == 70000
+    seg.close()
+
+
+def test_td_full_size_sampled(ctx):
+    """The 2^20-sample, 1024-template workload searched with two-polarization
+    templates, in the benchmark's launch configuration: a seeded sample of
+    templates and every injection's template against the oracle."""
+    wl, bank, injs, x64, psd, x128 = C.workload_case("fp32-2^20")
+    seg = ctx.segment(_dev(x64), _dev(psd), wl.n, wl.fs, wl.f_low)
+    tdp = ctx.td_params(seg, bank)
+    peaks, trig, cnt = ctx.td_find_triggers(seg, tdp, wl.snr_threshold, wl.window,
+                                            cap=1 << 20)
+    _sync()
+    P = ci.triggers_to_numpy(peaks)
+    Tr = ci.triggers_to_numpy(trig, int(cnt.cpu()[0]))
+    rng = np.random.default_rng(4646)
+    sample = sorted(set(i.tmpl for i in injs) | set(rng.choice(len(bank), 4, replace=False).tolist()))
+    for i in sample:
+        zo, sp, sc = T.td_series(x128, psd, wl.n, wl.fs, wl.f_low, *bank[i])
+        C.check_peak(P[i], zo)
+        C.check_triggers(Tr[Tr["tmpl"] == i], zo, wl.window, wl.snr_threshold)
+    # (the injections here are 2PN stationary-phase chirps; a 2.5PN
+    # time-domain template of the same masses matches them only partly, so
+    # no recovery is asserted: the oracle comparison above is the check)
+    for inj in injs:
+        print(f"injection snr {inj.snr} at {inj.j0}: td template peak "
+              f"{int(P[inj.tmpl]['index'])} rho {math.sqrt(float(P[inj.tmpl]['rho2'])):.2f}")
+    seg.close()

@@ -119,6 +119,12 @@ def test_ctypes_structs_match_header(tmp_path):
         lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
         for fname, _ in cls._fields_:
             lines.append(f'  printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    dtypes = {"ci_trigger": ci.TRIGGER_DTYPE, "ci_tparams": ci.TPARAMS_DTYPE,
+              "ci_tdparams": ci.TDPARAMS_DTYPE}
+    for cname, dt in dtypes.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname in dt.names:
+            lines.append(f'  printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
     lines += ["  return 0;", "}"]
     src = tmp_path / "layout.c"
     src.write_text("\n".join(lines) + "\n")
@@ -130,3 +136,7 @@ def test_ctypes_structs_match_header(tmp_path):
         assert got[(cname, "size")] == ctypes.sizeof(cls), cname
         for fname, _ in cls._fields_:
             assert got[(cname, fname)] == getattr(cls, fname).offset, (cname, fname)
+    for cname, dt in dtypes.items():
+        assert got[(cname, "size")] == dt.itemsize, cname
+        for fname in dt.names:
+            assert got[(cname, fname)] == dt.fields[fname][1], (cname, fname)
