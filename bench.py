@@ -69,6 +69,8 @@ def parse():
     p.add_argument("--no-chisq", action="store_true",
                    help="skip timing the chi-squared veto at the per-template peaks")
     p.add_argument("--chisq-bands", type=int, default=16)
+    p.add_argument("--no-td", action="store_true",
+                   help="skip the paper's two-polarization time-domain template form")
     p.add_argument("--precision", default="fp32", choices=sorted(PRECISIONS),
                    help="arithmetic of the headline run")
     p.add_argument("--no-split", action="store_true",
@@ -194,6 +196,44 @@ def chisq_timing(ctx, ci, seg, params, peaks, n_t, bands, reps=10):
             "bins_per_s": round(bins / (ms / 1e3), 1),
             "median_chi2_per_dof": round(float(np.median(fin)) / (2 * bands - 2), 3)
             if len(fin) else None}
+
+
+def td_timing(args, ctx, ci, seg, xt, psd_d, bank, n_t, cap, peaks, trig, count, wl,
+              headline):
+    """The same step with the paper's own template form: time-domain
+    two-polarization templates generated, transformed and normalised per
+    batch, correlated, two real inverse transforms packed into one, merged
+    search.  Bytes per template that the form moves through HBM: generation
+    8n, template transform 16n, sigma^2 8n, pass 1 16n (both mirror bins)
+    + 8n, pass 2 8n = 64n."""
+    import torch
+    tdp = ctx.td_params(seg, bank)
+
+    def step():
+        ctx.segment_update(seg, xt, psd_d)
+        ctx.td_params(seg, bank, out=tdp)
+        ctx.td_find_triggers(seg, tdp, wl.snr_threshold, wl.window, cap=cap, merge=True,
+                             peaks=peaks, trig=trig, count=count)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    steps = max(2, args.steps // 2)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        step()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    v = n_t / (ms / 1e3)
+    gbs = 64.0 * wl.n * n_t / (ms / 1e3) / 1e9
+    log(f"[bench] two-polarization form: {ms:.3f} ms/step, {v:.0f} templates/s")
+    return {"value": round(v, 1), "unit": "templates/s", "ms_per_step": round(ms, 4),
+            "steps": steps, "vs_headline": round(v / headline, 3),
+            "model_bytes_per_template": 64 * wl.n, "model_gbs": round(gbs, 1),
+            "model_frac": round(gbs / HBM_PEAK_GBS, 4),
+            "merged_windows": int(count.cpu()[0])}
 
 
 def run_classes(args, lib, ctx, wl):
@@ -423,6 +463,9 @@ def main():
         out["precision_paths"] = paths
     if not args.no_chisq:
         out["chisq_veto"] = chisq_timing(ctx, ci, seg, params, peaks, n_t, args.chisq_bands)
+    if not args.no_td:
+        out["two_polarization"] = td_timing(args, ctx, ci, seg, xt, psd_d, bank, n_t, cap,
+                                            peaks, trig, count, wl, value)
     if not args.no_copy_probe:
         out["copy_probe_gbs"] = round(copy_probe_gbs(), 1)
     if not args.no_cpu_baseline:
