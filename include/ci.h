@@ -16,6 +16,7 @@
  *   ci_chisq            the chi-squared veto planned in the Conclusions
  *   ci_td_*             the paper's own template form: time-domain
  *                       generator, two polarizations, two C2R + madd2
+ *   ci_stream_*         the per-chunk loop over a continuous stream
  *
  * Conventions shared by every call
  * --------------------------------
@@ -300,6 +301,56 @@ int ci_td_find_triggers(ci_ctx* ctx, const ci_segment* seg, const ci_tdparams* d
                         int64_t n, float snr_threshold, int64_t window, int64_t j_lo,
                         int64_t j_hi, ci_trigger* d_peaks, ci_trigger* d_trig, int64_t cap,
                         int64_t* d_count, int32_t merge_across_templates, void* stream);
+
+/* --- continuous stream processing ---------------------------------------------
+ * The per-chunk loop of "Matched filtering" run over a continuous strain
+ * stream: overlap-save segments of n samples with stride n/2 (segment s
+ * covers global samples [s n/2, s n/2 + n)), each searched over its valid
+ * half j in [n/4, 3n/4), so that consecutive valid regions tile the stream
+ * once and chirps up to n/4 samples long need no wrap-around.  Per segment,
+ * on the device: the spectrum x~_k = dt sum_j x_j e^{-2 pi i jk/n}; the PSD
+ * estimate, the Hann-windowed periodogram P_k = 2 |X_k|^2 / (T 3/8),
+ * X_k = dt sum_j sin^2(pi j/n) x_j e^{-2 pi i jk/n}, averaged over the
+ * in-band bins [k - h, k + h] intersected with [k_low, n/2 - 1] (S_k = 0
+ * outside that band); the segment update, the templates' sigma^2 and the
+ * merged search of ci_find_triggers (FP32, the context's launch
+ * configuration).  Trigger indices and windows are global.
+ * Host samples are staged through pinned memory and copied on a stream of
+ * their own, so copies overlap the search of earlier segments. */
+typedef struct ci_stream ci_stream;  /* opaque */
+
+typedef struct {
+  int64_t n;              /* segment length: power of two, 2^16 .. 2^21 */
+  double fs, f_low;
+  int32_t psd_half_width; /* h: 0 .. 256 */
+  float snr_threshold;    /* lambda (rho^2 > lambda^2 triggers) */
+  int64_t window;         /* W: 1 .. n/2, dividing n/2 */
+  int64_t cap;            /* merged triggers kept per segment, >= 1 */
+} ci_stream_spec;
+
+/* bank_host[n_templates] is copied.  CI_EINVAL for a bad spec or bank. */
+int ci_stream_create(ci_ctx* ctx, const ci_stream_spec* spec, const ci_template* bank_host,
+                     int64_t n_templates, ci_stream** out);
+/* Waits for the stream's work, frees it.  Destroy a stream before its
+ * context. */
+int ci_stream_destroy(ci_stream* s);
+/* Append `count` samples (host, float32) and enqueue every segment they
+ * complete.  Returns once the samples are staged; may wait for earlier
+ * copies and, when two segments are already in flight, for the older. */
+int ci_stream_push(ci_stream* s, const float* host_x, int64_t count);
+/* Collect triggers of finished segments, in segment order (so in global
+ * window order): host_out[0 .. *n_out) receives at most `cap`; the rest
+ * stay queued for the next call.  wait != 0 first waits for every
+ * enqueued segment.  *segments_done (may be NULL): segments collected so
+ * far.  A segment whose merged list overflowed its cap contributes its
+ * first `cap` windows and sets bit 0 of *flags (may be NULL). */
+int ci_stream_poll(ci_stream* s, int32_t wait, ci_trigger* host_out, int64_t cap,
+                   int64_t* n_out, int64_t* segments_done, int32_t* flags);
+/* Inspection: waits for the stream's work and copies the spectrum
+ * (complex64 [n/2 + 1]) and PSD estimate (double [n/2 + 1]) of the last
+ * segment processed to device buffers (either may be NULL); *segment
+ * receives its index (-1 before the first). */
+int ci_stream_last(ci_stream* s, void* d_xtilde, double* d_psd, int64_t* segment);
 
 /* --- chi-squared veto ---------------------------------------------------------
  * The signal-consistency test the Conclusions plan as the next stage of the

@@ -34,7 +34,8 @@ EXPORTED_SYMBOLS = (
     "ci_segment_update", "ci_set_timing", "ci_kernel_times",
     "ci_length_classes", "ci_search_classes", "ci_get_tune", "ci_set_tune",
     "ci_autotune", "ci_chisq", "ci_td_params", "ci_td_templates",
-    "ci_td_matched_filter", "ci_td_find_triggers",
+    "ci_td_matched_filter", "ci_td_find_triggers", "ci_stream_create",
+    "ci_stream_destroy", "ci_stream_push", "ci_stream_poll", "ci_stream_last",
 )
 RUN_GRAPH = 1
 
@@ -109,6 +110,12 @@ class _Tune(ctypes.Structure):
 
 _vp, _i32, _i64, _f32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_float
 
+
+class _StreamSpec(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("fs", ctypes.c_double), ("f_low", ctypes.c_double),
+                ("psd_half_width", ctypes.c_int32), ("snr_threshold", ctypes.c_float),
+                ("window", ctypes.c_int64), ("cap", ctypes.c_int64)]
+
 _SIGS = {
     "ci_version": (ctypes.c_char_p, []),
     "ci_last_error": (ctypes.c_char_p, [_vp]),
@@ -137,6 +144,13 @@ _SIGS = {
     "ci_autotune": (ctypes.c_int, [_vp, _vp, _vp, _i64, _i32, _f32, _i64,
                                    ctypes.POINTER(_Tune), _vp]),
     "ci_chisq": (ctypes.c_int, [_vp, _vp, _vp, _i64, _vp, _i64, _i32, _vp, _vp]),
+    "ci_stream_create": (ctypes.c_int, [_vp, ctypes.POINTER(_StreamSpec), _vp, _i64,
+                                        ctypes.POINTER(_vp)]),
+    "ci_stream_destroy": (ctypes.c_int, [_vp]),
+    "ci_stream_push": (ctypes.c_int, [_vp, _vp, _i64]),
+    "ci_stream_poll": (ctypes.c_int, [_vp, _i32, _vp, _i64, ctypes.POINTER(_i64),
+                                      ctypes.POINTER(_i64), ctypes.POINTER(_i32)]),
+    "ci_stream_last": (ctypes.c_int, [_vp, _vp, _vp, ctypes.POINTER(_i64)]),
     "ci_td_params": (ctypes.c_int, [_vp, _vp, _vp, _i64, _vp, _vp]),
     "ci_td_templates": (ctypes.c_int, [_vp, _vp, _vp, _i64, _vp, _vp, _vp, _vp]),
     "ci_td_matched_filter": (ctypes.c_int, [_vp, _vp, _vp, _i64, _vp, _vp]),
@@ -224,6 +238,51 @@ class Segment:
     def close(self):
         if self.handle:
             self.ctx.lib.dll.ci_segment_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Stream:
+    """A ci_stream: overlap-save search of a continuous float32 strain
+    stream (segments of n samples, stride n/2, valid half searched)."""
+
+    def __init__(self, ctx: "Context", handle: int, spec):
+        self.ctx, self.handle, self.spec = ctx, handle, spec
+
+    def push(self, x):
+        x = np.ascontiguousarray(np.asarray(x, dtype=np.float32).reshape(-1))
+        self.ctx._chk(self.ctx.lib.dll.ci_stream_push(self.handle, x.ctypes.data, x.size))
+
+    def poll(self, wait: bool = False, cap: int = 1 << 16):
+        """(structured trigger array, segments collected, flags)."""
+        out = np.zeros(max(cap, 1), dtype=TRIGGER_DTYPE)
+        k, segs, fl = _i64(), _i64(), _i32()
+        self.ctx._chk(self.ctx.lib.dll.ci_stream_poll(
+            self.handle, 1 if wait else 0, out.ctypes.data, cap, ctypes.byref(k),
+            ctypes.byref(segs), ctypes.byref(fl)))
+        return out[:k.value].copy(), segs.value, fl.value
+
+    def last(self):
+        """(spectrum complex64 [n/2+1], PSD float64 [n/2+1], segment index)
+        of the last segment processed (blocking)."""
+        import torch
+        m = self.spec.n // 2 + 1
+        dev = torch.device("cuda", self.ctx.device)
+        xt = torch.empty(m, dtype=torch.complex64, device=dev)
+        ps = torch.empty(m, dtype=torch.float64, device=dev)
+        seg = _i64()
+        self.ctx._chk(self.ctx.lib.dll.ci_stream_last(self.handle, _ptr(xt), _ptr(ps),
+                                                      ctypes.byref(seg)))
+        return xt.cpu().numpy(), ps.cpu().numpy(), seg.value
+
+    def close(self):
+        if self.handle:
+            self.ctx.lib.dll.ci_stream_destroy(self.handle)
             self.handle = None
 
     def __del__(self):
@@ -384,6 +443,16 @@ class Context:
             self.handle, seg.handle, _ptr(params), n, _ptr(trig), n_trig, bands,
             _ptr(out), _stream(stream)))
         return out[:n_trig]
+
+    def stream(self, bank, n: int, fs: float, f_low: float, thr: float, window: int,
+               psd_half_width: int = 16, cap: int = 1 << 12) -> Stream:
+        bank = np.ascontiguousarray(np.asarray(bank, dtype=np.float64).reshape(-1, 2))
+        spec = _StreamSpec(n, fs, f_low, psd_half_width, thr, window, cap)
+        h = _vp()
+        self._chk(self.lib.dll.ci_stream_create(self.handle, ctypes.byref(spec),
+                                                bank.ctypes.data, bank.shape[0],
+                                                ctypes.byref(h)))
+        return Stream(self, h.value, spec)
 
     # --- the paper's two-polarization (time-domain) template form ---------
 

@@ -605,6 +605,45 @@ int td_batches(Ctx* ctx, const Seg* seg, const ci_tdparams* d_tdp, int64_t n, hi
 struct ci_ctx : Ctx {};
 struct ci_segment : Seg {};
 
+// Continuous stream state.  Samples go through pinned staging into a device
+// ring of 4n floats on the copy stream `cs`; segments are processed in order
+// on the compute stream `ks` (the search forks onto the context's streams
+// and joins back); results of the last two segments wait in device slots
+// and are moved to the host queue in order.
+struct ci_stream {
+  Ctx* ctx = nullptr;
+  ci_stream_spec spec;
+  Seg* seg = nullptr;
+  int64_t nt = 0;                 // templates
+  ci_tparams* d_params = nullptr; // [nt], sigma^2 refreshed per segment
+  float* ring = nullptr;          // [4n]
+  int64_t rmask = 0;
+  float2* uv = nullptr;           // [2][n] transform scratch
+  float2* y = nullptr;            // [2][n] intermediate
+  float2* xt = nullptr;           // [n/2 + 1] segment spectrum
+  double* pg = nullptr;           // [n/2 + 1] periodogram
+  double* psd = nullptr;          // [n/2 + 1] PSD estimate
+  static constexpr int kRes = 2;  // result slots in flight
+  ci_trigger* d_peaks[kRes] = {};
+  ci_trigger* d_trig[kRes] = {};
+  int64_t* d_count[kRes] = {};
+  int64_t slot_seg[kRes] = {-1, -1};  // segment held by the slot, -1: none
+  hipEvent_t done[kRes] = {};
+  float* stage[2] = {};           // pinned staging
+  int64_t stage_len = 0;
+  hipEvent_t stage_ev[2] = {};
+  bool stage_armed[2] = {false, false};
+  int stage_next = 0;
+  hipStream_t cs = nullptr, ks = nullptr;
+  hipEvent_t copy_ev = nullptr, gather_ev = nullptr;
+  bool gather_armed = false;
+  int64_t pushed = 0;             // samples received
+  int64_t next_seg = 0;           // next segment to enqueue
+  int64_t collected = 0;          // segments moved to the host queue
+  std::vector<ci_trigger> queue;  // collected, not yet returned
+  int32_t flags = 0;
+};
+
 extern "C" {
 
 const char* ci_version(void) { return "ci 0.1 (gfx950)"; }
@@ -1057,6 +1096,313 @@ int ci_td_find_triggers(ci_ctx* ctx, const ci_segment* seg, const ci_tdparams* d
   if (rc != CI_OK) return rc;
   return enqueue_jobs(ctx, jobs, slot, CI_FP32, snr_threshold * snr_threshold, window,
                       merge_across_templates ? 1 : 0, static_cast<hipStream_t>(stream));
+}
+
+// --- continuous stream ----------------------------------------------------
+
+namespace {
+
+void free_stream(ci_stream* s) {
+  if (!s) return;
+  if (s->ks) (void)hipStreamSynchronize(s->ks);
+  if (s->cs) (void)hipStreamSynchronize(s->cs);
+  if (s->seg) {
+    auto& v = s->ctx->segs;
+    for (size_t i = 0; i < v.size(); ++i)
+      if (v[i] == s->seg) {
+        v[i] = v.back();
+        v.pop_back();
+        break;
+      }
+    free_seg(s->seg);
+  }
+  void* dev[] = {s->d_params, s->ring, s->uv, s->y, s->xt, s->pg, s->psd};
+  for (void* p : dev)
+    if (p) (void)hipFree(p);
+  for (int i = 0; i < ci_stream::kRes; ++i) {
+    if (s->d_peaks[i]) (void)hipFree(s->d_peaks[i]);
+    if (s->d_trig[i]) (void)hipFree(s->d_trig[i]);
+    if (s->d_count[i]) (void)hipFree(s->d_count[i]);
+    if (s->done[i]) (void)hipEventDestroy(s->done[i]);
+  }
+  for (int i = 0; i < 2; ++i) {
+    if (s->stage[i]) (void)hipHostFree(s->stage[i]);
+    if (s->stage_ev[i]) (void)hipEventDestroy(s->stage_ev[i]);
+  }
+  if (s->copy_ev) (void)hipEventDestroy(s->copy_ev);
+  if (s->gather_ev) (void)hipEventDestroy(s->gather_ev);
+  if (s->cs) (void)hipStreamDestroy(s->cs);
+  if (s->ks) (void)hipStreamDestroy(s->ks);
+  delete s;
+}
+
+// Move the finished results of slot i (segment slot_seg[i]) to the host
+// queue with global indices and windows.  Blocking.
+int collect_slot(ci_stream* s, int i) {
+  Ctx* ctx = s->ctx;
+  if (s->slot_seg[i] < 0) return CI_OK;
+  hipError_t e = hipEventSynchronize(s->done[i]);
+  int64_t cnt = 0;
+  if (e == hipSuccess) e = hipMemcpy(&cnt, s->d_count[i], sizeof cnt, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hipfail(ctx, e, "stream result wait");
+  int64_t keep = cnt < s->spec.cap ? cnt : s->spec.cap;
+  if (cnt > s->spec.cap) s->flags |= 1;
+  const size_t base = s->queue.size();
+  s->queue.resize(base + (size_t)keep);
+  if (keep > 0) {
+    e = hipMemcpy(s->queue.data() + base, s->d_trig[i], sizeof(ci_trigger) * (size_t)keep,
+                  hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hipfail(ctx, e, "stream result copy");
+  }
+  const int64_t off = s->slot_seg[i] * (s->spec.n / 2);
+  const int64_t woff = off / s->spec.window;
+  for (size_t k = base; k < s->queue.size(); ++k) {
+    s->queue[k].index += off;
+    s->queue[k].window += woff;
+  }
+  s->slot_seg[i] = -1;
+  ++s->collected;
+  return CI_OK;
+}
+
+// Enqueue segment s->next_seg on ks (its samples are in the ring).
+int enqueue_segment(ci_stream* s) {
+  Ctx* ctx = s->ctx;
+  const int64_t seg_i = s->next_seg;
+  const int slot = (int)(seg_i % ci_stream::kRes);
+  // the slot's previous segment must be collected first (segment order)
+  for (int64_t q = s->collected; q <= seg_i - ci_stream::kRes; ++q) {
+    const int r = collect_slot(s, (int)(q % ci_stream::kRes));
+    if (r != CI_OK) return r;
+  }
+  const int64_t n = s->spec.n;
+  hipError_t e = hipStreamWaitEvent(s->ks, s->copy_ev, 0);
+  if (e != hipSuccess) return hipfail(ctx, e, "stream copy ordering");
+  e = launch_stream_spectra(s->seg, s->ring, s->rmask, seg_i * (n / 2), s->uv, s->y, s->xt, s->pg,
+                            s->psd, s->spec.psd_half_width, s->ks);
+  if (e != hipSuccess) return hipfail(ctx, e, "stream spectrum launch");
+  e = hipEventRecord(s->gather_ev, s->ks);
+  if (e != hipSuccess) return hipfail(ctx, e, "stream event");
+  s->gather_armed = true;
+  e = launch_segment(s->seg, s->xt, s->psd, s->ks);
+  if (e == hipSuccess) e = launch_params(s->seg, s->d_params, s->nt, nullptr, s->ks);
+  if (e != hipSuccess) return hipfail(ctx, e, "stream segment launch");
+  std::vector<Job> jobs(1);
+  Job& jb = jobs[0];
+  jb.seg = s->seg;
+  jb.params = s->d_params;
+  jb.n = s->nt;
+  jb.j_lo = n / 4;
+  jb.j_hi = 3 * n / 4;
+  jb.peaks = s->d_peaks[slot];
+  jb.trig = s->d_trig[slot];
+  jb.cap = s->spec.cap;
+  jb.count = s->d_count[slot];
+  int rc = check_job(ctx, jb, CI_FP32, s->spec.snr_threshold, s->spec.window);
+  if (rc != CI_OK) return rc;
+  size_t ys = 0;
+  rc = prepare_jobs(ctx, jobs, &ys);
+  if (rc != CI_OK) return rc;
+  rc = enqueue_jobs(ctx, jobs, ys, CI_FP32, s->spec.snr_threshold * s->spec.snr_threshold,
+                    s->spec.window, 1, s->ks);
+  if (rc != CI_OK) return rc;
+  e = hipEventRecord(s->done[slot], s->ks);
+  if (e != hipSuccess) return hipfail(ctx, e, "stream event");
+  s->slot_seg[slot] = seg_i;
+  ++s->next_seg;
+  return CI_OK;
+}
+
+}  // namespace
+
+int ci_stream_create(ci_ctx* ctx, const ci_stream_spec* spec, const ci_template* bank_host,
+                     int64_t n_templates, ci_stream** out) {
+  if (!ctx) return fail(nullptr, CI_EINVAL, "null context");
+  if (!spec || !out) return fail(ctx, CI_EINVAL, "null spec or output handle");
+  if (n_templates < 1 || !bank_host) return fail(ctx, CI_EINVAL, "empty bank");
+  if (check_bank(ctx, bank_host, n_templates) != CI_OK) return CI_EINVAL;
+  const int64_t n = spec->n;
+  if (ilog2_exact(n) < 16 || ilog2_exact(n) > 21)
+    return fail(ctx, CI_EINVAL, "n = %lld is not a power of two in 2^16 .. 2^21", (long long)n);
+  if (spec->psd_half_width < 0 || spec->psd_half_width > 256)
+    return fail(ctx, CI_EINVAL, "psd_half_width %d outside 0..256", spec->psd_half_width);
+  if (spec->window < 1 || spec->window > n / 2 || (n / 2) % spec->window != 0)
+    return fail(ctx, CI_EINVAL, "window %lld must divide n/2", (long long)spec->window);
+  if (spec->cap < 1) return fail(ctx, CI_EINVAL, "cap must be >= 1");
+  if (!isfinite(spec->snr_threshold) || spec->snr_threshold < 0.f)
+    return fail(ctx, CI_EINVAL, "threshold must be finite and >= 0");
+  DeviceGuard dg(ctx->device);
+  if (!dg.ok) return fail(ctx, CI_EHIP, "cannot select device %d", ctx->device);
+  ci_stream* s = new (std::nothrow) ci_stream();
+  if (!s) return fail(ctx, CI_ENOMEM, "stream allocation");
+  s->ctx = ctx;
+  s->spec = *spec;
+  s->nt = n_templates;
+  const int64_t half = n / 2;
+  hipError_t e = hipSuccess;
+  auto al = [&](void** p, size_t bytes) {
+    if (e == hipSuccess) e = hipMalloc(p, bytes);
+  };
+  al((void**)&s->d_params, sizeof(ci_tparams) * (size_t)n_templates);
+  al((void**)&s->ring, sizeof(float) * 4 * (size_t)n);
+  al((void**)&s->uv, sizeof(float2) * 2 * (size_t)n);
+  al((void**)&s->y, sizeof(float2) * 2 * (size_t)n);
+  al((void**)&s->xt, sizeof(float2) * (size_t)(half + 1));
+  al((void**)&s->pg, sizeof(double) * (size_t)(half + 1));
+  al((void**)&s->psd, sizeof(double) * (size_t)(half + 1));
+  for (int i = 0; i < ci_stream::kRes; ++i) {
+    al((void**)&s->d_peaks[i], sizeof(ci_trigger) * (size_t)n_templates);
+    al((void**)&s->d_trig[i], sizeof(ci_trigger) * (size_t)spec->cap);
+    al((void**)&s->d_count[i], sizeof(int64_t));
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&s->done[i], hipEventDisableTiming);
+  }
+  s->stage_len = n < (int64_t(1) << 20) ? n : (int64_t(1) << 20);
+  for (int i = 0; i < 2; ++i) {
+    if (e == hipSuccess)
+      e = hipHostMalloc((void**)&s->stage[i], sizeof(float) * (size_t)s->stage_len,
+                        hipHostMallocDefault);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&s->stage_ev[i], hipEventDisableTiming);
+  }
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&s->copy_ev, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&s->gather_ev, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->cs, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->ks, hipStreamNonBlocking);
+  if (e != hipSuccess) {
+    free_stream(s);
+    return fail(ctx, CI_ENOMEM, "stream buffers: %s", hipGetErrorString(e));
+  }
+  s->rmask = 4 * n - 1;
+  // the segment (grid tables now; data per segment) and the templates'
+  // constants (grid only; sigma^2 per segment)
+  ci_segment_spec ss{n, spec->fs, spec->f_low};
+  std::vector<float2> zx((size_t)(half + 1), make_float2(0.f, 0.f));
+  std::vector<double> one((size_t)(half + 1), 1.0);
+  float2* dx = nullptr;
+  double* dp = nullptr;
+  e = hipMalloc((void**)&dx, sizeof(float2) * zx.size());
+  if (e == hipSuccess) e = hipMalloc((void**)&dp, sizeof(double) * one.size());
+  if (e == hipSuccess)
+    e = hipMemcpy(dx, zx.data(), sizeof(float2) * zx.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(dp, one.data(), sizeof(double) * one.size(), hipMemcpyHostToDevice);
+  int rc = CI_OK;
+  ci_segment* sg = nullptr;
+  if (e == hipSuccess) rc = ci_segment_create(ctx, &ss, dx, dp, s->ks, &sg);
+  if (e == hipSuccess && rc == CI_OK) e = hipStreamSynchronize(s->ks);
+  if (dx) (void)hipFree(dx);
+  if (dp) (void)hipFree(dp);
+  if (e != hipSuccess || rc != CI_OK) {
+    if (sg) (void)ci_segment_destroy(sg);
+    free_stream(s);
+    return rc != CI_OK ? rc : hipfail(ctx, e, "stream segment");
+  }
+  s->seg = sg;
+  std::vector<ci_tparams> hp((size_t)n_templates);
+  for (int64_t i = 0; i < n_templates; ++i) host_params(bank_host[i], sg->host, &hp[(size_t)i]);
+  e = hipMemcpy(s->d_params, hp.data(), sizeof(ci_tparams) * hp.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    free_stream(s);
+    return hipfail(ctx, e, "stream parameter upload");
+  }
+  *out = s;
+  return CI_OK;
+}
+
+int ci_stream_destroy(ci_stream* s) {
+  if (!s) return CI_OK;
+  DeviceGuard g(s->ctx ? s->ctx->device : 0);
+  free_stream(s);
+  return CI_OK;
+}
+
+int ci_stream_push(ci_stream* s, const float* host_x, int64_t count) {
+  if (!s) return fail(nullptr, CI_EINVAL, "null stream");
+  Ctx* ctx = s->ctx;
+  if (count < 0) return fail(ctx, CI_EINVAL, "negative count");
+  if (count > 0 && !host_x) return fail(ctx, CI_EINVAL, "null samples");
+  DeviceGuard dg(ctx->device);
+  if (!dg.ok) return fail(ctx, CI_EHIP, "cannot select device %d", ctx->device);
+  const int64_t n = s->spec.n, R = s->rmask + 1;
+  int64_t done_in = 0;
+  while (done_in < count) {
+    // one piece: within the staging buffer, before the ring wraps, and not
+    // past the end of the next segment (so segments are enqueued in time)
+    int64_t c = count - done_in;
+    if (c > s->stage_len) c = s->stage_len;
+    const int64_t pos = s->pushed & s->rmask;
+    if (c > R - pos) c = R - pos;
+    const int64_t need = s->next_seg * (n / 2) + n - s->pushed;
+    if (c > need) c = need;
+    const int b = s->stage_next;
+    s->stage_next ^= 1;
+    hipError_t e = hipSuccess;
+    if (s->stage_armed[b]) e = hipEventSynchronize(s->stage_ev[b]);
+    if (e != hipSuccess) return hipfail(ctx, e, "staging wait");
+    memcpy(s->stage[b], host_x + done_in, sizeof(float) * (size_t)c);
+    // ring positions about to be overwritten were last read by the
+    // gathers already enqueued
+    if (s->gather_armed) e = hipStreamWaitEvent(s->cs, s->gather_ev, 0);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(s->ring + pos, s->stage[b], sizeof(float) * (size_t)c,
+                         hipMemcpyHostToDevice, s->cs);
+    if (e == hipSuccess) e = hipEventRecord(s->stage_ev[b], s->cs);
+    if (e == hipSuccess) e = hipEventRecord(s->copy_ev, s->cs);
+    if (e != hipSuccess) return hipfail(ctx, e, "stream copy");
+    s->stage_armed[b] = true;
+    s->pushed += c;
+    done_in += c;
+    while (s->pushed >= s->next_seg * (n / 2) + n) {
+      const int rc = enqueue_segment(s);
+      if (rc != CI_OK) return rc;
+    }
+  }
+  return CI_OK;
+}
+
+int ci_stream_poll(ci_stream* s, int32_t wait, ci_trigger* host_out, int64_t cap, int64_t* n_out,
+                   int64_t* segments_done, int32_t* flags) {
+  if (!s) return fail(nullptr, CI_EINVAL, "null stream");
+  Ctx* ctx = s->ctx;
+  if (cap < 0 || !n_out || (cap > 0 && !host_out))
+    return fail(ctx, CI_EINVAL, "bad output arguments");
+  DeviceGuard dg(ctx->device);
+  if (!dg.ok) return fail(ctx, CI_EHIP, "cannot select device %d", ctx->device);
+  while (s->collected < s->next_seg) {
+    const int i = (int)(s->collected % ci_stream::kRes);
+    if (!wait) {
+      const hipError_t q = hipEventQuery(s->done[i]);
+      if (q == hipErrorNotReady) {
+        (void)hipGetLastError();  // not an error: leave no sticky status
+        break;
+      }
+      if (q != hipSuccess) return hipfail(ctx, q, "stream event query");
+    }
+    const int rc = collect_slot(s, i);
+    if (rc != CI_OK) return rc;
+  }
+  const int64_t k = (int64_t)s->queue.size() < cap ? (int64_t)s->queue.size() : cap;
+  if (k > 0) memcpy(host_out, s->queue.data(), sizeof(ci_trigger) * (size_t)k);
+  s->queue.erase(s->queue.begin(), s->queue.begin() + k);
+  *n_out = k;
+  if (segments_done) *segments_done = s->collected;
+  if (flags) *flags = s->flags;
+  return CI_OK;
+}
+
+int ci_stream_last(ci_stream* s, void* d_xtilde, double* d_psd, int64_t* segment) {
+  if (!s) return fail(nullptr, CI_EINVAL, "null stream");
+  Ctx* ctx = s->ctx;
+  DeviceGuard dg(ctx->device);
+  if (!dg.ok) return fail(ctx, CI_EHIP, "cannot select device %d", ctx->device);
+  hipError_t e = hipStreamSynchronize(s->ks);
+  const size_t m = (size_t)(s->spec.n / 2 + 1);
+  if (e == hipSuccess && d_xtilde)
+    e = hipMemcpy(d_xtilde, s->xt, sizeof(float2) * m, hipMemcpyDeviceToDevice);
+  if (e == hipSuccess && d_psd)
+    e = hipMemcpy(d_psd, s->psd, sizeof(double) * m, hipMemcpyDeviceToDevice);
+  if (e != hipSuccess) return hipfail(ctx, e, "stream inspection");
+  if (segment) *segment = s->next_seg - 1;
+  return CI_OK;
 }
 
 int ci_chisq(ci_ctx* ctx, const ci_segment* seg, const ci_tparams* d_params, int64_t n,

@@ -184,6 +184,12 @@ hipError_t launch_td_prep(const BatchArgs& a, hipStream_t st);
 hipError_t launch_td_gen(const BatchArgs& a, hipStream_t st);
 // Spectra H~+ / H~x and sigma^2 of a prepared batch (either may be null).
 hipError_t launch_td_export(const BatchArgs& a, void* d_hf, double* d_sigma2, hipStream_t st);
+// Stream segment starting at global sample `start` of the device ring
+// (capacity rmask + 1): spectrum xt [n/2 + 1], periodogram pg and PSD
+// estimate psd [n/2 + 1] (half-width h); uv and y are [2][n] scratch.
+hipError_t launch_stream_spectra(const Seg* seg, const float* ring, int64_t rmask, int64_t start,
+                                 float2* uv, float2* y, float2* xt, double* pg, double* psd,
+                                 int h, hipStream_t st);
 // sigma^2 partial sums per two-polarization template
 constexpr int kTdChunks = 16;
 hipError_t launch_pass2_trig(const BatchArgs& a, hipStream_t st);

@@ -1498,9 +1498,13 @@ P2Args make_p2(const BatchArgs& a) {
   if (a.td) {
     p.flagp = reinterpret_cast<const char*>(&a.td->flags);
     p.flag_stride = (int)sizeof(ci_tdparams);
-  } else {
+  } else if (a.params) {
     p.flagp = reinterpret_cast<const char*>(&a.params->flags);
     p.flag_stride = (int)sizeof(ci_tparams);
+  } else {
+    // plain transforms (series mode without templates): no finaliser
+    p.flagp = nullptr;
+    p.flag_stride = 0;
   }
   p.tw = a.seg->tw2048;
   p.tw64 = a.seg->tw64;
@@ -1692,6 +1696,88 @@ hipError_t dispatch(const Plan& p, F f) {
 }
 
 }  // namespace
+
+// ---------------------------------------------------------------------------
+// continuous stream: segment spectrum and PSD estimate
+// ---------------------------------------------------------------------------
+
+// Segment samples from the device ring (capacity rmask + 1, a power of two)
+// as two complex inputs: x_j and w_j x_j, w_j = sin^2(pi j / n).
+__global__ __launch_bounds__(256) void k_stream_gather(const float* __restrict__ ring,
+                                                       int64_t rmask, int64_t start, int64_t n,
+                                                       float2* __restrict__ uv) {
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (j >= n) return;
+  const float x = ring[(start + j) & rmask];
+  // sin^2(pi j/n) = (1 - cos(2 pi j/n)) / 2, the cosine in revolutions
+  const float w = 0.5f * (1.f - __builtin_amdgcn_cosf((float)j / (float)n));
+  uv[j] = make_float2(x, 0.f);
+  uv[n + j] = make_float2(w * x, 0.f);
+}
+
+// From V = IDFT of the two inputs (real inputs, so the forward DFT is the
+// conjugate): x~_k = dt conj(V0_k) and the periodogram
+// P_k = 2 |dt V1_k|^2 / (T 3/8) in FP64, k = 0..n/2.
+__global__ __launch_bounds__(256) void k_stream_spec(const float2* __restrict__ V, int64_t n,
+                                                     double dt, float2* __restrict__ xt,
+                                                     double* __restrict__ pg) {
+  const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (k > n / 2) return;
+  const float2 a = V[k], b = V[n + k];
+  xt[k] = make_float2((float)(dt * a.x), (float)(-dt * a.y));
+  const double T = dt * (double)n;
+  pg[k] = 2.0 * dt * dt * ((double)b.x * b.x + (double)b.y * b.y) / (T * 0.375);
+}
+
+// PSD estimate: the mean of the periodogram over the in-band bins
+// [k - h, k + h] intersected with [kl, kh]; 0 outside [kl, kh].
+__global__ __launch_bounds__(256) void k_stream_psd(const double* __restrict__ pg, int64_t kl,
+                                                    int64_t kh, int h, int64_t half,
+                                                    double* __restrict__ psd) {
+  const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (k > half) return;
+  double v = 0.0;
+  if (k >= kl && k <= kh) {
+    const int64_t a = k - h > kl ? k - h : kl, b = k + h < kh ? k + h : kh;
+    double s = 0.0;
+    for (int64_t i = a; i <= b; ++i) s += pg[i];
+    v = s / (double)(b - a + 1);
+  }
+  psd[k] = v;
+}
+
+hipError_t launch_stream_spectra(const Seg* seg, const float* ring, int64_t rmask, int64_t start,
+                                 float2* uv, float2* y, float2* xt, double* pg, double* psd,
+                                 int h, hipStream_t st) {
+  const SegDev& hd = seg->host;
+  const int64_t n = hd.n;
+  hipLaunchKernelGGL(k_stream_gather, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, ring,
+                     rmask, start, n, uv);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  BatchArgs a = {};
+  a.seg = seg;
+  a.plan = seg->plan;
+  a.nb = 2;
+  a.bmax = 2;
+  a.precision = CI_FP32;
+  a.uv = uv;
+  a.y = y;
+  a.d_z = uv;
+  e = dispatch(a.plan, [&](auto inst) {
+    typedef decltype(inst) I;
+    hipError_t r = I::template p1mem<0>(a, false, st);
+    return r == hipSuccess ? I::p2s(a, st) : r;
+  });
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_stream_spec, dim3((unsigned)((hd.half + 1 + 255) / 256)), dim3(256), 0, st,
+                     uv, n, 1.0 / hd.fs, xt, pg);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_stream_psd, dim3((unsigned)((hd.half + 1 + 255) / 256)), dim3(256), 0, st,
+                     pg, (int64_t)hd.k_low, hd.half - 1, h, hd.half, psd);
+  return hipGetLastError();
+}
 
 hipError_t launch_td_gen(const BatchArgs& a, hipStream_t st) {
   hipLaunchKernelGGL(k_td_gen, dim3((unsigned)(a.seg->host.n / 256), (unsigned)a.nb), dim3(256),

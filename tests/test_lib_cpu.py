@@ -113,7 +113,8 @@ def test_ctypes_structs_match_header(tmp_path):
         pytest.skip("no gcc")
     inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
     structs = {"ci_tune": ci._Tune, "ci_class_job": ci._ClassJob, "ci_bank_spec": ci._BankSpec,
-               "ci_segment_spec": ci._SegSpec, "ci_kernel_time": ci._KernelTime}
+               "ci_segment_spec": ci._SegSpec, "ci_kernel_time": ci._KernelTime,
+               "ci_stream_spec": ci._StreamSpec}
     lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "ci.h"', "int main(void) {"]
     for cname, cls in structs.items():
         lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
