@@ -71,6 +71,9 @@ def parse():
     p.add_argument("--chisq-bands", type=int, default=16)
     p.add_argument("--no-td", action="store_true",
                    help="skip the paper's two-polarization time-domain template form")
+    p.add_argument("--no-stream", action="store_true",
+                   help="skip the continuous-stream leg (overlap-save segments from host samples)")
+    p.add_argument("--stream-segments", type=int, default=16)
     p.add_argument("--precision", default="fp32", choices=sorted(PRECISIONS),
                    help="arithmetic of the headline run")
     p.add_argument("--no-split", action="store_true",
@@ -196,6 +199,42 @@ def chisq_timing(ctx, ci, seg, params, peaks, n_t, bands, reps=10):
             "bins_per_s": round(bins / (ms / 1e3), 1),
             "median_chi2_per_dof": round(float(np.median(fin)) / (2 * bands - 2), 3)
             if len(fin) else None}
+
+
+def stream_timing(args, ctx, bank, wl, headline):
+    """Continuous stream: float32 strain pushed from host memory in chunks
+    of 2^18 samples, overlap-save segments of n with stride n/2, per
+    segment the spectrum, the PSD estimate, the templates' sigma^2 and the
+    merged search of the bank over the valid half.  Timed from the first
+    push to the last segment's triggers on the host."""
+    import torch
+    from paper_1006_4644_amd import synth
+    n, fs = wl.n, wl.fs
+    warm, K = 2, max(2, args.stream_segments)
+    total = n + (warm + K - 1) * n // 2
+    # coloured Gaussian noise of the workload's PSD as a time series
+    xt = synth.make_noise(total, fs, wl.f_low, synth.make_psd(total, fs), wl.noise_seed + 77)
+    x = (np.fft.irfft(xt, total) * fs).astype(np.float32)
+    st = ctx.stream(bank, n, fs, wl.f_low, wl.snr_threshold, wl.window, psd_half_width=16,
+                    cap=1 << 12)
+    first = n + (warm - 1) * n // 2
+    st.push(x[:first])
+    st.poll(wait=True)
+    torch.cuda.synchronize()
+    chunk = 1 << 18
+    t0 = time.perf_counter()
+    for a in range(first, total, chunk):
+        st.push(x[a:a + chunk])
+    trig, done, flags = st.poll(wait=True)
+    dt = time.perf_counter() - t0
+    st.close()
+    segs = done - warm
+    v = segs * len(bank) / dt
+    log(f"[bench] stream: {segs} segments in {dt * 1e3:.1f} ms, {v:.0f} templates/s")
+    return {"segments": segs, "n": n, "stride": n // 2, "ms_per_segment": round(dt * 1e3 / segs, 3),
+            "templates_per_s": round(v, 1), "vs_headline": round(v / headline, 3),
+            "realtime_factor": round(segs * (n // 2) / fs / dt, 1),
+            "merged_triggers": int(len(trig)), "overflow": int(flags & 1)}
 
 
 def td_timing(args, ctx, ci, seg, xt, psd_d, bank, n_t, cap, peaks, trig, count, wl,
@@ -463,6 +502,8 @@ def main():
         out["precision_paths"] = paths
     if not args.no_chisq:
         out["chisq_veto"] = chisq_timing(ctx, ci, seg, params, peaks, n_t, args.chisq_bands)
+    if not args.no_stream:
+        out["stream"] = stream_timing(args, ctx, bank, wl, value)
     if not args.no_td:
         out["two_polarization"] = td_timing(args, ctx, ci, seg, xt, psd_d, bank, n_t, cap,
                                             peaks, trig, count, wl, value)
