@@ -17,6 +17,8 @@
  *   ci_td_*             the paper's own template form: time-domain
  *                       generator, two polarizations, two C2R + madd2
  *   ci_stream_*         the per-chunk loop over a continuous stream
+ *   ci_bank_metric,     template placement at a set mismatch
+ *   ci_make_bank_lattice
  *
  * Conventions shared by every call
  * --------------------------------
@@ -351,6 +353,42 @@ int ci_stream_poll(ci_stream* s, int32_t wait, ci_trigger* host_out, int64_t cap
  * segment processed to device buffers (either may be NULL); *segment
  * receives its index (-1 before the first). */
 int ci_stream_last(ci_stream* s, void* d_xtilde, double* d_psd, int64_t* segment);
+
+/* --- template-bank placement ---------------------------------------------------
+ * The bank of "Matched filtering" placed so that every point of the mass
+ * range loses at most a set fraction of SNR to its nearest template (the
+ * paper's footnote: 2-5 % mismatch).  Coordinates: the chirp times at
+ * f_0 = f_low,
+ *   tau_0 = 5 / (256 pi f0 eta) (pi M f0)^{-5/3},  tau_3 = 1 / (8 f0 eta) (pi M f0)^{-2/3}.
+ * Metric (Owen, PRD 53, 6749 (1996)): with w(f) = f^{-7/3}/S on the
+ * template's band of the grid (n, fs), J the w-weighted mean, psi_a the
+ * derivative of the 2PN stationary phase along tau_a and C the
+ * J-covariance of (2 pi f, psi_0, psi_3),
+ *   gamma_ab = (1/2) (C_ab - C_at C_bt / C_tt),   1 - match ~ gamma_ab dtau^a dtau^b,
+ * the match maximised over phase and (continuous) time.  Host only.
+ *
+ * ci_bank_metric: gamma_out = {g_00, g_03, g_33} at (m1, m2); psd_host
+ * [n/2 + 1].  CI_EINVAL for bad masses or an empty band. */
+int ci_bank_metric(const double* psd_host, int64_t n, double fs, double f_low, double m1,
+                   double m2, double* gamma_out);
+
+typedef struct {
+  double m_min, m_max;   /* component masses, 0 < m_min < m_max */
+  double min_match;      /* e.g. 0.97 for 3 % mismatch, in (0.5, 1) */
+} ci_lattice_spec;
+
+/* Hexagonal lattice in (tau_0, tau_3) for the mass range
+ * m_min <= m2 <= m1 <= m_max.  The metric is sampled over the range and a
+ * constant metric G is taken that bounds every sample (the centre's,
+ * scaled by the largest eigenvalue ratio, times 1.05); lattice points with
+ * G-distance sqrt(1 - min_match) / side sqrt(3 (1 - min_match)) cover the
+ * range, those outside it but within the covering radius are moved to the
+ * nearest point of its boundary.  out_host[0 .. min(count, cap)) receives
+ * (m1, m2) with m1 >= m2; *count the number placed (CI_ETRUNC when above
+ * cap; cap = 0 and out_host = NULL query the count). */
+int ci_make_bank_lattice(const ci_lattice_spec* spec, const double* psd_host, int64_t n,
+                         double fs, double f_low, ci_template* out_host, int64_t cap,
+                         int64_t* count);
 
 /* --- chi-squared veto ---------------------------------------------------------
  * The signal-consistency test the Conclusions plan as the next stage of the

@@ -36,6 +36,7 @@ EXPORTED_SYMBOLS = (
     "ci_autotune", "ci_chisq", "ci_td_params", "ci_td_templates",
     "ci_td_matched_filter", "ci_td_find_triggers", "ci_stream_create",
     "ci_stream_destroy", "ci_stream_push", "ci_stream_poll", "ci_stream_last",
+    "ci_bank_metric", "ci_make_bank_lattice",
 )
 RUN_GRAPH = 1
 
@@ -111,6 +112,11 @@ class _Tune(ctypes.Structure):
 _vp, _i32, _i64, _f32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_float
 
 
+class _LatticeSpec(ctypes.Structure):
+    _fields_ = [("m_min", ctypes.c_double), ("m_max", ctypes.c_double),
+                ("min_match", ctypes.c_double)]
+
+
 class _StreamSpec(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("fs", ctypes.c_double), ("f_low", ctypes.c_double),
                 ("psd_half_width", ctypes.c_int32), ("snr_threshold", ctypes.c_float),
@@ -147,6 +153,11 @@ _SIGS = {
     "ci_stream_create": (ctypes.c_int, [_vp, ctypes.POINTER(_StreamSpec), _vp, _i64,
                                         ctypes.POINTER(_vp)]),
     "ci_stream_destroy": (ctypes.c_int, [_vp]),
+    "ci_bank_metric": (ctypes.c_int, [_vp, _i64, ctypes.c_double, ctypes.c_double,
+                                      ctypes.c_double, ctypes.c_double, _vp]),
+    "ci_make_bank_lattice": (ctypes.c_int, [ctypes.POINTER(_LatticeSpec), _vp, _i64,
+                                            ctypes.c_double, ctypes.c_double, _vp, _i64,
+                                            ctypes.POINTER(_i64)]),
     "ci_stream_push": (ctypes.c_int, [_vp, _vp, _i64]),
     "ci_stream_poll": (ctypes.c_int, [_vp, _i32, _vp, _i64, ctypes.POINTER(_i64),
                                       ctypes.POINTER(_i64), ctypes.POINTER(_i32)]),
@@ -213,6 +224,28 @@ class Library:
                                    out.ctypes.data if n else None)
         self.check(rc)
         return out
+
+    def bank_metric(self, psd, n: int, fs: float, f_low: float, m1: float, m2: float):
+        """Metric gamma (2 x 2) in (tau_0, tau_3) at (m1, m2) (host only)."""
+        psd = np.ascontiguousarray(np.asarray(psd, dtype=np.float64))
+        g = np.zeros(3)
+        self.check(self.dll.ci_bank_metric(psd.ctypes.data, n, fs, f_low, m1, m2, g.ctypes.data))
+        return np.array([[g[0], g[1]], [g[1], g[2]]])
+
+    def make_bank_lattice(self, m_min: float, m_max: float, min_match: float, psd, n: int,
+                          fs: float, f_low: float) -> np.ndarray:
+        """(count, 2) float64 bank of (m1, m2) covering the mass range at
+        min_match (host only)."""
+        psd = np.ascontiguousarray(np.asarray(psd, dtype=np.float64))
+        spec = _LatticeSpec(m_min, m_max, min_match)
+        cnt = _i64()
+        self.check(self.dll.ci_make_bank_lattice(ctypes.byref(spec), psd.ctypes.data, n, fs,
+                                                 f_low, None, 0, ctypes.byref(cnt)))
+        out = np.zeros((max(cnt.value, 1), 2))
+        self.check(self.dll.ci_make_bank_lattice(ctypes.byref(spec), psd.ctypes.data, n, fs,
+                                                 f_low, out.ctypes.data, cnt.value,
+                                                 ctypes.byref(cnt)))
+        return out[:cnt.value]
 
     def length_classes(self, bank, fs: float, f_low: float, classes) -> np.ndarray:
         """Class index per template: the shortest of `classes` (increasing

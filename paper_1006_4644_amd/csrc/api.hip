@@ -602,6 +602,14 @@ int td_batches(Ctx* ctx, const Seg* seg, const ci_tdparams* d_tdp, int64_t n, hi
 
 }  // namespace
 
+namespace ci {
+// Error of a call that has no context (ci_last_error(NULL) reads it).
+int report_error(int code, const char* msg) {
+  g_err = msg;
+  return code;
+}
+}  // namespace ci
+
 struct ci_ctx : Ctx {};
 struct ci_segment : Seg {};
 

@@ -1,0 +1,310 @@
+// bank.hip -- template-bank placement at a set mismatch (host only).
+//
+// The bank of the per-chunk loop is a set of (m1, m2) points placed so that
+// no point of the mass range loses more than a set fraction of SNR to its
+// nearest template.  Coordinates are the chirp times (tau_0, tau_3) at
+// f_0 = f_low; the metric is Owen's (PRD 53, 6749 (1996)): the match of two
+// nearby chirps, maximised over phase and time, is 1 - gamma_ab dtau^a dtau^b
+// with gamma half the covariance, under the weight f^{-7/3}/S on the band,
+// of the phase derivatives along tau_a after projecting out 2 pi f.
+#include <math.h>
+#include <stdint.h>
+#include <stdio.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "ci_impl.h"
+
+namespace {
+
+constexpr double kTSun = 4.925490947641267e-6;  // G M_sun / c^3, seconds
+constexpr double kPi = 3.14159265358979323846;
+
+struct Band {
+  int64_t kl, kh;
+};
+
+// Search band of (M, eta) on the grid: [ceil(f_low T), min(floor(f_isco T), n/2 - 1)].
+Band band_of(double M, int64_t n, double fs, double f_low) {
+  const double T = (double)n / fs;
+  const double f_isco = 1.0 / (6.0 * sqrt(6.0) * kPi * M);
+  Band b;
+  b.kl = (int64_t)ceil(f_low * T);
+  const double kh = floor(f_isco * T);
+  b.kh = kh < (double)(n / 2 - 1) ? (int64_t)kh : n / 2 - 1;
+  return b;
+}
+
+// 2PN stationary phase Psi(f) (t_c = phi_c = 0, radians) from (M, eta).
+double psi2pn(double f, double M, double eta) {
+  const double v = cbrt(kPi * M * f);
+  const double v2 = v * v;
+  const double pn = 1.0 + (3715.0 / 756.0 + 55.0 * eta / 9.0) * v2 - 16.0 * kPi * v2 * v +
+                    (15293365.0 / 508032.0 + 27145.0 * eta / 504.0 + 3085.0 * eta * eta / 72.0) *
+                        v2 * v2;
+  return -0.25 * kPi + 3.0 / (128.0 * eta * v2 * v2 * v) * pn;
+}
+
+void chirp_times(double m1, double m2, double f0, double* t0, double* t3) {
+  const double M = (m1 + m2) * kTSun;
+  const double eta = m1 * m2 / ((m1 + m2) * (m1 + m2));
+  const double x = kPi * M * f0;
+  *t0 = 5.0 / (256.0 * kPi * f0 * eta) * pow(x, -5.0 / 3.0);
+  *t3 = 1.0 / (8.0 * f0 * eta) * pow(x, -2.0 / 3.0);
+}
+
+// (M seconds, eta) from chirp times (eta may exceed 1/4 off the physical
+// region).
+void m_eta(double t0, double t3, double f0, double* M, double* eta) {
+  const double x = 5.0 * t3 / (32.0 * kPi * t0);  // pi M f0
+  *M = x / (kPi * f0);
+  *eta = 1.0 / (8.0 * f0 * t3) * pow(x, -2.0 / 3.0);
+}
+
+// gamma = {g00, g03, g33} at (m1, m2) on its own band; false for an empty band.
+bool metric_at(const double* psd, int64_t n, double fs, double f_low, double m1, double m2,
+               double* g) {
+  const double M = (m1 + m2) * kTSun;
+  const Band b = band_of(M, n, fs, f_low);
+  if (b.kh < b.kl) return false;
+  double t[2];
+  chirp_times(m1, m2, f_low, &t[0], &t[1]);
+  // phase derivatives along tau_0 and tau_3 by central differences
+  double Mp[2], ep[2], Mm[2], em[2], h[2];
+  for (int a = 0; a < 2; ++a) {
+    h[a] = 1e-6 * t[a];
+    double tp[2] = {t[0], t[1]}, tm[2] = {t[0], t[1]};
+    tp[a] += h[a];
+    tm[a] -= h[a];
+    m_eta(tp[0], tp[1], f_low, &Mp[a], &ep[a]);
+    m_eta(tm[0], tm[1], f_low, &Mm[a], &em[a]);
+  }
+  const double df = fs / (double)n;
+  double sw = 0.0, s[3] = {0, 0, 0}, ss[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+  for (int64_t k = b.kl; k <= b.kh; ++k) {
+    const double f = (double)k * df;
+    const double w = pow(f, -7.0 / 3.0) / psd[k];
+    double p[3];
+    p[0] = 2.0 * kPi * f;
+    for (int a = 0; a < 2; ++a)
+      p[1 + a] = (psi2pn(f, Mp[a], ep[a]) - psi2pn(f, Mm[a], em[a])) / (2.0 * h[a]);
+    sw += w;
+    for (int i = 0; i < 3; ++i) {
+      s[i] += w * p[i];
+      for (int j = 0; j < 3; ++j) ss[i][j] += w * p[i] * p[j];
+    }
+  }
+  double C[3][3];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) C[i][j] = ss[i][j] / sw - (s[i] / sw) * (s[j] / sw);
+  g[0] = 0.5 * (C[1][1] - C[1][0] * C[1][0] / C[0][0]);
+  g[1] = 0.5 * (C[1][2] - C[1][0] * C[2][0] / C[0][0]);
+  g[2] = 0.5 * (C[2][2] - C[2][0] * C[2][0] / C[0][0]);
+  return true;
+}
+
+struct P2 {
+  double x, y;
+};
+
+// Closest point to p on segment [a, b].
+P2 closest_on_segment(P2 p, P2 a, P2 b) {
+  const double dx = b.x - a.x, dy = b.y - a.y;
+  const double l2 = dx * dx + dy * dy;
+  double t = l2 > 0 ? ((p.x - a.x) * dx + (p.y - a.y) * dy) / l2 : 0.0;
+  t = t < 0 ? 0 : (t > 1 ? 1 : t);
+  return P2{a.x + t * dx, a.y + t * dy};
+}
+
+// The part of a polygon with a <= x <= b (Sutherland-Hodgman against the
+// two half-planes).
+std::vector<P2> clip_half(const std::vector<P2>& in, double c, bool keep_ge) {
+  std::vector<P2> out;
+  if (in.empty()) return out;
+  auto ok = [&](const P2& p) { return keep_ge ? p.x >= c : p.x <= c; };
+  for (size_t i = 0; i < in.size(); ++i) {
+    const P2 a = in[i], b = in[(i + 1) % in.size()];
+    const bool ia = ok(a), ib = ok(b);
+    if (ia) out.push_back(a);
+    if (ia != ib) {
+      const double t = (c - a.x) / (b.x - a.x);
+      out.push_back(P2{c, a.y + t * (b.y - a.y)});
+    }
+  }
+  return out;
+}
+
+std::vector<P2> clip_slab(const std::vector<P2>& poly, double a, double b) {
+  return clip_half(clip_half(poly, a, true), b, false);
+}
+
+bool inside(const std::vector<P2>& poly, P2 p) {
+  bool in = false;
+  for (size_t i = 0, j = poly.size() - 1; i < poly.size(); j = i++) {
+    const P2 a = poly[i], b = poly[j];
+    if ((a.y > p.y) != (b.y > p.y) && p.x < (b.x - a.x) * (p.y - a.y) / (b.y - a.y) + a.x)
+      in = !in;
+  }
+  return in;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ci_bank_metric(const double* psd_host, int64_t n, double fs, double f_low, double m1,
+                   double m2, double* gamma_out) {
+  if (!psd_host || !gamma_out) return ci::report_error(CI_EINVAL, "null psd or output");
+  if (n < 16 || (n & (n - 1)) != 0 || !(fs > 0) || !(f_low > 0))
+    return ci::report_error(CI_EINVAL, "bad grid");
+  if (!(m1 > 0) || !(m2 > 0) || !isfinite(m1) || !isfinite(m2))
+    return ci::report_error(CI_EINVAL, "masses must be positive");
+  if (!metric_at(psd_host, n, fs, f_low, std::max(m1, m2), std::min(m1, m2), gamma_out))
+    return ci::report_error(CI_EINVAL, "empty band");
+  return CI_OK;
+}
+
+int ci_make_bank_lattice(const ci_lattice_spec* spec, const double* psd_host, int64_t n,
+                         double fs, double f_low, ci_template* out_host, int64_t cap,
+                         int64_t* count) {
+  if (!spec || !psd_host || !count) return ci::report_error(CI_EINVAL, "null argument");
+  if (cap < 0 || (cap > 0 && !out_host)) return ci::report_error(CI_EINVAL, "bad output");
+  const double lo = spec->m_min, hi = spec->m_max, mm = 1.0 - spec->min_match;
+  if (!(lo > 0) || !(hi > lo) || !isfinite(hi)) return ci::report_error(CI_EINVAL, "bad mass range");
+  if (!(spec->min_match > 0.5) || !(spec->min_match < 1.0))
+    return ci::report_error(CI_EINVAL, "min_match outside (0.5, 1)");
+  if (n < 16 || (n & (n - 1)) != 0 || !(fs > 0) || !(f_low > 0))
+    return ci::report_error(CI_EINVAL, "bad grid");
+  {
+    const Band b = band_of(2.0 * hi * kTSun, n, fs, f_low);
+    if (b.kh < b.kl) return ci::report_error(CI_EINVAL, "the heaviest templates have no band");
+  }
+  // boundary of the range in (tau_0, tau_3): m2 = lo (m1 up), m1 = hi (m2
+  // up), m1 = m2 (down)
+  const int S = 512;
+  std::vector<P2> region;
+  for (int e = 0; e < 3; ++e)
+    for (int i = 0; i < S; ++i) {
+      const double r = pow(hi / lo, (double)i / S);
+      double m1, m2;
+      if (e == 0) { m1 = lo * r; m2 = lo; }
+      else if (e == 1) { m1 = hi; m2 = lo * r; }
+      else { m1 = hi / r; m2 = m1; }
+      P2 t;
+      chirp_times(m1, m2, f_low, &t.x, &t.y);
+      region.push_back(t);
+    }
+  // metric samples on a log grid of (m1 >= m2)
+  struct Sample {
+    P2 t;
+    double g[3];
+  };
+  std::vector<Sample> samples;
+  const int G = 24;
+  for (int i = 0; i < G; ++i)
+    for (int j = 0; j <= i; ++j) {
+      const double m1 = lo * pow(hi / lo, (double)i / (G - 1));
+      const double m2 = lo * pow(hi / lo, (double)j / (G - 1));
+      Sample sm;
+      if (!metric_at(psd_host, n, fs, f_low, m1, m2, sm.g)) continue;
+      chirp_times(m1, m2, f_low, &sm.t.x, &sm.t.y);
+      samples.push_back(sm);
+    }
+  if (samples.empty()) return ci::report_error(CI_EINVAL, "no template of the range has a band");
+  double t0min = 1e300, t0max = -1e300;
+  for (const P2& p : region) {
+    t0min = std::min(t0min, p.x);
+    t0max = std::max(t0max, p.x);
+  }
+  // strips of equal width in log tau_0, each with its own bounding metric
+  // and lattice, covering its part of the range
+  const int K = 12;
+  const double R = sqrt(mm), side = sqrt(3.0 * mm), dy = side * sqrt(3.0) / 2.0;
+  std::vector<ci_template> out;
+  double work = 0.0;
+  for (int st = 0; st < K; ++st) {
+    const double a = t0min * pow(t0max / t0min, (double)st / K);
+    const double b = st == K - 1 ? t0max * (1 + 1e-12) : t0min * pow(t0max / t0min, (double)(st + 1) / K);
+    std::vector<P2> poly = clip_slab(region, a, b);
+    if (poly.size() < 3) continue;
+    // metric samples of the strip (the nearest ones when it holds few)
+    std::vector<const Sample*> in;
+    for (const Sample& sm : samples)
+      if (sm.t.x >= a && sm.t.x < b) in.push_back(&sm);
+    if (in.size() < 4) {
+      std::vector<std::pair<double, const Sample*>> by;
+      const double mid = sqrt(a * b);
+      for (const Sample& sm : samples) by.push_back({fabs(log(sm.t.x / mid)), &sm});
+      std::sort(by.begin(), by.end(),
+                [](const std::pair<double, const Sample*>& u, const std::pair<double, const Sample*>& v) {
+                  return u.first < v.first;
+                });
+      in.clear();
+      for (size_t q = 0; q < by.size() && q < 6; ++q) in.push_back(by[q].second);
+    }
+    // reference: the sample nearest the strip's middle; gc = L L^T
+    const Sample* ref = in[0];
+    for (const Sample* sm : in)
+      if (fabs(log(sm->t.x / sqrt(a * b))) < fabs(log(ref->t.x / sqrt(a * b)))) ref = sm;
+    const double* gc = ref->g;
+    const double l00 = sqrt(gc[0]), l10 = gc[1] / l00, l11 = sqrt(gc[2] - l10 * l10);
+    double scale = 1.0;
+    for (const Sample* sm : in) {
+      const double* g = sm->g;
+      // largest eigenvalue of L^-1 g L^-T
+      const double qa = g[0] / (l00 * l00);
+      const double qb = (g[1] - l10 * g[0] / l00) / (l00 * l11);
+      const double qc = (g[2] - 2.0 * l10 * g[1] / l00 + l10 * l10 * g[0] / (l00 * l00)) /
+                        (l11 * l11);
+      scale = std::max(scale, 0.5 * (qa + qc) + sqrt(0.25 * (qa - qc) * (qa - qc) + qb * qb));
+    }
+    scale *= 1.05;
+    // u = sqrt(scale) L^T tau: the bounding metric is the identity in u
+    const double sq = sqrt(scale);
+    std::vector<P2> pu;
+    for (const P2& t : poly) pu.push_back(P2{sq * (l00 * t.x + l10 * t.y), sq * l11 * t.y});
+    double xmin = 1e300, xmax = -1e300, ymin = 1e300, ymax = -1e300;
+    for (const P2& p : pu) {
+      xmin = std::min(xmin, p.x); xmax = std::max(xmax, p.x);
+      ymin = std::min(ymin, p.y); ymax = std::max(ymax, p.y);
+    }
+    xmin -= R; xmax += R; ymin -= R; ymax += R;
+    work += ((ymax - ymin) / dy + 1) * ((xmax - xmin) / side + 1);
+    if (work > 5e7) return ci::report_error(CI_EINVAL, "lattice too large (over 5e7 points)");
+    for (int64_t r = 0; ymin + r * dy <= ymax; ++r) {
+      const double y = ymin + r * dy, x0 = xmin + ((r & 1) ? 0.5 * side : 0.0);
+      for (int64_t c = 0; x0 + c * side <= xmax; ++c) {
+        P2 p{x0 + c * side, y};
+        if (!inside(pu, p)) {
+          // within the covering radius of the strip: move onto its boundary
+          P2 best{0, 0};
+          double bd = 1e300;
+          for (size_t q = 0; q < pu.size(); ++q) {
+            const P2 e = closest_on_segment(p, pu[q], pu[(q + 1) % pu.size()]);
+            const double d = (e.x - p.x) * (e.x - p.x) + (e.y - p.y) * (e.y - p.y);
+            if (d < bd) { bd = d; best = e; }
+          }
+          if (bd > R * R) continue;
+          p = best;
+        }
+        const double t3 = p.y / (sq * l11), t0 = (p.x / sq - l10 * t3) / l00;
+        double M, eta;
+        m_eta(t0, t3, f_low, &M, &eta);
+        if (!(eta > 0)) continue;
+        eta = std::min(eta, 0.25);
+        const double mt = M / kTSun, d = sqrt(std::max(0.0, 1.0 - 4.0 * eta));
+        ci_template tm;
+        tm.m1 = std::min(std::max(0.5 * mt * (1.0 + d), lo), hi);
+        tm.m2 = std::min(std::max(0.5 * mt * (1.0 - d), lo), tm.m1);
+        out.push_back(tm);
+      }
+    }
+  }
+  *count = (int64_t)out.size();
+  const int64_t k = std::min<int64_t>(cap, (int64_t)out.size());
+  for (int64_t i = 0; i < k; ++i) out_host[i] = out[(size_t)i];
+  return (int64_t)out.size() > cap && cap > 0 ? CI_ETRUNC : CI_OK;
+}
+
+}  // extern "C"

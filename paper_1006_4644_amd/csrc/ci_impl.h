@@ -198,5 +198,7 @@ hipError_t launch_fin(const BatchArgs& a, hipStream_t st);
 // hipSuccess when every kernel of a search with this plan and precision
 // fits the per-workgroup LDS limit, hipErrorInvalidConfiguration when not.
 hipError_t plan_fits(const Plan& p, int precision);
+// Error of a call that has no context (read by ci_last_error(NULL)).
+int report_error(int code, const char* msg);
 
 }  // namespace ci
