@@ -74,6 +74,8 @@ def parse():
     p.add_argument("--no-stream", action="store_true",
                    help="skip the continuous-stream leg (overlap-save segments from host samples)")
     p.add_argument("--stream-segments", type=int, default=16)
+    p.add_argument("--no-bank", action="store_true",
+                   help="skip the template-bank placement leg")
     p.add_argument("--precision", default="fp32", choices=sorted(PRECISIONS),
                    help="arithmetic of the headline run")
     p.add_argument("--no-split", action="store_true",
@@ -199,6 +201,55 @@ def chisq_timing(ctx, ci, seg, params, peaks, n_t, bands, reps=10):
             "bins_per_s": round(bins / (ms / 1e3), 1),
             "median_chi2_per_dof": round(float(np.median(fin)) / (2 * bands - 2), 3)
             if len(fin) else None}
+
+
+def bank_timing(ctx, ci, lib, seg, xt, psd, psd_d, wl, cap, headline, probes=8):
+    """A bank placed for the workload's mass range at 3 % mismatch (host),
+    its merged search timed on the workload's data, and its coverage probed
+    on the GPU: noise-free unit-SNR chirps of random masses in the range,
+    whose largest peak over the bank is their best match."""
+    import torch
+    n, fs, fl = wl.n, wl.fs, wl.f_low
+    t0 = time.perf_counter()
+    bank = lib.make_bank_lattice(wl.m_min, wl.m_max, 0.97, psd, n, fs, fl)
+    host_s = time.perf_counter() - t0
+    ctx.segment_update(seg, xt, psd_d)
+    params = ctx.gen_templates(seg, bank)
+    peaks = torch.empty((len(bank), 4), dtype=torch.int64, device=xt.device)
+    trig = torch.empty((cap, 4), dtype=torch.int64, device=xt.device)
+    count = torch.zeros(1, dtype=torch.int64, device=xt.device)
+    ctx.find_triggers(seg, params, wl.snr_threshold, wl.window, cap=cap, merge=True,
+                      peaks=peaks, trig=trig, count=count)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    ctx.find_triggers(seg, params, wl.snr_threshold, wl.window, cap=cap, merge=True,
+                      peaks=peaks, trig=trig, count=count)
+    e1.record()
+    torch.cuda.synchronize()
+    search_ms = e0.elapsed_time(e1)
+    rng = np.random.default_rng(wl.bank_seed + 5)
+    best = []
+    for _ in range(probes):
+        lm = np.exp(rng.uniform(math.log(wl.m_min), math.log(wl.m_max), 2))
+        m1, m2 = float(lm.max()), float(lm.min())
+        p1, ht = ctx.gen_templates(seg, [[m1, m2]], htilde=True)
+        torch.cuda.synchronize()
+        s2 = float(ci.params_to_numpy(p1)["sigma2"][0])
+        x = (ht[0] / math.sqrt(s2)).contiguous()
+        ctx.segment_update(seg, x, psd_d)
+        prm = ctx.gen_templates(seg, bank)
+        ctx.find_triggers(seg, prm, 0.5, n, cap=16, peaks=peaks)
+        torch.cuda.synchronize()
+        best.append(math.sqrt(float(ci.triggers_to_numpy(peaks)["rho2"].max())))
+    ctx.segment_update(seg, xt, psd_d)
+    log(f"[bench] bank: {len(bank)} templates placed in {host_s:.2f} s, search "
+        f"{search_ms:.1f} ms, best match over {probes} probes >= {min(best):.4f}")
+    return {"templates": int(len(bank)), "min_match": 0.97, "place_s": round(host_s, 3),
+            "mass_range": [wl.m_min, wl.m_max], "search_ms": round(search_ms, 3),
+            "templates_per_s": round(len(bank) / (search_ms / 1e3), 1),
+            "probe_best_match_min": round(min(best), 5),
+            "probe_best_match_median": round(float(np.median(best)), 5), "probes": probes}
 
 
 def stream_timing(args, ctx, bank, wl, headline):
@@ -504,6 +555,8 @@ def main():
         out["chisq_veto"] = chisq_timing(ctx, ci, seg, params, peaks, n_t, args.chisq_bands)
     if not args.no_stream:
         out["stream"] = stream_timing(args, ctx, bank, wl, value)
+    if not args.no_bank:
+        out["bank_placement"] = bank_timing(ctx, ci, lib, seg, xt, psd, psd_d, wl, cap, value)
     if not args.no_td:
         out["two_polarization"] = td_timing(args, ctx, ci, seg, xt, psd_d, bank, n_t, cap,
                                             peaks, trig, count, wl, value)
