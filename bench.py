@@ -83,7 +83,7 @@ def parse():
     p.add_argument("--no-autotune", action="store_true",
                    help="keep the default launch configuration")
     p.add_argument("--tune", default="",
-                   help="explicit launch configuration C,J,P2,BATCH (skips the autotuner)")
+                   help="explicit launch configuration C,J,P2,BATCH[,STREAMS] (skips the autotuner)")
     return p.parse_args()
 
 
@@ -96,15 +96,16 @@ def configure(ctx, ci, args, tune_calls):
             continue
         for seg, params, n, thr, window, l2 in tune_calls:
             if args.tune:
-                c, j, p2, b = (int(v) for v in args.tune.split(","))
-                ctx.set_tune(l2, prec, c, j, p2, b)
+                v = [int(x) for x in args.tune.split(",")]
+                ctx.set_tune(l2, prec, *v[:4], streams=v[4] if len(v) > 4 else 2)
                 cfg = ctx.get_tune(l2, prec)
             elif args.no_autotune:
                 cfg = ctx.get_tune(l2, prec)
             else:
                 cfg = ctx.autotune(seg, params, thr, window, n=n, precision=prec)
             out[f"{prec_name}/2^{l2}"] = {k: cfg[k] for k in
-                                          ("tile_c", "tile_j", "p2_per_cu", "batch", "tuned")}
+                                          ("tile_c", "tile_j", "p2_per_cu", "batch", "streams",
+                                           "tuned")}
             log(f"[bench] launch configuration {prec_name} 2^{l2}: {out[f'{prec_name}/2^{l2}']}")
     return out
 

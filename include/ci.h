@@ -480,14 +480,19 @@ typedef struct {
   int32_t candidates;   /* out (ci_autotune): configurations timed */
   int32_t rejected;     /* out (ci_autotune): configurations excluded
                            because their output differed */
+  int32_t streams;      /* compute streams the batches' passes alternate
+                           over: 2 (one batch's second pass overlaps the
+                           next batch's first) or 1 (in order); 0 means 2 */
+  int32_t reserved;
 } ci_tune;
 
 int ci_get_tune(ci_ctx* ctx, int32_t log2n, int32_t precision, ci_tune* out);
-/* Sets tile_c, tile_j, p2_per_cu and batch for (log2n, precision). */
+/* Sets tile_c, tile_j, p2_per_cu, batch and streams for (log2n, precision). */
 int ci_set_tune(ci_ctx* ctx, const ci_tune* cfg);
 
 /* Autotuner: times ci_find_triggers (no merge) on the given templates under
- * a coordinate search over tiles, second-pass residency and batch size,
+ * a coordinate search over tiles, second-pass residency, batch size and
+ * the number of compute streams,
  * starting from the default configuration; a candidate whose peaks,
  * trigger count or trigger list differ in any bit from the default's is
  * excluded.  Stores the fastest as the context's configuration for the

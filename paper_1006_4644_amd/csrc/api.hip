@@ -482,7 +482,7 @@ int enqueue_jobs(Ctx* ctx, const std::vector<Job>& jobs, size_t slot_elems, int3
     a.precision = precision;
     a.p2_per_cu = jb.cfg.p2_per_cu;
     for (int64_t t0 = 0; t0 < jb.n; ++b, t0 += jb.B) {
-      hipStream_t sb = ctx->ws[b & 1];
+      hipStream_t sb = ctx->ws[jb.cfg.streams == 1 ? 0 : (b & 1)];
       const int slot = (int)(b % kSlots);
       a.t0 = t0;
       a.nb = (int)((jb.n - t0) < jb.B ? (jb.n - t0) : jb.B);
@@ -1513,6 +1513,7 @@ int ci_get_tune(ci_ctx* ctx, int32_t log2n, int32_t precision, ci_tune* out) {
   out->p2_per_cu = t.p2_per_cu;
   out->tuned = t.tuned ? 1 : 0;
   out->batch = t.batch;
+  out->streams = t.streams;
   return CI_OK;
 }
 
@@ -1529,6 +1530,8 @@ int ci_set_tune(ci_ctx* ctx, const ci_tune* cfg) {
     return fail(ctx, CI_EINVAL, "p2_per_cu %d outside 0..8", cfg->p2_per_cu);
   if (cfg->batch < 0 || cfg->batch > 4096)
     return fail(ctx, CI_EINVAL, "batch %lld outside 0..4096", (long long)cfg->batch);
+  if (cfg->streams < 0 || cfg->streams > 2)
+    return fail(ctx, CI_EINVAL, "streams %d outside 0..2", cfg->streams);
   {
     DeviceGuard dg(ctx->device);
     if (!dg.ok) return fail(ctx, CI_EHIP, "cannot select device %d", ctx->device);
@@ -1539,6 +1542,7 @@ int ci_set_tune(ci_ctx* ctx, const ci_tune* cfg) {
   t.c = cfg->tile_c;
   t.j = cfg->tile_j;
   t.p2_per_cu = cfg->p2_per_cu;
+  t.streams = cfg->streams == 0 ? 2 : cfg->streams;
   t.batch = cfg->batch;
   t.tuned = false;
   return CI_OK;
@@ -1673,6 +1677,26 @@ int ci_autotune(ci_ctx* ctx, const ci_segment* seg, const ci_tparams* d_params, 
     if (rc == CI_OK && !same) ++rejected;
     else if (rc == CI_OK && ms < best_ms) { best = c; best_ms = ms; }
   }
+  // the in-order schedule (one compute stream) at each batch size: chosen
+  // when within 2 % of the overlapped one, whose launches share the device
+  // with the neighbouring batch's other pass
+  {
+    Tune in_order = best;
+    float io_ms = 0.f;
+    const int64_t bs1[5] = {best.batch, b0, b0 * 2, b0 * 4, b0 / 2};
+    for (int i = 0; i < 5 && rc == CI_OK; ++i) {
+      if (bs1[i] < 0 || bs1[i] > 4096 || (bs1[i] > 0 && bs1[i] >= 2 * n)) continue;
+      Tune c = best;
+      c.streams = 1;
+      c.batch = bs1[i];
+      float ms = 0.f;
+      bool same = false;
+      rc = trial(c, &ms, &same);
+      if (rc == CI_OK && !same) ++rejected;
+      else if (rc == CI_OK && (io_ms == 0.f || ms < io_ms)) { in_order = c; io_ms = ms; }
+    }
+    if (rc == CI_OK && io_ms > 0.f && io_ms <= best_ms * 1.02f) { best = in_order; best_ms = io_ms; }
+  }
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);
   (void)hipStreamSynchronize(st);
@@ -1696,6 +1720,7 @@ int ci_autotune(ci_ctx* ctx, const ci_segment* seg, const ci_tparams* d_params, 
     out->ms = best_ms;
     out->candidates = cands;
     out->rejected = rejected;
+    out->streams = best.streams;
   }
   return CI_OK;
 }

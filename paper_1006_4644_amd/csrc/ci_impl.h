@@ -56,6 +56,7 @@ struct Tune {
   int j = 4;             // j2 columns per pass-2 workgroup (4 or 8)
   int p2_per_cu = 2;     // resident pass-2 workgroups per CU (0: as many as fit)
   int64_t batch = 0;     // templates per batch (0: by intermediate size)
+  int streams = 2;       // compute streams the batches alternate over (1 or 2)
   bool tuned = false;    // chosen by the autotuner
 };
 

@@ -287,8 +287,9 @@ def test_full_size_fp32_workload_sampled(ctx):
 @pytest.mark.parametrize("tc,tj", [(4, 4), (4, 8), (8, 4), (8, 8)])
 @pytest.mark.parametrize("log2n", [16, 20, 21])
 def test_tile_shapes(ctx, tc, tj, log2n):
-    """Every pass-1 / pass-2 tile shape gives the oracle's series and peaks,
-    bit-identical to the default shape's."""
+    """Every pass-1 / pass-2 tile shape, with the batches in order on one
+    stream or alternating over two, gives the oracle's series and peaks,
+    bit-identical to the default configuration's."""
     n, fs, fl = 1 << log2n, 4096.0, 20.0
     bank = synth.draw_masses(3, 1.0, 20.0, "loguniform", 31 * tc + tj + log2n)
     inj = synth.InjectionSpec(float(bank[1, 0]), float(bank[1, 1]), 9.0,
@@ -298,7 +299,8 @@ def test_tile_shapes(ctx, tc, tj, log2n):
     params = ctx.gen_templates(seg, bank)
     z0 = ctx.matched_filter(seg, params)
     p0, t0, c0 = ctx.find_triggers(seg, params, 5.5, 4096, cap=256)
-    ctx.set_tune(log2n, ci.FP32, tc, tj, 1 + (tc + tj) % 3, 2)
+    ctx.set_tune(log2n, ci.FP32, tc, tj, 1 + (tc + tj) % 3, 2,
+                 streams=1 + (tc // 4 + tj // 4 + log2n) % 2)
     try:
         z = ctx.matched_filter(seg, params)
         peaks, trig, cnt = ctx.find_triggers(seg, params, 5.5, 4096, cap=256)
