@@ -164,3 +164,23 @@ def test_stream_cap_overflow_and_arguments(ctx):
         assert ei.value.code == ci.EINVAL
     with pytest.raises(ci.CiError):
         ctx.stream([[3.0, 2.0]], 3 << 15, fs, fl, 6.0, 4096)
+
+
+@pytest.mark.parametrize("log2n", [17, 18, 19, 21])
+def test_stream_spectrum_every_length(ctx, log2n):
+    """The segment transform and PSD estimate at the other segment lengths
+    (2^16 and 2^20 run above and in the benchmark's tests)."""
+    n, fs, fl, h = 1 << log2n, 4096.0, 20.0, 8
+    x32, x = _stream_data(n, 1, fs, fl, None, 40 + log2n)
+    st = ctx.stream([[3.0, 2.0]], n, fs, fl, 6.0, 4096, psd_half_width=h)
+    st.push(x32)
+    xt, psd, seg = st.last()
+    assert seg == 0
+    xo = SO.segment_spectrum(x, fs)
+    po = SO.psd_estimate(x, fs, fl, h)
+    band = po > 0
+    ex = np.max(np.abs(xt - xo)) / np.max(np.abs(xo))
+    ep = np.max(np.abs(psd[band] / po[band] - 1))
+    print(f"2^{log2n}: spectrum error {ex:.1e}, PSD error {ep:.1e}")
+    assert ex < 2e-6 and ep < 1e-5
+    st.close()

@@ -209,3 +209,28 @@ def test_td_full_size_sampled(ctx):
         print(f"injection snr {inj.snr} at {inj.j0}: td template peak "
               f"{int(P[inj.tmpl]['index'])} rho {math.sqrt(float(P[inj.tmpl]['rho2'])):.2f}")
     seg.close()
+
+
+@pytest.mark.parametrize("log2n", [16, 17, 18, 19, 20, 21])
+def test_td_series_every_length(ctx, log2n):
+    """Every transform length: the two-polarization series of an injected
+    template (and a second, mismatched one) against the oracle."""
+    n, fs, fl = 1 << log2n, 4096.0, 20.0
+    bank = np.array([[6.0, 4.0], [2.2, 1.9]]) if log2n < 21 else np.array([[6.0, 4.0]])
+    j0 = n // 3 + 11
+    x64, psd, x128 = _td_case(n, fs, fl, bank, (6.0, 4.0, 12.0, j0), 300 + log2n)
+    seg = ctx.segment(_dev(x64), _dev(psd), n, fs, fl)
+    tdp = ctx.td_params(seg, bank)
+    z = ctx.td_matched_filter(seg, tdp)
+    peaks, _, _ = ctx.td_find_triggers(seg, tdp, 6.0, 4096, cap=64)
+    _sync()
+    zg = z.cpu().numpy()
+    P = ci.triggers_to_numpy(peaks)
+    for i, (m1, m2) in enumerate(bank):
+        zo, _, _ = T.td_series(x128, psd, n, fs, fl, m1, m2)
+        e = C.series_error(zg[i], zo)
+        print(f"2^{log2n} template {i}: series error {e:.2e}")
+        assert e <= C.TOL_FP32
+        C.check_peak(P[i], zo)
+    assert abs(int(P[0]["index"]) - j0) <= 2
+    seg.close()
