@@ -1683,8 +1683,8 @@ int ci_autotune(ci_ctx* ctx, const ci_segment* seg, const ci_tparams* d_params, 
   {
     Tune in_order = best;
     float io_ms = 0.f;
-    const int64_t bs1[5] = {best.batch, b0, b0 * 2, b0 * 4, b0 / 2};
-    for (int i = 0; i < 5 && rc == CI_OK; ++i) {
+    const int64_t bs1[6] = {best.batch, b0, b0 * 2, b0 * 4, b0 * 8, b0 / 2};
+    for (int i = 0; i < 6 && rc == CI_OK; ++i) {
       if (bs1[i] < 0 || bs1[i] > 4096 || (bs1[i] > 0 && bs1[i] >= 2 * n)) continue;
       Tune c = best;
       c.streams = 1;
