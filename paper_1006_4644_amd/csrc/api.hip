@@ -652,6 +652,10 @@ struct ci_stream {
   int32_t flags = 0;
 };
 
+namespace {
+void release_stream(ci_stream* s);
+}
+
 extern "C" {
 
 const char* ci_version(void) { return "ci 0.1 (gfx950)"; }
@@ -677,6 +681,8 @@ int ci_ctx_create(int device, ci_ctx** out) {
 int ci_ctx_destroy(ci_ctx* ctx) {
   if (!ctx) return CI_OK;
   DeviceGuard g(ctx->device);
+  // streams still alive: release their device work and detach them
+  while (!ctx->streams.empty()) release_stream(ctx->streams.back());
   if (ctx->pin_ev) {
     (void)hipEventSynchronize(ctx->pin_ev);
     (void)hipEventDestroy(ctx->pin_ev);
@@ -1110,8 +1116,10 @@ int ci_td_find_triggers(ci_ctx* ctx, const ci_segment* seg, const ci_tdparams* d
 
 namespace {
 
-void free_stream(ci_stream* s) {
-  if (!s) return;
+// Release a stream's device resources; the struct itself stays (a detached
+// stream only accepts ci_stream_destroy).
+void release_stream(ci_stream* s) {
+  if (!s || !s->ctx) return;
   if (s->ks) (void)hipStreamSynchronize(s->ks);
   if (s->cs) (void)hipStreamSynchronize(s->cs);
   if (s->seg) {
@@ -1141,6 +1149,19 @@ void free_stream(ci_stream* s) {
   if (s->gather_ev) (void)hipEventDestroy(s->gather_ev);
   if (s->cs) (void)hipStreamDestroy(s->cs);
   if (s->ks) (void)hipStreamDestroy(s->ks);
+  auto& v = s->ctx->streams;
+  for (size_t i = 0; i < v.size(); ++i)
+    if (v[i] == s) {
+      v[i] = v.back();
+      v.pop_back();
+      break;
+    }
+  s->ctx = nullptr;
+}
+
+void free_stream(ci_stream* s) {
+  if (!s) return;
+  release_stream(s);
   delete s;
 }
 
@@ -1312,19 +1333,25 @@ int ci_stream_create(ci_ctx* ctx, const ci_stream_spec* spec, const ci_template*
     free_stream(s);
     return hipfail(ctx, e, "stream parameter upload");
   }
+  ctx->streams.push_back(s);
   *out = s;
   return CI_OK;
 }
 
 int ci_stream_destroy(ci_stream* s) {
   if (!s) return CI_OK;
-  DeviceGuard g(s->ctx ? s->ctx->device : 0);
-  free_stream(s);
+  if (s->ctx) {
+    DeviceGuard g(s->ctx->device);
+    free_stream(s);
+  } else {
+    delete s;  // detached: its context released it already
+  }
   return CI_OK;
 }
 
 int ci_stream_push(ci_stream* s, const float* host_x, int64_t count) {
   if (!s) return fail(nullptr, CI_EINVAL, "null stream");
+  if (!s->ctx) return fail(nullptr, CI_EINVAL, "the stream's context was destroyed");
   Ctx* ctx = s->ctx;
   if (count < 0) return fail(ctx, CI_EINVAL, "negative count");
   if (count > 0 && !host_x) return fail(ctx, CI_EINVAL, "null samples");
@@ -1370,6 +1397,7 @@ int ci_stream_push(ci_stream* s, const float* host_x, int64_t count) {
 int ci_stream_poll(ci_stream* s, int32_t wait, ci_trigger* host_out, int64_t cap, int64_t* n_out,
                    int64_t* segments_done, int32_t* flags) {
   if (!s) return fail(nullptr, CI_EINVAL, "null stream");
+  if (!s->ctx) return fail(nullptr, CI_EINVAL, "the stream's context was destroyed");
   Ctx* ctx = s->ctx;
   if (cap < 0 || !n_out || (cap > 0 && !host_out))
     return fail(ctx, CI_EINVAL, "bad output arguments");
@@ -1399,6 +1427,7 @@ int ci_stream_poll(ci_stream* s, int32_t wait, ci_trigger* host_out, int64_t cap
 
 int ci_stream_last(ci_stream* s, void* d_xtilde, double* d_psd, int64_t* segment) {
   if (!s) return fail(nullptr, CI_EINVAL, "null stream");
+  if (!s->ctx) return fail(nullptr, CI_EINVAL, "the stream's context was destroyed");
   Ctx* ctx = s->ctx;
   DeviceGuard dg(ctx->device);
   if (!dg.ok) return fail(ctx, CI_EHIP, "cannot select device %d", ctx->device);

@@ -102,6 +102,9 @@ struct Ctx {
   Tune tune[32][3];
   // live segments created on this context (detached when it is destroyed)
   std::vector<Seg*> segs;
+  // live streams created on this context (released and detached when it
+  // is destroyed)
+  std::vector<struct ci_stream*> streams;
   // instrumentation
   bool timing = false;
   std::vector<TimedLaunch> launches;

@@ -184,3 +184,26 @@ def test_stream_spectrum_every_length(ctx, log2n):
     print(f"2^{log2n}: spectrum error {ex:.1e}, PSD error {ep:.1e}")
     assert ex < 2e-6 and ep < 1e-5
     st.close()
+
+
+def test_stream_outlives_its_context(gpu_lib):
+    """A stream still alive when its context is destroyed is released and
+    detached: other calls reject it, destroying it afterwards is safe."""
+    n, fs, fl = 1 << 16, 4096.0, 20.0
+    x32, _ = _stream_data(n, 1, fs, fl, None, 9)
+    c = gpu_lib.context(0)
+    st = c.stream([[3.0, 2.0]], n, fs, fl, 6.0, 4096)
+    st.push(x32[:1000])
+    c.close()
+    with pytest.raises(ci.CiError) as ei:
+        st.push(x32[1000:2000])
+    assert ei.value.code == ci.EINVAL
+    st.close()
+    # the library keeps working
+    c2 = gpu_lib.context(0)
+    st2 = c2.stream([[3.0, 2.0]], n, fs, fl, 6.0, 4096)
+    st2.push(x32)
+    _, done, _ = st2.poll(wait=True)
+    assert done == 1
+    st2.close()
+    c2.close()
