@@ -314,7 +314,9 @@ int ci_td_find_triggers(ci_ctx* ctx, const ci_segment* seg, const ci_tdparams* d
  * estimate, the Hann-windowed periodogram P_k = 2 |X_k|^2 / (T 3/8),
  * X_k = dt sum_j sin^2(pi j/n) x_j e^{-2 pi i jk/n}, averaged over the
  * in-band bins [k - h, k + h] intersected with [k_low, n/2 - 1] (S_k = 0
- * outside that band); the segment update, the templates' sigma^2 and the
+ * outside that band), optionally averaged with the estimates of the
+ * previous segments (psd_segments); the segment update, the templates'
+ * sigma^2 and the
  * merged search of ci_find_triggers (FP32, the context's launch
  * configuration).  Trigger indices and windows are global.
  * Host samples are staged through pinned memory and copied on a stream of
@@ -328,6 +330,10 @@ typedef struct {
   float snr_threshold;    /* lambda (rho^2 > lambda^2 triggers) */
   int64_t window;         /* W: 1 .. n/2, dividing n/2 */
   int64_t cap;            /* merged triggers kept per segment, >= 1 */
+  int32_t psd_segments;   /* K: the PSD used for a segment is the mean of
+                             the estimates of it and the K - 1 before it
+                             (fewer at the start); 0 or 1: its own; <= 16 */
+  int32_t reserved;
 } ci_stream_spec;
 
 /* bank_host[n_templates] is copied.  CI_EINVAL for a bad spec or bank. */

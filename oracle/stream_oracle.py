@@ -27,7 +27,8 @@ is also what the GPU path implements):
   P_k = 2 |X_k|^2 / (T W2) with W2 = (1/n) sum w_j^2 = 3/8 (so E P_k = S_k
   for a slowly varying one-sided PSD S), smoothed over the in-band bins
   [k - h, k + h] intersected with [k_low, n/2 - 1] (Daniell's average);
-  S_k = 0 outside [k_low, n/2 - 1].
+  S_k = 0 outside [k_low, n/2 - 1]; optionally the mean of that estimate
+  over the segment and the K - 1 before it (Welch's average over time).
 * Search of each segment: the frequency-domain path of mf_oracle with that
   spectrum and PSD over [n/4, 3n/4), merged across templates per window;
   windows of W samples align globally because W divides n/2.
@@ -74,16 +75,19 @@ def psd_estimate(xs, fs: float, f_low: float, h: int):
 
 
 def stream_search(x, n: int, fs: float, f_low: float, bank, thr: float,
-                  window: int, h: int):
-    """Search every complete segment of the stream `x` (float64).  Returns
-    (per-segment list of {w_global: (tmpl, j_global, rho2)}, per-segment
-    PSD estimates, per-segment spectra)."""
+                  window: int, h: int, avg: int = 1):
+    """Search every complete segment of the stream `x` (float64), with the
+    PSD of segment s the mean of the estimates of segments
+    max(0, s - avg + 1) .. s.  Returns (per-segment list of
+    {w_global: (tmpl, j_global, rho2)}, per-segment PSDs used, per-segment
+    spectra)."""
     stride = n // 2
-    out, psds, specs = [], [], []
+    out, psds, specs, own = [], [], [], []
     for s in range(segment_count(len(x), n)):
         xs = x[s * stride:s * stride + n]
         xt = segment_spectrum(xs, fs)
-        S = psd_estimate(xs, fs, f_low, h)
+        own.append(psd_estimate(xs, fs, f_low, h))
+        S = np.mean(own[max(0, s - avg + 1):s + 1], axis=0)
         res = O.search(xt, S, n, fs, f_low, bank, thr, window, j_lo=n // 4,
                        j_hi=3 * n // 4)
         shift_w = (s * stride) // window

@@ -121,7 +121,8 @@ class _LatticeSpec(ctypes.Structure):
 class _StreamSpec(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("fs", ctypes.c_double), ("f_low", ctypes.c_double),
                 ("psd_half_width", ctypes.c_int32), ("snr_threshold", ctypes.c_float),
-                ("window", ctypes.c_int64), ("cap", ctypes.c_int64)]
+                ("window", ctypes.c_int64), ("cap", ctypes.c_int64),
+                ("psd_segments", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 _SIGS = {
     "ci_version": (ctypes.c_char_p, []),
@@ -480,9 +481,9 @@ class Context:
         return out[:n_trig]
 
     def stream(self, bank, n: int, fs: float, f_low: float, thr: float, window: int,
-               psd_half_width: int = 16, cap: int = 1 << 12) -> Stream:
+               psd_half_width: int = 16, cap: int = 1 << 12, psd_segments: int = 1) -> Stream:
         bank = np.ascontiguousarray(np.asarray(bank, dtype=np.float64).reshape(-1, 2))
-        spec = _StreamSpec(n, fs, f_low, psd_half_width, thr, window, cap)
+        spec = _StreamSpec(n, fs, f_low, psd_half_width, thr, window, cap, psd_segments)
         h = _vp()
         self._chk(self.lib.dll.ci_stream_create(self.handle, ctypes.byref(spec),
                                                 bank.ctypes.data, bank.shape[0],

@@ -631,6 +631,8 @@ struct ci_stream {
   float2* xt = nullptr;           // [n/2 + 1] segment spectrum
   double* pg = nullptr;           // [n/2 + 1] periodogram
   double* psd = nullptr;          // [n/2 + 1] PSD estimate
+  double* pring = nullptr;        // [K][n/2 + 1] earlier estimates (K > 1)
+  int K = 1;
   static constexpr int kRes = 2;  // result slots in flight
   ci_trigger* d_peaks[kRes] = {};
   ci_trigger* d_trig[kRes] = {};
@@ -1132,7 +1134,7 @@ void release_stream(ci_stream* s) {
       }
     free_seg(s->seg);
   }
-  void* dev[] = {s->d_params, s->ring, s->uv, s->y, s->xt, s->pg, s->psd};
+  void* dev[] = {s->d_params, s->ring, s->uv, s->y, s->xt, s->pg, s->psd, s->pring};
   for (void* p : dev)
     if (p) (void)hipFree(p);
   for (int i = 0; i < ci_stream::kRes; ++i) {
@@ -1213,6 +1215,11 @@ int enqueue_segment(ci_stream* s) {
   e = hipEventRecord(s->gather_ev, s->ks);
   if (e != hipSuccess) return hipfail(ctx, e, "stream event");
   s->gather_armed = true;
+  if (s->K > 1) {
+    const int cnt = seg_i + 1 < s->K ? (int)(seg_i + 1) : s->K;
+    e = launch_stream_avg(s->pring, s->K, (int)(seg_i % s->K), cnt, n / 2 + 1, s->psd, s->ks);
+    if (e != hipSuccess) return hipfail(ctx, e, "stream PSD average launch");
+  }
   e = launch_segment(s->seg, s->xt, s->psd, s->ks);
   if (e == hipSuccess) e = launch_params(s->seg, s->d_params, s->nt, nullptr, s->ks);
   if (e != hipSuccess) return hipfail(ctx, e, "stream segment launch");
@@ -1258,6 +1265,8 @@ int ci_stream_create(ci_ctx* ctx, const ci_stream_spec* spec, const ci_template*
   if (spec->window < 1 || spec->window > n / 2 || (n / 2) % spec->window != 0)
     return fail(ctx, CI_EINVAL, "window %lld must divide n/2", (long long)spec->window);
   if (spec->cap < 1) return fail(ctx, CI_EINVAL, "cap must be >= 1");
+  if (spec->psd_segments < 0 || spec->psd_segments > 16)
+    return fail(ctx, CI_EINVAL, "psd_segments %d outside 0..16", spec->psd_segments);
   if (!isfinite(spec->snr_threshold) || spec->snr_threshold < 0.f)
     return fail(ctx, CI_EINVAL, "threshold must be finite and >= 0");
   DeviceGuard dg(ctx->device);
@@ -1279,6 +1288,8 @@ int ci_stream_create(ci_ctx* ctx, const ci_stream_spec* spec, const ci_template*
   al((void**)&s->xt, sizeof(float2) * (size_t)(half + 1));
   al((void**)&s->pg, sizeof(double) * (size_t)(half + 1));
   al((void**)&s->psd, sizeof(double) * (size_t)(half + 1));
+  s->K = spec->psd_segments > 1 ? spec->psd_segments : 1;
+  if (s->K > 1) al((void**)&s->pring, sizeof(double) * (size_t)s->K * (size_t)(half + 1));
   for (int i = 0; i < ci_stream::kRes; ++i) {
     al((void**)&s->d_peaks[i], sizeof(ci_trigger) * (size_t)n_templates);
     al((void**)&s->d_trig[i], sizeof(ci_trigger) * (size_t)spec->cap);

@@ -194,6 +194,10 @@ hipError_t launch_td_export(const BatchArgs& a, void* d_hf, double* d_sigma2, hi
 hipError_t launch_stream_spectra(const Seg* seg, const float* ring, int64_t rmask, int64_t start,
                                  float2* uv, float2* y, float2* xt, double* pg, double* psd,
                                  int h, hipStream_t st);
+// Mean PSD over the last cnt segments (ring of K estimates of m bins; the
+// current one, in psd, goes to slot cur).
+hipError_t launch_stream_avg(double* ring, int K, int cur, int cnt, int64_t m, double* psd,
+                             hipStream_t st);
 // sigma^2 partial sums per two-polarization template
 constexpr int kTdChunks = 16;
 hipError_t launch_pass2_trig(const BatchArgs& a, hipStream_t st);

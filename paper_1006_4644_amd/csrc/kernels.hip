@@ -1762,6 +1762,26 @@ __global__ __launch_bounds__(256) void k_stream_psd(const double* __restrict__ p
   psd[k] = v;
 }
 
+// Welch's average over time: the segment's own estimate (in psd) goes to
+// ring slot `cur`; psd becomes the mean of the last `cnt` slots, oldest
+// first.
+__global__ __launch_bounds__(256) void k_stream_avg(double* __restrict__ ring, int K, int cur,
+                                                    int cnt, int64_t m, double* __restrict__ psd) {
+  const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (k >= m) return;
+  ring[(size_t)cur * m + k] = psd[k];
+  double s = 0.0;
+  for (int i = 0; i < cnt; ++i) s += ring[(size_t)((cur - cnt + 1 + i + K) % K) * m + k];
+  psd[k] = s / (double)cnt;
+}
+
+hipError_t launch_stream_avg(double* ring, int K, int cur, int cnt, int64_t m, double* psd,
+                             hipStream_t st) {
+  hipLaunchKernelGGL(k_stream_avg, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, st, ring, K,
+                     cur, cnt, m, psd);
+  return hipGetLastError();
+}
+
 hipError_t launch_stream_spectra(const Seg* seg, const float* ring, int64_t rmask, int64_t start,
                                  float2* uv, float2* y, float2* xt, double* pg, double* psd,
                                  int h, hipStream_t st) {

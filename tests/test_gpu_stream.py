@@ -207,3 +207,29 @@ def test_stream_outlives_its_context(gpu_lib):
     assert done == 1
     st2.close()
     c2.close()
+
+
+def test_stream_psd_average_over_segments(ctx):
+    """With psd_segments = K the PSD used for a segment is the mean of the
+    estimates of the last K segments: per segment against the oracle, and
+    the triggers of a noisy stream searched with it."""
+    n, fs, fl, h, K, thr, W = 1 << 16, 4096.0, 20.0, 8, 3, 4.5, 4096
+    segs = 5
+    x32, x = _stream_data(n, segs, fs, fl, None, 61)
+    bank = np.array([[3.0, 2.0], [6.0, 1.5]])
+    st = ctx.stream(bank, n, fs, fl, thr, W, psd_half_width=h, psd_segments=K)
+    orc, psds, _ = SO.stream_search(x, n, fs, fl, bank, thr, W, h, avg=K)
+    G = []
+    for s in range(segs):
+        lo = 0 if s == 0 else n + (s - 1) * n // 2
+        st.push(x32[lo:n + s * n // 2])
+        _, psd, seg = st.last()
+        assert seg == s
+        band = psds[s] > 0
+        ep = np.max(np.abs(psd[band] / psds[s][band] - 1))
+        assert ep < 1e-5, (s, ep)
+    G, done, _ = st.poll(wait=True)
+    assert done == segs
+    print(f"{len(G)} merged triggers with a {K}-segment PSD")
+    _compare_merged(G, orc, thr)
+    st.close()
