@@ -444,7 +444,8 @@ int prepare_jobs(Ctx* ctx, std::vector<Job>& jobs, size_t* slot_elems) {
 // Enqueue the jobs on stream st.  The batches of all jobs (global batch
 // counter b) alternate their two passes between the internal streams
 // ws[b & 1], so one batch's second pass overlaps the next batch's first
-// pass, across job boundaries too; the finalisers run on ws[2] in batch
+// pass, across job boundaries too (with a configuration of one stream,
+// all passes run in order on ws[0]); the finalisers run on ws[2] in batch
 // order, which keeps each job's trigger list ordered.  Batch b uses slot
 // set b % kSlots: its first pass waits for the finaliser of batch
 // b - kSlots (the slot's previous user), its finaliser for its own second
