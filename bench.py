@@ -253,7 +253,7 @@ def bank_timing(ctx, ci, lib, seg, xt, psd, psd_d, wl, cap, headline, probes=8):
             "probe_best_match_median": round(float(np.median(best)), 5), "probes": probes}
 
 
-def stream_timing(args, ctx, bank, wl, headline):
+def stream_timing(args, ctx, ci, bank, wl, headline):
     """Continuous stream: float32 strain pushed from host memory in chunks
     of 2^18 samples, overlap-save segments of n with stride n/2, per
     segment the spectrum, the PSD estimate, the templates' sigma^2 and the
@@ -267,26 +267,31 @@ def stream_timing(args, ctx, bank, wl, headline):
     # coloured Gaussian noise of the workload's PSD as a time series
     xt = synth.make_noise(total, fs, wl.f_low, synth.make_psd(total, fs), wl.noise_seed + 77)
     x = (np.fft.irfft(xt, total) * fs).astype(np.float32)
-    st = ctx.stream(bank, n, fs, wl.f_low, wl.snr_threshold, wl.window, psd_half_width=16,
-                    cap=1 << 12)
     first = n + (warm - 1) * n // 2
-    st.push(x[:first])
-    st.poll(wait=True)
-    torch.cuda.synchronize()
     chunk = 1 << 18
-    t0 = time.perf_counter()
-    for a in range(first, total, chunk):
-        st.push(x[a:a + chunk])
-    trig, done, flags = st.poll(wait=True)
-    dt = time.perf_counter() - t0
-    st.close()
-    segs = done - warm
-    v = segs * len(bank) / dt
-    log(f"[bench] stream: {segs} segments in {dt * 1e3:.1f} ms, {v:.0f} templates/s")
+    res = {}
+    for tag, prec in (("fp32", ci.FP32), ("split-bf16", ci.SPLIT_BF16)):
+        st = ctx.stream(bank, n, fs, wl.f_low, wl.snr_threshold, wl.window, psd_half_width=16,
+                        cap=1 << 12, precision=prec)
+        st.push(x[:first])
+        st.poll(wait=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for a in range(first, total, chunk):
+            st.push(x[a:a + chunk])
+        trig, done, flags = st.poll(wait=True)
+        dt = time.perf_counter() - t0
+        st.close()
+        segs = done - warm
+        v = segs * len(bank) / dt
+        log(f"[bench] stream ({tag}): {segs} segments in {dt * 1e3:.1f} ms, {v:.0f} templates/s")
+        res[tag] = (segs, dt, v, trig, flags)
+    segs, dt, v, trig, flags = res["fp32"]
     return {"segments": segs, "n": n, "stride": n // 2, "ms_per_segment": round(dt * 1e3 / segs, 3),
             "templates_per_s": round(v, 1), "vs_headline": round(v / headline, 3),
             "realtime_factor": round(segs * (n // 2) / fs / dt, 1),
-            "merged_triggers": int(len(trig)), "overflow": int(flags & 1)}
+            "merged_triggers": int(len(trig)), "overflow": int(flags & 1),
+            "split_bf16_templates_per_s": round(res["split-bf16"][2], 1)}
 
 
 def td_timing(args, ctx, ci, seg, xt, psd_d, bank, n_t, cap, peaks, trig, count, wl,
@@ -555,7 +560,7 @@ def main():
     if not args.no_chisq:
         out["chisq_veto"] = chisq_timing(ctx, ci, seg, params, peaks, n_t, args.chisq_bands)
     if not args.no_stream:
-        out["stream"] = stream_timing(args, ctx, bank, wl, value)
+        out["stream"] = stream_timing(args, ctx, ci, bank, wl, value)
     if not args.no_bank:
         out["bank_placement"] = bank_timing(ctx, ci, lib, seg, xt, psd, psd_d, wl, cap, value)
     if not args.no_td:

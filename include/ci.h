@@ -317,8 +317,8 @@ int ci_td_find_triggers(ci_ctx* ctx, const ci_segment* seg, const ci_tdparams* d
  * outside that band), optionally averaged with the estimates of the
  * previous segments (psd_segments); the segment update, the templates'
  * sigma^2 and the
- * merged search of ci_find_triggers (FP32, the context's launch
- * configuration).  Trigger indices and windows are global.
+ * merged search of ci_find_triggers (at the spec's precision, the
+ * context's launch configuration).  Trigger indices and windows are global.
  * Host samples are staged through pinned memory and copied on a stream of
  * their own, so copies overlap the search of earlier segments. */
 typedef struct ci_stream ci_stream;  /* opaque */
@@ -333,7 +333,9 @@ typedef struct {
   int32_t psd_segments;   /* K: the PSD used for a segment is the mean of
                              the estimates of it and the K - 1 before it
                              (fewer at the start); 0 or 1: its own; <= 16 */
-  int32_t reserved;
+  int32_t precision;      /* of the search: CI_FP32 | CI_SPLIT_BF16 |
+                             CI_SPLIT_FP16 (the segment transform and the
+                             PSD estimate are FP32 / FP64 either way) */
 } ci_stream_spec;
 
 /* bank_host[n_templates] is copied.  CI_EINVAL for a bad spec or bank. */

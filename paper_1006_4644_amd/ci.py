@@ -122,7 +122,7 @@ class _StreamSpec(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("fs", ctypes.c_double), ("f_low", ctypes.c_double),
                 ("psd_half_width", ctypes.c_int32), ("snr_threshold", ctypes.c_float),
                 ("window", ctypes.c_int64), ("cap", ctypes.c_int64),
-                ("psd_segments", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("psd_segments", ctypes.c_int32), ("precision", ctypes.c_int32)]
 
 _SIGS = {
     "ci_version": (ctypes.c_char_p, []),
@@ -481,9 +481,11 @@ class Context:
         return out[:n_trig]
 
     def stream(self, bank, n: int, fs: float, f_low: float, thr: float, window: int,
-               psd_half_width: int = 16, cap: int = 1 << 12, psd_segments: int = 1) -> Stream:
+               psd_half_width: int = 16, cap: int = 1 << 12, psd_segments: int = 1,
+               precision: int = FP32) -> Stream:
         bank = np.ascontiguousarray(np.asarray(bank, dtype=np.float64).reshape(-1, 2))
-        spec = _StreamSpec(n, fs, f_low, psd_half_width, thr, window, cap, psd_segments)
+        spec = _StreamSpec(n, fs, f_low, psd_half_width, thr, window, cap, psd_segments,
+                           precision)
         h = _vp()
         self._chk(self.lib.dll.ci_stream_create(self.handle, ctypes.byref(spec),
                                                 bank.ctypes.data, bank.shape[0],

@@ -1235,13 +1235,13 @@ int enqueue_segment(ci_stream* s) {
   jb.trig = s->d_trig[slot];
   jb.cap = s->spec.cap;
   jb.count = s->d_count[slot];
-  int rc = check_job(ctx, jb, CI_FP32, s->spec.snr_threshold, s->spec.window);
+  int rc = check_job(ctx, jb, s->spec.precision, s->spec.snr_threshold, s->spec.window);
   if (rc != CI_OK) return rc;
   size_t ys = 0;
   rc = prepare_jobs(ctx, jobs, &ys);
   if (rc != CI_OK) return rc;
-  rc = enqueue_jobs(ctx, jobs, ys, CI_FP32, s->spec.snr_threshold * s->spec.snr_threshold,
-                    s->spec.window, 1, s->ks);
+  rc = enqueue_jobs(ctx, jobs, ys, s->spec.precision,
+                    s->spec.snr_threshold * s->spec.snr_threshold, s->spec.window, 1, s->ks);
   if (rc != CI_OK) return rc;
   e = hipEventRecord(s->done[slot], s->ks);
   if (e != hipSuccess) return hipfail(ctx, e, "stream event");
@@ -1266,6 +1266,8 @@ int ci_stream_create(ci_ctx* ctx, const ci_stream_spec* spec, const ci_template*
   if (spec->window < 1 || spec->window > n / 2 || (n / 2) % spec->window != 0)
     return fail(ctx, CI_EINVAL, "window %lld must divide n/2", (long long)spec->window);
   if (spec->cap < 1) return fail(ctx, CI_EINVAL, "cap must be >= 1");
+  if (spec->precision < CI_FP32 || spec->precision > CI_SPLIT_FP16)
+    return fail(ctx, CI_EINVAL, "unknown precision %d", spec->precision);
   if (spec->psd_segments < 0 || spec->psd_segments > 16)
     return fail(ctx, CI_EINVAL, "psd_segments %d outside 0..16", spec->psd_segments);
   if (!isfinite(spec->snr_threshold) || spec->snr_threshold < 0.f)

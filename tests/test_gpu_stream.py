@@ -233,3 +233,36 @@ def test_stream_psd_average_over_segments(ctx):
     print(f"{len(G)} merged triggers with a {K}-segment PSD")
     _compare_merged(G, orc, thr)
     st.close()
+
+
+@pytest.mark.parametrize("prec", [ci.SPLIT_BF16, ci.SPLIT_FP16])
+def test_stream_split_precision(ctx, prec):
+    """A stream searched on the split-precision path: merged triggers as the
+    oracle's within the split bar (rho within 1e-3)."""
+    n, fs, fl, h, thr, W = 1 << 16, 4096.0, 30.0, 16, 4.5, 4096
+    segs = 4
+    inj = (8.0, 6.0, 25.0, 3 * n // 2 + 5000)
+    x32, x = _stream_data(n, segs, fs, fl, inj, 11)
+    bank = np.array([[8.0, 6.0], [3.0, 2.0], [12.0, 10.0], [5.0, 1.5]])
+    st = ctx.stream(bank, n, fs, fl, thr, W, psd_half_width=h, precision=prec)
+    st.push(x32)
+    G, done, _ = st.poll(wait=True)
+    assert done == segs
+    orc, _, _ = SO.stream_search(x, n, fs, fl, bank, thr, W, h)
+    om = {}
+    for d in orc:
+        om.update(d)
+    gm = {int(t["window"]): t for t in G}
+    for w in set(gm) | set(om):
+        if w in gm and w in om:
+            assert abs(math.sqrt(float(gm[w]["rho2"])) - math.sqrt(om[w][2])) <= \
+                1e-3 * math.sqrt(om[w][2]), (w, gm[w], om[w])
+        else:
+            r2 = float(gm[w]["rho2"]) if w in gm else om[w][2]
+            assert abs(math.sqrt(r2) - thr) <= 1e-3 * thr, (w, r2)
+    hit = G[G["rho2"] > 15.0 ** 2]
+    assert len(hit) == 1 and abs(int(hit[0]["index"]) - inj[3]) <= 1
+    with pytest.raises(ci.CiError) as ei:
+        ctx.stream(bank, n, fs, fl, thr, W, precision=7)
+    assert ei.value.code == ci.EINVAL
+    st.close()
