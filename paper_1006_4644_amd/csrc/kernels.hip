@@ -1289,7 +1289,7 @@ __global__ void k_init_call(ci_trigger* mrec, int nwin, u64* run, int64_t* d_cou
 // chi-squared veto at trigger samples
 // ---------------------------------------------------------------------------
 
-constexpr int kChiThreads = 256;
+constexpr int kChiThreads = 512;
 constexpr int kChiMaxBands = 64;
 
 // Sum of a double2 over the workgroup (every thread gets the result).
