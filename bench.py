@@ -299,9 +299,9 @@ def td_timing(args, ctx, ci, seg, xt, psd_d, bank, n_t, cap, peaks, trig, count,
     """The same step with the paper's own template form: time-domain
     two-polarization templates generated, transformed and normalised per
     batch, correlated, two real inverse transforms packed into one, merged
-    search.  Bytes per template that the form moves through HBM: generation
-    8n, template transform 16n, sigma^2 8n, pass 1 16n (both mirror bins)
-    + 8n, pass 2 8n = 64n."""
+    search.  Bytes per template that the form moves through HBM: template
+    transform 24n (u generated inside its first pass), sigma^2 8n, pass 1
+    16n (both mirror bins) + 8n, pass 2 8n = 64n - 8n = 56n."""
     import torch
     tdp = ctx.td_params(seg, bank)
 
@@ -323,11 +323,11 @@ def td_timing(args, ctx, ci, seg, xt, psd_d, bank, n_t, cap, peaks, trig, count,
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / steps
     v = n_t / (ms / 1e3)
-    gbs = 64.0 * wl.n * n_t / (ms / 1e3) / 1e9
+    gbs = 56.0 * wl.n * n_t / (ms / 1e3) / 1e9
     log(f"[bench] two-polarization form: {ms:.3f} ms/step, {v:.0f} templates/s")
     return {"value": round(v, 1), "unit": "templates/s", "ms_per_step": round(ms, 4),
             "steps": steps, "vs_headline": round(v / headline, 3),
-            "model_bytes_per_template": 64 * wl.n, "model_gbs": round(gbs, 1),
+            "model_bytes_per_template": 56 * wl.n, "model_gbs": round(gbs, 1),
             "model_frac": round(gbs / HBM_PEAK_GBS, 4),
             "merged_windows": int(count.cpu()[0])}
 

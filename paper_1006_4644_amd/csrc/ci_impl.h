@@ -180,9 +180,9 @@ struct BatchArgs {
 };
 
 hipError_t launch_pass1(const BatchArgs& a, bool zero_trig, hipStream_t st);
-// Two-polarization templates of a batch: generate u = h_+ + i h_x into
-// a.uv, replace it by V = IDFT(u), and form the sigma^2 partials in a.sig.
-// launch_pass1 then reads V when a.td is set.
+// Two-polarization templates of a batch: V = IDFT(u) of u = h_+ + i h_x
+// (generated inside the transform's first pass) into a.uv, and the sigma^2
+// partials in a.sig.  launch_pass1 then reads V when a.td is set.
 hipError_t launch_td_prep(const BatchArgs& a, hipStream_t st);
 // The generation step alone (u into a.uv).
 hipError_t launch_td_gen(const BatchArgs& a, hipStream_t st);

@@ -569,9 +569,26 @@ struct SrcTd {
   }
 };
 
+// Input of the template transform generated on the fly: the sample
+// u_j = h_+ + i h_x of a two-polarization template (as k_td_gen writes it).
+struct SrcGen {
+  const ci_tdparams& T;
+  int64_t n;
+  double fs;
+  __device__ __forceinline__ float2 operator()(int j) const {
+    const int64_t m = n - j;
+    if ((T.flags & CI_TMPL_EMPTY) || m < T.m_lo || m > T.m_hi) return make_float2(0.f, 0.f);
+    const double v = td_solve_v(T, -(double)m / fs);
+    const float fr = td_phase_frac(T, v);
+    const float a = (float)(v * v);
+    return make_float2(a * __builtin_amdgcn_cosf(fr), a * __builtin_amdgcn_sinf(fr));
+  }
+};
+
 // Pass 1 over a spectrum held in memory, every bin possibly nonzero.
 // MODE 0: the plain inverse DFT of a.uv.  MODE 1: the two-polarization
-// correlator built from a.uv = IDFT(h_+ + i h_x) and w0.
+// correlator built from a.uv = IDFT(h_+ + i h_x) and w0.  MODE 2: the
+// inverse DFT of u = h_+ + i h_x generated on the fly (no u in memory).
 template <int N1, int N2, int C, int MODE>
 __global__ __launch_bounds__(C * N2 / 16) void k_pass1_mem(P1Args a) {
   constexpr int N = N1 * N2;
@@ -595,6 +612,10 @@ __global__ __launch_bounds__(C * N2 / 16) void k_pass1_mem(P1Args a) {
   const float2* vb = a.uv + (size_t)b * N;
   if constexpr (MODE == 0) {
     pass1_tile<N1, N2, C, 16, false>(a, SrcMem{vb}, b, tile, lds, twl, t, c);
+  } else if constexpr (MODE == 2) {
+    const ci_tdparams& T = a.tdp[b];
+    pass1_tile<N1, N2, C, 16, false>(a, SrcGen{T, (int64_t)N, a.sd->fs}, b, tile, lds, twl, t,
+                                     c);
   } else {
     // sigma^2 sums in a fixed order
     const double* sg = a.sig + (size_t)b * kTdChunks * 2;
@@ -1822,14 +1843,13 @@ hipError_t launch_td_gen(const BatchArgs& a, hipStream_t st) {
 }
 
 hipError_t launch_td_prep(const BatchArgs& a, hipStream_t st) {
-  hipError_t e = launch_td_gen(a, st);
-  if (e != hipSuccess) return e;
-  // V = IDFT(u), through the intermediate, back into the same buffer
+  // V = IDFT(u), u generated inside the first pass, through the
+  // intermediate into a.uv
   BatchArgs c = a;
   c.d_z = a.uv;
-  e = dispatch(c.plan, [&](auto inst) {
+  hipError_t e = dispatch(c.plan, [&](auto inst) {
     typedef decltype(inst) I;
-    hipError_t r = I::template p1mem<0>(c, false, st);
+    hipError_t r = I::template p1mem<2>(c, false, st);
     return r == hipSuccess ? I::p2s(c, st) : r;
   });
   if (e != hipSuccess) return e;
