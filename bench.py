@@ -301,7 +301,7 @@ def td_timing(args, ctx, ci, seg, xt, psd_d, bank, n_t, cap, peaks, trig, count,
     batch, correlated, two real inverse transforms packed into one, merged
     search.  Bytes per template that the form moves through HBM: template
     transform 24n (u generated inside its first pass), sigma^2 8n, pass 1
-    16n (both mirror bins) + 8n, pass 2 8n = 64n - 8n = 56n."""
+    16n (both mirror bins) + 8n, pass 2 8n: 56n in all."""
     import torch
     tdp = ctx.td_params(seg, bank)
 
