@@ -1,7 +1,6 @@
 """Template-bank placement (host library, CPU): the metric against the
 oracle's, the lattice's range and determinism, and its coverage checked by
 the oracle's brute-force match."""
-import math
 
 import numpy as np
 import pytest

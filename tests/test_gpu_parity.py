@@ -8,7 +8,6 @@ trigger indices exact except where the oracle's own values tie within that
 tolerance, and windows whose maximum lies within tolerance of the threshold
 may go either way.
 """
-import math
 
 import numpy as np
 import pytest
