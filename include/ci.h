@@ -386,11 +386,12 @@ typedef struct {
 } ci_lattice_spec;
 
 /* Hexagonal lattice in (tau_0, tau_3) for the mass range
- * m_min <= m2 <= m1 <= m_max.  The metric is sampled over the range and a
- * constant metric G is taken that bounds every sample (the centre's,
- * scaled by the largest eigenvalue ratio, times 1.05); lattice points with
- * G-distance sqrt(1 - min_match) / side sqrt(3 (1 - min_match)) cover the
- * range, those outside it but within the covering radius are moved to the
+ * m_min <= m2 <= m1 <= m_max.  The metric is sampled over the range; in
+ * each of 12 strips of log tau_0 a constant metric G is taken, the one of
+ * least determinant that bounds every sample of the strip (G - g positive
+ * semi-definite), times 1.05; lattice points with covering radius
+ * sqrt(1 - min_match) (side sqrt(3 (1 - min_match))) in G cover the strip,
+ * those outside it but within the covering radius are moved to the
  * nearest point of its boundary.  out_host[0 .. min(count, cap)) receives
  * (m1, m2) with m1 >= m2; *count the number placed (CI_ETRUNC when above
  * cap; cap = 0 and out_host = NULL query the count). */

@@ -149,6 +149,60 @@ bool inside(const std::vector<P2>& poly, P2 p) {
   return in;
 }
 
+// Bounding metric of a set of metrics g_i = {g00, g03, g33}: G = s S with
+// det S = 1 and s the smallest factor for which G dominates every g_i (its
+// unit ellipse lies inside each of theirs), minimised over the orientation
+// and aspect of S by a compass search started from the shape of g_start.
+// With S^-1 = [[p, q], [q, r]] the largest eigenvalue of S^-1 g is
+// t/2 + sqrt(t^2/4 - det g), t = p g00 + 2 q g03 + r g33.
+struct Shape {
+  double th, la;  // orientation, log square root of the aspect
+};
+
+double bound_factor(const std::vector<const double*>& gs, Shape sh) {
+  const double c = cos(sh.th), s = sin(sh.th), a = exp(-sh.la), b = exp(sh.la);
+  const double p = a * c * c + b * s * s, q = (a - b) * c * s, r = a * s * s + b * c * c;
+  double need = 0.0;
+  for (const double* g : gs) {
+    const double t = p * g[0] + 2.0 * q * g[1] + r * g[2];
+    const double d = g[0] * g[2] - g[1] * g[1];
+    need = std::max(need, 0.5 * t + sqrt(std::max(0.0, 0.25 * t * t - d)));
+  }
+  return need;
+}
+
+void bounding_metric(const std::vector<const double*>& gs, const double* g_start, double* G) {
+  // shape of g_start: eigenvalues e0 >= e1 at angle th of the first
+  const double tr = g_start[0] + g_start[2];
+  const double dd = sqrt(0.25 * (g_start[0] - g_start[2]) * (g_start[0] - g_start[2]) +
+                         g_start[1] * g_start[1]);
+  const double e0 = 0.5 * tr + dd, e1 = 0.5 * tr - dd;
+  Shape best{0.5 * atan2(2.0 * g_start[1], g_start[0] - g_start[2]), 0.5 * log(e0 / e1)};
+  double fb = bound_factor(gs, best);
+  double st_th = 0.1, st_la = 0.25;
+  while (st_th > 1e-6 || st_la > 1e-6) {
+    bool moved = false;
+    const Shape trial[4] = {{best.th + st_th, best.la}, {best.th - st_th, best.la},
+                            {best.th, best.la + st_la}, {best.th, best.la - st_la}};
+    for (const Shape& t : trial) {
+      const double f = bound_factor(gs, t);
+      if (f < fb) {
+        fb = f;
+        best = t;
+        moved = true;
+      }
+    }
+    if (!moved) {
+      st_th *= 0.5;
+      st_la *= 0.5;
+    }
+  }
+  const double c = cos(best.th), s = sin(best.th), a = exp(best.la), b = exp(-best.la);
+  G[0] = fb * (a * c * c + b * s * s);
+  G[1] = fb * (a - b) * c * s;
+  G[2] = fb * (a * s * s + b * c * c);
+}
+
 }  // namespace
 
 extern "C" {
@@ -243,23 +297,17 @@ int ci_make_bank_lattice(const ci_lattice_spec* spec, const double* psd_host, in
       in.clear();
       for (size_t q = 0; q < by.size() && q < 6; ++q) in.push_back(by[q].second);
     }
-    // reference: the sample nearest the strip's middle; gc = L L^T
+    // the strip's metric: the smallest one that bounds its samples (search
+    // started from the sample nearest the strip's middle), gc = L L^T
     const Sample* ref = in[0];
     for (const Sample* sm : in)
       if (fabs(log(sm->t.x / sqrt(a * b))) < fabs(log(ref->t.x / sqrt(a * b)))) ref = sm;
-    const double* gc = ref->g;
+    std::vector<const double*> gs;
+    for (const Sample* sm : in) gs.push_back(sm->g);
+    double gc[3];
+    bounding_metric(gs, ref->g, gc);
     const double l00 = sqrt(gc[0]), l10 = gc[1] / l00, l11 = sqrt(gc[2] - l10 * l10);
-    double scale = 1.0;
-    for (const Sample* sm : in) {
-      const double* g = sm->g;
-      // largest eigenvalue of L^-1 g L^-T
-      const double qa = g[0] / (l00 * l00);
-      const double qb = (g[1] - l10 * g[0] / l00) / (l00 * l11);
-      const double qc = (g[2] - 2.0 * l10 * g[1] / l00 + l10 * l10 * g[0] / (l00 * l00)) /
-                        (l11 * l11);
-      scale = std::max(scale, 0.5 * (qa + qc) + sqrt(0.25 * (qa - qc) * (qa - qc) + qb * qb));
-    }
-    scale *= 1.05;
+    const double scale = 1.05;
     // u = sqrt(scale) L^T tau: the bounding metric is the identity in u
     const double sq = sqrt(scale);
     std::vector<P2> pu;
