@@ -1642,7 +1642,7 @@ int ci_autotune(ci_ctx* ctx, const ci_segment* seg, const ci_tparams* d_params, 
     return ci_find_triggers(ctx, seg, d_params, n, precision, snr_threshold, window, 0, 0, d_pk,
                             d_tr, cap, d_cnt, 0, stream);
   };
-  // time one configuration (best of three after a warm-up call) and check
+  // time one configuration (best of five after a warm-up call) and check
   // that its outputs equal the reference configuration's bit for bit
   auto trial = [&](const Tune& cand, float* ms, bool* same) -> int {
     ctx->tune[l2][precision] = cand;
@@ -1654,7 +1654,7 @@ int ci_autotune(ci_ctx* ctx, const ci_segment* seg, const ci_tparams* d_params, 
     *same = cnt == ref_cnt && memcmp(pk.data(), ref_pk.data(), pk_b) == 0 && tr.size() == ref_tr.size() &&
             (tr.empty() || memcmp(tr.data(), ref_tr.data(), sizeof(ci_trigger) * tr.size()) == 0);
     float bestt = 0.f;
-    for (int rep = 0; rep < 3; ++rep) {
+    for (int rep = 0; rep < 5; ++rep) {
       hipError_t x = hipEventRecord(e0, st);
       if (x != hipSuccess) return hipfail(ctx, x, "autotune timing");
       r = call();
@@ -1721,8 +1721,10 @@ int ci_autotune(ci_ctx* ctx, const ci_segment* seg, const ci_tparams* d_params, 
     else if (rc == CI_OK && ms < best_ms) { best = c; best_ms = ms; }
   }
   // the in-order schedule (one compute stream) at each batch size: chosen
-  // when within 2 % of the overlapped one, whose launches share the device
-  // with the neighbouring batch's other pass
+  // when within 5 % of the overlapped one, whose launches share the device
+  // with the neighbouring batch's other pass (at 2^20 the two differ by
+  // less than the spread of repeated trials, and only in-order launches
+  // can be timed against their own bytes)
   {
     Tune in_order = best;
     float io_ms = 0.f;
@@ -1738,7 +1740,7 @@ int ci_autotune(ci_ctx* ctx, const ci_segment* seg, const ci_tparams* d_params, 
       if (rc == CI_OK && !same) ++rejected;
       else if (rc == CI_OK && (io_ms == 0.f || ms < io_ms)) { in_order = c; io_ms = ms; }
     }
-    if (rc == CI_OK && io_ms > 0.f && io_ms <= best_ms * 1.02f) { best = in_order; best_ms = io_ms; }
+    if (rc == CI_OK && io_ms > 0.f && io_ms <= best_ms * 1.05f) { best = in_order; best_ms = io_ms; }
   }
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);
