@@ -11,6 +11,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
 #include <new>
 #include <string>
 #include <vector>
@@ -1725,9 +1726,12 @@ int ci_autotune(ci_ctx* ctx, const ci_segment* seg, const ci_tparams* d_params, 
   // with the neighbouring batch's other pass (at 2^20 the two differ by
   // less than the spread of repeated trials, and only in-order launches
   // can be timed against their own bytes)
+  // Among in-order batch sizes within 1 % of the fastest, the largest is
+  // kept (fewer launches; the choice then varies less between runs).
   {
-    Tune in_order = best;
-    float io_ms = 0.f;
+    Tune io_c[6];
+    float io_t[6];
+    int nio = 0;
     const int64_t bs1[6] = {best.batch, b0, b0 * 2, b0 * 4, b0 * 8, b0 / 2};
     for (int i = 0; i < 6 && rc == CI_OK; ++i) {
       if (bs1[i] < 0 || bs1[i] > 4096 || (bs1[i] > 0 && bs1[i] >= 2 * n)) continue;
@@ -1738,9 +1742,20 @@ int ci_autotune(ci_ctx* ctx, const ci_segment* seg, const ci_tparams* d_params, 
       bool same = false;
       rc = trial(c, &ms, &same);
       if (rc == CI_OK && !same) ++rejected;
-      else if (rc == CI_OK && (io_ms == 0.f || ms < io_ms)) { in_order = c; io_ms = ms; }
+      else if (rc == CI_OK) { io_c[nio] = c; io_t[nio] = ms; ++nio; }
     }
-    if (rc == CI_OK && io_ms > 0.f && io_ms <= best_ms * 1.05f) { best = in_order; best_ms = io_ms; }
+    if (rc == CI_OK && nio > 0) {
+      float io_ms = io_t[0];
+      for (int i = 1; i < nio; ++i) io_ms = std::min(io_ms, io_t[i]);
+      int pick = -1;
+      for (int i = 0; i < nio; ++i) {
+        if (io_t[i] > io_ms * 1.01f) continue;
+        const int64_t bi = io_c[i].batch > 0 ? io_c[i].batch : b0;
+        const int64_t bp = pick < 0 ? -1 : (io_c[pick].batch > 0 ? io_c[pick].batch : b0);
+        if (bi > bp) pick = i;
+      }
+      if (io_t[pick] <= best_ms * 1.05f) { best = io_c[pick]; best_ms = io_t[pick]; }
+    }
   }
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);
