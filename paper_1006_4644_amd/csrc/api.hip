@@ -199,7 +199,12 @@ void host_td_params(const ci_template& tm, const SegDev& sd, ci_tdparams* T) {
 
 int ensure_ybuf(Ctx* ctx, size_t bytes) {
   if (ctx->ybytes >= bytes) return CI_OK;
-  if (ctx->ybuf) (void)hipFree(ctx->ybuf);
+  // the old buffer may still be used by enqueued work: wait for the
+  // device (the caller's device is current) before freeing it
+  if (ctx->ybuf) {
+    (void)hipDeviceSynchronize();
+    (void)hipFree(ctx->ybuf);
+  }
   ctx->ybuf = nullptr;
   ctx->ybytes = 0;
   hipError_t e = hipMalloc(&ctx->ybuf, bytes);
@@ -211,7 +216,12 @@ int ensure_ybuf(Ctx* ctx, size_t bytes) {
 
 int ensure_tdbuf(Ctx* ctx, size_t bytes) {
   if (ctx->tdbytes >= bytes) return CI_OK;
-  if (ctx->tdbuf) (void)hipFree(ctx->tdbuf);
+  // the old buffer may still be used by enqueued work: wait for the
+  // device (the caller's device is current) before freeing it
+  if (ctx->tdbuf) {
+    (void)hipDeviceSynchronize();
+    (void)hipFree(ctx->tdbuf);
+  }
   ctx->tdbuf = nullptr;
   ctx->tdbytes = 0;
   hipError_t e = hipMalloc(&ctx->tdbuf, bytes);
@@ -268,7 +278,12 @@ void carve_trig(char* p, int64_t bmax, int64_t nwin, int64_t ntile2, TrigWork* t
 
 int ensure_tbuf(Ctx* ctx, size_t total) {
   if (ctx->tbytes >= total) return CI_OK;
-  if (ctx->tbuf) (void)hipFree(ctx->tbuf);
+  // the old buffer may still be used by enqueued work: wait for the
+  // device (the caller's device is current) before freeing it
+  if (ctx->tbuf) {
+    (void)hipDeviceSynchronize();
+    (void)hipFree(ctx->tbuf);
+  }
   ctx->tbuf = nullptr;
   ctx->tbytes = 0;
   hipError_t e = hipMalloc(&ctx->tbuf, total);
