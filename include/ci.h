@@ -27,9 +27,13 @@
  *   message readable through ci_last_error().  HIP launch failures map to
  *   CI_EHIP.
  * - GPU work is enqueued asynchronously on the caller's hipStream_t (passed
- *   as void*; NULL means the default stream).  The library never
- *   synchronises the stream itself; results are valid after the caller
- *   synchronises.
+ *   as void*; NULL means the default stream).  The library does not
+ *   synchronise the caller's stream; results are valid after the caller
+ *   synchronises.  Calls that block instead: ci_autotune, the *_destroy
+ *   calls, the ci_stream_* calls as each documents, and any call whose
+ *   context workspace has to grow (it waits for the device before
+ *   releasing the old buffer; workspaces only grow, so this happens on the
+ *   first calls at a new size).
  * - The caller owns every buffer it passes.  No call keeps a caller pointer
  *   after it returns.  The library owns only ci_ctx and ci_segment objects
  *   and their device workspaces, released by the matching *_destroy call.
