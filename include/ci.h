@@ -391,7 +391,8 @@ typedef struct {
 
 /* Hexagonal lattice in (tau_0, tau_3) for the mass range
  * m_min <= m2 <= m1 <= m_max.  The metric is sampled over the range; in
- * each of 12 strips of log tau_0 a constant metric G is taken, the one of
+ * each of 12 strips of log tau_0 (fewer when the range is less than 120
+ * covering radii long along tau_0) a constant metric G is taken, the one of
  * least determinant that bounds every sample of the strip (G - g positive
  * semi-definite), times 1.05; lattice points with covering radius
  * sqrt(1 - min_match) (side sqrt(3 (1 - min_match))) in G cover the strip,

@@ -272,9 +272,15 @@ int ci_make_bank_lattice(const ci_lattice_spec* spec, const double* psd_host, in
     t0max = std::max(t0max, p.x);
   }
   // strips of equal width in log tau_0, each with its own bounding metric
-  // and lattice, covering its part of the range
-  const int K = 12;
+  // and lattice, covering its part of the range: 12, or fewer when the
+  // range spans less than 10 covering radii per strip along tau_0 (each
+  // strip adds edge points, which dominate a narrow range)
   const double R = sqrt(mm), side = sqrt(3.0 * mm), dy = side * sqrt(3.0) / 2.0;
+  std::vector<double> g00;
+  for (const Sample& sm : samples) g00.push_back(sm.g[0]);
+  std::nth_element(g00.begin(), g00.begin() + g00.size() / 2, g00.end());
+  const double extent = sqrt(g00[g00.size() / 2]) * (t0max - t0min);
+  const int K = (int)std::min(12.0, std::max(1.0, floor(extent / (10.0 * R))));
   std::vector<ci_template> out;
   double work = 0.0;
   for (int st = 0; st < K; ++st) {

@@ -72,3 +72,39 @@ def test_lattice_coverage_by_brute_force_match(lib):
         worst = min(worst, best)
     print(f"{len(bank)} templates, worst best-match {worst:.4f}")
     assert worst >= mm
+
+
+def test_lattice_narrow_range_and_density(lib):
+    """A range narrower than one covering radius gets one or two
+    templates inside it; a bank never holds fewer templates than the
+    hexagonal area estimate (the integral of sqrt(det gamma) over the
+    range, over the cell area 3 sqrt(3) (1 - MM) / 2, here from the
+    oracle's metric on a mass grid), the thinnest covering of the plane.
+    The upper bound only guards against regressions: on a range a few
+    covering radii wide the edge points dominate (about 6x here)."""
+    n, fs, fl, mm = 1 << 16, 4096.0, 40.0, 0.97
+    psd = synth.make_psd(n, fs)
+    narrow = lib.make_bank_lattice(5.0, 5.02, mm, psd, n, fs, fl)
+    assert 1 <= len(narrow) <= 2
+    assert np.all(narrow >= 5.0) and np.all(narrow <= 5.02)
+    lo, hi, G = 3.0, 8.0, 16
+    bank = lib.make_bank_lattice(lo, hi, mm, psd, n, fs, fl)
+    ls = np.linspace(np.log(lo), np.log(hi), G + 1)
+    lc, dl = 0.5 * (ls[1:] + ls[:-1]), ls[1] - ls[0]
+    area = 0.0
+    for i, a in enumerate(lc):
+        for j, b in enumerate(lc[:i + 1]):
+            m1, m2 = np.exp(a), np.exp(b)
+            g = B.metric(psd, n, fs, fl, m1, m2)
+            h = 1e-5
+            J = np.column_stack([
+                (np.array(B.chirp_times(m1 * (1 + h), m2, fl))
+                 - np.array(B.chirp_times(m1 * (1 - h), m2, fl))) / (2 * h * m1),
+                (np.array(B.chirp_times(m1, m2 * (1 + h), fl))
+                 - np.array(B.chirp_times(m1, m2 * (1 - h), fl))) / (2 * h * m2)])
+            w = 0.5 if i == j else 1.0
+            area += w * np.sqrt(np.linalg.det(g)) * abs(np.linalg.det(J)) * m1 * m2 * dl * dl
+    ideal = area / (1.5 * np.sqrt(3.0) * (1.0 - mm))
+    print(f"{len(bank)} templates, area estimate {ideal:.0f}")
+    assert len(bank) >= 0.9 * ideal
+    assert len(bank) <= 8.0 * ideal
