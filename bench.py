@@ -547,8 +547,29 @@ def main():
             dev = max(abs(math.sqrt(pks["rho2"][i.tmpl]) - math.sqrt(pk32["rho2"][i.tmpl]))
                       / math.sqrt(pk32["rho2"][i.tmpl]) for i in injs if i.tmpl >= 0) \
                 if any(i.tmpl >= 0 for i in injs) else None
+            # the path's dominant kernel against the HBM roofline, and the
+            # matrix-core rate of its second pass (radix-16 DFT-matrix
+            # stages: 12 R3 16x16x32 products of 16384 flops per column of
+            # N1 = 256 R3 points, N2 columns per template)
+            dn = max(kts, key=lambda k: kts[k][2])
+            dl, dt, dk = kts[dn]
+            d_ach = Y_BYTES[tag] * wl.n * (dt / dl) / (dk / dl / 1e3) / 1e9
+            lg = int(round(math.log2(wl.n)))
+            n1 = 1 << ((lg + 1) // 2)
+            mx_flop = 12 * (n1 // 256) * 16384 * (wl.n // n1)
+            pl, pt, pk_ms = kts["pass2"]
+            mx_tf = mx_flop * (pt / pl) / (pk_ms / pl / 1e3) / 1e12
             paths[tag] = {"value": round(v, 1), "ms_per_step": round(tms / args.steps, 4),
                           "speedup_vs_headline": round(v / value, 3),
+                          "roofline": {"bound": "hbm", "achieved": round(d_ach, 1),
+                                       "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                       "frac": round(d_ach / HBM_PEAK_GBS, 4), "kernel": dn,
+                                       "avg_launch_ms": round(dk / dl, 4),
+                                       "templates_per_launch": dt / dl},
+                          "mfma_pass2": ({"achieved": round(mx_tf, 1), "peak": 2500.0,
+                                          "unit": "TFLOP/s", "frac": round(mx_tf / 2500.0, 4),
+                                          "flop_per_template": mx_flop}
+                                         if tag != "fp32" else None),
                           "path_hbm_frac": round(2.0 * Y_BYTES[tag] * wl.n * n_t
                                                  / (tms / args.steps / 1e3) / 1e9
                                                  / HBM_PEAK_GBS, 4),
