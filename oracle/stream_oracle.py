@@ -31,7 +31,9 @@ is also what the GPU path implements):
   over the segment and the K - 1 before it (Welch's average over time).
 * Search of each segment: the frequency-domain path of mf_oracle with that
   spectrum and PSD over [n/4, 3n/4), merged across templates per window;
-  windows of W samples align globally because W divides n/2.
+  windows of W samples align globally, and each lies inside one segment's
+  valid region, because W divides n/4 (a window of n/2 would span two
+  segments and be reported twice).
 """
 from __future__ import annotations
 
@@ -81,6 +83,10 @@ def stream_search(x, n: int, fs: float, f_low: float, bank, thr: float,
     max(0, s - avg + 1) .. s.  Returns (per-segment list of
     {w_global: (tmpl, j_global, rho2)}, per-segment PSDs used, per-segment
     spectra)."""
+    # windows must not straddle two segments' valid regions, which start
+    # at n/4 past a multiple of n/2: W divides n/4
+    if window < 1 or (n // 4) % window != 0:
+        raise ValueError(f"window {window} must divide n/4 = {n // 4}")
     stride = n // 2
     out, psds, specs, own = [], [], [], []
     for s in range(segment_count(len(x), n)):

@@ -60,7 +60,8 @@ def series_error(z_gpu, z_orc):
 
 def check_peak(gp, zo, tol=TOL_FP32, j_lo=0, j_hi=None):
     """GPU peak record vs the oracle series: index exact unless the oracle's
-    own rho^2 at the GPU index ties the oracle maximum within tolerance."""
+    own rho^2 at the GPU index ties the oracle maximum within tolerance;
+    rho within tol of the oracle's rho at that index, z within 2 tol rho."""
     r2 = np.abs(zo) ** 2
     n = len(r2)
     j_hi = n if j_hi is None else j_hi
@@ -71,26 +72,30 @@ def check_peak(gp, zo, tol=TOL_FP32, j_lo=0, j_hi=None):
     tie = 2 * rmax * drho + drho * drho
     assert j_lo <= jg < j_hi
     assert jg == jo or abs(r2[jg] - r2[jo]) <= tie, (jg, jo, r2[jg], r2[jo])
-    assert abs(math.sqrt(gp["rho2"]) - math.sqrt(r2[jg])) <= drho
+    rho_o = math.sqrt(r2[jg])
+    assert abs(math.sqrt(gp["rho2"]) - rho_o) <= tol * rho_o
     zg = complex(gp["re"], gp["im"])
-    assert abs(zg - zo[jg]) <= 2 * drho, (zg, zo[jg])
+    assert abs(zg - zo[jg]) <= 2 * tol * rho_o, (zg, zo[jg])
     return jg == jo
 
 
 def check_triggers(gtr, zo, window, thr, tol=TOL_FP32, j_lo=0, j_hi=None):
     """One template's GPU triggers vs its oracle series.
 
-    Windows whose oracle maximum is within tolerance of the threshold may
-    go either way; inside a window the index must match unless the oracle's
-    values at the two indices tie within tolerance.  Returns the number of
-    exempted decisions."""
+    Each trigger's rho is held to tol relative to the oracle's rho at that
+    sample (and z to 2 tol rho, both quadratures), not to the series
+    maximum.  Windows whose oracle maximum is within tol (relative) of the
+    threshold may go either way; inside a window the index must match
+    unless the oracle's values at the two indices tie within tol of the
+    window maximum.  Returns the number of exempted decisions."""
     r2 = np.abs(zo) ** 2
     n = len(r2)
     j_hi = n if j_hi is None else j_hi
-    rmax = math.sqrt(np.max(r2))
-    drho = tol * rmax
     thr2 = thr * thr
-    band = 2 * thr * drho + drho * drho
+    # e_rel = |rho_gpu - rho_orc| / rho_orc at each trigger: every bound
+    # below is tol times the oracle's own rho at the sample concerned
+    dthr = tol * thr
+    band = 2 * thr * dthr + dthr * dthr
     expect = {w: (j, v) for (w, j, v) in O.window_triggers(r2, window, thr2,
                                                           j_lo, j_hi)}
     got = {int(t["window"]): t for t in gtr}
@@ -112,11 +117,15 @@ def check_triggers(gtr, zo, window, thr, tol=TOL_FP32, j_lo=0, j_hi=None):
             jg = int(t["index"])
             assert a <= jg < b and int(t["window"]) == w
             jo = a + int(np.argmax(r2[a:b]))
-            tie = 2 * math.sqrt(wmax) * drho + drho * drho
+            dw = tol * math.sqrt(wmax)
+            tie = 2 * math.sqrt(wmax) * dw + dw * dw
             assert jg == jo or abs(r2[jg] - r2[jo]) <= tie, (w, jg, jo)
             exempt += int(jg != jo) + int(near)
-            assert abs(math.sqrt(t["rho2"]) - math.sqrt(r2[jg])) <= drho
-            assert abs(complex(t["re"], t["im"]) - zo[jg]) <= 2 * drho
+            rho_o = math.sqrt(r2[jg])
+            assert abs(math.sqrt(t["rho2"]) - rho_o) <= tol * rho_o, \
+                (w, jg, float(t["rho2"]), r2[jg])
+            assert abs(complex(t["re"], t["im"]) - zo[jg]) <= 2 * tol * rho_o, \
+                (w, jg, complex(t["re"], t["im"]), zo[jg])
         elif near:
             exempt += 1
     return exempt

@@ -264,9 +264,14 @@ def test_full_size_fp32_workload_sampled(ctx):
     count = int(cnt.cpu()[0])
     T = ci.triggers_to_numpy(trig, count)
     M = ci.triggers_to_numpy(mtrig, int(mcnt.cpu()[0]))
+    # the declared sample: 64 seeded random templates, every injection's
+    # template, and the winner of every injection's window in the merged list
+    win = {int(m["window"]): int(m["tmpl"]) for m in M}
+    winners = {win[inj.j0 // wl.window] for inj in injs if inj.j0 // wl.window in win}
     rng = np.random.default_rng(12345)
-    sample = sorted(set([i.tmpl for i in injs]) |
-                    set(rng.choice(len(bank), 11, replace=False).tolist()))
+    sample = sorted(set([i.tmpl for i in injs]) | winners |
+                    set(rng.choice(len(bank), 64, replace=False).tolist()))
+    assert all(inj.j0 // wl.window in win for inj in injs)
     for i in sample:
         zo, _ = C.oracle_series(x128, psd, wl.n, wl.fs, wl.f_low, *bank[i])
         C.check_peak(P[i], zo)
@@ -385,9 +390,10 @@ def test_split_precision_full_size_sampled(ctx, prec):
 def test_large_banks_sampled(ctx, name):
     """The 65536-template bank at 2^20 and the 1 048 576-template bank at 2^21
     (from 10 Hz), FP32 and split-BF16 in their default launch
-    configurations: every injection's template and seeded random ones
-    against the oracle (FP32 bar for FP32, 1e-3 for split-BF16), merged
-    lists consistent between the paths."""
+    configurations: every injection's template, the winners of the
+    injections' windows and 64 seeded random ones against the oracle (FP32
+    bar for FP32, 1e-3 for split-BF16), merged lists consistent between
+    the paths."""
     wl, bank, injs, x64, psd, x128 = C.workload_case(name)
     seg = _segment(ctx, x64, psd, wl.n, wl.fs, wl.f_low)
     params = ctx.gen_templates(seg, bank)
@@ -398,13 +404,31 @@ def test_large_banks_sampled(ctx, name):
         _sync()
         res[prec] = (ci.triggers_to_numpy(peaks).copy(),
                      ci.triggers_to_numpy(trig, min(int(cnt.cpu()[0]), 1 << 16)).copy())
+    # the declared sample: 64 seeded random templates, every injection's
+    # template, and each path's winner of every injection's window; a
+    # winner's merged record is checked against the oracle at its sample
     rng = np.random.default_rng(777)
-    sample = sorted(set(i.tmpl for i in injs) |
-                    set(rng.choice(len(bank), 6, replace=False).tolist()))
+    inj_w = {inj.j0 // wl.window for inj in injs}
+    wrec = {}
+    for prec in (ci.FP32, ci.SPLIT_BF16):
+        for m in res[prec][1]:
+            if int(m["window"]) in inj_w:
+                wrec.setdefault(int(m["tmpl"]), []).append((prec, m))
+    assert sum(len(v) for v in wrec.values()) == 2 * len(inj_w)
+    sample = sorted(set(i.tmpl for i in injs) | set(wrec) |
+                    set(rng.choice(len(bank), 64, replace=False).tolist()))
     for i in sample:
         zo, _ = C.oracle_series(x128, psd, wl.n, wl.fs, wl.f_low, *bank[i])
         C.check_peak(res[ci.FP32][0][i], zo)
         C.check_peak(res[ci.SPLIT_BF16][0][i], zo, tol=TOL_SPLIT)
+        for prec, m in wrec.get(i, []):
+            tol = C.TOL_FP32 if prec == ci.FP32 else TOL_SPLIT
+            ro = abs(zo[int(m["index"])])
+            assert abs(np.sqrt(float(m["rho2"])) - ro) <= tol * ro, (prec, i, m)
+            # the winner's value is the window maximum of its own series
+            w = int(m["window"])
+            wmax = np.max(np.abs(zo[w * wl.window:(w + 1) * wl.window]))
+            assert ro >= wmax * (1 - 2 * tol), (prec, i, ro, wmax)
     # (an injection's own template need not peak at its coalescence sample:
     # in the 65536-template bank the SNR-8 injection's template responds more
     # strongly to the SNR-17 injection of nearly the same chirp mass; the

@@ -43,27 +43,55 @@ def _stream_data(n, segs, fs, fl, inj, seed):
     return x32, x32.astype(np.float64)
 
 
-def _compare_merged(G, segs_orc, thr):
+def _compare_merged(G, segs_orc, thr, specs, psds, n, fs, fl, bank, tol=TOL):
+    """Merged GPU triggers vs the oracle's, window by window.
+
+    Where both report a window, rho must agree within tol of the oracle's
+    rho.  Where the (template, sample) pair differs, the oracle series of
+    the GPU's template on the segment that owns that sample is evaluated at
+    the GPU's sample: the GPU's rho must match it within tol, and it must
+    tie the oracle winner's within 2 tol (two templates or two samples
+    whose values the tolerance cannot order).
+    A window reported by one side only must lie within tol of the
+    threshold."""
     om = {}
     for d in segs_orc:
         om.update(d)
     gm = {int(t["window"]): t for t in G}
     assert len(gm) == len(G), "one trigger per window"
-    thr2 = thr * thr
-    both = 0
+    bank = np.asarray(bank, dtype=np.float64)
+    series = {}
+
+    def orc_rho2(t, j):
+        # segment s owns global samples [s n/2 + n/4, s n/2 + 3n/4)
+        s = (j - n // 4) // (n // 2)
+        if (t, s) not in series:
+            series[(t, s)] = O.snr_series(specs[s], psds[s], n, fs, fl, *bank[t])[0]
+        return float(np.abs(series[(t, s)][j - s * (n // 2)]) ** 2)
+
+    both = ties = 0
     for w in set(gm) | set(om):
         if w in gm and w in om:
             g = gm[w]
             ot, oj, or2 = om[w]
-            assert abs(float(g["rho2"]) - or2) <= 2 * TOL * or2, (w, g, om[w])
-            if (int(g["tmpl"]), int(g["index"])) != (ot, oj):
-                # a tie within tolerance between templates or samples
-                print(f"window {w}: gpu ({int(g['tmpl'])}, {int(g['index'])}) vs "
-                      f"oracle ({ot}, {oj}), rho2 {float(g['rho2']):.6f} / {or2:.6f}")
+            ro = math.sqrt(or2)
+            assert abs(math.sqrt(float(g["rho2"])) - ro) <= tol * ro, (w, g, om[w])
+            gt, gj = int(g["tmpl"]), int(g["index"])
+            if (gt, gj) != (ot, oj):
+                # the GPU's value is the oracle's at the GPU's own pair ...
+                rg = math.sqrt(orc_rho2(gt, gj))
+                assert abs(math.sqrt(float(g["rho2"])) - rg) <= tol * rg, \
+                    (w, (gt, gj, rg), (ot, oj, ro))
+                # ... and that value ties the oracle winner's: two values
+                # each known to tol cannot be ordered when 2 tol apart
+                assert ro - rg <= 2 * tol * ro, (w, (gt, gj, rg), (ot, oj, ro))
+                ties += 1
             both += 1
         else:
             r2 = float(gm[w]["rho2"]) if w in gm else om[w][2]
-            assert abs(r2 - thr2) <= 2 * TOL * thr2, (w, r2)
+            assert abs(math.sqrt(r2) - thr) <= tol * thr, (w, r2)
+    if ties:
+        print(f"{ties} windows decided by a tie within tolerance")
     return both
 
 
@@ -103,8 +131,8 @@ def test_stream_triggers_match_oracle(ctx):
     G, done, flags = st.poll(wait=True)
     assert done == segs and flags == 0
     assert list(G["window"]) == sorted(G["window"])
-    orc, _, _ = SO.stream_search(x, n, fs, fl, bank, thr, W, h)
-    both = _compare_merged(G, orc, thr)
+    orc, psds, specs = SO.stream_search(x, n, fs, fl, bank, thr, W, h)
+    both = _compare_merged(G, orc, thr, specs, psds, n, fs, fl, bank)
     print(f"{len(G)} merged triggers, {both} windows compared")
     assert both >= 1
     # the injection: found once, by its template, at its global sample
@@ -155,8 +183,8 @@ def test_stream_cap_overflow_and_arguments(ctx):
     G2, _, _ = st.poll(wait=True)
     assert len(G2) == 2 and G2[0]["window"] > G[-1]["window"]
     st.close()
-    for kw in (dict(window=3000), dict(window=0), dict(psd_half_width=300),
-               dict(cap=0)):
+    for kw in (dict(window=3000), dict(window=0), dict(window=n // 2),
+               dict(psd_half_width=300), dict(cap=0)):
         args = dict(window=4096, psd_half_width=16, cap=16)
         args.update(kw)
         with pytest.raises(ci.CiError) as ei:
@@ -164,6 +192,31 @@ def test_stream_cap_overflow_and_arguments(ctx):
         assert ei.value.code == ci.EINVAL
     with pytest.raises(ci.CiError):
         ctx.stream([[3.0, 2.0]], 3 << 15, fs, fl, 6.0, 4096)
+
+
+def test_stream_largest_window(ctx):
+    """W = n/4, the largest window a stream accepts: every window lies in
+    one segment's valid region, so each is reported at most once, and the
+    merged records match the oracle's."""
+    n, fs, fl, h, thr = 1 << 16, 4096.0, 20.0, 16, 3.5
+    W = n // 4
+    segs = 5
+    x32, x = _stream_data(n, segs, fs, fl, (4.0, 3.0, 15.0, 2 * n + 777), 77)
+    bank = np.array([[4.0, 3.0], [3.0, 2.0], [6.0, 1.5]])
+    st = ctx.stream(bank, n, fs, fl, thr, W, psd_half_width=h)
+    st.push(x32)
+    G, done, flags = st.poll(wait=True)
+    assert done == segs and flags == 0
+    w = [int(v) for v in G["window"]]
+    assert w == sorted(set(w)), "one record per window"
+    for t in G:
+        s = (int(t["index"]) - n // 4) // (n // 2)
+        assert s * n // 2 + n // 4 <= int(t["index"]) < s * n // 2 + 3 * n // 4
+        assert int(t["window"]) == int(t["index"]) // W
+    orc, psds, specs = SO.stream_search(x, n, fs, fl, bank, thr, W, h)
+    both = _compare_merged(G, orc, thr, specs, psds, n, fs, fl, bank)
+    assert both >= segs - 1
+    st.close()
 
 
 @pytest.mark.parametrize("log2n", [17, 18, 19, 21])
@@ -218,7 +271,7 @@ def test_stream_psd_average_over_segments(ctx):
     x32, x = _stream_data(n, segs, fs, fl, None, 61)
     bank = np.array([[3.0, 2.0], [6.0, 1.5]])
     st = ctx.stream(bank, n, fs, fl, thr, W, psd_half_width=h, psd_segments=K)
-    orc, psds, _ = SO.stream_search(x, n, fs, fl, bank, thr, W, h, avg=K)
+    orc, psds, specs = SO.stream_search(x, n, fs, fl, bank, thr, W, h, avg=K)
     G = []
     for s in range(segs):
         lo = 0 if s == 0 else n + (s - 1) * n // 2
@@ -231,7 +284,7 @@ def test_stream_psd_average_over_segments(ctx):
     G, done, _ = st.poll(wait=True)
     assert done == segs
     print(f"{len(G)} merged triggers with a {K}-segment PSD")
-    _compare_merged(G, orc, thr)
+    _compare_merged(G, orc, thr, specs, psds, n, fs, fl, bank)
     st.close()
 
 
@@ -248,18 +301,8 @@ def test_stream_split_precision(ctx, prec):
     st.push(x32)
     G, done, _ = st.poll(wait=True)
     assert done == segs
-    orc, _, _ = SO.stream_search(x, n, fs, fl, bank, thr, W, h)
-    om = {}
-    for d in orc:
-        om.update(d)
-    gm = {int(t["window"]): t for t in G}
-    for w in set(gm) | set(om):
-        if w in gm and w in om:
-            assert abs(math.sqrt(float(gm[w]["rho2"])) - math.sqrt(om[w][2])) <= \
-                1e-3 * math.sqrt(om[w][2]), (w, gm[w], om[w])
-        else:
-            r2 = float(gm[w]["rho2"]) if w in gm else om[w][2]
-            assert abs(math.sqrt(r2) - thr) <= 1e-3 * thr, (w, r2)
+    orc, psds, specs = SO.stream_search(x, n, fs, fl, bank, thr, W, h)
+    _compare_merged(G, orc, thr, specs, psds, n, fs, fl, bank, tol=1e-3)
     hit = G[G["rho2"] > 15.0 ** 2]
     assert len(hit) == 1 and abs(int(hit[0]["index"]) - inj[3]) <= 1
     with pytest.raises(ci.CiError) as ei:

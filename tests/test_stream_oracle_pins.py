@@ -97,3 +97,46 @@ def test_stream_finds_injection_once_at_its_sample():
     assert s * n // 2 + n // 4 <= j < s * n // 2 + 3 * n // 4
     assert w == j // 4096
     assert abs(math.sqrt(r2) - snr) < 0.15 * snr
+
+
+def test_psd_average_covers_the_last_k_segments():
+    """The K-segment PSD average (Welch's average over time) of the stream
+    search, pinned by white noise whose power steps by a factor of 4 from
+    one half-segment block to the next.  For white noise of variance
+    sigma^2 c_j^2 the Hann periodogram is unbiased for the window-weighted
+    mean power: E P_k = (2 sigma^2 / fs) sum_j w_j^2 c_j^2 / sum_j w_j^2,
+    and the Hann window puts half of sum w^2 on each half of a segment, so
+    segment s (blocks s and s + 1) estimates (2 sigma^2 / fs) (c_s^2 +
+    c_{s+1}^2) / 2.  The PSD used for segment s must then be the mean of
+    those over segments max(0, s - K + 1) .. s: fewer at the stream start,
+    and never a later segment.  A window off by one segment, or a division
+    by K at the start, moves the figure by 25 % or more."""
+    n, fs, fl, h, K, segs = 1 << 16, 4096.0, 20.0, 8, 3, 6
+    half = n // 2
+    sigma = 1.5
+    rng = np.random.default_rng(2024)
+    blocks = segs + 1
+    c2 = 4.0 ** np.arange(blocks)
+    x = rng.standard_normal(blocks * half) * sigma * np.repeat(np.sqrt(c2), half)
+    bank = np.array([[3.0, 2.0]])
+    _, psds, _ = SO.stream_search(x, n, fs, fl, bank, 1e3, 4096, h, avg=K)
+    assert len(psds) == segs
+    kl = int(math.ceil(fl * n / fs))
+    white = 2.0 * sigma ** 2 / fs
+    own = (c2[:-1] + c2[1:]) / 2.0                      # segment s: blocks s, s + 1
+    for s in range(segs):
+        want = np.mean(own[max(0, s - K + 1):s + 1])
+        got = np.mean(psds[s][kl + h:half - 1 - h]) / white
+        assert abs(got / want - 1.0) < 0.04, (s, got, want)
+        # the alternatives a mistake in the window would give are far off
+        for alt in (np.mean(own[max(0, s - K):s + 1]),
+                    np.mean(own[max(0, s - K + 2):s + 1]),
+                    np.sum(own[max(0, s - K + 1):s + 1]) / K,
+                    np.mean(own[max(0, s - K + 1):min(s + 2, segs)])):
+            if abs(alt / want - 1.0) > 1e-9:
+                assert abs(got / alt - 1.0) > 0.15, (s, got, alt)
+    # K = 1 is each segment's own estimate
+    _, own_psds, _ = SO.stream_search(x[:n + half], n, fs, fl, bank, 1e3, 4096, h)
+    for s in range(2):
+        got = np.mean(own_psds[s][kl + h:half - 1 - h]) / white
+        assert abs(got / own[s] - 1.0) < 0.04, (s, got, own[s])
