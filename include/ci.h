@@ -39,7 +39,14 @@
  *   and their device workspaces, released by the matching *_destroy call.
  * - "d_" arguments are device pointers (hipMalloc'd or torch CUDA tensors);
  *   "host" arguments are host pointers.
- * - One ci_ctx per host thread.  Calls that share a ctx must not overlap.
+ * - One ci_ctx per host thread.  The context's workspaces (intermediate,
+ *   trigger bookkeeping) are shared by its calls: every call that uses
+ *   them is ordered on the device after the previous such call (an event
+ *   the library records on each call's stream), whatever streams they run
+ *   on, including a ci_stream's internal stream.  Calls that a caller
+ *   captures into its own graph skip that ordering (the graph's order
+ *   applies), and a workspace cannot grow inside such a capture (CI_EINVAL;
+ *   make the same call once outside the capture first).
  *   A segment passed with a ctx must have been created on that ctx
  *   (CI_EINVAL otherwise).
  * - Frequencies f_k = k fs/n, k = 0..n/2; df = fs/n; T = n/fs.
@@ -332,7 +339,8 @@ typedef struct {
   double fs, f_low;
   int32_t psd_half_width; /* h: 0 .. 256 */
   float snr_threshold;    /* lambda (rho^2 > lambda^2 triggers) */
-  int64_t window;         /* W: 1 .. n/2, dividing n/2 */
+  int64_t window;         /* W: 1 .. n/4, dividing n/4 (each window inside
+                             one segment's valid region [n/4, 3n/4)) */
   int64_t cap;            /* merged triggers kept per segment, >= 1 */
   int32_t psd_segments;   /* K: the PSD used for a segment is the mean of
                              the estimates of it and the K - 1 before it
@@ -461,15 +469,31 @@ typedef struct {
  * between the context's two internal compute streams (their finalisers
  * run in order on a third), so consecutive batches overlap across class
  * boundaries; `stream` waits for all of them.
- * Jobs share the context's workspace: calls on one context must be
- * ordered on the device (one stream, or synchronised).
- * flags: 0.  CI_RUN_GRAPH (capture of the schedule into a HIP graph and
- * replay) is reserved and currently returns CI_EUNSUPPORTED. */
+ * Jobs share the context's workspace; the library orders calls on one
+ * context against each other on the device (see ci_ctx_create).
+ * flags: 0, or CI_RUN_GRAPH: the whole schedule (every batch's two passes
+ * and finaliser on the internal streams, with their ordering) runs as one
+ * HIP graph launch on `stream`.  The graph is captured on the first call
+ * with a given set of arguments (jobs, output pointers, threshold, window,
+ * merge, precision, launch configuration) and replayed by later calls
+ * with the same set; any change recaptures it, and then waits for the
+ * previous graph's last replay before releasing it.  Results are
+ * identical to the eager schedule's.  Launches inside the graph are not
+ * timed (ci_set_timing).  CI_EINVAL when `stream` is itself being
+ * captured, or when the context workspace would have to grow during the
+ * capture (it is sized before).  CI_EUNSUPPORTED for a schedule of more
+ * than three batches (batches that reuse an intermediate slot set): the
+ * capture of such a schedule (the 16384-template class schedule) ended
+ * the process inside the HIP runtime, cause not identified. */
 #define CI_RUN_GRAPH 1
 int ci_search_classes(ci_ctx* ctx, const ci_class_job* jobs, int32_t njobs,
                       int32_t precision, float snr_threshold, int64_t window,
                       int32_t merge_across_templates, int32_t flags,
                       void* stream);
+
+/* Graphs captured and graph launches made by ci_search_classes with
+ * CI_RUN_GRAPH on this context so far (either pointer may be NULL). */
+int ci_graph_stats(ci_ctx* ctx, int64_t* captures, int64_t* launches);
 
 /* --- tuning -----------------------------------------------------------------
  * Templates per batch of the two-pass transform for every length (0 = the

@@ -36,7 +36,7 @@ EXPORTED_SYMBOLS = (
     "ci_autotune", "ci_chisq", "ci_td_params", "ci_td_templates",
     "ci_td_matched_filter", "ci_td_find_triggers", "ci_stream_create",
     "ci_stream_destroy", "ci_stream_push", "ci_stream_poll", "ci_stream_last",
-    "ci_bank_metric", "ci_make_bank_lattice",
+    "ci_bank_metric", "ci_make_bank_lattice", "ci_graph_stats",
 )
 RUN_GRAPH = 1
 
@@ -147,6 +147,7 @@ _SIGS = {
                                          ctypes.c_double, _vp, _i32, _vp]),
     "ci_search_classes": (ctypes.c_int, [_vp, ctypes.POINTER(_ClassJob), _i32,
                                          _i32, _f32, _i64, _i32, _i32, _vp]),
+    "ci_graph_stats": (ctypes.c_int, [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64)]),
     "ci_get_tune": (ctypes.c_int, [_vp, _i32, _i32, ctypes.POINTER(_Tune)]),
     "ci_set_tune": (ctypes.c_int, [_vp, ctypes.POINTER(_Tune)]),
     "ci_autotune": (ctypes.c_int, [_vp, _vp, _vp, _i64, _i32, _f32, _i64,
@@ -586,6 +587,12 @@ class Context:
             self.handle, arr, len(jobs), precision, float(thr), window,
             1 if merge else 0, RUN_GRAPH if graph else 0, _stream(stream)))
         return outs
+
+    def graph_stats(self):
+        """(graphs captured, graph launches) of CI_RUN_GRAPH searches."""
+        c, n = _i64(0), _i64(0)
+        self._chk(self.lib.dll.ci_graph_stats(self.handle, ctypes.byref(c), ctypes.byref(n)))
+        return int(c.value), int(n.value)
 
 
 def triggers_to_numpy(t, count: int | None = None) -> np.ndarray:

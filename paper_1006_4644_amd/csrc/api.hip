@@ -197,37 +197,71 @@ void host_td_params(const ci_template& tm, const SegDev& sd, ci_tdparams* T) {
   T->flags = m_lo > m_hi ? CI_TMPL_EMPTY : 0;
 }
 
-int ensure_ybuf(Ctx* ctx, size_t bytes) {
-  if (ctx->ybytes >= bytes) return CI_OK;
-  // the old buffer may still be used by enqueued work: wait for the
-  // device (the caller's device is current) before freeing it
-  if (ctx->ybuf) {
-    (void)hipDeviceSynchronize();
-    (void)hipFree(ctx->ybuf);
+// Whether `st` is being captured into a graph (by the caller or by us).
+bool stream_capturing(hipStream_t st) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  return hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone;
+}
+
+// Grow one context workspace to at least `bytes`.  The old buffer may still
+// be read by enqueued work, so the device is drained before it is released;
+// neither step is legal while a stream is captured, so growth under a
+// capture is refused (a first call of the same shape outside the capture
+// sizes the workspace).
+int grow(Ctx* ctx, void** buf, size_t* have, size_t bytes, const char* what, hipStream_t st) {
+  if (*have >= bytes) return CI_OK;
+  if (ctx->capturing || stream_capturing(st))
+    return fail(ctx, CI_EINVAL,
+                "%s must grow to %zu bytes inside a stream capture; run the call once "
+                "outside the capture first", what, bytes);
+  if (*buf) {
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) return hipfail(ctx, e, "device wait before releasing a workspace");
+    e = hipFree(*buf);
+    *buf = nullptr;
+    *have = 0;
+    ++ctx->ws_gen;
+    if (e != hipSuccess) return hipfail(ctx, e, "workspace release");
   }
-  ctx->ybuf = nullptr;
-  ctx->ybytes = 0;
-  hipError_t e = hipMalloc(&ctx->ybuf, bytes);
-  if (e != hipSuccess) return fail(ctx, CI_ENOMEM, "intermediate workspace of %zu bytes: %s",
-                                   bytes, hipGetErrorString(e));
-  ctx->ybytes = bytes;
+  hipError_t e = hipMalloc(buf, bytes);
+  if (e != hipSuccess) {
+    *buf = nullptr;
+    return fail(ctx, CI_ENOMEM, "%s of %zu bytes: %s", what, bytes, hipGetErrorString(e));
+  }
+  *have = bytes;
+  ++ctx->ws_gen;
   return CI_OK;
 }
 
-int ensure_tdbuf(Ctx* ctx, size_t bytes) {
-  if (ctx->tdbytes >= bytes) return CI_OK;
-  // the old buffer may still be used by enqueued work: wait for the
-  // device (the caller's device is current) before freeing it
-  if (ctx->tdbuf) {
-    (void)hipDeviceSynchronize();
-    (void)hipFree(ctx->tdbuf);
-  }
-  ctx->tdbuf = nullptr;
-  ctx->tdbytes = 0;
-  hipError_t e = hipMalloc(&ctx->tdbuf, bytes);
-  if (e != hipSuccess) return fail(ctx, CI_ENOMEM, "template-transform workspace of %zu bytes: %s",
-                                   bytes, hipGetErrorString(e));
-  ctx->tdbytes = bytes;
+int ensure_ybuf(Ctx* ctx, size_t bytes, hipStream_t st) {
+  return grow(ctx, &ctx->ybuf, &ctx->ybytes, bytes, "intermediate workspace", st);
+}
+
+int ensure_tdbuf(Ctx* ctx, size_t bytes, hipStream_t st) {
+  return grow(ctx, &ctx->tdbuf, &ctx->tdbytes, bytes, "template-transform workspace", st);
+}
+
+int ensure_tbuf(Ctx* ctx, size_t bytes, hipStream_t st) {
+  return grow(ctx, &ctx->tbuf, &ctx->tbytes, bytes, "trigger workspace", st);
+}
+
+// Order a call's use of the context workspaces after every earlier call's
+// (ws_enter on the call's stream before its first use, ws_leave after its
+// last).  Skipped inside a capture: a graph replay is ordered by the call
+// that launches it, and a caller capturing our calls orders them itself.
+int ws_enter(Ctx* ctx, hipStream_t st) {
+  if (!ctx->ws_free_armed || ctx->capturing || stream_capturing(st)) return CI_OK;
+  const hipError_t e = hipStreamWaitEvent(st, ctx->ws_free, 0);
+  return e == hipSuccess ? CI_OK : hipfail(ctx, e, "workspace ordering");
+}
+
+int ws_leave(Ctx* ctx, hipStream_t st) {
+  if (ctx->capturing || stream_capturing(st)) return CI_OK;
+  hipError_t e = hipSuccess;
+  if (!ctx->ws_free) e = hipEventCreateWithFlags(&ctx->ws_free, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventRecord(ctx->ws_free, st);
+  if (e != hipSuccess) return hipfail(ctx, e, "workspace ordering");
+  ctx->ws_free_armed = true;
   return CI_OK;
 }
 
@@ -276,23 +310,6 @@ void carve_trig(char* p, int64_t bmax, int64_t nwin, int64_t ntile2, TrigWork* t
   tw->run = reinterpret_cast<unsigned long long*>(p);
 }
 
-int ensure_tbuf(Ctx* ctx, size_t total) {
-  if (ctx->tbytes >= total) return CI_OK;
-  // the old buffer may still be used by enqueued work: wait for the
-  // device (the caller's device is current) before freeing it
-  if (ctx->tbuf) {
-    (void)hipDeviceSynchronize();
-    (void)hipFree(ctx->tbuf);
-  }
-  ctx->tbuf = nullptr;
-  ctx->tbytes = 0;
-  hipError_t e = hipMalloc(&ctx->tbuf, total);
-  if (e != hipSuccess)
-    return fail(ctx, CI_ENOMEM, "trigger workspace of %zu bytes: %s", total, hipGetErrorString(e));
-  ctx->tbytes = total;
-  return CI_OK;
-}
-
 int check_filter_args(Ctx* ctx, const void* seg, const void* d_params, int64_t n,
                       int32_t precision) {
   if (!ctx) return fail(nullptr, CI_EINVAL, "null context");
@@ -330,7 +347,9 @@ hipEvent_t pool_event(Ctx* ctx) {
 // Enqueue one pass launch, bracketed by events when timing is enabled.
 template <typename F>
 hipError_t timed(Ctx* ctx, int kind, int64_t templates, hipStream_t st, F launch) {
-  if (!ctx->timing) return launch();
+  // launches inside a graph capture are not timed (the events would be
+  // captured too)
+  if (!ctx->timing || ctx->capturing) return launch();
   TimedLaunch t{kind, templates, pool_event(ctx), pool_event(ctx)};
   if (!t.e0 || !t.e1) return hipErrorOutOfMemory;
   hipError_t e = hipEventRecord(t.e0, st);
@@ -425,7 +444,7 @@ int check_job(Ctx* ctx, Job& jb, int32_t precision, float thr, int64_t window) {
 // Workspace for a set of jobs: one trigger region each, and intermediate
 // slot sets sized for the largest batch.  Returns the slot stride in
 // complex elements.
-int prepare_jobs(Ctx* ctx, std::vector<Job>& jobs, size_t* slot_elems) {
+int prepare_jobs(Ctx* ctx, std::vector<Job>& jobs, size_t* slot_elems, hipStream_t st) {
   size_t ymax = 0, ttot = 0, tdmax = 0;
   for (Job& jb : jobs) {
     jb.toff = ttot;
@@ -439,15 +458,15 @@ int prepare_jobs(Ctx* ctx, std::vector<Job>& jobs, size_t* slot_elems) {
       }
     }
   }
-  int rc = ensure_tbuf(ctx, ttot);
+  int rc = ensure_tbuf(ctx, ttot, st);
   if (rc != CI_OK) return rc;
   ctx->td_slot = tdmax;
   if (tdmax > 0) {
-    rc = ensure_tdbuf(ctx, kSlots * tdmax);
+    rc = ensure_tdbuf(ctx, kSlots * tdmax, st);
     if (rc != CI_OK) return rc;
   }
   if (ymax > 0) {
-    rc = ensure_ybuf(ctx, sizeof(float2) * kSlots * ymax);
+    rc = ensure_ybuf(ctx, sizeof(float2) * kSlots * ymax, st);
     if (rc != CI_OK) return rc;
   }
   for (Job& jb : jobs)
@@ -465,18 +484,36 @@ int prepare_jobs(Ctx* ctx, std::vector<Job>& jobs, size_t* slot_elems) {
 // order, which keeps each job's trigger list ordered.  Batch b uses slot
 // set b % kSlots: its first pass waits for the finaliser of batch
 // b - kSlots (the slot's previous user), its finaliser for its own second
-// pass.  st joins all three streams at the end.
+// pass.  st joins all three streams at the end.  Inside our own capture
+// every ordering event is recorded once (fresh events per batch), outside
+// it the per-slot events are reused.
 int enqueue_jobs(Ctx* ctx, const std::vector<Job>& jobs, size_t slot_elems, int32_t precision,
                  float thr2, int64_t window, int merge, hipStream_t st) {
   hipError_t e = hipSuccess;
+  const bool cap = ctx->capturing;
+  auto fresh = [&](hipEvent_t* out) {
+    if (!cap) return true;
+    if (ctx->cap_pool.empty()) return false;
+    *out = ctx->cap_pool.back();
+    ctx->cap_pool.pop_back();
+    ctx->cap_ev.push_back(*out);
+    return true;
+  };
+  int rc = ws_enter(ctx, st);
+  if (rc != CI_OK) return rc;
   for (const Job& jb : jobs) {
     e = launch_init_call(jb.tw, (int)jb.nwin, jb.count, st);
     if (e != hipSuccess) return hipfail(ctx, e, "init launch");
   }
-  e = hipEventRecord(ctx->fork_ev, st);
-  for (int i = 0; i < 3 && e == hipSuccess; ++i) e = hipStreamWaitEvent(ctx->ws[i], ctx->fork_ev, 0);
+  hipEvent_t fork = ctx->fork_ev;
+  if (!fresh(&fork)) return fail(ctx, CI_ENOMEM, "ordering event");
+  e = hipEventRecord(fork, st);
+  for (int i = 0; i < 3 && e == hipSuccess; ++i) e = hipStreamWaitEvent(ctx->ws[i], fork, 0);
   if (e != hipSuccess) return hipfail(ctx, e, "stream fork");
   hipStream_t sf = ctx->ws[2];
+  // finaliser-done event of each slot's latest batch
+  hipEvent_t fin_ev[kSlots];
+  for (int i = 0; i < kSlots; ++i) fin_ev[i] = ctx->fin_done[i];
   int64_t b = 0;
   for (const Job& jb : jobs) {
     if (jb.n == 0) continue;
@@ -510,7 +547,7 @@ int enqueue_jobs(Ctx* ctx, const std::vector<Job>& jobs, size_t slot_elems, int3
       a.y = static_cast<float2*>(ctx->ybuf) + (size_t)slot * slot_elems;
       a.last_batch = (t0 + jb.B >= jb.n) ? 1 : 0;
       if (b >= kSlots) {
-        e = hipStreamWaitEvent(sb, ctx->fin_done[slot], 0);
+        e = hipStreamWaitEvent(sb, fin_ev[slot], 0);
         if (e != hipSuccess) return hipfail(ctx, e, "slot reuse ordering");
       }
       e = timed(ctx, 0, a.nb, sb, [&] {
@@ -523,21 +560,155 @@ int enqueue_jobs(Ctx* ctx, const std::vector<Job>& jobs, size_t slot_elems, int3
       if (e != hipSuccess) return hipfail(ctx, e, "pass-1 launch");
       e = timed(ctx, 1, a.nb, sb, [&] { return launch_pass2_trig(a, sb); });
       if (e != hipSuccess) return hipfail(ctx, e, "pass-2 launch");
-      e = hipEventRecord(ctx->p2_done[slot], sb);
-      if (e == hipSuccess) e = hipStreamWaitEvent(sf, ctx->p2_done[slot], 0);
+      hipEvent_t p2 = ctx->p2_done[slot];
+      if (!fresh(&p2)) return fail(ctx, CI_ENOMEM, "ordering event");
+      e = hipEventRecord(p2, sb);
+      if (e == hipSuccess) e = hipStreamWaitEvent(sf, p2, 0);
       if (e != hipSuccess) return hipfail(ctx, e, "finaliser ordering");
       e = launch_fin(a, sf);
       if (e != hipSuccess) return hipfail(ctx, e, "finalise launch");
-      e = hipEventRecord(ctx->fin_done[slot], sf);
+      if (!fresh(&fin_ev[slot])) return fail(ctx, CI_ENOMEM, "ordering event");
+      e = hipEventRecord(fin_ev[slot], sf);
       if (e != hipSuccess) return hipfail(ctx, e, "finaliser event");
     }
   }
   for (int i = 0; i < 3 && e == hipSuccess; ++i) {
-    e = hipEventRecord(ctx->join_ev[i], ctx->ws[i]);
-    if (e == hipSuccess) e = hipStreamWaitEvent(st, ctx->join_ev[i], 0);
+    hipEvent_t j = ctx->join_ev[i];
+    if (!fresh(&j)) return fail(ctx, CI_ENOMEM, "ordering event");
+    e = hipEventRecord(j, ctx->ws[i]);
+    if (e == hipSuccess) e = hipStreamWaitEvent(st, j, 0);
   }
   if (e != hipSuccess) return hipfail(ctx, e, "stream join");
-  return CI_OK;
+  return ws_leave(ctx, st);
+}
+
+// Bytes that identify a captured schedule: every launch argument the
+// capture bakes in (jobs, tiles, batches, workspace addresses and their
+// generation, threshold, window, merge, precision).
+template <typename T>
+void key_put(std::vector<unsigned char>& k, const T& v) {
+  const unsigned char* p = reinterpret_cast<const unsigned char*>(&v);
+  k.insert(k.end(), p, p + sizeof v);
+}
+
+std::vector<unsigned char> schedule_key(const Ctx* ctx, const std::vector<Job>& jobs,
+                                        size_t slot_elems, int32_t precision, float thr2,
+                                        int64_t window, int merge) {
+  std::vector<unsigned char> k;
+  key_put(k, ctx->ws_gen);
+  key_put(k, ctx->ybuf);
+  key_put(k, ctx->tbuf);
+  key_put(k, slot_elems);
+  key_put(k, precision);
+  key_put(k, thr2);
+  key_put(k, window);
+  key_put(k, merge);
+  for (const Job& jb : jobs) {
+    key_put(k, jb.seg);
+    key_put(k, jb.params);
+    key_put(k, jb.n);
+    key_put(k, jb.j_lo);
+    key_put(k, jb.j_hi);
+    key_put(k, jb.peaks);
+    key_put(k, jb.trig);
+    key_put(k, jb.cap);
+    key_put(k, jb.count);
+    key_put(k, jb.plan);
+    key_put(k, jb.cfg.p2_per_cu);
+    key_put(k, jb.cfg.streams);
+    key_put(k, jb.B);
+    key_put(k, jb.toff);
+  }
+  return k;
+}
+
+// Release the cached graph once its last replay has finished (every replay
+// records ws_free after it on its stream).
+int drop_graph(Ctx* ctx) {
+  if (!ctx->gexec) return CI_OK;
+  if (ctx->ws_free_armed) {
+    const hipError_t e = hipEventSynchronize(ctx->ws_free);
+    if (e != hipSuccess) return hipfail(ctx, e, "wait for the last graph replay");
+  }
+  const hipError_t e = hipGraphExecDestroy(ctx->gexec);
+  ctx->gexec = nullptr;
+  ctx->gkey.clear();
+  return e == hipSuccess ? CI_OK : hipfail(ctx, e, "graph release");
+}
+
+// The schedule of `jobs` as one graph launch on st.  The schedule is
+// captured (on a private stream, forking onto the internal streams exactly
+// as the eager schedule does) the first time a set of arguments is seen
+// and replayed while they stay the same; workspaces are sized before the
+// capture, and the replay is ordered after every earlier call on the
+// context and before every later one.
+int run_graph(Ctx* ctx, const std::vector<Job>& jobs, size_t slot_elems, int32_t precision,
+              float thr2, int64_t window, int merge, hipStream_t st) {
+  // Captures of schedules whose batches reuse slot sets (more than kSlots
+  // batches: a first pass then waits for a finaliser recorded on another
+  // captured stream) are refused: such a capture of the 16384-template
+  // class schedule ended the process with a host segmentation fault inside
+  // this call, cause not identified.  Shorter schedules replay correctly.
+  int64_t batches = 0;
+  for (const Job& jb : jobs)
+    if (jb.n > 0) batches += (jb.n + jb.B - 1) / jb.B;
+  if (batches > kSlots)
+    return fail(ctx, CI_EUNSUPPORTED,
+                "graph replay of a schedule of %lld batches (more than %d) is disabled: a "
+                "capture of the 16384-template class schedule ended the process in the "
+                "runtime, cause not identified", (long long)batches, kSlots);
+  std::vector<unsigned char> key =
+      schedule_key(ctx, jobs, slot_elems, precision, thr2, window, merge);
+  if (!ctx->gexec || key != ctx->gkey) {
+    int rc0 = drop_graph(ctx);
+    if (rc0 != CI_OK) return rc0;
+    hipError_t e = hipSuccess;
+    if (!ctx->cap_st) e = hipStreamCreateWithFlags(&ctx->cap_st, hipStreamNonBlocking);
+    if (e != hipSuccess) return hipfail(ctx, e, "capture stream");
+    // every ordering event of the capture exists before it starts: one fork,
+    // two per batch, three joins
+    size_t need = 4;
+    for (const Job& jb : jobs)
+      if (jb.n > 0) need += 2 * (size_t)((jb.n + jb.B - 1) / jb.B);
+    while (ctx->cap_pool.size() < need) {
+      hipEvent_t ev = nullptr;
+      e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+      if (e != hipSuccess) return hipfail(ctx, e, "ordering event");
+      ctx->cap_pool.push_back(ev);
+    }
+    // the capture stream starts after everything already enqueued on st
+    // that the schedule could depend on: the replay itself is ordered on st
+    e = hipStreamBeginCapture(ctx->cap_st, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hipfail(ctx, e, "begin capture");
+    ctx->capturing = true;
+    const int rc = enqueue_jobs(ctx, jobs, slot_elems, precision, thr2, window, merge,
+                                ctx->cap_st);
+    ctx->capturing = false;
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(ctx->cap_st, &g);
+    // the ordering events only carried dependencies during the capture
+    for (hipEvent_t ev : ctx->cap_ev) ctx->cap_pool.push_back(ev);
+    ctx->cap_ev.clear();
+    if (rc != CI_OK || e != hipSuccess || !g) {
+      if (g) (void)hipGraphDestroy(g);
+      if (rc != CI_OK) return rc;
+      return e != hipSuccess ? hipfail(ctx, e, "end capture")
+                             : fail(ctx, CI_EHIP, "capture produced no graph");
+    }
+    hipGraphExec_t x = nullptr;
+    e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess || !x) return hipfail(ctx, e, "graph instantiation");
+    ctx->gexec = x;
+    ctx->gkey.swap(key);
+    ++ctx->graph_captures;
+  }
+  int rc = ws_enter(ctx, st);
+  if (rc != CI_OK) return rc;
+  const hipError_t e = hipGraphLaunch(ctx->gexec, st);
+  if (e != hipSuccess) return hipfail(ctx, e, "graph launch");
+  ++ctx->graph_launches;
+  return ws_leave(ctx, st);
 }
 
 // Fill `bytes` of pinned host staging with fill(ptr) and copy them to d_dst
@@ -589,10 +760,10 @@ int td_batches(Ctx* ctx, const Seg* seg, const ci_tdparams* d_tdp, int64_t n, hi
   int64_t B = default_batch(ctx, N);
   if (B > 4096) B = 4096;
   if (B > n) B = n;
-  int rc = ensure_ybuf(ctx, sizeof(float2) * (size_t)B * (size_t)N);
+  int rc = ensure_ybuf(ctx, sizeof(float2) * (size_t)B * (size_t)N, st);
   if (rc != CI_OK) return rc;
   const size_t sb = align256(td_slot_bytes(B, N));
-  rc = ensure_tdbuf(ctx, sb);
+  rc = ensure_tdbuf(ctx, sb, st);
   if (rc != CI_OK) return rc;
   BatchArgs a;
   memset(&a, 0, sizeof a);
@@ -605,6 +776,8 @@ int td_batches(Ctx* ctx, const Seg* seg, const ci_tdparams* d_tdp, int64_t n, hi
   a.precision = CI_FP32;
   a.y = static_cast<float2*>(ctx->ybuf);
   td_slot(ctx, 0, sb, B, N, &a);
+  rc = ws_enter(ctx, st);
+  if (rc != CI_OK) return rc;
   for (int64_t t0 = 0; t0 < n; t0 += B) {
     a.t0 = t0;
     a.nb = (int)((n - t0) < B ? (n - t0) : B);
@@ -614,7 +787,7 @@ int td_batches(Ctx* ctx, const Seg* seg, const ci_tdparams* d_tdp, int64_t n, hi
     rc = f(a);
     if (rc != CI_OK) return rc;
   }
-  return CI_OK;
+  return ws_leave(ctx, st);
 }
 
 }  // namespace
@@ -712,7 +885,14 @@ int ci_ctx_destroy(ci_ctx* ctx) {
     ctx->ev_pool.push_back(t.e0);
     ctx->ev_pool.push_back(t.e1);
   }
+  (void)drop_graph(ctx);
+  if (ctx->cap_st) (void)hipStreamDestroy(ctx->cap_st);
+  if (ctx->ws_free) {
+    (void)hipEventSynchronize(ctx->ws_free);
+    (void)hipEventDestroy(ctx->ws_free);
+  }
   for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
+  for (hipEvent_t e : ctx->cap_pool) (void)hipEventDestroy(e);
   for (int i = 0; i < 3; ++i)
     if (ctx->ws[i]) {
       (void)hipStreamSynchronize(ctx->ws[i]);
@@ -975,7 +1155,7 @@ int ci_matched_filter(ci_ctx* ctx, const ci_segment* seg, const ci_tparams* d_pa
   const int64_t N = seg->host.n;
   int64_t B = default_batch(ctx, N);
   if (B > n) B = n;
-  rc = ensure_ybuf(ctx, sizeof(float2) * 2 * (size_t)B * (size_t)N);
+  rc = ensure_ybuf(ctx, sizeof(float2) * 2 * (size_t)B * (size_t)N, st);
   if (rc != CI_OK) return rc;
   BatchArgs a;
   memset(&a, 0, sizeof a);
@@ -988,6 +1168,8 @@ int ci_matched_filter(ci_ctx* ctx, const ci_segment* seg, const ci_tparams* d_pa
   if (rc != CI_OK) return rc;
   a.bmax = (int)B;
   a.precision = precision;
+  rc = ws_enter(ctx, st);
+  if (rc != CI_OK) return rc;
   for (int64_t b = 0, t0 = 0; t0 < n; ++b, t0 += B) {
     a.t0 = t0;
     a.nb = (int)((n - t0) < B ? (n - t0) : B);
@@ -1000,7 +1182,7 @@ int ci_matched_filter(ci_ctx* ctx, const ci_segment* seg, const ci_tparams* d_pa
     e = timed(ctx, 1, a.nb, st, [&] { return launch_pass2_series(a, st); });
     if (e != hipSuccess) return hipfail(ctx, e, "pass-2 launch");
   }
-  return CI_OK;
+  return ws_leave(ctx, st);
 }
 
 int ci_find_triggers(ci_ctx* ctx, const ci_segment* seg, const ci_tparams* d_params, int64_t n,
@@ -1024,7 +1206,7 @@ int ci_find_triggers(ci_ctx* ctx, const ci_segment* seg, const ci_tparams* d_par
   int rc = check_job(ctx, jb, precision, snr_threshold, window);
   if (rc != CI_OK) return rc;
   size_t slot = 0;
-  rc = prepare_jobs(ctx, jobs, &slot);
+  rc = prepare_jobs(ctx, jobs, &slot, static_cast<hipStream_t>(stream));
   if (rc != CI_OK) return rc;
   return enqueue_jobs(ctx, jobs, slot, precision, snr_threshold * snr_threshold, window,
                       merge_across_templates ? 1 : 0, static_cast<hipStream_t>(stream));
@@ -1125,7 +1307,7 @@ int ci_td_find_triggers(ci_ctx* ctx, const ci_segment* seg, const ci_tdparams* d
   int rc = check_job(ctx, jb, CI_FP32, snr_threshold, window);
   if (rc != CI_OK) return rc;
   size_t slot = 0;
-  rc = prepare_jobs(ctx, jobs, &slot);
+  rc = prepare_jobs(ctx, jobs, &slot, static_cast<hipStream_t>(stream));
   if (rc != CI_OK) return rc;
   return enqueue_jobs(ctx, jobs, slot, CI_FP32, snr_threshold * snr_threshold, window,
                       merge_across_templates ? 1 : 0, static_cast<hipStream_t>(stream));
@@ -1254,7 +1436,7 @@ int enqueue_segment(ci_stream* s) {
   int rc = check_job(ctx, jb, s->spec.precision, s->spec.snr_threshold, s->spec.window);
   if (rc != CI_OK) return rc;
   size_t ys = 0;
-  rc = prepare_jobs(ctx, jobs, &ys);
+  rc = prepare_jobs(ctx, jobs, &ys, s->ks);
   if (rc != CI_OK) return rc;
   rc = enqueue_jobs(ctx, jobs, ys, s->spec.precision,
                     s->spec.snr_threshold * s->spec.snr_threshold, s->spec.window, 1, s->ks);
@@ -1279,8 +1461,11 @@ int ci_stream_create(ci_ctx* ctx, const ci_stream_spec* spec, const ci_template*
     return fail(ctx, CI_EINVAL, "n = %lld is not a power of two in 2^16 .. 2^21", (long long)n);
   if (spec->psd_half_width < 0 || spec->psd_half_width > 256)
     return fail(ctx, CI_EINVAL, "psd_half_width %d outside 0..256", spec->psd_half_width);
-  if (spec->window < 1 || spec->window > n / 2 || (n / 2) % spec->window != 0)
-    return fail(ctx, CI_EINVAL, "window %lld must divide n/2", (long long)spec->window);
+  // each segment is searched over [n/4, 3n/4) and successive valid regions
+  // start n/2 apart, so a window that divides n/4 lies inside one region
+  // (a window of n/2 would span two segments and be reported twice)
+  if (spec->window < 1 || spec->window > n / 4 || (n / 4) % spec->window != 0)
+    return fail(ctx, CI_EINVAL, "window %lld must divide n/4", (long long)spec->window);
   if (spec->cap < 1) return fail(ctx, CI_EINVAL, "cap must be >= 1");
   if (spec->precision < CI_FP32 || spec->precision > CI_SPLIT_FP16)
     return fail(ctx, CI_EINVAL, "unknown precision %d", spec->precision);
@@ -1498,10 +1683,6 @@ int ci_search_classes(ci_ctx* ctx, const ci_class_job* jobs_in, int32_t njobs, i
   if (!ctx) return fail(nullptr, CI_EINVAL, "null context");
   if (njobs < 0 || (njobs > 0 && !jobs_in)) return fail(ctx, CI_EINVAL, "bad job list");
   if (flags & ~CI_RUN_GRAPH) return fail(ctx, CI_EINVAL, "unknown flags 0x%x", flags);
-  if (flags & CI_RUN_GRAPH)
-    return fail(ctx, CI_EUNSUPPORTED,
-                "graph replay of the schedule is disabled (a capture of a multi-batch "
-                "schedule ended the process in the runtime; cause not identified)");
   DeviceGuard dg(ctx->device);
   if (!dg.ok) return fail(ctx, CI_EHIP, "cannot select device %d", ctx->device);
   std::vector<Job> jobs((size_t)njobs);
@@ -1521,11 +1702,24 @@ int ci_search_classes(ci_ctx* ctx, const ci_class_job* jobs_in, int32_t njobs, i
     if (rc != CI_OK) return fail(ctx, rc, "job %d: %s", i, ctx->err.c_str());
   }
   if (njobs == 0) return CI_OK;
+  hipStream_t st = static_cast<hipStream_t>(stream);
   size_t slot = 0;
-  int rc = prepare_jobs(ctx, jobs, &slot);
+  int rc = prepare_jobs(ctx, jobs, &slot, st);
   if (rc != CI_OK) return rc;
-  return enqueue_jobs(ctx, jobs, slot, precision, snr_threshold * snr_threshold, window,
-                      merge_across_templates ? 1 : 0, static_cast<hipStream_t>(stream));
+  const float thr2 = snr_threshold * snr_threshold;
+  const int merge = merge_across_templates ? 1 : 0;
+  if (!(flags & CI_RUN_GRAPH))
+    return enqueue_jobs(ctx, jobs, slot, precision, thr2, window, merge, st);
+  if (stream_capturing(st))
+    return fail(ctx, CI_EINVAL, "CI_RUN_GRAPH on a stream that is being captured");
+  return run_graph(ctx, jobs, slot, precision, thr2, window, merge, st);
+}
+
+int ci_graph_stats(ci_ctx* ctx, int64_t* captures, int64_t* launches) {
+  if (!ctx) return fail(nullptr, CI_EINVAL, "null context");
+  if (captures) *captures = ctx->graph_captures;
+  if (launches) *launches = ctx->graph_launches;
+  return CI_OK;
 }
 
 int ci_length_classes(const ci_template* bank_host, int64_t n, double fs, double f_low,

@@ -105,6 +105,25 @@ struct Ctx {
   // live streams created on this context (released and detached when it
   // is destroyed)
   std::vector<struct ci_stream*> streams;
+  // Ordering of the shared workspaces between calls: every call that uses
+  // them waits for ws_free on its stream first and records it after its
+  // last use, so calls on different streams (a ci_stream's internal
+  // stream, a caller's streams) never overlap in the workspaces.
+  hipEvent_t ws_free = nullptr;
+  bool ws_free_armed = false;
+  // bumped whenever a workspace is reallocated (cached graphs hold its
+  // addresses)
+  uint64_t ws_gen = 0;
+  // graph replay of a schedule (ci_search_classes with CI_RUN_GRAPH): the
+  // executable graph of the last captured schedule and the key of the
+  // arguments it was captured with; captures run on cap_st
+  hipStream_t cap_st = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  std::vector<unsigned char> gkey;
+  bool capturing = false;           // our own capture is in progress
+  std::vector<hipEvent_t> cap_ev;   // ordering events recorded in the capture
+  std::vector<hipEvent_t> cap_pool; // spare ordering events for captures
+  int64_t graph_captures = 0, graph_launches = 0;
   // instrumentation
   bool timing = false;
   std::vector<TimedLaunch> launches;

@@ -107,21 +107,106 @@ def test_classes_match_per_class_calls(ctx, gpu_lib, merge):
         s["seg"].close()
 
 
-@pytest.mark.skip(reason="graph replay of the schedule is disabled: a graph-captured "
-                  "run of the 16384-template class schedule ended the process with a "
-                  "host segmentation fault inside the library call; cause not "
-                  "identified, the library returns CI_EUNSUPPORTED for CI_RUN_GRAPH")
-def test_classes_graph_replay(ctx, gpu_lib):
+def _fixed_outputs(jobs, cap):
+    import torch
+    out = []
+    for j in jobs:
+        dev = j["params"].device
+        out.append(dict(j, peaks=torch.empty((j["n"], 4), dtype=torch.int64, device=dev),
+                        trig=torch.empty((cap, 4), dtype=torch.int64, device=dev),
+                        count=torch.zeros(1, dtype=torch.int64, device=dev)))
+    return out
+
+
+def _poison(jobs):
+    for j in jobs:
+        j["peaks"].fill_(-7)
+        j["trig"].fill_(-7)
+        j["count"].fill_(-7)
+
+
+@pytest.mark.parametrize("merge", [False, True])
+def test_classes_graph_replay(ctx, gpu_lib, merge):
+    """CI_RUN_GRAPH: the schedule is captured once and replayed while its
+    arguments stay the same; every replay equals the eager schedule bit for
+    bit, with eager work on the same context and synchronisations in
+    between; new output buffers recapture it."""
     fs, fl, thr, W, cap = 4096.0, 20.0, 5.0, 4096, 4096
     classes = (1 << 16, 1 << 17, 1 << 18)
     bank = synth.draw_masses(40, 1.0, 12.0, "loguniform", 515)
     cls, setup = _class_setup(ctx, gpu_lib, bank, classes, fs, fl, 9100)
-    ref = _per_class(ctx, setup, thr, W, cap, False)
-    jobs = _jobs(setup, cap)
-    for rep in range(3):
-        _same(ref, _collect(ctx.search_classes(jobs, thr, W, graph=True), cap))
+    ref = _per_class(ctx, setup, thr, W, cap, merge)
+    jobs = _fixed_outputs(_jobs(setup, cap), cap)
+    c0, l0 = ctx.graph_stats()
+    for rep in range(4):
+        _poison(jobs)
+        outs = ctx.search_classes(jobs, thr, W, merge=merge, graph=True)
+        _same(ref, _collect(outs, cap))
+        # eager work on the context between replays (other tiles' workspace use)
+        ctx.find_triggers(jobs[0]["seg"], jobs[0]["params"], thr + 1.0, 1024, cap=8)
+        _sync()
+    c1, l1 = ctx.graph_stats()
+    assert (c1 - c0, l1 - l0) == (1, 4)
+    # new outputs: a new capture, same results
+    jobs2 = _fixed_outputs(_jobs(setup, cap), cap)
+    _same(ref, _collect(ctx.search_classes(jobs2, thr, W, merge=merge, graph=True), cap))
+    assert ctx.graph_stats() == (c1 + 1, l1 + 1)
+    # eager again into the first buffers after the replays
+    _poison(jobs)
+    _same(ref, _collect(ctx.search_classes(jobs, thr, W, merge=merge), cap))
+    # schedules whose batches reuse slot sets are not captured
+    ctx.set_batch(8)
+    try:
+        with pytest.raises(ci.CiError) as ei:
+            ctx.search_classes(jobs, thr, W, merge=merge, graph=True)
+        assert ei.value.code == ci.EUNSUPPORTED
+    finally:
+        ctx.set_batch(0)
     for s in setup:
         s["seg"].close()
+
+
+@pytest.mark.skip(reason="a stream capture of the 16384-template class schedule (59 batches "
+                  "over two forked compute streams and a finaliser stream, slot sets reused "
+                  "across streams) ended the process with a host segmentation fault inside "
+                  "ci_search_classes; cause not identified, so captures of schedules of more "
+                  "than kSlots batches return CI_EUNSUPPORTED")
+def test_classes_graph_replay_batched_workload(ctx, gpu_lib):
+    """The 16384-template uneven bank (log-uniform 1-30 Msun from 20 Hz, in
+    length classes 2^17..2^20, one noise segment per class, merged
+    triggers) as one graph launch: three replays, each bit-identical to the
+    eager schedule."""
+    import torch
+    wl = synth.WORKLOADS["batched-classes"]
+    bank = synth.draw_masses(wl.n_templates, wl.m_min, wl.m_max, wl.dist, wl.bank_seed)
+    classes = synth.CLASS_LENGTHS
+    cls = gpu_lib.length_classes(bank, wl.fs, wl.f_low, classes)
+    cap = 1 << 16
+    setup, jobs = [], []
+    for c, n in enumerate(classes):
+        idx = np.nonzero(cls == c)[0]
+        if len(idx) == 0:
+            continue
+        psd = synth.make_psd(n, wl.fs)
+        x = synth.make_noise(n, wl.fs, wl.f_low, psd, synth.class_noise_seed(wl, c))
+        seg = ctx.segment(_dev(x.astype(np.complex64)), _dev(psd), n, wl.fs, wl.f_low)
+        params = ctx.gen_templates(seg, bank[idx])
+        setup.append(seg)
+        jobs.append(dict(seg=seg, params=params, n=len(idx), cap=cap))
+    assert len(jobs) == 4 and sum(j["n"] for j in jobs) == wl.n_templates
+    eager = _fixed_outputs(jobs, cap)
+    ref = _collect(ctx.search_classes(eager, wl.snr_threshold, wl.window, merge=True), cap)
+    assert sum(r[2] for r in ref) > 0
+    g = _fixed_outputs(jobs, cap)
+    c0, l0 = ctx.graph_stats()
+    for rep in range(3):
+        _poison(g)
+        outs = ctx.search_classes(g, wl.snr_threshold, wl.window, merge=True, graph=True)
+        _same(ref, _collect(outs, cap))
+        torch.cuda.synchronize()
+    assert ctx.graph_stats() == (c0 + 1, l0 + 3)
+    for seg in setup:
+        seg.close()
 
 
 def test_classes_against_oracle(ctx, gpu_lib):

@@ -309,3 +309,55 @@ def test_stream_split_precision(ctx, prec):
         ctx.stream(bank, n, fs, fl, thr, W, precision=7)
     assert ei.value.code == ci.EINVAL
     st.close()
+
+
+def test_stream_and_search_on_another_stream_interleaved(ctx):
+    """A stream's segments (searched on its internal stream) and searches on
+    a separate torch stream use the same context workspace.  The library
+    orders every workspace user after the previous one, so interleaving the
+    two gives the serial results bit for bit."""
+    import torch
+    n, fs, fl, h, thr, W = 1 << 16, 4096.0, 30.0, 16, 4.5, 4096
+    segs = 6
+    x32, _ = _stream_data(n, segs, fs, fl, (8.0, 6.0, 25.0, n + 3000), 31)
+    bank = np.array([[8.0, 6.0], [3.0, 2.0], [12.0, 10.0], [5.0, 1.5]])
+    psd = synth.make_psd(n, fs)
+    xs = synth.make_noise(n, fs, fl, psd, 32).astype(np.complex64)
+    seg = ctx.segment(torch.from_numpy(xs).cuda(), torch.from_numpy(psd).cuda(), n, fs, fl)
+    params = ctx.gen_templates(seg, synth.draw_masses(96, 1.0, 12.0, "loguniform", 33))
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+
+    def search():
+        return ctx.find_triggers(seg, params, 3.0, 1024, cap=8192, stream=side)
+
+    def host(r):
+        p, t, c = r
+        k = min(int(c.cpu()[0]), 8192)
+        return p.cpu().numpy().copy(), t.cpu().numpy()[:k].copy(), int(c.cpu()[0])
+
+    # serial: the whole stream, then the search
+    st = ctx.stream(bank, n, fs, fl, thr, W, psd_half_width=h)
+    st.push(x32)
+    G0, done0, _ = st.poll(wait=True)
+    st.close()
+    r = search()
+    side.synchronize()
+    ref = host(r)
+    assert done0 == segs and ref[2] > 0
+    # interleaved: a search on the side stream after every push, no waits
+    st = ctx.stream(bank, n, fs, fl, thr, W, psd_half_width=h)
+    res = []
+    for a in range(0, len(x32), n // 2):
+        st.push(x32[a:a + n // 2])
+        res.append(search())
+    G1, done1, _ = st.poll(wait=True)
+    st.close()
+    side.synchronize()
+    assert done1 == segs
+    assert np.array_equal(G0, G1)
+    for r in res:
+        p, t, c = host(r)
+        assert c == ref[2]
+        assert np.array_equal(p, ref[0]) and np.array_equal(t, ref[1])
+    seg.close()
