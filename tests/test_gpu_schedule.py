@@ -154,12 +154,31 @@ def test_classes_graph_replay(ctx, gpu_lib, merge):
     # eager again into the first buffers after the replays
     _poison(jobs)
     _same(ref, _collect(ctx.search_classes(jobs, thr, W, merge=merge), cap))
-    # schedules whose batches reuse slot sets are not captured
+    for s in setup:
+        s["seg"].close()
+
+
+@pytest.mark.parametrize("merge", [False, True])
+def test_classes_graph_replay_many_batches(ctx, gpu_lib, merge):
+    """Batches of 8 templates: the schedule has more batches than slot sets,
+    so the graph reuses each slot set several times (one chain of kernel
+    nodes); three replays equal the eager schedule bit for bit."""
+    fs, fl, thr, W, cap = 4096.0, 20.0, 4.0, 2048, 4096
+    classes = (1 << 16, 1 << 17, 1 << 18)
+    bank = synth.draw_masses(48, 1.0, 12.0, "loguniform", 717)
+    cls, setup = _class_setup(ctx, gpu_lib, bank, classes, fs, fl, 9300)
     ctx.set_batch(8)
     try:
-        with pytest.raises(ci.CiError) as ei:
-            ctx.search_classes(jobs, thr, W, merge=merge, graph=True)
-        assert ei.value.code == ci.EUNSUPPORTED
+        ref = _per_class(ctx, setup, thr, W, cap, merge)
+        assert sum(r[2] for r in ref) > 0
+        jobs = _fixed_outputs(_jobs(setup, cap), cap)
+        assert sum((j["n"] + 7) // 8 for j in jobs) > 3
+        c0, l0 = ctx.graph_stats()
+        for rep in range(3):
+            _poison(jobs)
+            _same(ref, _collect(ctx.search_classes(jobs, thr, W, merge=merge, graph=True),
+                                cap))
+        assert ctx.graph_stats() == (c0 + 1, l0 + 3)
     finally:
         ctx.set_batch(0)
     for s in setup:
@@ -251,10 +270,21 @@ def test_empty_class_and_bad_jobs(ctx, gpu_lib):
     assert e.value.code == ci.EINVAL and "job 0" in str(e.value)
     with pytest.raises(ci.CiError):
         ctx.search_classes([dict(seg=seg, params=params, n=3)], 5.0, 0)
-    # graph replay is reserved: an error before any work is enqueued
-    with pytest.raises(ci.CiError) as e:
-        ctx.search_classes([dict(seg=seg, params=params, n=3)], 5.0, 4096, graph=True)
-    assert e.value.code == ci.EUNSUPPORTED
+    # unknown flags: an error before any work is enqueued
+    arr = (ci._ClassJob * 1)()
+    arr[0] = ci._ClassJob(seg.handle, ci._ptr(params), 3, 0, 0, ci._ptr(outs[1][0]),
+                          ci._ptr(outs[1][1]), 16, ci._ptr(outs[1][2]))
+    rc = ctx.lib.dll.ci_search_classes(ctx.handle, arr, 1, ci.FP32, 5.0, 4096, 0, 2,
+                                       ci._stream())
+    assert rc == ci.EINVAL
+    # an empty job inside a graph-replayed schedule
+    cnt.fill_(99)
+    g = ctx.search_classes([dict(seg=seg, params=params, n=0, count=cnt),
+                            dict(seg=seg, params=params, n=3)], 5.0, 4096, graph=True)
+    _sync()
+    assert int(cnt.cpu()[0]) == 0
+    assert np.array_equal(_np(g[1][0]), _np(outs[1][0]))
+    assert int(g[1][2].cpu()[0]) == int(outs[1][2].cpu()[0])
     seg.close()
 
 
