@@ -471,9 +471,11 @@ typedef struct {
  * boundaries; `stream` waits for all of them.
  * Jobs share the context's workspace; the library orders calls on one
  * context against each other on the device (see ci_ctx_create).
- * flags: 0, or CI_RUN_GRAPH: the whole schedule (every batch's two passes
- * and finaliser on the internal streams, with their ordering) runs as one
- * HIP graph launch on `stream`.  The graph is captured on the first call
+ * flags: 0, or CI_RUN_GRAPH: the whole schedule runs as one HIP graph
+ * launch on `stream`: a chain of kernel nodes (the calls' initialisation,
+ * then per batch its first pass, second pass and finaliser, in order; the
+ * eager schedule's overlap of consecutive batches on two streams is not
+ * kept).  The graph is captured on the first call
  * with a given set of arguments (jobs, output pointers, threshold, window,
  * merge, precision, launch configuration) and replayed by later calls
  * with the same set; any change recaptures it, and then waits for the
@@ -481,10 +483,7 @@ typedef struct {
  * identical to the eager schedule's.  Launches inside the graph are not
  * timed (ci_set_timing).  CI_EINVAL when `stream` is itself being
  * captured, or when the context workspace would have to grow during the
- * capture (it is sized before).  CI_EUNSUPPORTED for a schedule of more
- * than three batches (batches that reuse an intermediate slot set): the
- * capture of such a schedule (the 16384-template class schedule) ended
- * the process inside the HIP runtime, cause not identified. */
+ * capture (it is sized before). */
 #define CI_RUN_GRAPH 1
 int ci_search_classes(ci_ctx* ctx, const ci_class_job* jobs, int32_t njobs,
                       int32_t precision, float snr_threshold, int64_t window,

@@ -484,36 +484,29 @@ int prepare_jobs(Ctx* ctx, std::vector<Job>& jobs, size_t* slot_elems, hipStream
 // order, which keeps each job's trigger list ordered.  Batch b uses slot
 // set b % kSlots: its first pass waits for the finaliser of batch
 // b - kSlots (the slot's previous user), its finaliser for its own second
-// pass.  st joins all three streams at the end.  Inside our own capture
-// every ordering event is recorded once (fresh events per batch), outside
-// it the per-slot events are reused.
+// pass.  st joins all three streams at the end.
+// Inside our own graph capture every launch goes on st in order (first
+// pass, second pass, finaliser per batch): the graph is one chain of
+// kernel nodes with no event dependencies, and the stream order alone
+// keeps the slot sets apart.
 int enqueue_jobs(Ctx* ctx, const std::vector<Job>& jobs, size_t slot_elems, int32_t precision,
                  float thr2, int64_t window, int merge, hipStream_t st) {
   hipError_t e = hipSuccess;
-  const bool cap = ctx->capturing;
-  auto fresh = [&](hipEvent_t* out) {
-    if (!cap) return true;
-    if (ctx->cap_pool.empty()) return false;
-    *out = ctx->cap_pool.back();
-    ctx->cap_pool.pop_back();
-    ctx->cap_ev.push_back(*out);
-    return true;
-  };
+  const bool chain = ctx->capturing;
+  float2* ybase = static_cast<float2*>(ctx->ybuf);
   int rc = ws_enter(ctx, st);
   if (rc != CI_OK) return rc;
   for (const Job& jb : jobs) {
     e = launch_init_call(jb.tw, (int)jb.nwin, jb.count, st);
     if (e != hipSuccess) return hipfail(ctx, e, "init launch");
   }
-  hipEvent_t fork = ctx->fork_ev;
-  if (!fresh(&fork)) return fail(ctx, CI_ENOMEM, "ordering event");
-  e = hipEventRecord(fork, st);
-  for (int i = 0; i < 3 && e == hipSuccess; ++i) e = hipStreamWaitEvent(ctx->ws[i], fork, 0);
-  if (e != hipSuccess) return hipfail(ctx, e, "stream fork");
-  hipStream_t sf = ctx->ws[2];
-  // finaliser-done event of each slot's latest batch
-  hipEvent_t fin_ev[kSlots];
-  for (int i = 0; i < kSlots; ++i) fin_ev[i] = ctx->fin_done[i];
+  if (!chain) {
+    e = hipEventRecord(ctx->fork_ev, st);
+    for (int i = 0; i < 3 && e == hipSuccess; ++i)
+      e = hipStreamWaitEvent(ctx->ws[i], ctx->fork_ev, 0);
+    if (e != hipSuccess) return hipfail(ctx, e, "stream fork");
+  }
+  hipStream_t sf = chain ? st : ctx->ws[2];
   int64_t b = 0;
   for (const Job& jb : jobs) {
     if (jb.n == 0) continue;
@@ -536,7 +529,7 @@ int enqueue_jobs(Ctx* ctx, const std::vector<Job>& jobs, size_t slot_elems, int3
     a.precision = precision;
     a.p2_per_cu = jb.cfg.p2_per_cu;
     for (int64_t t0 = 0; t0 < jb.n; ++b, t0 += jb.B) {
-      hipStream_t sb = ctx->ws[jb.cfg.streams == 1 ? 0 : (b & 1)];
+      hipStream_t sb = chain ? st : ctx->ws[jb.cfg.streams == 1 ? 0 : (b & 1)];
       const int slot = (int)(b % kSlots);
       a.t0 = t0;
       a.nb = (int)((jb.n - t0) < jb.B ? (jb.n - t0) : jb.B);
@@ -544,10 +537,10 @@ int enqueue_jobs(Ctx* ctx, const std::vector<Job>& jobs, size_t slot_elems, int3
       a.params = jb.td ? nullptr : jb.params + t0;
       a.td = jb.td ? jb.td + t0 : nullptr;
       if (jb.td) td_slot(ctx, slot, ctx->td_slot, jb.B, jb.seg->host.n, &a);
-      a.y = static_cast<float2*>(ctx->ybuf) + (size_t)slot * slot_elems;
+      a.y = ybase + (size_t)slot * slot_elems;
       a.last_batch = (t0 + jb.B >= jb.n) ? 1 : 0;
-      if (b >= kSlots) {
-        e = hipStreamWaitEvent(sb, fin_ev[slot], 0);
+      if (!chain && b >= kSlots) {
+        e = hipStreamWaitEvent(sb, ctx->fin_done[slot], 0);
         if (e != hipSuccess) return hipfail(ctx, e, "slot reuse ordering");
       }
       e = timed(ctx, 0, a.nb, sb, [&] {
@@ -560,25 +553,26 @@ int enqueue_jobs(Ctx* ctx, const std::vector<Job>& jobs, size_t slot_elems, int3
       if (e != hipSuccess) return hipfail(ctx, e, "pass-1 launch");
       e = timed(ctx, 1, a.nb, sb, [&] { return launch_pass2_trig(a, sb); });
       if (e != hipSuccess) return hipfail(ctx, e, "pass-2 launch");
-      hipEvent_t p2 = ctx->p2_done[slot];
-      if (!fresh(&p2)) return fail(ctx, CI_ENOMEM, "ordering event");
-      e = hipEventRecord(p2, sb);
-      if (e == hipSuccess) e = hipStreamWaitEvent(sf, p2, 0);
-      if (e != hipSuccess) return hipfail(ctx, e, "finaliser ordering");
+      if (!chain) {
+        e = hipEventRecord(ctx->p2_done[slot], sb);
+        if (e == hipSuccess) e = hipStreamWaitEvent(sf, ctx->p2_done[slot], 0);
+        if (e != hipSuccess) return hipfail(ctx, e, "finaliser ordering");
+      }
       e = launch_fin(a, sf);
       if (e != hipSuccess) return hipfail(ctx, e, "finalise launch");
-      if (!fresh(&fin_ev[slot])) return fail(ctx, CI_ENOMEM, "ordering event");
-      e = hipEventRecord(fin_ev[slot], sf);
-      if (e != hipSuccess) return hipfail(ctx, e, "finaliser event");
+      if (!chain) {
+        e = hipEventRecord(ctx->fin_done[slot], sf);
+        if (e != hipSuccess) return hipfail(ctx, e, "finaliser event");
+      }
     }
   }
-  for (int i = 0; i < 3 && e == hipSuccess; ++i) {
-    hipEvent_t j = ctx->join_ev[i];
-    if (!fresh(&j)) return fail(ctx, CI_ENOMEM, "ordering event");
-    e = hipEventRecord(j, ctx->ws[i]);
-    if (e == hipSuccess) e = hipStreamWaitEvent(st, j, 0);
+  if (!chain) {
+    for (int i = 0; i < 3 && e == hipSuccess; ++i) {
+      e = hipEventRecord(ctx->join_ev[i], ctx->ws[i]);
+      if (e == hipSuccess) e = hipStreamWaitEvent(st, ctx->join_ev[i], 0);
+    }
+    if (e != hipSuccess) return hipfail(ctx, e, "stream join");
   }
-  if (e != hipSuccess) return hipfail(ctx, e, "stream join");
   return ws_leave(ctx, st);
 }
 
@@ -637,26 +631,14 @@ int drop_graph(Ctx* ctx) {
 }
 
 // The schedule of `jobs` as one graph launch on st.  The schedule is
-// captured (on a private stream, forking onto the internal streams exactly
-// as the eager schedule does) the first time a set of arguments is seen
-// and replayed while they stay the same; workspaces are sized before the
-// capture, and the replay is ordered after every earlier call on the
-// context and before every later one.
+// captured on a private stream as one chain of kernel nodes (init, then
+// per batch first pass, second pass, finaliser; no events, so no
+// dependencies between captured streams) the first time a set of
+// arguments is seen, and replayed while they stay the same; workspaces are
+// sized before the capture, and the replay is ordered after every earlier
+// call on the context and before every later one.
 int run_graph(Ctx* ctx, const std::vector<Job>& jobs, size_t slot_elems, int32_t precision,
               float thr2, int64_t window, int merge, hipStream_t st) {
-  // Captures of schedules whose batches reuse slot sets (more than kSlots
-  // batches: a first pass then waits for a finaliser recorded on another
-  // captured stream) are refused: such a capture of the 16384-template
-  // class schedule ended the process with a host segmentation fault inside
-  // this call, cause not identified.  Shorter schedules replay correctly.
-  int64_t batches = 0;
-  for (const Job& jb : jobs)
-    if (jb.n > 0) batches += (jb.n + jb.B - 1) / jb.B;
-  if (batches > kSlots)
-    return fail(ctx, CI_EUNSUPPORTED,
-                "graph replay of a schedule of %lld batches (more than %d) is disabled: a "
-                "capture of the 16384-template class schedule ended the process in the "
-                "runtime, cause not identified", (long long)batches, kSlots);
   std::vector<unsigned char> key =
       schedule_key(ctx, jobs, slot_elems, precision, thr2, window, merge);
   if (!ctx->gexec || key != ctx->gkey) {
@@ -665,17 +647,6 @@ int run_graph(Ctx* ctx, const std::vector<Job>& jobs, size_t slot_elems, int32_t
     hipError_t e = hipSuccess;
     if (!ctx->cap_st) e = hipStreamCreateWithFlags(&ctx->cap_st, hipStreamNonBlocking);
     if (e != hipSuccess) return hipfail(ctx, e, "capture stream");
-    // every ordering event of the capture exists before it starts: one fork,
-    // two per batch, three joins
-    size_t need = 4;
-    for (const Job& jb : jobs)
-      if (jb.n > 0) need += 2 * (size_t)((jb.n + jb.B - 1) / jb.B);
-    while (ctx->cap_pool.size() < need) {
-      hipEvent_t ev = nullptr;
-      e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
-      if (e != hipSuccess) return hipfail(ctx, e, "ordering event");
-      ctx->cap_pool.push_back(ev);
-    }
     // the capture stream starts after everything already enqueued on st
     // that the schedule could depend on: the replay itself is ordered on st
     e = hipStreamBeginCapture(ctx->cap_st, hipStreamCaptureModeThreadLocal);
@@ -686,9 +657,6 @@ int run_graph(Ctx* ctx, const std::vector<Job>& jobs, size_t slot_elems, int32_t
     ctx->capturing = false;
     hipGraph_t g = nullptr;
     e = hipStreamEndCapture(ctx->cap_st, &g);
-    // the ordering events only carried dependencies during the capture
-    for (hipEvent_t ev : ctx->cap_ev) ctx->cap_pool.push_back(ev);
-    ctx->cap_ev.clear();
     if (rc != CI_OK || e != hipSuccess || !g) {
       if (g) (void)hipGraphDestroy(g);
       if (rc != CI_OK) return rc;
@@ -892,7 +860,6 @@ int ci_ctx_destroy(ci_ctx* ctx) {
     (void)hipEventDestroy(ctx->ws_free);
   }
   for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
-  for (hipEvent_t e : ctx->cap_pool) (void)hipEventDestroy(e);
   for (int i = 0; i < 3; ++i)
     if (ctx->ws[i]) {
       (void)hipStreamSynchronize(ctx->ws[i]);

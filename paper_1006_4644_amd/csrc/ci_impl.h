@@ -121,8 +121,6 @@ struct Ctx {
   hipGraphExec_t gexec = nullptr;
   std::vector<unsigned char> gkey;
   bool capturing = false;           // our own capture is in progress
-  std::vector<hipEvent_t> cap_ev;   // ordering events recorded in the capture
-  std::vector<hipEvent_t> cap_pool; // spare ordering events for captures
   int64_t graph_captures = 0, graph_launches = 0;
   // instrumentation
   bool timing = false;
