@@ -273,6 +273,29 @@ int ci_find_triggers(ci_ctx* ctx, const ci_segment* seg,
                      int64_t cap, int64_t* d_count,
                      int32_t merge_across_templates, void* stream);
 
+/* --- search without allocation -----------------------------------------------
+ * For callers that cannot allocate device memory while they run (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same search as ci_find_triggers, same arguments, same results bit for
+ * bit, with every intermediate in a fixed device scratch area of 64 MiB per
+ * GPU (a file-scope device array of the library, held until the process
+ * ends) instead of the context's workspaces.  The call allocates nothing and
+ * creates no stream or event: all launches go on `stream`, in order, in
+ * batches of as many templates as fit the scratch (2 at n_seg = 2^20,
+ * 1 at 2^21), so it is slower than ci_find_triggers.  CI_EINVAL when even
+ * one template per batch does not fit (n_seg times 24 bytes plus the
+ * trigger bookkeeping of n_seg / window windows).  Every such call on one
+ * GPU shares that GPU's scratch: calls that overlap on the device (other
+ * streams, other contexts, other host threads) race and give wrong
+ * results; order them.  Timing (ci_set_timing) does not record these
+ * launches. */
+int ci_find_triggers_noalloc(ci_ctx* ctx, const ci_segment* seg,
+                             const ci_tparams* d_params, int64_t n, int32_t precision,
+                             float snr_threshold, int64_t window, int64_t j_lo,
+                             int64_t j_hi, ci_trigger* d_peaks, ci_trigger* d_trig,
+                             int64_t cap, int64_t* d_count,
+                             int32_t merge_across_templates, void* stream);
+
 /* --- the paper's two-polarization form ----------------------------------------
  * The template form of "Template generation" and of the per-template loop
  * of "Matched filtering": both polarizations generated in the time domain,

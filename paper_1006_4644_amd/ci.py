@@ -37,6 +37,7 @@ EXPORTED_SYMBOLS = (
     "ci_td_matched_filter", "ci_td_find_triggers", "ci_stream_create",
     "ci_stream_destroy", "ci_stream_push", "ci_stream_poll", "ci_stream_last",
     "ci_bank_metric", "ci_make_bank_lattice", "ci_graph_stats",
+    "ci_find_triggers_noalloc",
 )
 RUN_GRAPH = 1
 
@@ -143,6 +144,9 @@ _SIGS = {
     "ci_find_triggers": (ctypes.c_int, [_vp, _vp, _vp, _i64, _i32, _f32, _i64,
                                         _i64, _i64, _vp, _vp, _i64, _vp, _i32,
                                         _vp]),
+    "ci_find_triggers_noalloc": (ctypes.c_int, [_vp, _vp, _vp, _i64, _i32, _f32, _i64,
+                                                _i64, _i64, _vp, _vp, _i64, _vp, _i32,
+                                                _vp]),
     "ci_length_classes": (ctypes.c_int, [_vp, _i64, ctypes.c_double,
                                          ctypes.c_double, _vp, _i32, _vp]),
     "ci_search_classes": (ctypes.c_int, [_vp, ctypes.POINTER(_ClassJob), _i32,
@@ -442,6 +446,20 @@ class Context:
             1 if merge else 0, _stream(stream)))
         return peaks, trig, count
 
+
+    def find_triggers_noalloc(self, seg: Segment, params, thr: float, window: int,
+                              peaks, trig, count, n: int | None = None, j_lo: int = 0,
+                              j_hi: int = 0, merge: bool = False, precision: int = FP32,
+                              stream=None):
+        """The search without allocation (the library's fixed scratch): the
+        caller passes every output tensor; returns them."""
+        n = params.shape[0] if n is None else n
+        cap = trig.shape[0]
+        self._chk(self.lib.dll.ci_find_triggers_noalloc(
+            self.handle, seg.handle, _ptr(params), n, precision, float(thr),
+            window, j_lo, j_hi, _ptr(peaks), _ptr(trig), cap, _ptr(count),
+            1 if merge else 0, _stream(stream)))
+        return peaks, trig, count
 
     def get_tune(self, log2n: int, precision: int = FP32) -> dict:
         t = _Tune()

@@ -12,6 +12,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -41,6 +42,36 @@ int fail(Ctx* ctx, int code, const char* fmt, ...) {
 
 int hipfail(Ctx* ctx, hipError_t e, const char* what) {
   return fail(ctx, CI_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+// Device scratch of the no-allocation search (ci_find_triggers_noalloc):
+// the intermediate slot sets and the trigger bookkeeping of one call.  One
+// copy per GPU the library runs on, held until the process ends; calls
+// share it, so calls that overlap on one GPU race.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+// Device address of `scratch` per HIP device.  The host-side name is only a
+// stand-in for the symbol, never a device address: kernels and copies get
+// the address looked up here, once per device, with that device current.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+int scratch_address(int device, void** out) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (device < 0 || device >= kMaxDevices)
+    return fail(nullptr, CI_EUNSUPPORTED, "device %d beyond the scratch table", device);
+  if (!g_scratch_ptr[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(nullptr, CI_EHIP, "scratch address on device %d: %s", device,
+                  hipGetErrorString(e));
+    g_scratch_ptr[device] = p;
+  }
+  *out = g_scratch_ptr[device];
+  return CI_OK;
 }
 
 // Selects the context's device for the duration of a call.
@@ -349,7 +380,7 @@ template <typename F>
 hipError_t timed(Ctx* ctx, int kind, int64_t templates, hipStream_t st, F launch) {
   // launches inside a graph capture are not timed (the events would be
   // captured too)
-  if (!ctx->timing || ctx->capturing) return launch();
+  if (!ctx->timing || ctx->capturing || ctx->noalloc_call) return launch();
   TimedLaunch t{kind, templates, pool_event(ctx), pool_event(ctx)};
   if (!t.e0 || !t.e1) return hipErrorOutOfMemory;
   hipError_t e = hipEventRecord(t.e0, st);
@@ -489,12 +520,17 @@ int prepare_jobs(Ctx* ctx, std::vector<Job>& jobs, size_t* slot_elems, hipStream
 // pass, second pass, finaliser per batch): the graph is one chain of
 // kernel nodes with no event dependencies, and the stream order alone
 // keeps the slot sets apart.
+// With `ybase` set (the no-allocation entry point) the intermediate lives
+// there instead of the context workspace, every launch goes on st in order
+// and the context's workspace ordering is not involved.
 int enqueue_jobs(Ctx* ctx, const std::vector<Job>& jobs, size_t slot_elems, int32_t precision,
-                 float thr2, int64_t window, int merge, hipStream_t st) {
+                 float thr2, int64_t window, int merge, hipStream_t st,
+                 float2* ybase = nullptr) {
   hipError_t e = hipSuccess;
-  const bool chain = ctx->capturing;
-  float2* ybase = static_cast<float2*>(ctx->ybuf);
-  int rc = ws_enter(ctx, st);
+  const bool chain = ctx->capturing || ybase != nullptr;
+  const bool own_ws = ybase == nullptr;
+  if (own_ws) ybase = static_cast<float2*>(ctx->ybuf);
+  int rc = own_ws ? ws_enter(ctx, st) : CI_OK;
   if (rc != CI_OK) return rc;
   for (const Job& jb : jobs) {
     e = launch_init_call(jb.tw, (int)jb.nwin, jb.count, st);
@@ -573,7 +609,7 @@ int enqueue_jobs(Ctx* ctx, const std::vector<Job>& jobs, size_t slot_elems, int3
     }
     if (e != hipSuccess) return hipfail(ctx, e, "stream join");
   }
-  return ws_leave(ctx, st);
+  return own_ws ? ws_leave(ctx, st) : CI_OK;
 }
 
 // Bytes that identify a captured schedule: every launch argument the
@@ -831,9 +867,17 @@ int ci_ctx_create(int device, ci_ctx** out) {
   if (e != hipSuccess) return fail(nullptr, CI_EHIP, "hipGetDeviceCount: %s", hipGetErrorString(e));
   if (device < 0 || device >= ndev)
     return fail(nullptr, CI_EINVAL, "device %d out of range (%d devices)", device, ndev);
+  void* sp = nullptr;
+  {
+    DeviceGuard dg(device);
+    if (!dg.ok) return fail(nullptr, CI_EHIP, "cannot select device %d", device);
+    const int rc = scratch_address(device, &sp);
+    if (rc != CI_OK) return rc;
+  }
   ci_ctx* c = new (std::nothrow) ci_ctx();
   if (!c) return fail(nullptr, CI_ENOMEM, "context allocation");
   c->device = device;
+  c->scratch = sp;
   *out = c;
   return CI_OK;
 }
@@ -1177,6 +1221,56 @@ int ci_find_triggers(ci_ctx* ctx, const ci_segment* seg, const ci_tparams* d_par
   if (rc != CI_OK) return rc;
   return enqueue_jobs(ctx, jobs, slot, precision, snr_threshold * snr_threshold, window,
                       merge_across_templates ? 1 : 0, static_cast<hipStream_t>(stream));
+}
+
+int ci_find_triggers_noalloc(ci_ctx* ctx, const ci_segment* seg, const ci_tparams* d_params,
+                             int64_t n, int32_t precision, float snr_threshold, int64_t window,
+                             int64_t j_lo, int64_t j_hi, ci_trigger* d_peaks, ci_trigger* d_trig,
+                             int64_t cap, int64_t* d_count, int32_t merge_across_templates,
+                             void* stream) {
+  if (!ctx) return fail(nullptr, CI_EINVAL, "null context");
+  if (!ctx->scratch) return fail(ctx, CI_EHIP, "no scratch address for device %d", ctx->device);
+  DeviceGuard dg(ctx->device);
+  if (!dg.ok) return fail(ctx, CI_EHIP, "cannot select device %d", ctx->device);
+  std::vector<Job> jobs(1);
+  Job& jb = jobs[0];
+  jb.seg = seg;
+  jb.params = d_params;
+  jb.n = n;
+  jb.j_lo = j_lo;
+  jb.j_hi = j_hi;
+  jb.peaks = d_peaks;
+  jb.trig = d_trig;
+  jb.cap = cap;
+  jb.count = d_count;
+  int rc = check_job(ctx, jb, precision, snr_threshold, window);
+  if (rc != CI_OK) return rc;
+  // the largest batch (at most the configured one) whose slot sets and
+  // trigger bookkeeping fit the scratch
+  const int64_t N = jb.seg->host.n;
+  const int64_t ntile2 = jb.plan.n2 / jb.plan.j;
+  auto bytes = [&](int64_t B) {
+    return align256(sizeof(float2) * kSlots * (size_t)B * (size_t)N) +
+           trig_bytes(B, jb.nwin, ntile2);
+  };
+  int64_t B = jb.B;
+  while (B > 1 && bytes(B) > kScratchBytes) --B;
+  if (bytes(B) > kScratchBytes)
+    return fail(ctx, CI_EINVAL,
+                "n_seg = %lld with %lld windows needs %zu bytes of scratch for one template "
+                "per batch; the no-allocation search has %zu",
+                (long long)N, (long long)jb.nwin, bytes(1), kScratchBytes);
+  jb.B = B;
+  jb.toff = 0;
+  char* base = static_cast<char*>(ctx->scratch);
+  carve_trig(base + align256(sizeof(float2) * kSlots * (size_t)B * (size_t)N), B, jb.nwin,
+             ntile2, &jb.tw);
+  ctx->noalloc_call = true;
+  rc = enqueue_jobs(ctx, jobs, (size_t)B * (size_t)N, precision,
+                    snr_threshold * snr_threshold, window, merge_across_templates ? 1 : 0,
+                    static_cast<hipStream_t>(stream), reinterpret_cast<float2*>(base));
+  ctx->noalloc_call = false;
+  return rc;
 }
 
 // --- the two-polarization (time-domain) template form ---------------------

@@ -122,6 +122,10 @@ struct Ctx {
   std::vector<unsigned char> gkey;
   bool capturing = false;           // our own capture is in progress
   int64_t graph_captures = 0, graph_launches = 0;
+  // device address of the no-allocation search's scratch on this device,
+  // and whether such a call is being enqueued (no timing events then)
+  void* scratch = nullptr;
+  bool noalloc_call = false;
   // instrumentation
   bool timing = false;
   std::vector<TimedLaunch> launches;
