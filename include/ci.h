@@ -70,7 +70,7 @@ extern "C" {
 #define CI_EINVAL (-1)        /* bad argument or shape                     */
 #define CI_ENOMEM (-2)        /* device or host allocation failed          */
 #define CI_EHIP (-3)          /* a HIP runtime call or launch failed       */
-#define CI_ETRUNC (-4)        /* reserved: a host-visible capacity overflow */
+#define CI_ETRUNC (-4)        /* capacity overflow seen on the host       */
 #define CI_EUNSUPPORTED (-5)  /* valid request this build does not handle  */
 
 /* arithmetic of the inverse transform */
@@ -261,7 +261,9 @@ int ci_matched_filter(ci_ctx* ctx, const ci_segment* seg,
  *   the smaller template id), ordered by window (the reduction of the
  *   candidate set to local maxima).
  * d_count (int64, device): receives the total number of triggers.  When it
- * exceeds `cap`, only the first `cap` in the stated order are written.
+ * exceeds `cap`, only the first `cap` in the stated order are written; the
+ * call still returns CI_OK (the count exists only on the device once the
+ * stream has run: compare *d_count with cap after synchronising).
  * rho2 of a trigger is the value that decided it; re/im are recomputed at
  * that index from the same transform's intermediate with FP64 accumulation.
  * window: W >= 1.  j_hi <= 0 means n_seg.  precision as for
@@ -577,6 +579,18 @@ typedef struct {
 } ci_kernel_time;
 
 int ci_set_timing(ci_ctx* ctx, int32_t enable);
+
+/* Streaming bandwidth of the device, for comparing the search's kernels
+ * with what plain memory traffic reaches: kind 0 writes `bytes` of d_buf
+ * (16-byte non-temporal stores), 1 reads them (16-byte non-temporal loads),
+ * 2 copies the first `bytes` of d_buf onto the next `bytes` (d_buf holds
+ * 2 x bytes).  Grid-stride loops over 8 workgroups of 256 lanes per compute
+ * unit.  *gbs: the best of `reps` timed launches (after one warm-up), in
+ * 1e9 bytes/s moved (read plus written for a copy).  Blocking; the buffer's
+ * contents are overwritten (kinds 0 and 2).  bytes: a multiple of 16,
+ * >= 4096. */
+int ci_hbm_probe(ci_ctx* ctx, int32_t kind, void* d_buf, int64_t bytes, int32_t reps,
+                 double* gbs);
 int ci_kernel_times(ci_ctx* ctx, ci_kernel_time* pass1, ci_kernel_time* pass2);
 
 #ifdef __cplusplus

@@ -37,7 +37,7 @@ EXPORTED_SYMBOLS = (
     "ci_td_matched_filter", "ci_td_find_triggers", "ci_stream_create",
     "ci_stream_destroy", "ci_stream_push", "ci_stream_poll", "ci_stream_last",
     "ci_bank_metric", "ci_make_bank_lattice", "ci_graph_stats",
-    "ci_find_triggers_noalloc",
+    "ci_find_triggers_noalloc", "ci_hbm_probe",
 )
 RUN_GRAPH = 1
 
@@ -152,6 +152,8 @@ _SIGS = {
     "ci_search_classes": (ctypes.c_int, [_vp, ctypes.POINTER(_ClassJob), _i32,
                                          _i32, _f32, _i64, _i32, _i32, _vp]),
     "ci_graph_stats": (ctypes.c_int, [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64)]),
+    "ci_hbm_probe": (ctypes.c_int, [_vp, _i32, _vp, _i64, _i32,
+                                    ctypes.POINTER(ctypes.c_double)]),
     "ci_get_tune": (ctypes.c_int, [_vp, _i32, _i32, ctypes.POINTER(_Tune)]),
     "ci_set_tune": (ctypes.c_int, [_vp, ctypes.POINTER(_Tune)]),
     "ci_autotune": (ctypes.c_int, [_vp, _vp, _vp, _i64, _i32, _f32, _i64,
@@ -605,6 +607,14 @@ class Context:
             self.handle, arr, len(jobs), precision, float(thr), window,
             1 if merge else 0, RUN_GRAPH if graph else 0, _stream(stream)))
         return outs
+
+    def hbm_probe(self, kind: int, buf, nbytes: int, reps: int = 10) -> float:
+        """Streaming bandwidth in GB/s: kind 0 write, 1 read, 2 copy (buf holds
+        2 x nbytes for a copy)."""
+        g = ctypes.c_double(0.0)
+        self._chk(self.lib.dll.ci_hbm_probe(self.handle, kind, _ptr(buf), nbytes, reps,
+                                            ctypes.byref(g)))
+        return float(g.value)
 
     def graph_stats(self):
         """(graphs captured, graph launches) of CI_RUN_GRAPH searches."""

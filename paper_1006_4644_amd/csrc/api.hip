@@ -1776,6 +1776,44 @@ int ci_search_classes(ci_ctx* ctx, const ci_class_job* jobs_in, int32_t njobs, i
   return run_graph(ctx, jobs, slot, precision, thr2, window, merge, st);
 }
 
+int ci_hbm_probe(ci_ctx* ctx, int32_t kind, void* d_buf, int64_t bytes, int32_t reps,
+                 double* gbs) {
+  if (!ctx) return fail(nullptr, CI_EINVAL, "null context");
+  if (kind < 0 || kind > 2) return fail(ctx, CI_EINVAL, "unknown probe kind %d", kind);
+  if (!d_buf || !gbs) return fail(ctx, CI_EINVAL, "null buffer or output");
+  if (bytes < 16 * 256 || bytes % 16 != 0)
+    return fail(ctx, CI_EINVAL, "probe size %lld: a multiple of 16 bytes, >= 4096",
+                (long long)bytes);
+  if (reps < 1 || reps > 1000) return fail(ctx, CI_EINVAL, "reps %d outside 1..1000", reps);
+  DeviceGuard dg(ctx->device);
+  if (!dg.ok) return fail(ctx, CI_EHIP, "cannot select device %d", ctx->device);
+  int cus = 0;
+  hipError_t e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device);
+  if (e != hipSuccess) return hipfail(ctx, e, "device attribute");
+  hipStream_t st = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  double best = 0.0;
+  for (int r = -1; r < reps && e == hipSuccess; ++r) {  // r = -1: warm-up
+    e = hipEventRecord(e0, st);
+    if (e == hipSuccess) e = launch_probe(kind, d_buf, bytes, 8 * cus, st);
+    if (e == hipSuccess) e = hipEventRecord(e1, st);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    const double moved = (kind == 2 ? 2.0 : 1.0) * (double)bytes;
+    if (e == hipSuccess && r >= 0 && ms > 0.f) best = std::max(best, moved / (ms * 1e-3) / 1e9);
+  }
+  if (e1) (void)hipEventDestroy(e1);
+  if (e0) (void)hipEventDestroy(e0);
+  if (st) (void)hipStreamDestroy(st);
+  if (e != hipSuccess) return hipfail(ctx, e, "bandwidth probe");
+  *gbs = best;
+  return CI_OK;
+}
+
 int ci_graph_stats(ci_ctx* ctx, int64_t* captures, int64_t* launches) {
   if (!ctx) return fail(nullptr, CI_EINVAL, "null context");
   if (captures) *captures = ctx->graph_captures;

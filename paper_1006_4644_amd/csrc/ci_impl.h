@@ -166,6 +166,9 @@ hipError_t launch_init_call(const TrigWork& tw, int nwin, int64_t* d_count,
 hipError_t launch_chisq(const Seg* s, const ci_tparams* d_params, int64_t ntmpl,
                         const ci_trigger* d_trig, int64_t ntrig, int bands, double* d_out,
                         hipStream_t st);
+// Streaming probe over `bytes` of buf: kind 0 writes, 1 reads, 2 copies the
+// first half onto the second (bytes per half).
+hipError_t launch_probe(int kind, void* buf, int64_t bytes, int blocks, hipStream_t st);
 // Matrix-core operand tables of a segment (after its FP64 twiddles exist).
 hipError_t launch_mx_tables(Seg* s, hipStream_t st);
 

@@ -1307,6 +1307,69 @@ __global__ void k_init_call(ci_trigger* mrec, int nwin, u64* run, int64_t* d_cou
 }
 
 // ---------------------------------------------------------------------------
+// streaming bandwidth probes (the device's write, read and copy ceilings)
+// ---------------------------------------------------------------------------
+
+// Grid-stride loops over 16-byte elements, four in flight per lane, with
+// the non-temporal hints the search's intermediate uses.
+typedef float f4v __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(256) void k_probe_write(f4v* __restrict__ p, int64_t n4, float v) {
+  const int64_t g = (int64_t)gridDim.x * 256;
+  const f4v w = {v, v, v, v};
+  for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < n4; i += 4 * g) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (i + u * g < n4) __builtin_nontemporal_store(w, &p[i + u * g]);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_probe_read(const f4v* __restrict__ p, int64_t n4,
+                                                     float* __restrict__ sink) {
+  const int64_t g = (int64_t)gridDim.x * 256;
+  float acc = 0.f;
+  for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < n4; i += 4 * g) {
+    f4v v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const f4v z = {0.f, 0.f, 0.f, 0.f};
+      v[u] = i + u * g < n4 ? __builtin_nontemporal_load(&p[i + u * g]) : z;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc += (v[u].x + v[u].y) + (v[u].z + v[u].w);
+  }
+  // never true for the probe's data (zeros): keeps the loads alive
+  if (acc == 12345.f) sink[0] = acc;
+}
+
+__global__ __launch_bounds__(256) void k_probe_copy(const f4v* __restrict__ src,
+                                                     f4v* __restrict__ dst, int64_t n4) {
+  const int64_t g = (int64_t)gridDim.x * 256;
+  for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < n4; i += 4 * g) {
+    f4v v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (i + u * g < n4) v[u] = __builtin_nontemporal_load(&src[i + u * g]);
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (i + u * g < n4) __builtin_nontemporal_store(v[u], &dst[i + u * g]);
+  }
+}
+
+hipError_t launch_probe(int kind, void* buf, int64_t bytes, int blocks, hipStream_t st) {
+  const int64_t n4 = bytes / 16;
+  f4v* p = static_cast<f4v*>(buf);
+  if (kind == 0)
+    hipLaunchKernelGGL(k_probe_write, dim3(blocks), dim3(256), 0, st, p, n4, 0.f);
+  else if (kind == 1)
+    hipLaunchKernelGGL(k_probe_read, dim3(blocks), dim3(256), 0, st, p, n4,
+                       reinterpret_cast<float*>(p));
+  else
+    hipLaunchKernelGGL(k_probe_copy, dim3(blocks), dim3(256), 0, st, p, p + n4, n4);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // chi-squared veto at trigger samples
 // ---------------------------------------------------------------------------
 

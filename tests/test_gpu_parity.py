@@ -199,6 +199,19 @@ def test_empty_template_and_cap_overflow(ctx, tiny):
     assert int(P[3]["index"]) == -1 and float(P[3]["rho2"]) == 0.0
     assert not np.any(F["tmpl"] == 3)
     assert ci.params_to_numpy(params)["flags"][3] == ci.TMPL_EMPTY
+    # the documented overflow behaviour: the call succeeds (it is
+    # asynchronous), *d_count holds the true total and the list its first
+    # `cap` entries in the stated order, (template, window) unmerged ...
+    assert list(zip(F["tmpl"], F["window"])) == sorted(zip(F["tmpl"], F["window"]))
+    # ... and by window when merged
+    mp, mt, mc = ctx.find_triggers(tiny["seg"], params, 2.0, 1024, cap=100000, merge=True)
+    sp, st, sc = ctx.find_triggers(tiny["seg"], params, 2.0, 1024, cap=3, merge=True)
+    _sync()
+    mtot = int(mc.cpu()[0])
+    assert mtot > 3 and int(sc.cpu()[0]) == mtot
+    M = ci.triggers_to_numpy(mt, mtot)
+    assert list(M["window"]) == sorted(M["window"]) and len(set(M["window"])) == mtot
+    assert np.array_equal(ci.triggers_to_numpy(st, 3), M[:3])
 
 
 def test_argument_errors(ctx, tiny):
