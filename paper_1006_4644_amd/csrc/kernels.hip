@@ -363,6 +363,8 @@ struct P1Args {
   u64* wkeys;
   unsigned int* bdone;
   int64_t nzero_w;         // entries of wkeys to clear
+  u64* mkey;               // the batch's merge keys [nwin] (cleared too)
+  int nwin;
   int nb;
   // two-polarization templates (k_pass1_mem)
   const float2* uv;        // [nb][n] spectrum in memory, natural order
@@ -505,6 +507,7 @@ __global__ __launch_bounds__(C * N2 / 16) void k_pass1(P1Args a) {
     const int64_t gid = blockIdx.x * (int64_t)blockDim.x + tid;
     const int64_t gsz = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = gid; i < a.nzero_w; i += gsz) a.wkeys[i] = 0ull;
+    for (int64_t i = gid; i < a.nwin; i += gsz) a.mkey[i] = 0ull;
     if (gid == 0) a.bdone[0] = 0u;
   }
 
@@ -601,6 +604,7 @@ __global__ __launch_bounds__(C * N2 / 16) void k_pass1_mem(P1Args a) {
     const int64_t gid = blockIdx.x * (int64_t)blockDim.x + tid;
     const int64_t gsz = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = gid; i < a.nzero_w; i += gsz) a.wkeys[i] = 0ull;
+    for (int64_t i = gid; i < a.nwin; i += gsz) a.mkey[i] = 0ull;
     if (gid == 0) a.bdone[0] = 0u;
   }
   float2* twl = lds + Col<N2, C>::LDS_ELEMS;
@@ -730,6 +734,8 @@ struct P2Args {
   u64* ppart;                // [nb][ntile2] per-workgroup peak keys
   int ntile2;                // pass-2 workgroups per template
   u64* wkeys;                // [nb][nwin]
+  u64* mkey;                 // [nwin] per window: max over the batch of
+                             // (rho^2 bits, complemented template index)
   unsigned int* bdone;       // [1]
   int* cnt;                  // [nb]
   int* sidx;                 // [nb][nwin]
@@ -817,6 +823,10 @@ __device__ void finalize_template(const P2Args& a, int b, void* ldsv) {
         st[pos] = e;
         sx[w] = pos;
         ++pos;
+        // the batch's best template per window (larger rho^2; ties to the
+        // smaller template), for the merge
+        if (a.merge)
+          atomicMax(&a.mkey[w], (key & 0xFFFFFFFF00000000ull) | (u64)(0xFFFFFFFFu - (unsigned)b));
       }
     }
     __syncthreads();
@@ -851,43 +861,43 @@ __device__ void place_batch(const P2Args& a, void* ldsv) {
   const int tid = threadIdx.x, nt = blockDim.x;
   int* iscr = reinterpret_cast<int*>(ldsv);
   if (!a.merge) {
-    // offsets in template order
+    // offsets in template order: each lane sums a run of templates, one
+    // workgroup scan over the runs
     __shared__ long long s_base;
     if (tid == 0) s_base = (long long)a.run[0];
-    __syncthreads();
+    const int per = (a.nb + nt - 1) / nt;
+    const int b0 = tid * per, b1 = min(b0 + per, a.nb);
+    int mine = 0;
+    for (int b = b0; b < b1; ++b) mine += a.cnt[b];
+    int total = 0;
+    int off = block_excl_scan(mine, iscr, &total);
     const long long base = s_base;
-    long long acc = 0;
-    // serial prefix over the batch (nb is small)
-    if (tid == 0) {
-      for (int b = 0; b < a.nb; ++b) {
-        iscr[b] = (int)acc;
-        acc += a.cnt[b];
-      }
-      a.run[0] = (u64)(base + acc);
-      a.d_count[0] = base + acc;
-    }
-    __syncthreads();
-    for (int b = tid; b < a.nb; b += nt) {
+    for (int b = b0; b < b1; ++b) {
       const int c = a.cnt[b];
       const ci_trigger* st = a.stage + (size_t)b * a.nwin;
       for (int i = 0; i < c; ++i) {
-        const long long p = base + iscr[b] + i;
+        const long long p = base + off + i;
         if (p < a.cap) a.d_trig[p] = st[i];
       }
+      off += c;
+    }
+    if (tid == 0) {
+      a.run[0] = (u64)(base + total);
+      a.d_count[0] = base + total;
     }
     return;
   }
-  // merge: per window, largest rho^2 over templates, earlier template wins ties
+  // merge: per window, largest rho^2 over templates, earlier template wins
+  // ties (within the batch through the merge key, across batches because
+  // a later batch must be strictly larger)
   for (int w = tid; w < a.nwin; w += nt) {
-    ci_trigger best = a.mrec[w];
-    for (int b = 0; b < a.nb; ++b) {
-      const u64 key = aload(&a.wkeys[(size_t)b * a.nwin + w]);
-      if (key == 0ull) continue;
-      const float r2 = __uint_as_float((unsigned int)(key >> 32));
-      if (best.tmpl < 0 || r2 > best.rho2)
-        best = a.stage[(size_t)b * a.nwin + a.sidx[(size_t)b * a.nwin + w]];
-    }
-    a.mrec[w] = best;
+    const u64 key = aload(&a.mkey[w]);
+    if (key == 0ull) continue;
+    const int b = (int)(0xFFFFFFFFu - (unsigned int)(key & 0xFFFFFFFFull));
+    const float r2 = __uint_as_float((unsigned int)(key >> 32));
+    const ci_trigger best = a.mrec[w];
+    if (best.tmpl < 0 || r2 > best.rho2)
+      a.mrec[w] = a.stage[(size_t)b * a.nwin + a.sidx[(size_t)b * a.nwin + w]];
   }
   if (!a.last_batch) return;
   __syncthreads();
@@ -1584,10 +1594,14 @@ P1Args make_p1(const BatchArgs& a, bool zero_trig) {
     p.wkeys = a.tw.wkeys + (size_t)s * a.bmax * a.nwin;
     p.bdone = a.tw.bdone + s;
     p.nzero_w = (int64_t)a.nb * a.nwin;
+    p.mkey = a.tw.mkey + (size_t)s * a.nwin;
+    p.nwin = a.nwin;
   } else {
     p.wkeys = nullptr;
     p.bdone = nullptr;
     p.nzero_w = 0;
+    p.mkey = nullptr;
+    p.nwin = 0;
   }
   return p;
 }
@@ -1615,6 +1629,7 @@ P2Args make_p2(const BatchArgs& a) {
   p.ppart = a.tw.ppart ? a.tw.ppart + (size_t)s * a.bmax * p.ntile2 : nullptr;
   p.wkeys = a.tw.wkeys ? a.tw.wkeys + (size_t)s * a.bmax * a.nwin : nullptr;
   p.bdone = a.tw.bdone ? a.tw.bdone + s : nullptr;
+  p.mkey = a.tw.mkey ? a.tw.mkey + (size_t)s * a.nwin : nullptr;
   p.cnt = a.tw.cnt ? a.tw.cnt + (size_t)s * a.bmax : nullptr;
   p.sidx = a.tw.sidx ? a.tw.sidx + (size_t)s * a.bmax * a.nwin : nullptr;
   p.stage = a.tw.stage ? a.tw.stage + (size_t)s * a.bmax * a.nwin : nullptr;
