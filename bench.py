@@ -83,7 +83,8 @@ def parse():
     p.add_argument("--no-autotune", action="store_true",
                    help="keep the default launch configuration")
     p.add_argument("--tune", default="",
-                   help="explicit launch configuration C,J,P2,BATCH[,STREAMS] (skips the autotuner)")
+                   help="explicit launch configuration C,J,P2,BATCH[,STREAMS[,P2_WAVE]] "
+                        "(skips the autotuner)")
     return p.parse_args()
 
 
@@ -97,7 +98,8 @@ def configure(ctx, ci, args, tune_calls):
         for seg, params, n, thr, window, l2 in tune_calls:
             if args.tune:
                 v = [int(x) for x in args.tune.split(",")]
-                ctx.set_tune(l2, prec, *v[:4], streams=v[4] if len(v) > 4 else 2)
+                ctx.set_tune(l2, prec, *v[:4], streams=v[4] if len(v) > 4 else 2,
+                             p2_wave=v[5] if len(v) > 5 else 0)
                 cfg = ctx.get_tune(l2, prec)
             elif args.no_autotune:
                 cfg = ctx.get_tune(l2, prec)
@@ -105,7 +107,7 @@ def configure(ctx, ci, args, tune_calls):
                 cfg = ctx.autotune(seg, params, thr, window, n=n, precision=prec)
             out[f"{prec_name}/2^{l2}"] = {k: cfg[k] for k in
                                           ("tile_c", "tile_j", "p2_per_cu", "batch", "streams",
-                                           "tuned")}
+                                           "p2_wave", "tuned")}
             log(f"[bench] launch configuration {prec_name} 2^{l2}: {out[f'{prec_name}/2^{l2}']}")
     return out
 
@@ -239,7 +241,8 @@ def cpu_baseline_all(pool, k, wl, budget_s):
     workload: the oracle's cost does not depend on the data values)."""
     rng = np.random.default_rng(2025)
     order = rng.permutation(wl.n_templates)
-    shares = [(order[i::k], budget_s) for i in range(k)]
+    # each worker walks its share of the bank, cycling, until the budget ends
+    shares = [(np.tile(order[i::k], 64), budget_s) for i in range(k)]
     res = pool.map(_cpu_worker_run, shares)
     done = sum(r[0] for r in res)
     # the workers run side by side: the aggregate rate is the sum of theirs

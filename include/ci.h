@@ -545,11 +545,16 @@ typedef struct {
   int32_t streams;      /* compute streams the batches' passes alternate
                            over: 2 (one batch's second pass overlaps the
                            next batch's first) or 1 (in order); 0 means 2 */
-  int32_t reserved;
+  int32_t p2_wave;      /* FP32 second pass at n1 = 512 or 1024 (2^17 ..
+                           2^20): 1 hands each column to one wave after its
+                           first stage (one cross-wave exchange, per-wave
+                           post-pass), 0 keeps the columns spread over the
+                           workgroup; ignored elsewhere */
 } ci_tune;
 
 int ci_get_tune(ci_ctx* ctx, int32_t log2n, int32_t precision, ci_tune* out);
-/* Sets tile_c, tile_j, p2_per_cu, batch and streams for (log2n, precision). */
+/* Sets tile_c, tile_j, p2_per_cu, batch, streams and p2_wave for (log2n,
+ * precision). */
 int ci_set_tune(ci_ctx* ctx, const ci_tune* cfg);
 
 /* Autotuner: times ci_find_triggers (no merge) on the given templates under

@@ -105,7 +105,7 @@ class _Tune(ctypes.Structure):
                 ("p2_per_cu", ctypes.c_int32), ("tuned", ctypes.c_int32),
                 ("batch", ctypes.c_int64), ("ms", ctypes.c_double),
                 ("candidates", ctypes.c_int32), ("rejected", ctypes.c_int32),
-                ("streams", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("streams", ctypes.c_int32), ("p2_wave", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -470,9 +470,11 @@ class Context:
         return t.as_dict()
 
     def set_tune(self, log2n: int, precision: int = FP32, tile_c: int = 8,
-                 tile_j: int = 4, p2_per_cu: int = 2, batch: int = 0, streams: int = 2):
+                 tile_j: int = 4, p2_per_cu: int = 2, batch: int = 0, streams: int = 2,
+                 p2_wave: int = 0):
         t = _Tune(log2n, precision, tile_c, tile_j, p2_per_cu, 0, batch)
         t.streams = streams
+        t.p2_wave = p2_wave
         self._chk(self.lib.dll.ci_set_tune(self.handle, ctypes.byref(t)))
 
     def autotune(self, seg: Segment, params, thr: float, window: int,

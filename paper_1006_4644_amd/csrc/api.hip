@@ -377,20 +377,31 @@ hipEvent_t pool_event(Ctx* ctx) {
   return e;
 }
 
-// Enqueue one pass launch, bracketed by events when timing is enabled.
+// Enqueue one pass launch, timed when timing is enabled: a single kernel
+// launch records the events itself (a.ev0 / a.ev1), a launch of several
+// kernels (the two-polarization first pass) is bracketed by event records.
 template <typename F>
-hipError_t timed(Ctx* ctx, int kind, int64_t templates, hipStream_t st, F launch) {
+hipError_t timed(Ctx* ctx, int kind, int64_t templates, hipStream_t st, BatchArgs& a, F launch) {
   // launches inside a graph capture are not timed (the events would be
   // captured too)
   if (!ctx->timing || ctx->capturing || ctx->noalloc_call) return launch();
   TimedLaunch t{kind, templates, pool_event(ctx), pool_event(ctx)};
   if (!t.e0 || !t.e1) return hipErrorOutOfMemory;
-  hipError_t e = hipEventRecord(t.e0, st);
-  if (e != hipSuccess) return e;
-  e = launch();
-  if (e != hipSuccess) return e;
-  e = hipEventRecord(t.e1, st);
-  if (e != hipSuccess) return e;
+  hipError_t e;
+  if (!a.td) {
+    a.ev0 = t.e0;
+    a.ev1 = t.e1;
+    e = launch();
+    a.ev0 = a.ev1 = nullptr;
+    if (e != hipSuccess) return e;
+  } else {
+    e = hipEventRecord(t.e0, st);
+    if (e != hipSuccess) return e;
+    e = launch();
+    if (e != hipSuccess) return e;
+    e = hipEventRecord(t.e1, st);
+    if (e != hipSuccess) return e;
+  }
   ctx->launches.push_back(t);
   return hipSuccess;
 }
@@ -481,7 +492,7 @@ int prepare_jobs(Ctx* ctx, std::vector<Job>& jobs, size_t* slot_elems, hipStream
   size_t ymax = 0, ttot = 0, tdmax = 0;
   for (Job& jb : jobs) {
     jb.toff = ttot;
-    ttot += trig_bytes(jb.B, jb.nwin, jb.plan.n2 / jb.plan.j);
+    ttot += trig_bytes(jb.B, jb.nwin, jb.plan.n2);
     if (jb.n > 0) {
       const size_t y = (size_t)jb.B * (size_t)jb.seg->host.n;
       if (y > ymax) ymax = y;
@@ -503,8 +514,7 @@ int prepare_jobs(Ctx* ctx, std::vector<Job>& jobs, size_t* slot_elems, hipStream
     if (rc != CI_OK) return rc;
   }
   for (Job& jb : jobs)
-    carve_trig(static_cast<char*>(ctx->tbuf) + jb.toff, jb.B, jb.nwin, jb.plan.n2 / jb.plan.j,
-               &jb.tw);
+    carve_trig(static_cast<char*>(ctx->tbuf) + jb.toff, jb.B, jb.nwin, jb.plan.n2, &jb.tw);
   *slot_elems = ymax;
   return ensure_streams(ctx);
 }
@@ -566,6 +576,7 @@ int enqueue_jobs(Ctx* ctx, const std::vector<Job>& jobs, size_t slot_elems, int3
     a.merge = merge;
     a.precision = precision;
     a.p2_per_cu = jb.cfg.p2_per_cu;
+    a.p2_wave = jb.cfg.p2_wave;
     for (int64_t t0 = 0; t0 < jb.n; ++b, t0 += jb.B) {
       hipStream_t sb = chain ? st : ctx->ws[jb.cfg.streams == 1 ? 0 : (b & 1)];
       const int slot = (int)(b % kSlots);
@@ -581,7 +592,7 @@ int enqueue_jobs(Ctx* ctx, const std::vector<Job>& jobs, size_t slot_elems, int3
         e = hipStreamWaitEvent(sb, ctx->fin_done[slot], 0);
         if (e != hipSuccess) return hipfail(ctx, e, "slot reuse ordering");
       }
-      e = timed(ctx, 0, a.nb, sb, [&] {
+      e = timed(ctx, 0, a.nb, sb, a, [&] {
         if (a.td) {
           const hipError_t r = launch_td_prep(a, sb);
           if (r != hipSuccess) return r;
@@ -589,7 +600,7 @@ int enqueue_jobs(Ctx* ctx, const std::vector<Job>& jobs, size_t slot_elems, int3
         return launch_pass1(a, true, sb);
       });
       if (e != hipSuccess) return hipfail(ctx, e, "pass-1 launch");
-      e = timed(ctx, 1, a.nb, sb, [&] { return launch_pass2_trig(a, sb); });
+      e = timed(ctx, 1, a.nb, sb, a, [&] { return launch_pass2_trig(a, sb); });
       if (e != hipSuccess) return hipfail(ctx, e, "pass-2 launch");
       if (!chain) {
         e = hipEventRecord(ctx->p2_done[slot], sb);
@@ -647,6 +658,7 @@ std::vector<unsigned char> schedule_key(const Ctx* ctx, const std::vector<Job>& 
     key_put(k, jb.count);
     key_put(k, jb.plan);
     key_put(k, jb.cfg.p2_per_cu);
+    key_put(k, jb.cfg.p2_wave);
     key_put(k, jb.cfg.streams);
     key_put(k, jb.B);
     key_put(k, jb.toff);
@@ -1190,9 +1202,9 @@ int ci_matched_filter(ci_ctx* ctx, const ci_segment* seg, const ci_tparams* d_pa
     a.params = d_params + t0;
     a.y = static_cast<float2*>(ctx->ybuf) + (size_t)a.slot * B * N;
     a.d_z = static_cast<float2*>(d_z) + (size_t)t0 * N;
-    hipError_t e = timed(ctx, 0, a.nb, st, [&] { return launch_pass1(a, false, st); });
+    hipError_t e = timed(ctx, 0, a.nb, st, a, [&] { return launch_pass1(a, false, st); });
     if (e != hipSuccess) return hipfail(ctx, e, "pass-1 launch");
-    e = timed(ctx, 1, a.nb, st, [&] { return launch_pass2_series(a, st); });
+    e = timed(ctx, 1, a.nb, st, a, [&] { return launch_pass2_series(a, st); });
     if (e != hipSuccess) return hipfail(ctx, e, "pass-2 launch");
   }
   return ws_leave(ctx, st);
@@ -1250,7 +1262,7 @@ int ci_find_triggers_noalloc(ci_ctx* ctx, const ci_segment* seg, const ci_tparam
   // the largest batch (at most the configured one) whose slot sets and
   // trigger bookkeeping fit the scratch
   const int64_t N = jb.seg->host.n;
-  const int64_t ntile2 = jb.plan.n2 / jb.plan.j;
+  const int64_t ntile2 = jb.plan.n2;  // peak partials per template, upper bound
   auto bytes = [&](int64_t B) {
     return align256(sizeof(float2) * kSlots * (size_t)B * (size_t)N) +
            trig_bytes(B, jb.nwin, ntile2);
@@ -1868,6 +1880,7 @@ int ci_get_tune(ci_ctx* ctx, int32_t log2n, int32_t precision, ci_tune* out) {
   out->tuned = t.tuned ? 1 : 0;
   out->batch = t.batch;
   out->streams = t.streams;
+  out->p2_wave = t.p2_wave;
   return CI_OK;
 }
 
@@ -1886,6 +1899,8 @@ int ci_set_tune(ci_ctx* ctx, const ci_tune* cfg) {
     return fail(ctx, CI_EINVAL, "batch %lld outside 0..4096", (long long)cfg->batch);
   if (cfg->streams < 0 || cfg->streams > 2)
     return fail(ctx, CI_EINVAL, "streams %d outside 0..2", cfg->streams);
+  if (cfg->p2_wave < 0 || cfg->p2_wave > 1)
+    return fail(ctx, CI_EINVAL, "p2_wave %d outside 0..1", cfg->p2_wave);
   {
     DeviceGuard dg(ctx->device);
     if (!dg.ok) return fail(ctx, CI_EHIP, "cannot select device %d", ctx->device);
@@ -1898,6 +1913,7 @@ int ci_set_tune(ci_ctx* ctx, const ci_tune* cfg) {
   t.p2_per_cu = cfg->p2_per_cu;
   t.streams = cfg->streams == 0 ? 2 : cfg->streams;
   t.batch = cfg->batch;
+  t.p2_wave = cfg->p2_wave;
   t.tuned = false;
   return CI_OK;
 }
@@ -2009,6 +2025,21 @@ int ci_autotune(ci_ctx* ctx, const ci_segment* seg, const ci_tparams* d_params, 
     if (rc == CI_OK && !same) ++rejected;
     else if (rc == CI_OK && ms < best_ms) { best = c; best_ms = ms; }
   }
+  // the FP32 second pass with wave-owned columns (n1 = 512 or 1024), at
+  // both second-pass tile widths (its LDS and registers differ from the
+  // other second pass's, so its best width may too)
+  for (int jw = 4; jw <= 8 && rc == CI_OK && precision == CI_FP32 && l2 >= 17 && l2 <= 20;
+       jw += 4) {
+    Tune c = best;
+    c.p2_wave = 1;
+    c.j = jw;
+    if (plan_fits(plan_for(l2, c.c, c.j), precision) != hipSuccess) continue;
+    float ms = 0.f;
+    bool same = false;
+    rc = trial(c, &ms, &same);
+    if (rc == CI_OK && !same) ++rejected;
+    else if (rc == CI_OK && ms < best_ms) { best = c; best_ms = ms; }
+  }
   for (int p2 = 0; p2 <= 4 && rc == CI_OK; ++p2) {
     if (p2 == best.p2_per_cu) continue;
     Tune c = best;
@@ -2091,6 +2122,7 @@ int ci_autotune(ci_ctx* ctx, const ci_segment* seg, const ci_tparams* d_params, 
     out->candidates = cands;
     out->rejected = rejected;
     out->streams = best.streams;
+    out->p2_wave = best.p2_wave;
   }
   return CI_OK;
 }

@@ -58,6 +58,7 @@ struct Tune {
   int p2_per_cu = 2;     // resident pass-2 workgroups per CU (0: as many as fit)
   int64_t batch = 0;     // templates per batch (0: by intermediate size)
   int streams = 2;       // compute streams the batches alternate over (1 or 2)
+  int p2_wave = 0;       // FP32 second pass with wave-owned columns (n1 512, 1024)
   bool tuned = false;    // chosen by the autotuner
 };
 
@@ -197,11 +198,15 @@ struct BatchArgs {
   // series mode
   float2* d_z;                // first template's series
   int p2_per_cu;              // pass-2 workgroups per CU (0: as many as fit)
+  int p2_wave;                // FP32 second pass with wave-owned columns
   int precision;              // CI_FP32 | CI_SPLIT_BF16 | CI_SPLIT_FP16
   // two-polarization templates (null td: the frequency-domain chirp)
   const ci_tdparams* td;      // batch's first template
   float2* uv;                 // [bmax][n] template transform of this slot set
   double* sig;                // [bmax][kTdChunks][2] sigma^2 partials
+  // timing: when set, the next transform-pass launch records these at its
+  // start and end
+  hipEvent_t ev0, ev1;
 };
 
 hipError_t launch_pass1(const BatchArgs& a, bool zero_trig, hipStream_t st);

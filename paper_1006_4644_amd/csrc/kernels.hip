@@ -11,6 +11,7 @@
 // Template normalisation (sigma^2) is one lookup in the chunk's FP64
 // running sum; the chirp phase is evaluated in FP64 and reduced mod 2 pi
 // before FP32 trigonometry.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include "ci_impl.h"
@@ -1062,6 +1063,177 @@ __global__ __launch_bounds__(J * N1 / 16, 4) void k_pass2_trig(P2Args a) {
   }
 }
 
+// Completion of this wave's LDS operations (the exchange rows are private
+// to the wave, so no workgroup barrier is needed).
+__device__ __forceinline__ void wave_lds_sync() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
+
+// ---------------------------------------------------------------------------
+// pass 2 with wave-owned columns after the first stage (FP32, N1 = 512 or
+// 1024)
+// ---------------------------------------------------------------------------
+// The column DFT of k_pass2_trig with the same arithmetic in the same order,
+// laid out so that only one exchange crosses waves.  Lanes load and run
+// stage 1 as there (column cc = tid % J, t = tid / J: coalesced 512-byte
+// reads of the intermediate).  The exchange after stage 1 hands every
+// column to Lp consecutive lanes of one wave (cb = tid / Lp, tb = tid %
+// Lp); the exchange between stage 2 and the radix-R3 stage then stays
+// inside the wave (its own column's LDS, no workgroup barrier), and the
+// post-pass reduces per wave (one peak partial per wave).  Two workgroup
+// barriers per tile instead of five.
+// LDS: column-major exchange regions of X float2 per column.  Exchange 1
+// stores (row a, position t) of column c at c X + a S1 + t; exchange 2
+// stores (row d, position s) at c X + s RS + d.  The paddings make the
+// stores and loads of each exchange touch distinct banks for 32
+// consecutive lanes.
+template <int N1, int J>
+struct WaveCol {
+  static constexpr int L = N1, Lp = L / 16, R3 = L / 256;
+  static_assert(R3 == 2 || R3 == 4, "N1 = 512 or 1024");
+  static_assert((J * Lp) % 64 == 0, "whole waves");
+  static constexpr int S1 = Lp + R3;
+  static constexpr int X = 16 * S1 + 32 / J;
+  static constexpr int RS = L / R3 + 32 / R3;
+  static_assert(R3 * RS <= X, "exchange 2 fits the column region");
+  static constexpr int NW = J * Lp / 64;      // waves per workgroup
+  static constexpr size_t lds_bytes() { return (size_t)(J * X + N1) * sizeof(float2); }
+};
+
+template <int N1, int N2, int C, int J>
+__global__ __launch_bounds__(J * N1 / 16, 4) void k_pass2w(P2Args a) {
+  using W = WaveCol<N1, J>;
+  constexpr int Lp = W::Lp, R3 = W::R3, S1 = W::S1, X = W::X, RS = W::RS;
+  constexpr int TILES = N2 / J;
+  extern __shared__ float2 lds[];
+  const unsigned tid = threadIdx.x;
+  const unsigned cc = tid % J, t = tid / J;         // load / stage-1 layout
+  const unsigned cb = tid / Lp, tb = tid % Lp;      // stage-2 / stage-3 layout
+  const unsigned a0 = tb / R3, s2 = tb % R3;
+  const unsigned lane = tid & 63, wave = tid >> 6;
+  const int total = a.nb * TILES;
+
+  float2* twl = lds + J * X;
+  for (unsigned e = tid; e < (unsigned)N1; e += blockDim.x) twl[e] = a.tw[e * (2048 / N1)];
+  __syncthreads();
+
+  float2 xn[16];
+  const int G = gridDim.x;
+  int item = blockIdx.x;
+  if (item < total) load_item<N1, N2, C, J>(xn, a, item, cc, t);
+  for (; item < total; item += G) {
+    float2 x[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) x[r] = xn[r];
+    if (item + G < total) load_item<N1, N2, C, J>(xn, a, item + G, cc, t);
+    const int b = item / TILES, tile = item % TILES;
+
+    // stage 1: radix 16 over m, twiddle w_L^{a t}
+    idft16(x);
+    {
+      const char* twb = reinterpret_cast<const char*>(twl);
+      const unsigned step = t * (unsigned)sizeof(float2);
+      unsigned off = 0;
+#pragma unroll
+      for (int q = 1; q < 16; ++q) {
+        off += step;
+        x[q] = cmul(x[q], *reinterpret_cast<const float2*>(twb + off));
+      }
+    }
+    // exchange 1 (across waves): the previous tile's column regions are
+    // free once every wave is past its exchange 2
+    __syncthreads();
+    {
+      float2* pw = lds + cc * X + t;
+#pragma unroll
+      for (int q = 0; q < 16; ++q) pw[q * S1] = x[q];
+    }
+    __syncthreads();
+    // stage 2: row a0, positions s2 + R3 q; radix 16 over q, twiddle
+    // w_{16 R3}^{a2 s2}
+    {
+      const float2* pr = lds + cb * X + a0 * S1 + s2;
+#pragma unroll
+      for (int q = 0; q < 16; ++q) x[q] = pr[q * R3];
+    }
+    idft16(x);
+    {
+      const char* twb = reinterpret_cast<const char*>(twl);
+      const unsigned step = s2 * 16u * (unsigned)sizeof(float2);
+      unsigned off = 0;
+#pragma unroll
+      for (int a2 = 1; a2 < 16; ++a2) {
+        off += step;
+        x[a2] = cmul(x[a2], *reinterpret_cast<const float2*>(twb + off));
+      }
+    }
+    // exchange 2 (inside the wave, in its own column region, which no
+    // other wave reads): row d = a0 + 16 a2 at position s2, then rows
+    // d = tb + Lp i at every position s
+    {
+      float2* pw = lds + cb * X + s2 * RS + a0;
+#pragma unroll
+      for (int a2 = 0; a2 < 16; ++a2) pw[16 * a2] = x[a2];
+    }
+    wave_lds_sync();
+    {
+      const float2* pr = lds + cb * X + tb;
+#pragma unroll
+      for (int s = 0; s < R3; ++s)
+#pragma unroll
+        for (int i = 0; i < 16 / R3; ++i) x[i * R3 + s] = pr[s * RS + Lp * i];
+    }
+    idft_groups<R3>(x);
+
+    // post-pass of this wave's samples: register r holds j1 = tb +
+    // Col::off(r) of column j2 = tile J + cb
+    using K = Col<N1, J>;
+    const unsigned j2 = tile * J + cb;
+    auto jof = [&](int kk) {
+      return j2 + (unsigned)N2 * (unsigned)K::out((int)tb, K::reg_by_order(kk));
+    };
+    float r2[16];
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk) {
+      const float2 z = x[K::reg_by_order(kk)];
+      r2[kk] = fmaf(z.x, z.x, z.y * z.y);
+    }
+    if (!a.full) {
+#pragma unroll
+      for (int kk = 0; kk < 16; ++kk) {
+        const int j = (int)jof(kk);
+        if (j < a.jlo32 || j >= a.jhi32) r2[kk] = -1.f;
+      }
+    }
+    float m = r2[0];
+#pragma unroll
+    for (int kk = 1; kk < 16; ++kk) m = fmaxf(m, r2[kk]);
+    if (__any(m > a.thr2)) {
+      u64* wk = a.wkeys + (size_t)b * a.nwin;
+#pragma unroll
+      for (int kk = 0; kk < 16; ++kk) {
+        if (r2[kk] > a.thr2) {
+          const unsigned j = jof(kk);
+          const u64 key = ((u64)__float_as_uint(r2[kk]) << 32) | (u64)(0xFFFFFFFFu - j);
+          atomicMax(&wk[j / a.win32], key);
+        }
+      }
+    }
+    float M = m;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) M = fmaxf(M, __shfl_xor(M, o, 64));
+    unsigned jm = 0xFFFFFFFFu;
+    if (M >= 0.f && m == M) {
+#pragma unroll
+      for (int kk = 15; kk >= 0; --kk)
+        if (r2[kk] == M) jm = jof(kk);
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) jm = min(jm, (unsigned)__shfl_xor((int)jm, o, 64));
+    if (lane == 0)
+      a.ppart[((size_t)b * TILES + tile) * W::NW + wave] =
+          M >= 0.f ? (((u64)__float_as_uint(M) << 32) | (u64)(0xFFFFFFFFu - jm)) : 0ull;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // split-precision second pass: a radix-R3 stage on the vector units, then
 // two radix-16 DFT-matrix stages on the matrix cores.  For a column of
@@ -1122,9 +1294,6 @@ __device__ __forceinline__ void idft_r(float2 (&x)[R]) {
   }
 }
 
-// Completion of this wave's LDS operations (the exchange rows are private
-// to the wave, so no workgroup barrier is needed).
-__device__ __forceinline__ void wave_lds_sync() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
 
 constexpr int kXS = 18;  // row stride (complex) of the stage-C exchange
 
@@ -1606,6 +1775,12 @@ P1Args make_p1(const BatchArgs& a, bool zero_trig) {
   return p;
 }
 
+// The wave-owned-column second pass applies to FP32 searches at n1 = 512
+// or 1024.
+bool uses_p2_wave(const BatchArgs& a) {
+  return a.p2_wave && a.precision == CI_FP32 && !a.d_z && (a.plan.n1 == 512 || a.plan.n1 == 1024);
+}
+
 P2Args make_p2(const BatchArgs& a) {
   P2Args p;
   const int s = a.slot;
@@ -1625,8 +1800,10 @@ P2Args make_p2(const BatchArgs& a) {
   p.y = a.y;
   p.t0 = a.t0;
   p.nb = a.nb;
-  p.ntile2 = a.plan.n2 / a.plan.j;
-  p.ppart = a.tw.ppart ? a.tw.ppart + (size_t)s * a.bmax * p.ntile2 : nullptr;
+  // peak partials per template: one per second-pass workgroup, or one per
+  // wave with wave-owned columns; slot sets are sized for n2 per template
+  p.ntile2 = uses_p2_wave(a) ? a.plan.n2 * (a.plan.n1 / 16) / 64 : a.plan.n2 / a.plan.j;
+  p.ppart = a.tw.ppart ? a.tw.ppart + (size_t)s * a.bmax * a.plan.n2 : nullptr;
   p.wkeys = a.tw.wkeys ? a.tw.wkeys + (size_t)s * a.bmax * a.nwin : nullptr;
   p.bdone = a.tw.bdone ? a.tw.bdone + s : nullptr;
   p.mkey = a.tw.mkey ? a.tw.mkey + (size_t)s * a.nwin : nullptr;
@@ -1656,6 +1833,18 @@ P2Args make_p2(const BatchArgs& a) {
           : a.precision == CI_SPLIT_FP16 ? a.seg->mxa2[1]
                                          : nullptr;
   return p;
+}
+
+// Launch on st; with the batch's timing events set, the launch itself
+// records them when it starts and ends (no separate event packets).
+template <typename K, typename Arg>
+hipError_t launch_timed(K kern, dim3 grid, dim3 block, size_t lds, hipStream_t st,
+                        const BatchArgs& a, const Arg& arg) {
+  if (a.ev0)
+    hipExtLaunchKernelGGL(kern, grid, block, (uint32_t)lds, st, a.ev0, a.ev1, 0u, arg);
+  else
+    hipLaunchKernelGGL(kern, grid, block, lds, st, arg);
+  return hipGetLastError();
 }
 
 // Whether a kernel's dynamic plus static LDS fits one workgroup's limit.
@@ -1688,6 +1877,8 @@ struct Inst {
                      (size_t)(Col<N1, J>::LDS_ELEMS + N1) * sizeof(float2));
       if (e == hipSuccess)
         e = lds_fits(k_pass2_series<N1, N2, C, J>, (size_t)Col<N1, J>::LDS_ELEMS * sizeof(float2));
+      if constexpr (N1 == 512 || N1 == 1024)
+        if (e == hipSuccess) e = lds_fits(k_pass2w<N1, N2, C, J>, WaveCol<N1, J>::lds_bytes());
     } else if (precision == CI_SPLIT_BF16) {
       e = lds_fits(k_pass1<N1, N2, C, true>, (size_t)(Col<N2, C>::LDS_ELEMS + N2) * sizeof(float2));
       if (e == hipSuccess) e = lds_fits(k_p2mx<N1, N2, C, J, kBF16, 0>, p2mx_lds_bytes<N1>(J));
@@ -1710,9 +1901,8 @@ struct Inst {
     auto kern = k_pass1<N1, N2, C, H>;
     hipError_t e = set_lds(kern, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(kern, dim3((unsigned)(a.nb * (N1 / C))), dim3(C * N2 / 16), lds, st,
-                       make_p1(a, zero));
-    return hipGetLastError();
+    return launch_timed(kern, dim3((unsigned)(a.nb * (N1 / C))), dim3(C * N2 / 16), lds, st, a,
+                        make_p1(a, zero));
   }
   template <int MODE>
   static hipError_t p1mem(const BatchArgs& a, bool zero, hipStream_t st) {
@@ -1720,9 +1910,8 @@ struct Inst {
     auto kern = k_pass1_mem<N1, N2, C, MODE>;
     hipError_t e = set_lds(kern, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(kern, dim3((unsigned)(a.nb * (N1 / C))), dim3(C * N2 / 16), lds, st,
-                       make_p1(a, zero));
-    return hipGetLastError();
+    return launch_timed(kern, dim3((unsigned)(a.nb * (N1 / C))), dim3(C * N2 / 16), lds, st, a,
+                        make_p1(a, zero));
   }
   static hipError_t p2t(const BatchArgs& a, hipStream_t st) {
     const size_t lds = (size_t)(Col<N1, J>::LDS_ELEMS + N1) * sizeof(float2);
@@ -1744,8 +1933,33 @@ struct Inst {
     long long grid = (long long)wpc * cus;
     if (grid > items) grid = items;
     if (grid < 1) grid = 1;
-    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(J * N1 / 16), lds, st, make_p2(a));
-    return hipGetLastError();
+    return launch_timed(kern, dim3((unsigned)grid), dim3(J * N1 / 16), lds, st, a, make_p2(a));
+  }
+  static hipError_t p2w(const BatchArgs& a, hipStream_t st) {
+    if constexpr (N1 == 512 || N1 == 1024) {
+      using W = WaveCol<N1, J>;
+      const size_t lds = W::lds_bytes();
+      auto kern = k_pass2w<N1, N2, C, J>;
+      hipError_t e = set_lds(kern, lds);
+      if (e != hipSuccess) return e;
+      static int per_cu = 0, cus = 0;
+      if (per_cu == 0) {
+        int dev = 0;
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, J * N1 / 16, lds);
+        if (e == hipSuccess) e = hipGetDevice(&dev);
+        if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e != hipSuccess) return e;
+        if (per_cu < 1) per_cu = 1;
+      }
+      const int wpc = (a.p2_per_cu > 0 && a.p2_per_cu < per_cu) ? a.p2_per_cu : per_cu;
+      const long long items = (long long)a.nb * (N2 / J);
+      long long grid = (long long)wpc * cus;
+      if (grid > items) grid = items;
+      if (grid < 1) grid = 1;
+      return launch_timed(kern, dim3((unsigned)grid), dim3(J * N1 / 16), lds, st, a, make_p2(a));
+    } else {
+      return p2t(a, st);
+    }
   }
   template <int PREC, int MODE>
   static hipError_t p2mx(const BatchArgs& a, hipStream_t st) {
@@ -1767,8 +1981,7 @@ struct Inst {
     long long grid = (long long)wpc * cus;
     if (grid > items) grid = items;
     if (grid < 1) grid = 1;
-    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(J * 64), lds, st, make_p2(a));
-    return hipGetLastError();
+    return launch_timed(kern, dim3((unsigned)grid), dim3(J * 64), lds, st, a, make_p2(a));
   }
   static hipError_t fin(const BatchArgs& a, hipStream_t st) {
     hipLaunchKernelGGL((k_fin<N1, N2, C>), dim3((unsigned)a.nb), dim3(256), kFinLds, st,
@@ -1780,9 +1993,8 @@ struct Inst {
     auto kern = k_pass2_series<N1, N2, C, J>;
     hipError_t e = set_lds(kern, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(kern, dim3((unsigned)(a.nb * (N2 / J))), dim3(J * N1 / 16), lds, st,
-                       make_p2(a));
-    return hipGetLastError();
+    return launch_timed(kern, dim3((unsigned)(a.nb * (N2 / J))), dim3(J * N1 / 16), lds, st, a,
+                        make_p2(a));
   }
 };
 
@@ -1961,6 +2173,7 @@ hipError_t launch_pass2_trig(const BatchArgs& a, hipStream_t st) {
     typedef decltype(inst) I;
     if (a.precision == CI_SPLIT_BF16) return I::template p2mx<kBF16, 0>(a, st);
     if (a.precision == CI_SPLIT_FP16) return I::template p2mx<kFP16, 0>(a, st);
+    if (uses_p2_wave(a)) return I::p2w(a, st);
     return I::p2t(a, st);
   });
 }

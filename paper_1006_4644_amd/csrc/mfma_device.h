@@ -77,7 +77,8 @@ __device__ __forceinline__ void split8(const float (&v)[8], typename MxT<PREC>::
 // part as FP16 and writes its FP16 result into its half of the packed word.
 template <int PREC>
 __device__ __forceinline__ void split8t(const float (&v)[8], typename MxT<PREC>::v8& hi,
-                                        typename MxT<PREC>::v8& lo) {
+                                        typename MxT<PREC>::v8& lo,
+                                        float pre = MxT<PREC>::kPre) {
   if constexpr (PREC == kBF16) {
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
@@ -90,7 +91,7 @@ __device__ __forceinline__ void split8t(const float (&v)[8], typename MxT<PREC>:
     unsigned hw[4], lw[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const float a = v[2 * i] * MxT<PREC>::kPre, b = v[2 * i + 1] * MxT<PREC>::kPre;
+      const float a = v[2 * i] * pre, b = v[2 * i + 1] * pre;
       h2 h;
       h.x = (_Float16)a;
       h.y = (_Float16)b;
@@ -114,12 +115,36 @@ __device__ __forceinline__ void split8t(const float (&v)[8], typename MxT<PREC>:
 // matrix rows [Re, -Im] (real outputs) and [Im, Re] (imaginary outputs),
 // high and low parts: A[0] re_hi, A[1] re_lo, A[2] im_hi, A[3] im_lo.
 // Returns outputs v = 4 g .. 4 g + 3 of instance j.
+//
+// FP16 range: the 2^6 pre-scale keeps FP16 operands finite while an
+// instance's inputs stay below 2^9 in magnitude.  When any input of a wave
+// exceeds that (a loud signal or glitch), each instance whose largest input
+// does gets its own power-of-two scale 2^(14 - floor(log2 max)) instead,
+// which puts its largest operand in [2^14, 2^15); its outputs are scaled
+// back exactly.  Instances below the limit keep the 2^6 pre-scale, so their
+// results are unchanged bit for bit, and the scale depends only on the
+// instance's own inputs (not on the launch configuration).
+constexpr float kF16Lim = 512.0f;
+
 template <int PREC>
 __device__ __forceinline__ void mx_prod(const typename MxT<PREC>::v8 (&A)[4], const float (&v)[8],
                                         f32x4& yr, f32x4& yi) {
   typedef MxT<PREC> M;
+  float pre = M::kPre;
+  if constexpr (PREC == kFP16) {
+    float m = 0.f;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) m = fmaxf(m, fabsf(v[e]));
+    if (__any(!(m <= kF16Lim))) {
+      // the instance's four lanes (l, l ^ 16, l ^ 32, l ^ 48) agree on it
+      m = fmaxf(m, __shfl_xor(m, 16, 64));
+      m = fmaxf(m, __shfl_xor(m, 32, 64));
+      // m = f 2^e with f in [1/2, 1): 2^(15 - e) m lies in [2^14, 2^15)
+      if (!(m <= kF16Lim)) pre = __builtin_amdgcn_ldexpf(1.0f, 15 - __builtin_amdgcn_frexp_expf(m));
+    }
+  }
   typename M::v8 bh, bl;
-  split8t<PREC>(v, bh, bl);
+  split8t<PREC>(v, bh, bl, pre);
   f32x4 z = {0.f, 0.f, 0.f, 0.f};
   yr = M::mma(A[0], bh, z);
   yi = M::mma(A[2], bh, z);
@@ -128,7 +153,7 @@ __device__ __forceinline__ void mx_prod(const typename MxT<PREC>::v8 (&A)[4], co
   yr = M::mma(A[1], bh, yr);
   yi = M::mma(A[3], bh, yi);
   if constexpr (M::kPre != 1.0f) {
-    constexpr float inv = 1.0f / M::kPre;
+    const float inv = 1.0f / pre;  // a power of two: exact
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       yr[e] *= inv;

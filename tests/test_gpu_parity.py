@@ -340,6 +340,52 @@ def test_tile_shapes(ctx, tc, tj, log2n):
     seg.close()
 
 
+@pytest.mark.parametrize("tj", [4, 8])
+@pytest.mark.parametrize("log2n", [17, 18, 19, 20])
+def test_second_pass_wave_columns(ctx, tj, log2n):
+    """The FP32 second pass with wave-owned columns after its first stage
+    (p2_wave) gives the default second pass's peaks and trigger lists bit
+    for bit (merged and unmerged, full and restricted search ranges), and
+    the oracle's peaks."""
+    n, fs, fl = 1 << log2n, 4096.0, 20.0
+    bank = synth.draw_masses(6, 1.0, 20.0, "loguniform", 77 + 3 * tj + log2n)
+    inj = synth.InjectionSpec(float(bank[2, 0]), float(bank[2, 1]), 12.0,
+                              n // 3 + 11, 0.7, 2)
+    x64, psd, x128 = C.make_case(n, fs, fl, bank, [inj], 3000 + log2n)
+    seg = _segment(ctx, x64, psd, n, fs, fl)
+    params = ctx.gen_templates(seg, bank)
+    cases = [dict(merge=False), dict(merge=True),
+             dict(merge=False, j_lo=n // 7 + 5, j_hi=n - n // 5 - 3)]
+    cap = 4096
+
+    def run():
+        out = []
+        for kw in cases:
+            p, t, c = ctx.find_triggers(seg, params, 4.0, 2048, cap=cap, **kw)
+            out.append((p, t, c))
+        _sync()
+        return [(p.cpu().numpy().copy(), t.cpu().numpy()[:min(int(c.cpu()[0]), cap)].copy(),
+                 int(c.cpu()[0])) for p, t, c in out]
+
+    ctx.set_tune(log2n, ci.FP32, 8, tj, 0, 0, streams=1)
+    try:
+        ref = run()
+        ctx.set_tune(log2n, ci.FP32, 8, tj, 0, 0, streams=1, p2_wave=1)
+        got = run()
+        assert ctx.get_tune(log2n, ci.FP32)["p2_wave"] == 1
+    finally:
+        ctx.set_tune(log2n, ci.FP32)
+    for (p0, t0, c0), (p1, t1, c1) in zip(ref, got):
+        assert c0 == c1 and c0 > 0
+        assert np.array_equal(p0, p1)
+        assert np.array_equal(t0, t1)
+    P = got[0][0].view(ci.TRIGGER_DTYPE).reshape(-1)
+    for i, (m1, m2) in enumerate(bank):
+        zo, _ = C.oracle_series(x128, psd, n, fs, fl, m1, m2)
+        C.check_peak(P[i], zo)
+    seg.close()
+
+
 # --------------------------------------------------------------------------
 # split-precision path: radix-16 stages on the matrix cores (bar: 1e-3)
 # --------------------------------------------------------------------------
@@ -372,6 +418,44 @@ def test_split_precision_series(ctx, prec, log2n):
         C.check_peak(P[i], zo, tol=TOL_SPLIT)
         C.check_triggers(T[T["tmpl"] == i], zo, 4096, 6.0, tol=TOL_SPLIT)
     assert abs(int(P[0]["index"]) - inj.j0) <= 2
+    seg.close()
+
+
+@pytest.mark.parametrize("prec", [ci.SPLIT_BF16, ci.SPLIT_FP16])
+@pytest.mark.parametrize("snr", [5.0e3, 5.0e4])
+@pytest.mark.parametrize("log2n", [16, 20])
+def test_split_precision_loud_signal(ctx, prec, snr, log2n):
+    """A loud chirp (optimal SNR 5e3 or 5e4, far above the 2^9 limit of
+    the FP16 operands' fixed 2^6 pre-scale in the last matrix-core stages):
+    the matrix-core instances whose inputs exceed the limit take their own
+    power-of-two scale, so the series, the peak and the triggers stay at
+    the split bar (relative to the series maximum and to each trigger's
+    own rho) on both split paths."""
+    n, fs, fl = 1 << log2n, 4096.0, 20.0
+    bank = synth.draw_masses(2, 1.0, 8.0, "loguniform", 900 + log2n)
+    inj = synth.InjectionSpec(float(bank[0, 0]), float(bank[0, 1]), snr,
+                              n // 4 + 17, 0.9, 0)
+    x64, psd, x128 = C.make_case(n, fs, fl, bank, [inj], 3100 + log2n)
+    seg = _segment(ctx, x64, psd, n, fs, fl)
+    params = ctx.gen_templates(seg, bank)
+    z = ctx.matched_filter(seg, params, precision=prec)
+    thr = 0.01 * snr
+    peaks, trig, cnt = ctx.find_triggers(seg, params, thr, 4096, cap=4096, precision=prec)
+    _sync()
+    zg = z.cpu().numpy()
+    assert np.all(np.isfinite(zg))
+    P = ci.triggers_to_numpy(peaks)
+    T = ci.triggers_to_numpy(trig, int(cnt.cpu()[0]))
+    for i, (m1, m2) in enumerate(bank):
+        zo, _ = C.oracle_series(x128, psd, n, fs, fl, m1, m2)
+        e = C.series_error(zg[i], zo)
+        print(f"precision {prec} snr {snr:g} n 2^{log2n} template {i}: series error {e:.2e}, "
+              f"max rho {np.max(np.abs(zo)):.4g}")
+        assert e <= TOL_SPLIT, e
+        C.check_peak(P[i], zo, tol=TOL_SPLIT)
+        C.check_triggers(T[T["tmpl"] == i], zo, 4096, thr, tol=TOL_SPLIT)
+    assert int(P[0]["index"]) == inj.j0
+    assert abs(np.sqrt(P[0]["rho2"]) / snr - 1) < 0.01
     seg.close()
 
 
