@@ -548,9 +548,19 @@ int enqueue_jobs(Ctx* ctx, const std::vector<Job>& jobs, size_t slot_elems, int3
     e = launch_init_call(jb.tw, (int)jb.nwin, jb.count, st);
     if (e != hipSuccess) return hipfail(ctx, e, "init launch");
   }
+  // In-order configurations (one compute stream for every job) run their
+  // passes on st itself; the finalisers still overlap the next batch on
+  // ws[2], except the last, which runs on st once the one before it is done
+  // (so nothing has to join back).
+  bool inorder = !chain;
+  int64_t nbatch = 0;
+  for (const Job& jb : jobs) {
+    if (jb.n > 0) nbatch += (jb.n + jb.B - 1) / jb.B;
+    if (jb.n > 0 && jb.cfg.streams != 1) inorder = false;
+  }
   if (!chain) {
     e = hipEventRecord(ctx->fork_ev, st);
-    for (int i = 0; i < 3 && e == hipSuccess; ++i)
+    for (int i = inorder ? 2 : 0; i < 3 && e == hipSuccess; ++i)
       e = hipStreamWaitEvent(ctx->ws[i], ctx->fork_ev, 0);
     if (e != hipSuccess) return hipfail(ctx, e, "stream fork");
   }
@@ -578,7 +588,7 @@ int enqueue_jobs(Ctx* ctx, const std::vector<Job>& jobs, size_t slot_elems, int3
     a.p2_per_cu = jb.cfg.p2_per_cu;
     a.p2_wave = jb.cfg.p2_wave;
     for (int64_t t0 = 0; t0 < jb.n; ++b, t0 += jb.B) {
-      hipStream_t sb = chain ? st : ctx->ws[jb.cfg.streams == 1 ? 0 : (b & 1)];
+      hipStream_t sb = (chain || inorder) ? st : ctx->ws[jb.cfg.streams == 1 ? 0 : (b & 1)];
       const int slot = (int)(b % kSlots);
       a.t0 = t0;
       a.nb = (int)((jb.n - t0) < jb.B ? (jb.n - t0) : jb.B);
@@ -602,20 +612,27 @@ int enqueue_jobs(Ctx* ctx, const std::vector<Job>& jobs, size_t slot_elems, int3
       if (e != hipSuccess) return hipfail(ctx, e, "pass-1 launch");
       e = timed(ctx, 1, a.nb, sb, a, [&] { return launch_pass2_trig(a, sb); });
       if (e != hipSuccess) return hipfail(ctx, e, "pass-2 launch");
-      if (!chain) {
+      const bool last_on_st = inorder && b == nbatch - 1;
+      if (last_on_st) {
+        // after the previous finaliser (batch order keeps the lists ordered)
+        if (b > 0) {
+          e = hipStreamWaitEvent(st, ctx->fin_done[(b - 1) % kSlots], 0);
+          if (e != hipSuccess) return hipfail(ctx, e, "finaliser ordering");
+        }
+      } else if (!chain) {
         e = hipEventRecord(ctx->p2_done[slot], sb);
         if (e == hipSuccess) e = hipStreamWaitEvent(sf, ctx->p2_done[slot], 0);
         if (e != hipSuccess) return hipfail(ctx, e, "finaliser ordering");
       }
-      e = launch_fin(a, sf);
+      e = launch_fin(a, last_on_st ? st : sf);
       if (e != hipSuccess) return hipfail(ctx, e, "finalise launch");
-      if (!chain) {
+      if (!chain && !last_on_st) {
         e = hipEventRecord(ctx->fin_done[slot], sf);
         if (e != hipSuccess) return hipfail(ctx, e, "finaliser event");
       }
     }
   }
-  if (!chain) {
+  if (!chain && !inorder) {
     for (int i = 0; i < 3 && e == hipSuccess; ++i) {
       e = hipEventRecord(ctx->join_ev[i], ctx->ws[i]);
       if (e == hipSuccess) e = hipStreamWaitEvent(st, ctx->join_ev[i], 0);
