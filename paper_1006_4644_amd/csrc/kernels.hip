@@ -1308,7 +1308,7 @@ constexpr size_t p2mx_lds_bytes(int J) {
 // X[u0 + 16 (4 g + e) + 256 p] (e < 4, p < R3) from the FP16 intermediate.
 // MODE 0: post-pass (peaks and window keys); MODE 1: store the series.
 template <int N1, int N2, int C, int J, int PREC, int MODE>
-__global__ __launch_bounds__(J * 64) void k_p2mx(P2Args a) {
+__global__ __launch_bounds__(J * 64, N1 <= 1024 ? 4 : 1) void k_p2mx(P2Args a) {
   constexpr int L = N1, R3 = L / 256, N = N1 * N2, TILES = N2 / J;
   typedef typename MxT<PREC>::v8 V8;
   extern __shared__ float2 lds[];
@@ -1348,6 +1348,19 @@ __global__ __launch_bounds__(J * 64) void k_p2mx(P2Args a) {
 #pragma unroll
         for (int e = 0; e < 4; ++e) x[p][e] = h2f(raw[p][e]);
     }
+    // FP16 operand range: the radix-R3 stage and a radix-16 stage grow
+    // magnitudes by at most 16 R3, so inputs within kF16Lim / (16 R3) keep
+    // every operand of both matrix-core stages within the limit and the
+    // per-instance check can be skipped for this tile
+    bool guard = false;
+    if constexpr (PREC == kFP16) {
+      float m = 0.f;
+#pragma unroll
+      for (int p = 0; p < R3; ++p)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) m = fmaxf(m, fmaxf(fabsf(x[p][e].x), fabsf(x[p][e].y)));
+      guard = __any(!(m <= kF16Lim / (16.0f * R3)));
+    }
     // stage A: radix-R3 over p
     if constexpr (R3 > 1) {
 #pragma unroll
@@ -1373,7 +1386,7 @@ __global__ __launch_bounds__(J * 64) void k_p2mx(P2Args a) {
         v[2 * e + 1] = x[b][e].y;
       }
       f32x4 yr, yi;
-      mx_prod<PREC>(A4, v, yr, yi);
+      mx_prod<PREC>(A4, v, yr, yi, guard);
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const unsigned E = (u0 * (unsigned)(b + R3 * (4 * g + e))) & (L - 1);
@@ -1392,7 +1405,7 @@ __global__ __launch_bounds__(J * 64) void k_p2mx(P2Args a) {
       wave_lds_sync();
       const float v[8] = {r0.x, r0.y, r0.z, r0.w, r1.x, r1.y, r1.z, r1.w};
       f32x4 yr, yi;
-      mx_prod<PREC>(wc, v, yr, yi);
+      mx_prod<PREC>(wc, v, yr, yi, guard);
 #pragma unroll
       for (int e = 0; e < 4; ++e) x[b][e] = make_float2(yr[e], yi[e]);
     }

@@ -126,12 +126,15 @@ __device__ __forceinline__ void split8t(const float (&v)[8], typename MxT<PREC>:
 // instance's own inputs (not on the launch configuration).
 constexpr float kF16Lim = 512.0f;
 
+// guard: false when the caller has shown that no input of this wave can
+// exceed the limit (the per-instance check is then skipped).
 template <int PREC>
 __device__ __forceinline__ void mx_prod(const typename MxT<PREC>::v8 (&A)[4], const float (&v)[8],
-                                        f32x4& yr, f32x4& yi) {
+                                        f32x4& yr, f32x4& yi, bool guard = true) {
   typedef MxT<PREC> M;
   float pre = M::kPre;
   if constexpr (PREC == kFP16) {
+    if (!guard) goto split;
     float m = 0.f;
 #pragma unroll
     for (int e = 0; e < 8; ++e) m = fmaxf(m, fabsf(v[e]));
@@ -143,6 +146,7 @@ __device__ __forceinline__ void mx_prod(const typename MxT<PREC>::v8 (&A)[4], co
       if (!(m <= kF16Lim)) pre = __builtin_amdgcn_ldexpf(1.0f, 15 - __builtin_amdgcn_frexp_expf(m));
     }
   }
+split:
   typename M::v8 bh, bl;
   split8t<PREC>(v, bh, bl, pre);
   f32x4 z = {0.f, 0.f, 0.f, 0.f};
