@@ -66,6 +66,9 @@ def parse():
                    help="time budget of the CPU oracle baseline")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-copy-probe", action="store_true")
+    p.add_argument("--no-graph", action="store_true",
+                   help="skip timing the headline search as graph replays")
+    p.add_argument("--graph-replays", type=int, default=20)
     p.add_argument("--no-chisq", action="store_true",
                    help="skip timing the chi-squared veto at the per-template peaks")
     p.add_argument("--chisq-bands", type=int, default=16)
@@ -252,6 +255,37 @@ def cpu_baseline_all(pool, k, wl, budget_s):
             "sample": f"{done} seeded-random templates of the {wl.name} bank (noise-only "
                       f"spectrum), full per-template search, FP64 numpy, {k} processes "
                       f"of one thread side by side, {el:.1f} s each"}
+
+
+def graph_timing(ctx, seg, params, peaks, trig, count, cap, wl, prec, n_t, reps):
+    """The headline search alone (segment and parameters resident) as one
+    graph launch of the whole schedule, captured once and replayed: the
+    median of `reps` individually timed replays after three warm-ups."""
+    import torch
+    job = [dict(seg=seg, params=params, n=n_t, cap=cap, peaks=peaks, trig=trig,
+                count=count)]
+    for _ in range(3):
+        ctx.search_classes(job, wl.snr_threshold, wl.window, merge=True, precision=prec,
+                           graph=True)
+    torch.cuda.synchronize()
+    ms = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        ctx.search_classes(job, wl.snr_threshold, wl.window, merge=True, precision=prec,
+                           graph=True)
+        e1.record()
+        torch.cuda.synchronize()
+        ms.append(e0.elapsed_time(e1))
+    captures, launches = ctx.graph_stats()
+    med = float(np.median(ms))
+    log(f"[bench] graph replay: median {med:.3f} ms over {reps} replays "
+        f"({captures} capture(s), {launches} launches)")
+    return {"median_ms": round(med, 4), "min_ms": round(min(ms), 4),
+            "max_ms": round(max(ms), 4), "replays": reps, "captures": captures,
+            "templates_per_s": round(n_t / (med / 1e3), 1),
+            "path_hbm_frac": round(2.0 * 8 * wl.n * n_t / (med / 1e3) / 1e9 / HBM_PEAK_GBS, 4)
+            if prec == 0 else None}
 
 
 def chisq_timing(ctx, ci, seg, params, peaks, n_t, bands, reps=10):
@@ -661,6 +695,11 @@ def main():
                           "injection_peak_rho_rel_dev_vs_headline": dev,
                           "merged_windows": found}
         out["precision_paths"] = paths
+    # the graph leg times the headline-sized bank (a replay of a large bank
+    # would take seconds each)
+    if not args.no_graph and n_t <= 4096:
+        out["graph_replay"] = graph_timing(ctx, seg, params, peaks, trig, count, cap, wl,
+                                           prec_code, n_t, args.graph_replays)
     if not args.no_chisq:
         out["chisq_veto"] = chisq_timing(ctx, ci, seg, params, peaks, n_t, args.chisq_bands)
     if not args.no_stream:

@@ -185,6 +185,31 @@ def test_classes_graph_replay_many_batches(ctx, gpu_lib, merge):
         s["seg"].close()
 
 
+@pytest.mark.parametrize("prec", [ci.SPLIT_BF16, ci.SPLIT_FP16])
+def test_classes_graph_replay_split_precision(ctx, gpu_lib, prec):
+    """Graph replay of a split-precision schedule (matrix-core second pass,
+    FP16 intermediate), 8-template batches: three replays equal the eager
+    schedule bit for bit."""
+    fs, fl, thr, W, cap = 4096.0, 20.0, 4.0, 2048, 4096
+    classes = (1 << 16, 1 << 17)
+    bank = synth.draw_masses(24, 1.0, 12.0, "loguniform", 818 + prec)
+    cls, setup = _class_setup(ctx, gpu_lib, bank, classes, fs, fl, 9400)
+    ctx.set_batch(8)
+    try:
+        jobs = _fixed_outputs(_jobs(setup, cap), cap)
+        ref = _collect(ctx.search_classes(jobs, thr, W, merge=True, precision=prec), cap)
+        assert sum(r[2] for r in ref) > 0
+        g = _fixed_outputs(_jobs(setup, cap), cap)
+        for rep in range(3):
+            _poison(g)
+            _same(ref, _collect(ctx.search_classes(g, thr, W, merge=True, precision=prec,
+                                                   graph=True), cap))
+    finally:
+        ctx.set_batch(0)
+    for s in setup:
+        s["seg"].close()
+
+
 @pytest.mark.skip(reason="a stream capture of the 16384-template class schedule (59 batches "
                   "over two forked compute streams and a finaliser stream, slot sets reused "
                   "across streams) ended the process with a host segmentation fault inside "
