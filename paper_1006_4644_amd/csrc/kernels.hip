@@ -700,6 +700,36 @@ __device__ double2 wave_direct_z(const T* __restrict__ yb, const double2* __rest
   return make_double2(re, im);
 }
 
+// Wave-wide maximum / minimum through data-parallel-primitive lane moves
+// (no LDS round trips): pairs, quads, 8- and 16-lane mirrors within each
+// row of 16 lanes, then the row broadcasts carry each row's result into the
+// next rows; lane 63 ends with the wave's value, which is read back to every
+// lane.  Lanes a move cannot source keep their own value.
+template <typename T, typename F>
+__device__ __forceinline__ T wave_reduce(T v, F op) {
+  int x = __builtin_bit_cast(int, v);
+  x = __builtin_bit_cast(int, op(__builtin_bit_cast(T, x), __builtin_bit_cast(T,
+                         __builtin_amdgcn_update_dpp(x, x, 0xB1, 0xF, 0xF, false))));   // quad_perm 1,0,3,2
+  x = __builtin_bit_cast(int, op(__builtin_bit_cast(T, x), __builtin_bit_cast(T,
+                         __builtin_amdgcn_update_dpp(x, x, 0x4E, 0xF, 0xF, false))));   // quad_perm 2,3,0,1
+  x = __builtin_bit_cast(int, op(__builtin_bit_cast(T, x), __builtin_bit_cast(T,
+                         __builtin_amdgcn_update_dpp(x, x, 0x141, 0xF, 0xF, false))));  // row_half_mirror
+  x = __builtin_bit_cast(int, op(__builtin_bit_cast(T, x), __builtin_bit_cast(T,
+                         __builtin_amdgcn_update_dpp(x, x, 0x140, 0xF, 0xF, false))));  // row_mirror
+  x = __builtin_bit_cast(int, op(__builtin_bit_cast(T, x), __builtin_bit_cast(T,
+                         __builtin_amdgcn_update_dpp(x, x, 0x142, 0xA, 0xF, false))));  // row_bcast:15
+  x = __builtin_bit_cast(int, op(__builtin_bit_cast(T, x), __builtin_bit_cast(T,
+                         __builtin_amdgcn_update_dpp(x, x, 0x143, 0xC, 0xF, false))));  // row_bcast:31
+  return __builtin_bit_cast(T, __builtin_amdgcn_readlane(x, 63));
+}
+
+__device__ __forceinline__ float wave_max(float v) {
+  return wave_reduce(v, [](float a, float b) { return fmaxf(a, b); });
+}
+__device__ __forceinline__ unsigned wave_min(unsigned v) {
+  return wave_reduce(v, [](unsigned a, unsigned b) { return a < b ? a : b; });
+}
+
 __device__ __forceinline__ u64 aload(const u64* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -959,9 +989,7 @@ __device__ __forceinline__ void tile_post(const float (&r2)[K], JF jof, const P2
       }
     }
   }
-  float wm = m;
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) wm = fmaxf(wm, __shfl_xor(wm, off, 64));
+  const float wm = wave_max(m);
   if (lane == 0) s_m[wave] = wm;
   __syncthreads();
   float M = s_m[0];
@@ -974,8 +1002,7 @@ __device__ __forceinline__ void tile_post(const float (&r2)[K], JF jof, const P2
       for (int i = K - 1; i >= 0; --i)
         if (r2[i] == M) jm = jof(i);
     }
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) jm = min(jm, (unsigned)__shfl_xor((int)jm, off, 64));
+    jm = wave_min(jm);
   }
   if (lane == 0) s_j[wave] = jm;
   __syncthreads();
@@ -1217,17 +1244,14 @@ __global__ __launch_bounds__(J * N1 / 16, 4) void k_pass2w(P2Args a) {
         }
       }
     }
-    float M = m;
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) M = fmaxf(M, __shfl_xor(M, o, 64));
+    const float M = wave_max(m);
     unsigned jm = 0xFFFFFFFFu;
     if (M >= 0.f && m == M) {
 #pragma unroll
       for (int kk = 15; kk >= 0; --kk)
         if (r2[kk] == M) jm = jof(kk);
     }
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) jm = min(jm, (unsigned)__shfl_xor((int)jm, o, 64));
+    jm = wave_min(jm);
     if (lane == 0)
       a.ppart[((size_t)b * TILES + tile) * W::NW + wave] =
           M >= 0.f ? (((u64)__float_as_uint(M) << 32) | (u64)(0xFFFFFFFFu - jm)) : 0ull;
