@@ -214,6 +214,53 @@ def test_empty_template_and_cap_overflow(ctx, tiny):
     assert np.array_equal(ci.triggers_to_numpy(st, 3), M[:3])
 
 
+@pytest.mark.parametrize("prec", [ci.FP32, ci.SPLIT_BF16])
+def test_degenerate_searches(ctx, tiny, prec):
+    """Edge cases of the search, against the oracle: no templates; a zero
+    threshold (every window's maximum is a trigger); windows of one sample
+    (nwin = n) and of the whole series; a one-sample search range at the
+    end of the series; all-zero data (every sample ties at rho^2 = 0: the
+    peak is sample 0 and, the threshold being strict, nothing triggers)."""
+    import torch
+    wl, n = tiny["wl"], tiny["wl"].n
+    tol = C.TOL_FP32 if prec == ci.FP32 else 1e-3
+    seg, params, zo = tiny["seg"], tiny["params"], tiny["zo"]
+    nt = len(zo)
+    # no templates: nothing is written but the count
+    cnt0 = torch.full((1,), 7, dtype=torch.int64, device="cuda")
+    ctx.find_triggers(seg, params, 6.0, 4096, n=0, count=cnt0, precision=prec)
+    _sync()
+    assert int(cnt0.cpu()[0]) == 0
+    cases = [dict(thr=0.0, W=4096), dict(thr=3.5, W=1), dict(thr=3.0, W=n),
+             dict(thr=0.0, W=1000, j_lo=n - 1, j_hi=n)]
+    for cs in cases:
+        jl, jh = cs.get("j_lo", 0), cs.get("j_hi", 0)
+        cap = nt * ((n + cs["W"] - 1) // cs["W"])
+        peaks, trig, cnt = ctx.find_triggers(seg, params, cs["thr"], cs["W"], j_lo=jl, j_hi=jh,
+                                             cap=cap, precision=prec)
+        _sync()
+        P = ci.triggers_to_numpy(peaks)
+        T = ci.triggers_to_numpy(trig, int(cnt.cpu()[0]))
+        for i in range(nt):
+            C.check_peak(P[i], zo[i], tol=tol, j_lo=jl, j_hi=jh or None)
+            C.check_triggers(T[T["tmpl"] == i], zo[i], cs["W"], cs["thr"], tol=tol, j_lo=jl,
+                             j_hi=jh or None)
+        if cs["thr"] == 0.0:
+            # every window of the range has a trigger (the data has no zeros)
+            nw = len({j // cs["W"] for j in range(jl, jh or n)})
+            assert int(cnt.cpu()[0]) == nt * nw
+    # all-zero data
+    zero = np.zeros(n // 2 + 1, dtype=np.complex64)
+    zseg = _segment(ctx, zero, tiny["psd"], n, wl.fs, wl.f_low)
+    zpar = ctx.gen_templates(zseg, tiny["bank"])
+    peaks, trig, cnt = ctx.find_triggers(zseg, zpar, 0.0, 4096, cap=64, precision=prec)
+    _sync()
+    P = ci.triggers_to_numpy(peaks)
+    assert int(cnt.cpu()[0]) == 0
+    assert np.all(P["index"] == 0) and np.all(P["rho2"] == 0.0)
+    zseg.close()
+
+
 def test_argument_errors(ctx, tiny):
     with pytest.raises(ci.CiError) as ei:
         ctx.find_triggers(tiny["seg"], tiny["params"], 6.0, 0)
