@@ -69,6 +69,9 @@ def parse():
     p.add_argument("--no-graph", action="store_true",
                    help="skip timing the headline search as graph replays")
     p.add_argument("--graph-replays", type=int, default=20)
+    p.add_argument("--chunk", type=int, default=0,
+                   help="also search the bank in resumable chunks of this many templates "
+                        "(device merge across chunks) and compare with the single call")
     p.add_argument("--no-chisq", action="store_true",
                    help="skip timing the chi-squared veto at the per-template peaks")
     p.add_argument("--chisq-bands", type=int, default=16)
@@ -83,6 +86,9 @@ def parse():
                    help="arithmetic of the headline run")
     p.add_argument("--no-split", action="store_true",
                    help="skip the comparison runs at the other precisions")
+    p.add_argument("--tune-cache", default=os.environ.get("CI_TUNE_CACHE", ""),
+                   help="JSON cache of autotuned launch configurations, keyed by device, "
+                        "length and precision (default: $CI_TUNE_CACHE; empty: none)")
     p.add_argument("--no-autotune", action="store_true",
                    help="keep the default launch configuration")
     p.add_argument("--tune", default="",
@@ -92,9 +98,17 @@ def parse():
 
 
 def configure(ctx, ci, args, tune_calls):
-    """Launch configuration per (length, precision): explicit, autotuned
-    (tune_calls: [(seg, params, n, thr, window, log2n)]), or the default."""
+    """Launch configuration per (length, precision): explicit, from the
+    launch-configuration cache (--tune-cache, default $CI_TUNE_CACHE) when it
+    holds this device's entry, autotuned (tune_calls: [(seg, params, n, thr,
+    window, log2n)]; then written to the cache), or the default."""
     out = {}
+    cached, key = set(), None
+    if args.tune_cache and not args.tune and not args.no_autotune:
+        key = ci.device_key(0)
+        cached = set(ci.load_tune_cache(ctx, args.tune_cache, key))
+        if cached:
+            log(f"[bench] launch configurations from {args.tune_cache}: {sorted(cached)}")
     for prec_name, (prec, _) in PRECISIONS.items():
         if args.no_split and prec_name != args.precision:
             continue
@@ -104,7 +118,7 @@ def configure(ctx, ci, args, tune_calls):
                 ctx.set_tune(l2, prec, *v[:4], streams=v[4] if len(v) > 4 else 2,
                              p2_wave=v[5] if len(v) > 5 else 0)
                 cfg = ctx.get_tune(l2, prec)
-            elif args.no_autotune:
+            elif args.no_autotune or (l2, prec) in cached:
                 cfg = ctx.get_tune(l2, prec)
             else:
                 cfg = ctx.autotune(seg, params, thr, window, n=n, precision=prec)
@@ -112,6 +126,8 @@ def configure(ctx, ci, args, tune_calls):
                                           ("tile_c", "tile_j", "p2_per_cu", "batch", "streams",
                                            "p2_wave", "tuned")}
             log(f"[bench] launch configuration {prec_name} 2^{l2}: {out[f'{prec_name}/2^{l2}']}")
+    if key is not None:
+        ci.save_tune_cache(ctx, args.tune_cache, key)
     return out
 
 
@@ -255,6 +271,28 @@ def cpu_baseline_all(pool, k, wl, budget_s):
             "sample": f"{done} seeded-random templates of the {wl.name} bank (noise-only "
                       f"spectrum), full per-template search, FP64 numpy, {k} processes "
                       f"of one thread side by side, {el:.1f} s each"}
+
+
+def chunked_timing(ctx, ci, seg, bank, wl, prec, chunk, peaks, trig, count, cap):
+    """The bank in chunks of `chunk` templates (generator constants, merged
+    search and device merge per chunk, no checkpoint), timed once, and its
+    results compared with the headline step's single call (the last step of
+    the timed run left its outputs in peaks / trig / count)."""
+    import torch
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    p, m, k = ctx.search_bank_chunked(seg, bank, wl.snr_threshold, wl.window, chunk,
+                                      precision=prec)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    kk, kr = int(k.cpu()[0]), int(count.cpu()[0])
+    same = kk == kr and torch.equal(p, peaks[:len(bank)]) and \
+        torch.equal(m[:kk], trig[:min(kr, cap)])
+    log(f"[bench] chunked ({chunk} templates per chunk): {ms:.1f} ms, same results: {same}")
+    return {"chunk": chunk, "ms": round(ms, 2), "templates_per_s": round(len(bank) / (ms / 1e3), 1),
+            "merged_windows": kk, "equal_to_single_call": bool(same)}
 
 
 def graph_timing(ctx, seg, params, peaks, trig, count, cap, wl, prec, n_t, reps):
@@ -651,6 +689,10 @@ def main():
         "merged_windows": nwin_found,
         "launch_config": tune_cfg,
     }
+    if args.chunk > 0:
+        # before the other precisions overwrite the headline run's outputs
+        out["chunked"] = chunked_timing(ctx, ci, seg, bank, wl, prec_code, args.chunk,
+                                        peaks, trig, count, cap)
     if not args.no_split:
         # the other arithmetic paths on the same workload; accuracy against
         # the FP64 oracle is checked by the test-suite, here the peak SNR of

@@ -275,6 +275,26 @@ int ci_find_triggers(ci_ctx* ctx, const ci_segment* seg,
                      int64_t cap, int64_t* d_count,
                      int32_t merge_across_templates, void* stream);
 
+/* --- merge of per-window trigger lists ---------------------------------------
+ * The reduction of the candidates to local maxima ("Matched filtering", the
+ * final step of the per-chunk pipeline) across calls that each searched
+ * part of one bank on the same segment (chunks of a large bank): d_a and
+ * d_b are merged lists as ci_find_triggers with merge_across_templates
+ * writes them (at most one entry per window, in window order); only their
+ * first min(*count, cap) entries are read.  d_out receives, per window
+ * w < nwin present in either, the entry with the larger rho2; on equal
+ * rho2 the one from d_a (call it with the earlier chunk as d_a to keep
+ * ties on the smaller template, as one call over the whole bank does).
+ * d_b's template ids are shifted by tmpl_offset_b (the bank index of its
+ * first template); d_a's are kept.  Window order; *d_count receives the
+ * number of windows, and only the first cap entries are written.  d_out
+ * may be d_a (accumulate in place) and d_count may be d_count_a.
+ * Asynchronous on `stream`; uses the context's workspace (nwin records). */
+int ci_merge_triggers(ci_ctx* ctx, const ci_trigger* d_a, const int64_t* d_count_a,
+                      int64_t cap_a, const ci_trigger* d_b, const int64_t* d_count_b,
+                      int64_t cap_b, int64_t tmpl_offset_b, int64_t nwin, ci_trigger* d_out,
+                      int64_t cap, int64_t* d_count, void* stream);
+
 /* --- search without allocation -----------------------------------------------
  * For callers that cannot allocate device memory while they run (code under
  * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):

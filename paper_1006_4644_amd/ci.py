@@ -8,6 +8,7 @@ there is no CPU fallback.
 from __future__ import annotations
 
 import ctypes
+import json
 import os
 
 import numpy as np
@@ -37,7 +38,7 @@ EXPORTED_SYMBOLS = (
     "ci_td_matched_filter", "ci_td_find_triggers", "ci_stream_create",
     "ci_stream_destroy", "ci_stream_push", "ci_stream_poll", "ci_stream_last",
     "ci_bank_metric", "ci_make_bank_lattice", "ci_graph_stats",
-    "ci_find_triggers_noalloc", "ci_hbm_probe",
+    "ci_find_triggers_noalloc", "ci_hbm_probe", "ci_merge_triggers",
 )
 RUN_GRAPH = 1
 
@@ -69,6 +70,10 @@ class CiError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"ci error {code}: {msg}")
         self.code = code
+
+
+class ChunkFailure(RuntimeError):
+    """Raised by Context.search_bank_chunked's failure injection."""
 
 
 class _Template(ctypes.Structure):
@@ -154,6 +159,8 @@ _SIGS = {
     "ci_graph_stats": (ctypes.c_int, [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64)]),
     "ci_hbm_probe": (ctypes.c_int, [_vp, _i32, _vp, _i64, _i32,
                                     ctypes.POINTER(ctypes.c_double)]),
+    "ci_merge_triggers": (ctypes.c_int, [_vp, _vp, _vp, _i64, _vp, _vp, _i64, _i64, _i64,
+                                         _vp, _i64, _vp, _vp]),
     "ci_get_tune": (ctypes.c_int, [_vp, _i32, _i32, ctypes.POINTER(_Tune)]),
     "ci_set_tune": (ctypes.c_int, [_vp, ctypes.POINTER(_Tune)]),
     "ci_autotune": (ctypes.c_int, [_vp, _vp, _vp, _i64, _i32, _f32, _i64,
@@ -610,6 +617,83 @@ class Context:
             1 if merge else 0, RUN_GRAPH if graph else 0, _stream(stream)))
         return outs
 
+    def merge_triggers(self, a, count_a, b, count_b, nwin: int, tmpl_offset_b: int = 0,
+                       out=None, count=None, stream=None):
+        """Merge two per-window trigger lists (rows of ci_trigger, device)
+        into out (default: a new tensor of nwin rows); returns (out, count)."""
+        import torch
+        if out is None:
+            out = torch.empty((max(nwin, 1), 4), dtype=torch.int64, device=a.device)
+        if count is None:
+            count = torch.zeros(1, dtype=torch.int64, device=a.device)
+        self._chk(self.lib.dll.ci_merge_triggers(
+            self.handle, _ptr(a), _ptr(count_a), a.shape[0], _ptr(b), _ptr(count_b),
+            b.shape[0], tmpl_offset_b, nwin, _ptr(out), out.shape[0], _ptr(count),
+            _stream(stream)))
+        return out, count
+
+    def search_bank_chunked(self, seg: "Segment", bank, thr: float, window: int, chunk: int,
+                            checkpoint: str | None = None, precision: int = FP32,
+                            fail_after: int | None = None):
+        """The whole bank searched in chunks of `chunk` templates with a
+        resumable cursor: per chunk its generator constants, the merged
+        search (peaks with bank-wide template ids) and the device merge
+        into the running per-window list.  With `checkpoint`, the cursor,
+        the peaks so far and the merged list are written after every chunk
+        (npz, replaced atomically), and a call that finds the file resumes
+        after its cursor.  fail_after=k raises ChunkFailure after k chunks
+        of this call (tests of the resume).  Returns (peaks [nt, 4], merged
+        [nwin, 4], count [1]) as device tensors; the same results as one
+        ci_find_triggers call over the bank with merging."""
+        import torch
+        bank = np.ascontiguousarray(bank, dtype=np.float64)
+        nt, n = len(bank), seg.n
+        nwin = (n + window - 1) // window
+        dev = torch.device("cuda", self.device)
+        i64 = torch.int64
+        peaks = torch.empty((max(nt, 1), 4), dtype=i64, device=dev)
+        merged = torch.empty((nwin, 4), dtype=i64, device=dev)
+        mcount = torch.zeros(1, dtype=i64, device=dev)
+        cursor = 0
+        meta = np.array([n, nt, window, chunk, precision, seg.fs, seg.f_low, thr],
+                        dtype=np.float64)
+        if checkpoint and os.path.exists(checkpoint):
+            with np.load(checkpoint, allow_pickle=False) as z:
+                if not np.array_equal(z["meta"], meta):
+                    raise ValueError(f"{checkpoint} belongs to another search")
+                cursor = int(z["cursor"])
+                if cursor > 0:
+                    peaks[:cursor] = torch.from_numpy(z["peaks"][:cursor]).to(dev)
+                m = z["merged"]
+                if len(m):
+                    merged[:len(m)] = torch.from_numpy(m).to(dev)
+                mcount.fill_(len(m))
+        params = torch.empty((max(min(chunk, nt), 1), 96), dtype=torch.uint8, device=dev)
+        ctrig = torch.empty((nwin, 4), dtype=i64, device=dev)
+        ccount = torch.zeros(1, dtype=i64, device=dev)
+        done = 0
+        for c0 in range(cursor, nt, chunk):
+            c1 = min(nt, c0 + chunk)
+            m = c1 - c0
+            self.gen_templates(seg, bank[c0:c1], out=params[:m])
+            self.find_triggers(seg, params, thr, window, n=m, cap=nwin, merge=True,
+                               peaks=peaks[c0:c1], trig=ctrig, count=ccount,
+                               precision=precision)
+            peaks[c0:c1, 0] += c0   # template ids of the chunk -> bank indices
+            self.merge_triggers(merged, mcount, ctrig, ccount, nwin, tmpl_offset_b=c0,
+                                out=merged, count=mcount)
+            done += 1
+            if checkpoint:
+                torch.cuda.synchronize(dev)
+                k = int(mcount.cpu()[0])
+                tmp = f"{checkpoint}.tmp{os.getpid()}.npz"
+                np.savez(tmp, meta=meta, cursor=np.int64(c1),
+                         peaks=peaks[:c1].cpu().numpy(), merged=merged[:k].cpu().numpy())
+                os.replace(tmp, checkpoint)
+            if fail_after is not None and done >= fail_after and c1 < nt:
+                raise ChunkFailure(f"injected failure after {done} chunks (cursor {c1})")
+        return peaks[:nt], merged, mcount
+
     def hbm_probe(self, kind: int, buf, nbytes: int, reps: int = 10) -> float:
         """Streaming bandwidth in GB/s: kind 0 write, 1 read, 2 copy (buf holds
         2 x nbytes for a copy)."""
@@ -623,6 +707,61 @@ class Context:
         c, n = _i64(0), _i64(0)
         self._chk(self.lib.dll.ci_graph_stats(self.handle, ctypes.byref(c), ctypes.byref(n)))
         return int(c.value), int(n.value)
+
+
+# --- launch-configuration cache ------------------------------------------------
+# Autotuned launch configurations as JSON, keyed by the device they were
+# tuned on, the transform length and the precision:
+#   {"entries": {"<device key>/<log2 n>/<precision>": {tile_c, tile_j, ...}}}
+TUNE_FIELDS = ("tile_c", "tile_j", "p2_per_cu", "batch", "streams", "p2_wave")
+
+
+def device_key(device: int = 0) -> str:
+    """Identity of a GPU for the cache: name, architecture, compute units."""
+    import torch
+    p = torch.cuda.get_device_properties(device)
+    return f"{p.name}|{getattr(p, 'gcnArchName', '')}|{p.multi_processor_count}"
+
+
+def save_tune_cache(ctx, path: str, key: str, lengths=range(16, 22),
+                    precisions=(FP32, SPLIT_BF16, SPLIT_FP16)) -> int:
+    """Merge ctx's autotuned configurations into the cache file (written
+    atomically); returns the number of entries written for `key`."""
+    data = {"entries": {}}
+    if os.path.exists(path):
+        with open(path) as fh:
+            data = json.load(fh)
+        data.setdefault("entries", {})
+    n = 0
+    for l2 in lengths:
+        for p in precisions:
+            t = ctx.get_tune(l2, p)
+            if t["tuned"]:
+                data["entries"][f"{key}/{l2}/{p}"] = {f: int(t[f]) for f in TUNE_FIELDS}
+                n += 1
+    tmp = f"{path}.tmp{os.getpid()}"
+    with open(tmp, "w") as fh:
+        json.dump(data, fh, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+    return n
+
+
+def load_tune_cache(ctx, path: str, key: str) -> list:
+    """Apply the cached configurations recorded for `key` to ctx; returns
+    the (log2 n, precision) pairs applied (none if the file is absent)."""
+    if not os.path.exists(path):
+        return []
+    with open(path) as fh:
+        data = json.load(fh)
+    done = []
+    for k, cfg in sorted(data.get("entries", {}).items()):
+        dk, l2, p = k.rsplit("/", 2)
+        if dk != key:
+            continue
+        ctx.set_tune(int(l2), int(p), cfg["tile_c"], cfg["tile_j"], cfg["p2_per_cu"],
+                     cfg["batch"], streams=cfg["streams"], p2_wave=cfg.get("p2_wave", 0))
+        done.append((int(l2), int(p)))
+    return done
 
 
 def triggers_to_numpy(t, count: int | None = None) -> np.ndarray:

@@ -950,6 +950,7 @@ int ci_ctx_destroy(ci_ctx* ctx) {
   if (ctx->ybuf) (void)hipFree(ctx->ybuf);
   if (ctx->tbuf) (void)hipFree(ctx->tbuf);
   if (ctx->tdbuf) (void)hipFree(ctx->tdbuf);
+  if (ctx->mbuf) (void)hipFree(ctx->mbuf);
   // segments still alive keep their buffers until ci_segment_destroy
   for (Seg* sg : ctx->segs) sg->ctx = nullptr;
   delete ctx;
@@ -1843,6 +1844,33 @@ int ci_hbm_probe(ci_ctx* ctx, int32_t kind, void* d_buf, int64_t bytes, int32_t 
   if (e != hipSuccess) return hipfail(ctx, e, "bandwidth probe");
   *gbs = best;
   return CI_OK;
+}
+
+int ci_merge_triggers(ci_ctx* ctx, const ci_trigger* d_a, const int64_t* d_count_a,
+                      int64_t cap_a, const ci_trigger* d_b, const int64_t* d_count_b,
+                      int64_t cap_b, int64_t tmpl_offset_b, int64_t nwin, ci_trigger* d_out,
+                      int64_t cap, int64_t* d_count, void* stream) {
+  if (!ctx) return fail(nullptr, CI_EINVAL, "null context");
+  if (nwin < 1 || nwin > (int64_t(1) << 31))
+    return fail(ctx, CI_EINVAL, "nwin %lld outside 1..2^31", (long long)nwin);
+  if (cap_a < 0 || cap_b < 0 || cap < 0) return fail(ctx, CI_EINVAL, "negative capacity");
+  if ((cap_a > 0 && (!d_a || !d_count_a)) || (cap_b > 0 && (!d_b || !d_count_b)))
+    return fail(ctx, CI_EINVAL, "null input list or count");
+  if (!d_count || (cap > 0 && !d_out)) return fail(ctx, CI_EINVAL, "null output");
+  if (tmpl_offset_b < 0) return fail(ctx, CI_EINVAL, "negative template offset");
+  DeviceGuard dg(ctx->device);
+  if (!dg.ok) return fail(ctx, CI_EHIP, "cannot select device %d", ctx->device);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  int rc = grow(ctx, &ctx->mbuf, &ctx->mbytes, sizeof(ci_trigger) * (size_t)nwin,
+                "merge workspace", st);
+  if (rc != CI_OK) return rc;
+  rc = ws_enter(ctx, st);
+  if (rc != CI_OK) return rc;
+  const hipError_t e = launch_merge(d_a, d_count_a, cap_a, d_b, d_count_b, cap_b, tmpl_offset_b,
+                                    nwin, static_cast<ci_trigger*>(ctx->mbuf), d_out, cap,
+                                    d_count, st);
+  if (e != hipSuccess) return hipfail(ctx, e, "merge launch");
+  return ws_leave(ctx, st);
 }
 
 int ci_graph_stats(ci_ctx* ctx, int64_t* captures, int64_t* launches) {

@@ -86,6 +86,9 @@ struct Ctx {
   // [B][n] complex64, then the sigma^2 partials [B][kTdChunks][2] doubles
   void* tdbuf = nullptr;
   size_t tdbytes = 0;
+  // per-window records of ci_merge_triggers
+  void* mbuf = nullptr;
+  size_t mbytes = 0;
   size_t td_slot = 0;          // bytes per slot set of the current call
   // pinned staging for parameter upload
   void* pin = nullptr;
@@ -167,6 +170,14 @@ hipError_t launch_init_call(const TrigWork& tw, int nwin, int64_t* d_count,
 // Chi-squared veto of ntrig triggers (bands 2..64).
 hipError_t launch_chisq(const Seg* s, const ci_tparams* d_params, int64_t ntmpl,
                         const ci_trigger* d_trig, int64_t ntrig, int bands, double* d_out,
+                        hipStream_t st);
+// Merge of two per-window trigger lists (at most one entry per window, the
+// first min(count, cap) entries of each read) into `out` in window order:
+// per window the larger rho^2, a's entry on equal values; b's template ids
+// shifted by off_b; dense is nwin records of scratch.
+hipError_t launch_merge(const ci_trigger* a, const int64_t* ca, int64_t cap_a, const ci_trigger* b,
+                        const int64_t* cb, int64_t cap_b, int64_t off_b, int64_t nwin,
+                        ci_trigger* dense, ci_trigger* out, int64_t cap, int64_t* d_count,
                         hipStream_t st);
 // Streaming probe over `bytes` of buf: kind 0 writes, 1 reads, 2 copies the
 // first half onto the second (bytes per half).

@@ -1523,6 +1523,87 @@ __global__ void k_init_call(ci_trigger* mrec, int nwin, u64* run, int64_t* d_cou
 }
 
 // ---------------------------------------------------------------------------
+// merge of two per-window trigger lists (chunks of one bank)
+// ---------------------------------------------------------------------------
+
+// Per-window records start empty.
+__global__ void k_merge_clear(ci_trigger* __restrict__ dense, int64_t nwin) {
+  const int64_t w = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (w < nwin) {
+    ci_trigger e;
+    e.tmpl = -1; e.index = -1; e.rho2 = -1.f; e.re = 0.f; e.im = 0.f; e.window = -1;
+    dense[w] = e;
+  }
+}
+
+// One list into the per-window records: its entry replaces the window's
+// record when that is empty or strictly smaller, so of two lists scattered
+// in turn the first keeps the window on equal rho^2 (the earlier chunk's,
+// smaller template).  Each list holds at most one entry per window, so no
+// two lanes of one launch write the same record.
+__global__ void k_merge_scatter(const ci_trigger* __restrict__ src, const int64_t* __restrict__ cnt,
+                                int64_t cap, int64_t off, int64_t nwin,
+                                ci_trigger* __restrict__ dense) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t n = cnt[0] < cap ? cnt[0] : cap;
+  if (i >= n) return;
+  ci_trigger e = src[i];
+  if (e.tmpl < 0 || e.window < 0 || e.window >= nwin) return;
+  e.tmpl += off;
+  const ci_trigger cur = dense[e.window];
+  if (cur.tmpl < 0 || e.rho2 > cur.rho2) dense[e.window] = e;
+}
+
+// Compaction of the records in window order (one workgroup).
+__global__ __launch_bounds__(256) void k_merge_compact(const ci_trigger* __restrict__ dense,
+                                                       int64_t nwin, ci_trigger* __restrict__ out,
+                                                       int64_t cap, int64_t* __restrict__ d_count) {
+  __shared__ int sh[256];
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int64_t per = (nwin + nt - 1) / nt;
+  const int64_t w0 = tid * per, w1 = w0 + per < nwin ? w0 + per : nwin;
+  int mine = 0;
+  for (int64_t w = w0; w < w1; ++w) mine += dense[w].tmpl >= 0;
+  int total = 0;
+  int64_t pos = block_excl_scan(mine, sh, &total);
+  for (int64_t w = w0; w < w1; ++w) {
+    const ci_trigger e = dense[w];
+    if (e.tmpl >= 0) {
+      if (pos < cap) out[pos] = e;
+      ++pos;
+    }
+  }
+  if (tid == 0) d_count[0] = total;
+}
+
+hipError_t launch_merge(const ci_trigger* a, const int64_t* ca, int64_t cap_a, const ci_trigger* b,
+                        const int64_t* cb, int64_t cap_b, int64_t off_b, int64_t nwin,
+                        ci_trigger* dense, ci_trigger* out, int64_t cap, int64_t* d_count,
+                        hipStream_t st) {
+  // a list holds at most one entry per window: nwin bounds its grid
+  if (cap_a > nwin) cap_a = nwin;
+  if (cap_b > nwin) cap_b = nwin;
+  const unsigned gw = (unsigned)((nwin + 255) / 256);
+  hipLaunchKernelGGL(k_merge_clear, dim3(gw), dim3(256), 0, st, dense, nwin);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (cap_a > 0) {
+    hipLaunchKernelGGL(k_merge_scatter, dim3((unsigned)((cap_a + 255) / 256)), dim3(256), 0, st,
+                       a, ca, cap_a, (int64_t)0, nwin, dense);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  if (cap_b > 0) {
+    hipLaunchKernelGGL(k_merge_scatter, dim3((unsigned)((cap_b + 255) / 256)), dim3(256), 0, st,
+                       b, cb, cap_b, off_b, nwin, dense);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_merge_compact, dim3(1), dim3(256), 0, st, dense, nwin, out, cap, d_count);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // streaming bandwidth probes (the device's write, read and copy ceilings)
 // ---------------------------------------------------------------------------
 

@@ -333,6 +333,20 @@ def test_autotune_keeps_results(ctx):
         (cfg["tile_c"], cfg["tile_j"], cfg["p2_per_cu"], cfg["batch"], 1)
     p1, t1, c1 = ctx.find_triggers(seg, params, 5.0, W, cap=4096)
     _same([ref], [(_np(p1), _np(t1)[:min(int(c1.cpu()[0]), 4096)], int(c1.cpu()[0]))])
+    # the chosen configuration through the JSON cache into a fresh context
+    import tempfile, os
+    key = ci.device_key(0)
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "tune.json")
+        assert ci.save_tune_cache(ctx, path, key) >= 1
+        c2 = ctx.lib.context(0)
+        try:
+            assert (18, ci.FP32) in ci.load_tune_cache(c2, path, key)
+            g2 = c2.get_tune(18)
+            assert all(g2[f] == got[f] for f in ci.TUNE_FIELDS)
+            assert ci.load_tune_cache(c2, path, key + "-other") == []
+        finally:
+            c2.close()
     ctx.set_tune(18, ci.FP32)
     assert ctx.get_tune(18)["tuned"] == 0
     seg.close()

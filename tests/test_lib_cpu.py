@@ -141,3 +141,35 @@ def test_ctypes_structs_match_header(tmp_path):
         assert got[(cname, "size")] == dt.itemsize, cname
         for fname in dt.names:
             assert got[(cname, fname)] == dt.fields[fname][1], (cname, fname)
+
+
+def test_tune_cache_roundtrip(tmp_path):
+    """The launch-configuration cache: tuned entries are written per device
+    key, length and precision, merged into an existing file, and applied
+    only to a context of the same device key."""
+    from paper_1006_4644_amd import ci
+
+    class Fake:
+        def __init__(self, tuned):
+            self.t = {}
+            self.tuned = tuned
+            self.applied = []
+
+        def get_tune(self, l2, p):
+            d = dict(tile_c=8, tile_j=4 + 4 * (l2 % 2), p2_per_cu=l2 % 5, batch=16 * l2,
+                     streams=1 + p % 2, p2_wave=l2 % 2, tuned=int((l2, p) in self.tuned))
+            return d
+
+        def set_tune(self, l2, p, c, j, p2, batch, streams=2, p2_wave=0):
+            self.applied.append((l2, p, c, j, p2, batch, streams, p2_wave))
+
+    path = str(tmp_path / "tune.json")
+    assert ci.load_tune_cache(Fake(set()), path, "dev") == []
+    assert ci.save_tune_cache(Fake({(20, 0), (17, 1)}), path, "devA") == 2
+    assert ci.save_tune_cache(Fake({(21, 2)}), path, "devB") == 1
+    fa = Fake(set())
+    assert sorted(ci.load_tune_cache(fa, path, "devA")) == [(17, 1), (20, 0)]
+    assert sorted(fa.applied) == [(17, 1, 8, 8, 2, 272, 2, 1), (20, 0, 8, 4, 0, 320, 1, 0)]
+    fb = Fake(set())
+    assert ci.load_tune_cache(fb, path, "devB") == [(21, 2)]
+    assert ci.load_tune_cache(Fake(set()), path, "other") == []
