@@ -317,7 +317,7 @@ size_t trig_bytes(int64_t bmax, int64_t nwin, int64_t ntile2) {
   const int64_t S = kSlots;
   return align256(sizeof(unsigned long long) * S * bmax * ntile2) +
          align256(sizeof(unsigned long long) * S * bmax * nwin) +
-         align256(sizeof(unsigned long long) * S * nwin) + align256(sizeof(unsigned int) * S) + align256(sizeof(int) * S * bmax) +
+         align256(sizeof(unsigned long long) * S * nwin) + align256(sizeof(int) * S * bmax) +
          align256(sizeof(int) * S * bmax * nwin) + align256(sizeof(ci_trigger) * S * bmax * nwin) +
          align256(sizeof(ci_trigger) * nwin) + align256(sizeof(unsigned long long));
 }
@@ -330,8 +330,6 @@ void carve_trig(char* p, int64_t bmax, int64_t nwin, int64_t ntile2, TrigWork* t
   p += align256(sizeof(unsigned long long) * S * bmax * nwin);
   tw->mkey = reinterpret_cast<unsigned long long*>(p);
   p += align256(sizeof(unsigned long long) * S * nwin);
-  tw->bdone = reinterpret_cast<unsigned int*>(p);
-  p += align256(sizeof(unsigned int) * S);
   tw->cnt = reinterpret_cast<int*>(p);
   p += align256(sizeof(int) * S * bmax);
   tw->sidx = reinterpret_cast<int*>(p);

@@ -43,7 +43,6 @@ struct TrigWork {
   unsigned long long* ppart;   // [kSlots][B][n2/j]  peak key per pass-2 workgroup
   unsigned long long* wkeys;   // [kSlots][B][nwin]  window key per template
   unsigned long long* mkey;    // [kSlots][nwin]     merge key per window
-  unsigned int* bdone;         // [kSlots]           finished templates
   int* cnt;                    // [kSlots][B]        triggers per template
   int* sidx;                   // [kSlots][B][nwin]  staging slot of window w
   ci_trigger* stage;           // [kSlots][B][nwin]  compacted triggers

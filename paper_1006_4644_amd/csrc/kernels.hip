@@ -362,7 +362,6 @@ struct P1Args {
   float2* y;               // intermediate, [nb][n] in tile layout
   // per-batch trigger state to clear (null when not searching)
   u64* wkeys;
-  unsigned int* bdone;
   int64_t nzero_w;         // entries of wkeys to clear
   u64* mkey;               // the batch's merge keys [nwin] (cleared too)
   int nwin;
@@ -406,6 +405,22 @@ __device__ __forceinline__ float2 ld_nt(const float2* p) {
   return make_float2(__builtin_nontemporal_load(&p->x), __builtin_nontemporal_load(&p->y));
 }
 __device__ __forceinline__ unsigned ld_nt(const unsigned* p) { return *p; }
+
+// Raw buffer descriptor of `bytes` bytes from p (gfx9 family: no swizzle,
+// 32-bit data format).  Buffer loads take the address as a descriptor held
+// in scalar registers plus a per-lane offset plus a scalar offset, so loads
+// whose lanes keep fixed offsets from a common base need no vector address
+// arithmetic.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void* p, unsigned bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
+}
+// 8 bytes at voff + soff (non-temporal) and 4 bytes at voff + soff.
+__device__ __forceinline__ float2 buf_ld_nt(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+  return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 2));
+}
+__device__ __forceinline__ unsigned buf_ld(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+  return __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0);
+}
 
 // w_N^e for 0 <= e < N from the two-level table.
 __device__ __forceinline__ float2 tw_n(const float2* __restrict__ twa,
@@ -509,7 +524,6 @@ __global__ __launch_bounds__(C * N2 / 16) void k_pass1(P1Args a) {
     const int64_t gsz = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = gid; i < a.nzero_w; i += gsz) a.wkeys[i] = 0ull;
     for (int64_t i = gid; i < a.nwin; i += gsz) a.mkey[i] = 0ull;
-    if (gid == 0) a.bdone[0] = 0u;
   }
 
   // w_{N2}^e, e < N2, in LDS after the exchange buffer (stage-1 and
@@ -606,7 +620,6 @@ __global__ __launch_bounds__(C * N2 / 16) void k_pass1_mem(P1Args a) {
     const int64_t gsz = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = gid; i < a.nzero_w; i += gsz) a.wkeys[i] = 0ull;
     for (int64_t i = gid; i < a.nwin; i += gsz) a.mkey[i] = 0ull;
-    if (gid == 0) a.bdone[0] = 0u;
   }
   float2* twl = lds + Col<N2, C>::LDS_ELEMS;
   for (int k = (int)tid; k < N2; k += (int)blockDim.x) twl[k] = a.tw[k * (2048 / N2)];
@@ -767,7 +780,6 @@ struct P2Args {
   u64* wkeys;                // [nb][nwin]
   u64* mkey;                 // [nwin] per window: max over the batch of
                              // (rho^2 bits, complemented template index)
-  unsigned int* bdone;       // [1]
   int* cnt;                  // [nb]
   int* sidx;                 // [nb][nwin]
   ci_trigger* stage;         // [nb][nwin]
@@ -953,13 +965,29 @@ __device__ void place_batch(const P2Args& a, void* ldsv) {
 // pass 2: second four-step pass + post-pass
 // ---------------------------------------------------------------------------
 
+// Byte offset of lane (cc, t)'s first pass-2 input, Y[k1 = t][j2 = cc],
+// from a tile's first column: the same for every tile.
+template <int N1, int N2, int C>
+__device__ __forceinline__ unsigned p2_lane_off(unsigned cc, unsigned t) {
+  return (((t / C) * N2 + cc) * C + (t % C)) * (unsigned)sizeof(float2);
+}
+
+// x[q] = Y[k1 = t + (N1/16) q][j2 = tile J + cc] of pass-2 item `item`
+// (as load_pass2), through a buffer descriptor at the tile's first column
+// (the same for every lane), the lane's fixed offset voff = p2_lane_off(cc,
+// t) and the constant offset of q.
 template <int N1, int N2, int C, int J>
-__device__ __forceinline__ void load_item(float2 (&x)[16], const P2Args& a, int item, unsigned cc,
-                                          unsigned t) {
+__device__ __forceinline__ void load_item(float2 (&x)[16], const P2Args& a, int item,
+                                          unsigned voff) {
   constexpr int N = N1 * N2;
   constexpr int TILES = N2 / J;
+  constexpr unsigned QS = (N1 / 16) * N2 * (unsigned)sizeof(float2);
   const int b = item / TILES, tile = item % TILES;
-  load_pass2<N1, N2, C, J>(x, a.y + (size_t)b * N, tile * J + cc, t);
+  const unsigned first = (unsigned)tile * J * C;
+  const __amdgpu_buffer_rsrc_t r =
+      buf_rsrc(a.y + (size_t)b * N + first, (N - first) * (unsigned)sizeof(float2));
+#pragma unroll
+  for (int q = 0; q < 16; ++q) x[q] = buf_ld_nt(r, voff, q * QS);
 }
 
 // Post-pass of one pass-2 tile (workgroup of NW waves).  r2[i], i < K, are
@@ -1012,6 +1040,38 @@ __device__ __forceinline__ void tile_post(const float (&r2)[K], JF jof, const P2
     for (int w = 1; w < NW; ++w) j = min(j, s_j[w]);
     a.ppart[pidx] = M >= 0.f ? (((u64)__float_as_uint(M) << 32) | (u64)(0xFFFFFFFFu - j)) : 0ull;
   }
+}
+
+// Post-pass of the samples one wave holds (wave-owned columns): as
+// tile_post, with the wave's peak key going to a.ppart[pidx] and no
+// workgroup barrier, so the waves of a workgroup run independently.
+template <int K, typename JF>
+__device__ __forceinline__ void wave_post(const float (&r2)[K], JF jof, const P2Args& a, int bt,
+                                          size_t pidx, unsigned lane) {
+  float m = r2[0];
+#pragma unroll
+  for (int i = 1; i < K; ++i) m = fmaxf(m, r2[i]);
+  if (__any(m > a.thr2)) {
+    u64* wk = a.wkeys + (size_t)bt * a.nwin;
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+      if (r2[i] > a.thr2) {
+        const unsigned j = jof(i);
+        const u64 key = ((u64)__float_as_uint(r2[i]) << 32) | (u64)(0xFFFFFFFFu - j);
+        atomicMax(&wk[j / a.win32], key);
+      }
+    }
+  }
+  const float M = wave_max(m);
+  unsigned jm = 0xFFFFFFFFu;
+  if (M >= 0.f && m == M) {
+#pragma unroll
+    for (int i = K - 1; i >= 0; --i)
+      if (r2[i] == M) jm = jof(i);
+  }
+  jm = wave_min(jm);
+  if (lane == 0)
+    a.ppart[pidx] = M >= 0.f ? (((u64)__float_as_uint(M) << 32) | (u64)(0xFFFFFFFFu - jm)) : 0ull;
 }
 
 template <int N1, int N2, int C, int J>
@@ -1077,15 +1137,16 @@ __global__ __launch_bounds__(J * N1 / 16, 4) void k_pass2_trig(P2Args a) {
   for (unsigned e = tid; e < (unsigned)N1; e += blockDim.x) twl[e] = a.tw[e * (2048 / N1)];
   __syncthreads();
 
+  const unsigned voff = p2_lane_off<N1, N2, C>(cc, t);
   float2 xn[16];
   const int G = gridDim.x;
   int item = blockIdx.x;
-  if (item < total) load_item<N1, N2, C, J>(xn, a, item, cc, t);
+  if (item < total) load_item<N1, N2, C, J>(xn, a, item, voff);
   for (; item < total; item += G) {
     float2 x[16];
 #pragma unroll
     for (int r = 0; r < 16; ++r) x[r] = xn[r];
-    if (item + G < total) load_item<N1, N2, C, J>(xn, a, item + G, cc, t);
+    if (item + G < total) load_item<N1, N2, C, J>(xn, a, item + G, voff);
     pass2_tile<N1, N2, C, J>(x, a, item, lds, twl, s_best, tid, cc, t);
   }
 }
@@ -1138,33 +1199,30 @@ __global__ __launch_bounds__(J * N1 / 16, 4) void k_pass2w(P2Args a) {
   const unsigned lane = tid & 63, wave = tid >> 6;
   const int total = a.nb * TILES;
 
-  float2* twl = lds + J * X;
-  for (unsigned e = tid; e < (unsigned)N1; e += blockDim.x) twl[e] = a.tw[e * (2048 / N1)];
+  // Twiddle tables behind the exchange regions, laid out so that a lane
+  // reads every twiddle at a fixed offset from one base address:
+  // t1[(q - 1) Lp + t] = w_L^{q t} (stage 1), t2[(a2 - 1) R3 + s2] =
+  // w_L^{16 a2 s2} (stage 2), q, a2 = 1..15.
+  float2* t1 = lds + J * X;
+  float2* t2 = t1 + 15 * Lp;
+  static_assert(15 * (Lp + R3) <= N1, "twiddle tables fit the reserved region");
+  for (unsigned e = tid; e < 15u * (Lp + R3); e += blockDim.x) {
+    unsigned x;
+    if (e < 15u * Lp) x = (e / Lp + 1) * (e % Lp);
+    else x = 16 * ((e - 15 * Lp) / R3 + 1) * ((e - 15 * Lp) % R3);
+    t1[e] = a.tw[(x % N1) * (2048 / N1)];
+  }
   __syncthreads();
+  const float2* t1l = t1 + t;
+  const float2* t2l = t2 + s2;
 
-  float2 xn[16];
-  const int G = gridDim.x;
-  int item = blockIdx.x;
-  if (item < total) load_item<N1, N2, C, J>(xn, a, item, cc, t);
-  for (; item < total; item += G) {
-    float2 x[16];
-#pragma unroll
-    for (int r = 0; r < 16; ++r) x[r] = xn[r];
-    if (item + G < total) load_item<N1, N2, C, J>(xn, a, item + G, cc, t);
+  auto tile_body = [&](float2 (&x)[16], int item) {
     const int b = item / TILES, tile = item % TILES;
 
     // stage 1: radix 16 over m, twiddle w_L^{a t}
     idft16(x);
-    {
-      const char* twb = reinterpret_cast<const char*>(twl);
-      const unsigned step = t * (unsigned)sizeof(float2);
-      unsigned off = 0;
 #pragma unroll
-      for (int q = 1; q < 16; ++q) {
-        off += step;
-        x[q] = cmul(x[q], *reinterpret_cast<const float2*>(twb + off));
-      }
-    }
+    for (int q = 1; q < 16; ++q) x[q] = cmul(x[q], t1l[(q - 1) * Lp]);
     // exchange 1 (across waves): the previous tile's column regions are
     // free once every wave is past its exchange 2
     __syncthreads();
@@ -1182,16 +1240,8 @@ __global__ __launch_bounds__(J * N1 / 16, 4) void k_pass2w(P2Args a) {
       for (int q = 0; q < 16; ++q) x[q] = pr[q * R3];
     }
     idft16(x);
-    {
-      const char* twb = reinterpret_cast<const char*>(twl);
-      const unsigned step = s2 * 16u * (unsigned)sizeof(float2);
-      unsigned off = 0;
 #pragma unroll
-      for (int a2 = 1; a2 < 16; ++a2) {
-        off += step;
-        x[a2] = cmul(x[a2], *reinterpret_cast<const float2*>(twb + off));
-      }
-    }
+    for (int a2 = 1; a2 < 16; ++a2) x[a2] = cmul(x[a2], t2l[(a2 - 1) * R3]);
     // exchange 2 (inside the wave, in its own column region, which no
     // other wave reads): row d = a0 + 16 a2 at position s2, then rows
     // d = tb + Lp i at every position s
@@ -1230,31 +1280,20 @@ __global__ __launch_bounds__(J * N1 / 16, 4) void k_pass2w(P2Args a) {
         if (j < a.jlo32 || j >= a.jhi32) r2[kk] = -1.f;
       }
     }
-    float m = r2[0];
+    wave_post<16>(r2, jof, a, b, ((size_t)b * TILES + tile) * W::NW + wave, lane);
+  };
+
+  const unsigned voff = p2_lane_off<N1, N2, C>(cc, t);
+  float2 xn[16];
+  const int G = gridDim.x;
+  int item = blockIdx.x;
+  if (item < total) load_item<N1, N2, C, J>(xn, a, item, voff);
+  for (; item < total; item += G) {
+    float2 x[16];
 #pragma unroll
-    for (int kk = 1; kk < 16; ++kk) m = fmaxf(m, r2[kk]);
-    if (__any(m > a.thr2)) {
-      u64* wk = a.wkeys + (size_t)b * a.nwin;
-#pragma unroll
-      for (int kk = 0; kk < 16; ++kk) {
-        if (r2[kk] > a.thr2) {
-          const unsigned j = jof(kk);
-          const u64 key = ((u64)__float_as_uint(r2[kk]) << 32) | (u64)(0xFFFFFFFFu - j);
-          atomicMax(&wk[j / a.win32], key);
-        }
-      }
-    }
-    const float M = wave_max(m);
-    unsigned jm = 0xFFFFFFFFu;
-    if (M >= 0.f && m == M) {
-#pragma unroll
-      for (int kk = 15; kk >= 0; --kk)
-        if (r2[kk] == M) jm = jof(kk);
-    }
-    jm = wave_min(jm);
-    if (lane == 0)
-      a.ppart[((size_t)b * TILES + tile) * W::NW + wave] =
-          M >= 0.f ? (((u64)__float_as_uint(M) << 32) | (u64)(0xFFFFFFFFu - jm)) : 0ull;
+    for (int r = 0; r < 16; ++r) x[r] = xn[r];
+    if (item + G < total) load_item<N1, N2, C, J>(xn, a, item + G, voff);
+    tile_body(x, item);
   }
 }
 
@@ -1336,19 +1375,30 @@ __global__ __launch_bounds__(J * 64, N1 <= 1024 ? 4 : 1) void k_p2mx(P2Args a) {
   constexpr int L = N1, R3 = L / 256, N = N1 * N2, TILES = N2 / J;
   typedef typename MxT<PREC>::v8 V8;
   extern __shared__ float2 lds[];
-  __shared__ float s_m[J];
-  __shared__ unsigned s_j[J];
-  float2* twl = lds;
+  // tws[(b 4 + e) 64 + l] = w_L^{u0 (b + R3 v1)} for lane l = u0 + 16 g,
+  // v1 = 4 g + e (the twiddle before stage C): a lane reads its sixteen at
+  // fixed offsets from one base address
+  float2* tws = lds;
   const uint4* afr = reinterpret_cast<const uint4*>(lds + L);
-  const unsigned tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const unsigned tid = threadIdx.x, lane = tid & 63;
+  const unsigned wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const unsigned u0 = lane & 15, g = lane >> 4;
   float2* xw = lds + L + (R3 + 1) * 256 * 2 + wave * 16 * kXS;
   {
     uint4* af = reinterpret_cast<uint4*>(lds + L);
-    for (int k = tid; k < L; k += J * 64) twl[k] = a.tw[k * (2048 / L)];
+    for (int k = tid; k < L; k += J * 64) {
+      const unsigned l = k & 63, be = k >> 6, ub = l & 15, gb = l >> 4;
+      const unsigned E = (ub * (be / 4 + R3 * (4 * gb + be % 4))) & (L - 1);
+      tws[k] = a.tw[E * (2048 / L)];
+    }
     for (int k = tid; k < (R3 + 1) * 256; k += J * 64) af[k] = a.mxa[k];
   }
   __syncthreads();
+  const float2* twt = tws + lane;
+  // byte offset of the lane's first input (k1 = u0 + 64 g) from the base of
+  // its column; input (p, e) adds k1 += 16 e + 256 p, a constant offset
+  const unsigned voff =
+      ((u0 / C + (64 / C) * g) * N2 * C + u0 % C) * (unsigned)sizeof(unsigned);
   V8 wc[4];
 #pragma unroll
   for (int f = 0; f < 4; ++f) wc[f] = __builtin_bit_cast(V8, afr[(R3 * 4 + f) * 64 + lane]);
@@ -1356,17 +1406,20 @@ __global__ __launch_bounds__(J * 64, N1 <= 1024 ? 4 : 1) void k_p2mx(P2Args a) {
   for (int item = blockIdx.x; item < total; item += gridDim.x) {
     const int bt = item / TILES, tile = item % TILES;
     const unsigned j2 = tile * J + wave;
-    const unsigned* yb = reinterpret_cast<const unsigned*>(a.y) + (size_t)bt * N;
     float2 x[R3][4];
     {
+      // column j2 of template bt: k1 = u0 + 16 (4 g + e) + 256 p lies at
+      // ((k1 / C) N2 + j2) C + k1 % C, the lane's offset plus a constant
+      const __amdgpu_buffer_rsrc_t r =
+          buf_rsrc(reinterpret_cast<const unsigned*>(a.y) + (size_t)bt * N + (size_t)j2 * C,
+                   (unsigned)(N - j2 * C) * (unsigned)sizeof(unsigned));
       unsigned raw[R3][4];
 #pragma unroll
       for (int p = 0; p < R3; ++p)
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const unsigned k1 = u0 + 16 * (4 * g + e) + 256 * p;
-          raw[p][e] = ld_nt(&yb[((k1 / C) * N2 + j2) * C + (k1 % C)]);
-        }
+        for (int e = 0; e < 4; ++e)
+          raw[p][e] = buf_ld(r, voff, ((16 / C) * e + (256 / C) * p) * N2 * C *
+                                          (unsigned)sizeof(unsigned));
 #pragma unroll
       for (int p = 0; p < R3; ++p)
 #pragma unroll
@@ -1412,10 +1465,7 @@ __global__ __launch_bounds__(J * 64, N1 <= 1024 ? 4 : 1) void k_p2mx(P2Args a) {
       f32x4 yr, yi;
       mx_prod<PREC>(A4, v, yr, yi, guard);
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const unsigned E = (u0 * (unsigned)(b + R3 * (4 * g + e))) & (L - 1);
-        x[b][e] = cmul(make_float2(yr[e], yi[e]), twl[E]);
-      }
+      for (int e = 0; e < 4; ++e) x[b][e] = cmul(make_float2(yr[e], yi[e]), twt[(b * 4 + e) * 64]);
     }
     // stage C per b through this wave's exchange rows: lane (u0, g) holds
     // v1 = 4 g + e; afterwards lane (v1 = l % 16, g) holds u0 = 4 g + e
@@ -1459,29 +1509,27 @@ __global__ __launch_bounds__(J * 64, N1 <= 1024 ? 4 : 1) void k_p2mx(P2Args a) {
           if (j < a.jlo32 || j >= a.jhi32) r2[i] = -1.f;
         }
       }
-      tile_post<4 * R3, J>(r2, jof, a, bt, (size_t)bt * TILES + tile, s_m, s_j, tid);
+      // one peak partial per column (wave)
+      wave_post<4 * R3>(r2, jof, a, bt, (size_t)bt * N2 + j2, lane);
     }
   }
 }
 
 // Per-batch finalisation: one workgroup per template reduces the pass-2
 // partials to the peak, recomputes z at the peak and at every window
-// trigger, and compacts the triggers; the last workgroup to finish places
-// the batch's triggers (or merges them) in order.  Only these few
-// workgroups use device-scope fences.
+// trigger, and compacts the triggers.  k_place, launched after it on the
+// same stream, then places the batch's triggers (or merges them) in order:
+// the kernel boundary makes every workgroup's results visible to it, with
+// no device-scope fence (each of which writes back a whole L2) inside
+// either kernel.
 template <int N1, int N2, int C>
 __global__ __launch_bounds__(256) void k_fin(P2Args a) {
   extern __shared__ float2 lds[];
-  const int tid = threadIdx.x;
-  const int b = blockIdx.x;
-  __shared__ int s_flag;
-  finalize_template<N1, N2, C>(a, b, lds);
-  __threadfence();
-  __syncthreads();
-  if (tid == 0) s_flag = (atomicAdd(&a.bdone[0], 1u) == (unsigned int)(a.nb - 1));
-  __syncthreads();
-  if (!s_flag) return;
-  __threadfence();
+  finalize_template<N1, N2, C>(a, blockIdx.x, lds);
+}
+
+__global__ __launch_bounds__(256) void k_place(P2Args a) {
+  extern __shared__ float2 lds[];
   place_batch(a, lds);
 }
 
@@ -1879,13 +1927,11 @@ P1Args make_p1(const BatchArgs& a, bool zero_trig) {
   if (zero_trig) {
     const int s = a.slot;
     p.wkeys = a.tw.wkeys + (size_t)s * a.bmax * a.nwin;
-    p.bdone = a.tw.bdone + s;
     p.nzero_w = (int64_t)a.nb * a.nwin;
     p.mkey = a.tw.mkey + (size_t)s * a.nwin;
     p.nwin = a.nwin;
   } else {
     p.wkeys = nullptr;
-    p.bdone = nullptr;
     p.nzero_w = 0;
     p.mkey = nullptr;
     p.nwin = 0;
@@ -1919,11 +1965,13 @@ P2Args make_p2(const BatchArgs& a) {
   p.t0 = a.t0;
   p.nb = a.nb;
   // peak partials per template: one per second-pass workgroup, or one per
-  // wave with wave-owned columns; slot sets are sized for n2 per template
-  p.ntile2 = uses_p2_wave(a) ? a.plan.n2 * (a.plan.n1 / 16) / 64 : a.plan.n2 / a.plan.j;
+  // wave with wave-owned columns (one per column on the split-precision
+  // paths); slot sets are sized for n2 per template
+  p.ntile2 = uses_p2_wave(a) ? a.plan.n2 * (a.plan.n1 / 16) / 64
+             : (a.precision != CI_FP32 && !a.d_z) ? a.plan.n2
+                                                   : a.plan.n2 / a.plan.j;
   p.ppart = a.tw.ppart ? a.tw.ppart + (size_t)s * a.bmax * a.plan.n2 : nullptr;
   p.wkeys = a.tw.wkeys ? a.tw.wkeys + (size_t)s * a.bmax * a.nwin : nullptr;
-  p.bdone = a.tw.bdone ? a.tw.bdone + s : nullptr;
   p.mkey = a.tw.mkey ? a.tw.mkey + (size_t)s * a.nwin : nullptr;
   p.cnt = a.tw.cnt ? a.tw.cnt + (size_t)s * a.bmax : nullptr;
   p.sidx = a.tw.sidx ? a.tw.sidx + (size_t)s * a.bmax * a.nwin : nullptr;
@@ -2102,8 +2150,11 @@ struct Inst {
     return launch_timed(kern, dim3((unsigned)grid), dim3(J * 64), lds, st, a, make_p2(a));
   }
   static hipError_t fin(const BatchArgs& a, hipStream_t st) {
-    hipLaunchKernelGGL((k_fin<N1, N2, C>), dim3((unsigned)a.nb), dim3(256), kFinLds, st,
-                       make_p2(a));
+    const P2Args p = make_p2(a);
+    hipLaunchKernelGGL((k_fin<N1, N2, C>), dim3((unsigned)a.nb), dim3(256), kFinLds, st, p);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_place, dim3(1), dim3(256), kFinLds, st, p);
     return hipGetLastError();
   }
   static hipError_t p2s(const BatchArgs& a, hipStream_t st) {
