@@ -160,6 +160,7 @@ void free_seg(Seg* s) {
   if (s->twb) (void)hipFree(s->twb);
   for (int i = 0; i < 2; ++i)
     if (s->mxa2[i]) (void)hipFree(s->mxa2[i]);
+  if (s->fpw) (void)hipFree(s->fpw);
   delete s;
 }
 
@@ -1048,6 +1049,7 @@ int ci_segment_create(ci_ctx* ctx, const ci_segment_spec* spec, const void* d_xt
   ALLOC(s->w, sizeof(float2) * half);
   ALLOC(s->w0, sizeof(float2) * half);
   ALLOC(s->isp, sizeof(double) * half);
+  ALLOC(s->fpw, sizeof(double2) * half);
   ALLOC(s->psum, sizeof(double) * half);
   ALLOC(s->bsum, sizeof(double) * (half / kSegBlock));
   ALLOC(s->tw2048, sizeof(float2) * 2048);
@@ -1091,7 +1093,8 @@ int ci_segment_create(ci_ctx* ctx, const ci_segment_spec* spec, const void* d_xt
       return hipfail(ctx, e, "segment table upload");
     }
   }
-  e = launch_segment(s, d_xtilde, d_psd, static_cast<hipStream_t>(stream));
+  e = launch_segment_powers(s, static_cast<hipStream_t>(stream));
+  if (e == hipSuccess) e = launch_segment(s, d_xtilde, d_psd, static_cast<hipStream_t>(stream));
   if (e == hipSuccess) e = launch_mx_tables(s, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) {
     free_seg(s);

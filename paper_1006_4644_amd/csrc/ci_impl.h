@@ -145,6 +145,8 @@ struct Seg {
   float2* w;         // [n/2]  PSD-weighted, scaled data spectrum
   float2* w0;        // [n/2]  g x~ / S (two-polarization templates)
   double* isp;       // [n/2]  1 / S on the band, 0 below it
+  double2* fpw;      // [n/2]  ((k df)^-7/3, (k df)^-7/6) on the band, 0 below
+                     // it: fixed by n, fs and f_low, computed at creation
   double* psum;      // [n/2]  running sum of 4 df f^-7/3 / S from k_low
   double* bsum;      // [n/2 / kSegBlock] block sums, then block offsets
   float2* tw2048;    // [2048] exp(2 pi i e / 2048)
@@ -162,6 +164,8 @@ constexpr int kSegBlock = 2048;
 // Kernel launchers (kernels.hip).
 hipError_t launch_segment(Seg* s, const void* d_xtilde, const double* d_psd,
                           hipStream_t st);
+// The segment's data-independent powers (fpw), once at creation.
+hipError_t launch_segment_powers(Seg* s, hipStream_t st);
 hipError_t launch_params(const Seg* s, ci_tparams* d_params, int64_t n,
                          void* d_htilde, hipStream_t st);
 hipError_t launch_init_call(const TrigWork& tw, int nwin, int64_t* d_count,

@@ -63,8 +63,27 @@ __device__ __forceinline__ float2 chirp_phasor(const ci_tparams& P, int k) {
 constexpr int kSegThreads = 256;
 constexpr int kSegPer = kSegBlock / kSegThreads;
 
-__device__ __forceinline__ double seg_term(int64_t k, int64_t kl, double df, const double* psd) {
-  return k >= kl ? 4.0 * df * pow((double)k * df, -7.0 / 3.0) / psd[k] : 0.0;
+__device__ __forceinline__ double seg_term(int64_t k, int64_t kl, double df, const double* psd,
+                                           const double2* fpw) {
+  return k >= kl ? 4.0 * df * fpw[k].x / psd[k] : 0.0;
+}
+
+// fpw[k] = ((k df)^-7/3, (k df)^-7/6) for k >= k_low, else 0: the powers of
+// the template norm and of the template amplitude, which depend only on the
+// segment's length, sample rate and cut-off (computed once per segment).
+__global__ __launch_bounds__(256) void k_seg_powers(const SegDev* __restrict__ sd,
+                                                    double2* __restrict__ fpw) {
+  const int64_t kl = sd->k_low, half = sd->half;
+  const double df = sd->df;
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < half;
+       k += (int64_t)gridDim.x * blockDim.x) {
+    double2 v = make_double2(0.0, 0.0);
+    if (k >= kl) {
+      const double f = (double)k * df;
+      v = make_double2(pow(f, -7.0 / 3.0), pow(f, -7.0 / 6.0));
+    }
+    fpw[k] = v;
+  }
 }
 
 // Exclusive scan of one double per lane over a 256-lane workgroup.
@@ -87,6 +106,7 @@ __device__ double block_excl_scan_d(double v, double* sh, double* total) {
 
 __global__ __launch_bounds__(kSegThreads) void k_seg_terms(const SegDev* __restrict__ sd,
                                                            const double* __restrict__ psd,
+                                                           const double2* __restrict__ fpw,
                                                            double* __restrict__ psum,
                                                            double* __restrict__ bsum) {
   __shared__ double sh[kSegThreads];
@@ -96,7 +116,7 @@ __global__ __launch_bounds__(kSegThreads) void k_seg_terms(const SegDev* __restr
   double s = 0.0;
 #pragma unroll
   for (int i = 0; i < kSegPer; ++i) {
-    const double v = seg_term(base + i, kl, df, psd);
+    const double v = seg_term(base + i, kl, df, psd, fpw);
     psum[base + i] = v;
     s += v;
   }
@@ -138,7 +158,8 @@ __global__ __launch_bounds__(kSegThreads) void k_seg_final(const SegDev* __restr
                                                            const double* __restrict__ boff,
                                                            float2* __restrict__ w,
                                                            float2* __restrict__ w0,
-                                                           double* __restrict__ isp) {
+                                                           double* __restrict__ isp,
+                                                           const double2* __restrict__ fpw) {
   __shared__ double sh[kSegThreads];
   const int64_t kl = sd->k_low;
   const double df = sd->df, g = sd->g;
@@ -162,7 +183,7 @@ __global__ __launch_bounds__(kSegThreads) void k_seg_final(const SegDev* __restr
     if (k >= kl) {
       is = 1.0 / psd[k];
       const double fac0 = g * is;
-      const double fac = fac0 * pow((double)k * df, -7.0 / 6.0);
+      const double fac = fac0 * fpw[k].y;
       const float2 x = xt[k];
       o = make_float2((float)((double)x.x * fac), (float)((double)x.y * fac));
       o0 = make_float2((float)((double)x.x * fac0), (float)((double)x.y * fac0));
@@ -1522,8 +1543,11 @@ __global__ __launch_bounds__(J * 64, N1 <= 1024 ? 4 : 1) void k_p2mx(P2Args a) {
 // the kernel boundary makes every workgroup's results visible to it, with
 // no device-scope fence (each of which writes back a whole L2) inside
 // either kernel.
+// At most 128 registers up to n1 = 1024 (at 2048 that would spill), so
+// that the finalisers take less of the register file from the first pass
+// they overlap.
 template <int N1, int N2, int C>
-__global__ __launch_bounds__(256) void k_fin(P2Args a) {
+__global__ __launch_bounds__(256, N1 <= 1024 ? 4 : 2) void k_fin(P2Args a) {
   extern __shared__ float2 lds[];
   finalize_template<N1, N2, C>(a, blockIdx.x, lds);
 }
@@ -1841,10 +1865,15 @@ Plan plan_for(int log2n, int c, int j) {
   return p;
 }
 
+hipError_t launch_segment_powers(Seg* s, hipStream_t st) {
+  hipLaunchKernelGGL(k_seg_powers, dim3(1024), dim3(256), 0, st, s->dev, s->fpw);
+  return hipGetLastError();
+}
+
 hipError_t launch_segment(Seg* s, const void* d_xtilde, const double* d_psd, hipStream_t st) {
   const int nblk = (int)(s->host.half / kSegBlock);
-  hipLaunchKernelGGL(k_seg_terms, dim3(nblk), dim3(kSegThreads), 0, st, s->dev, d_psd, s->psum,
-                     s->bsum);
+  hipLaunchKernelGGL(k_seg_terms, dim3(nblk), dim3(kSegThreads), 0, st, s->dev, d_psd, s->fpw,
+                     s->psum, s->bsum);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_seg_scan, dim3(1), dim3(1024), 0, st, s->dev, s->bsum, nblk);
@@ -1852,7 +1881,7 @@ hipError_t launch_segment(Seg* s, const void* d_xtilde, const double* d_psd, hip
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_seg_final, dim3(nblk), dim3(kSegThreads), 0, st, s->dev,
                      reinterpret_cast<const float2*>(d_xtilde), d_psd, s->psum, s->bsum, s->w,
-                     s->w0, s->isp);
+                     s->w0, s->isp, s->fpw);
   return hipGetLastError();
 }
 
