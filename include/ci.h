@@ -578,8 +578,9 @@ int ci_get_tune(ci_ctx* ctx, int32_t log2n, int32_t precision, ci_tune* out);
 int ci_set_tune(ci_ctx* ctx, const ci_tune* cfg);
 
 /* Autotuner: times ci_find_triggers (no merge) on the given templates under
- * a coordinate search over tiles, second-pass residency, batch size and
- * the number of compute streams,
+ * a coordinate search over tiles, the FP32 second-pass variant (p2_wave),
+ * second-pass residency, batch size and the number of compute streams
+ * (the last step jointly over batch size and second-pass tile width),
  * starting from the default configuration; a candidate whose peaks,
  * trigger count or trigger list differ in any bit from the default's is
  * excluded.  Stores the fastest as the context's configuration for the

@@ -2114,22 +2114,29 @@ int ci_autotune(ci_ctx* ctx, const ci_segment* seg, const ci_tparams* d_params, 
   // less than the spread of repeated trials, and only in-order launches
   // can be timed against their own bytes)
   // Among in-order batch sizes within 1 % of the fastest, the largest is
-  // kept (fewer launches; the choice then varies less between runs).
+  // kept (fewer launches; the choice then varies less between runs).  Both
+  // second-pass tile widths are tried at every batch size here: the best
+  // width at the default batch need not be the best at a larger one.
   {
-    Tune io_c[6];
-    float io_t[6];
+    Tune io_c[12];
+    float io_t[12];
     int nio = 0;
     const int64_t bs1[6] = {best.batch, b0, b0 * 2, b0 * 4, b0 * 8, b0 / 2};
-    for (int i = 0; i < 6 && rc == CI_OK; ++i) {
-      if (bs1[i] < 0 || bs1[i] > 4096 || (bs1[i] > 0 && bs1[i] >= 2 * n)) continue;
-      Tune c = best;
-      c.streams = 1;
-      c.batch = bs1[i];
-      float ms = 0.f;
-      bool same = false;
-      rc = trial(c, &ms, &same);
-      if (rc == CI_OK && !same) ++rejected;
-      else if (rc == CI_OK) { io_c[nio] = c; io_t[nio] = ms; ++nio; }
+    const int jws[2] = {best.j, best.j == 4 ? 8 : 4};
+    for (int w = 0; w < 2 && rc == CI_OK; ++w) {
+      if (plan_fits(plan_for(l2, best.c, jws[w]), precision) != hipSuccess) continue;
+      for (int i = 0; i < 6 && rc == CI_OK; ++i) {
+        if (bs1[i] < 0 || bs1[i] > 4096 || (bs1[i] > 0 && bs1[i] >= 2 * n)) continue;
+        Tune c = best;
+        c.streams = 1;
+        c.j = jws[w];
+        c.batch = bs1[i];
+        float ms = 0.f;
+        bool same = false;
+        rc = trial(c, &ms, &same);
+        if (rc == CI_OK && !same) ++rejected;
+        else if (rc == CI_OK) { io_c[nio] = c; io_t[nio] = ms; ++nio; }
+      }
     }
     if (rc == CI_OK && nio > 0) {
       float io_ms = io_t[0];
