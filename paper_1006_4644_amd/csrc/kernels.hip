@@ -60,7 +60,7 @@ __device__ __forceinline__ float2 chirp_phasor(const ci_tparams& P, int k) {
 // bins: (1) the terms 4 df f_k^{-7/3} / S_k on [k_low, n/2) and their
 // block sums, (2) the scan of the block sums, the total and the data scale
 // g, (3) the running sum inside each block plus the weighted spectrum.
-constexpr int kSegThreads = 256;
+constexpr int kSegThreads = 1024;
 constexpr int kSegPer = kSegBlock / kSegThreads;
 
 __device__ __forceinline__ double seg_term(int64_t k, int64_t kl, double df, const double* psd,
