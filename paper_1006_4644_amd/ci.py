@@ -646,6 +646,8 @@ class Context:
         [nwin, 4], count [1]) as device tensors; the same results as one
         ci_find_triggers call over the bank with merging."""
         import torch
+        if chunk < 1:
+            raise ValueError(f"chunk must be >= 1 (got {chunk})")
         bank = np.ascontiguousarray(bank, dtype=np.float64)
         nt, n = len(bank), seg.n
         nwin = (n + window - 1) // window
