@@ -1441,17 +1441,44 @@ __global__ __launch_bounds__(J * 64, N1 <= 1024 ? 4 : 1) void k_p2mx(P2Args a) {
         for (int e = 0; e < 4; ++e)
           raw[p][e] = buf_ld(r, voff, ((16 / C) * e + (256 / C) * p) * N2 * C *
                                           (unsigned)sizeof(unsigned));
+      if constexpr (PREC == kFP16 && R3 <= 4) {
+        // the FP16 path: stages A and B on the matrix cores from the stored
+        // words (exact FP16 operands, no conversion, no operand split)
+        f16x8 A[R3][4];
 #pragma unroll
-      for (int p = 0; p < R3; ++p)
+        for (int b = 0; b < R3; ++b)
 #pragma unroll
-        for (int e = 0; e < 4; ++e) x[p][e] = h2f(raw[p][e]);
+          for (int f = 0; f < 4; ++f) A[b][f] = __builtin_bit_cast(f16x8, afr[(b * 4 + f) * 64 + lane]);
+        f32x4 yr[R3], yi[R3];
+        mx_ab_f16<R3>(raw, A, yr, yi);
+#pragma unroll
+        for (int b = 0; b < R3; ++b)
+#pragma unroll
+          for (int e = 0; e < 4; ++e)
+            x[b][e] = cmul(make_float2(yr[b][e], yi[b][e]), twt[(b * 4 + e) * 64]);
+      } else {
+#pragma unroll
+        for (int p = 0; p < R3; ++p)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) x[p][e] = h2f(raw[p][e]);
+      }
     }
+    constexpr bool kFoldAB = PREC == kFP16 && R3 <= 4;
     // FP16 operand range: the radix-R3 stage and a radix-16 stage grow
     // magnitudes by at most 16 R3, so inputs within kF16Lim / (16 R3) keep
     // every operand of both matrix-core stages within the limit and the
-    // per-instance check can be skipped for this tile
+    // per-instance check can be skipped for this tile (with stages A and B
+    // done from the stored words, only stage C's operands are checked:
+    // x then holds its inputs, which a radix-16 stage grows at most 16-fold)
     bool guard = false;
-    if constexpr (PREC == kFP16) {
+    if constexpr (kFoldAB) {
+      float m = 0.f;
+#pragma unroll
+      for (int b = 0; b < R3; ++b)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) m = fmaxf(m, fmaxf(fabsf(x[b][e].x), fabsf(x[b][e].y)));
+      guard = __any(!(m <= kF16Lim / 16.0f));
+    } else if constexpr (PREC == kFP16) {
       float m = 0.f;
 #pragma unroll
       for (int p = 0; p < R3; ++p)
@@ -1460,7 +1487,7 @@ __global__ __launch_bounds__(J * 64, N1 <= 1024 ? 4 : 1) void k_p2mx(P2Args a) {
       guard = __any(!(m <= kF16Lim / (16.0f * R3)));
     }
     // stage A: radix-R3 over p
-    if constexpr (R3 > 1) {
+    if constexpr (R3 > 1 && !kFoldAB) {
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         float2 t[R3];
@@ -1473,7 +1500,7 @@ __global__ __launch_bounds__(J * 64, N1 <= 1024 ? 4 : 1) void k_p2mx(P2Args a) {
     }
     // stage B with the folded twiddle, then w_L^{u0 (b + R3 v1)}
 #pragma unroll
-    for (int b = 0; b < R3; ++b) {
+    for (int b = 0; b < (kFoldAB ? 0 : R3); ++b) {
       V8 A4[4];
 #pragma unroll
       for (int f = 0; f < 4; ++f) A4[f] = __builtin_bit_cast(V8, afr[(b * 4 + f) * 64 + lane]);

@@ -166,4 +166,54 @@ split:
   }
 }
 
+// Stages A and B of a column of length 256 R3 (R3 <= 4) from exact FP16
+// inputs.  Lane (u0, g) supplies raw[p][e] = X[u0 + 16 (4 g + e) + 256 p]
+// as packed (re, im) FP16 words, which are the B operand as stored.  The
+// radix-R3 factors w_R3^{b p} are 1, i, -1 or -i, so with (Re, Im) = the
+// real- and imaginary-output products of stage B's matrix M_b with X_p,
+//   sum_p w^{b p} (M_b X_p)  takes  (+Re, +Im), (-Im, +Re), (-Re, -Im) or
+//   (+Im, -Re)  per term,
+// accumulated into positive and negative FP32 accumulators (two products
+// per matrix part: M = M_hi + M_lo; the data need no split) and differenced
+// at the end: yr[b] + i yi[b] = M_b sum_p w^{b p} X_p for outputs
+// v1 = 4 g .. 4 g + 3 of instance u0.  A[b] holds the fragments of M_b as
+// mx_prod expects them (re_hi, re_lo, im_hi, im_lo).
+template <int R3>
+__device__ __forceinline__ void mx_ab_f16(const unsigned (&raw)[R3][4],
+                                          const f16x8 (&A)[R3][4], f32x4 (&yr)[R3],
+                                          f32x4 (&yi)[R3]) {
+  static_assert(R3 == 1 || R3 == 2 || R3 == 4, "factors 1, i, -1, -i only");
+  typedef MxT<kFP16> M;
+  f16x8 xv[R3];
+#pragma unroll
+  for (int p = 0; p < R3; ++p)
+    xv[p] = __builtin_bit_cast(f16x8, make_uint4(raw[p][0], raw[p][1], raw[p][2], raw[p][3]));
+#pragma unroll
+  for (int b = 0; b < R3; ++b) {
+    const f32x4 z = {0.f, 0.f, 0.f, 0.f};
+    f32x4 rp = z, rm = z, ip = z, im = z;
+#pragma unroll
+    for (int p = 0; p < R3; ++p) {
+      // w^{b p} as a power of i
+      const int q = (b * p * (4 / R3)) & 3;
+      const f16x8 x = xv[p];
+      if (q == 0) {
+        rp = M::mma(A[b][1], x, M::mma(A[b][0], x, rp));
+        ip = M::mma(A[b][3], x, M::mma(A[b][2], x, ip));
+      } else if (q == 1) {
+        rm = M::mma(A[b][3], x, M::mma(A[b][2], x, rm));
+        ip = M::mma(A[b][1], x, M::mma(A[b][0], x, ip));
+      } else if (q == 2) {
+        rm = M::mma(A[b][1], x, M::mma(A[b][0], x, rm));
+        im = M::mma(A[b][3], x, M::mma(A[b][2], x, im));
+      } else {
+        rp = M::mma(A[b][3], x, M::mma(A[b][2], x, rp));
+        im = M::mma(A[b][1], x, M::mma(A[b][0], x, im));
+      }
+    }
+    yr[b] = rp - rm;
+    yi[b] = ip - im;
+  }
+}
+
 }  // namespace ci
