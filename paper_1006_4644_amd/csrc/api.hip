@@ -2130,6 +2130,9 @@ int ci_autotune(ci_ctx* ctx, const ci_segment* seg, const ci_tparams* d_params, 
         Tune c = best;
         c.streams = 1;
         c.j = jws[w];
+        // the same resident waves per CU at the other width (a residency is
+        // counted in workgroups of J waves' worth of columns)
+        if (c.p2_per_cu > 0 && jws[w] != best.j) c.p2_per_cu = std::max(1, c.p2_per_cu * best.j / jws[w]);
         c.batch = bs1[i];
         float ms = 0.f;
         bool same = false;
