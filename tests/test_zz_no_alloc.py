@@ -29,7 +29,8 @@ def _outputs(count, cap):
             torch.full((1,), -7, dtype=torch.int64, device="cuda"))
 
 
-def test_noalloc_matches_find_triggers(gpu_lib):
+@pytest.mark.parametrize("prec", [ci.FP32, ci.SPLIT_BF16, ci.SPLIT_FP16])
+def test_noalloc_matches_find_triggers(gpu_lib, prec):
     import torch
     ctx = gpu_lib.context(0)
     cap = 1 << 14
@@ -38,15 +39,16 @@ def test_noalloc_matches_find_triggers(gpu_lib):
     for i, (n, count, W, merge) in enumerate(cases):
         seg, params = _case(ctx, n, count, 4100 + i)
         thr = 4.0
-        ref = ctx.find_triggers(seg, params, thr, W, cap=cap, merge=merge)
+        ref = ctx.find_triggers(seg, params, thr, W, cap=cap, merge=merge, precision=prec)
         torch.cuda.synchronize()
         rp, rt, rc = (t.cpu().numpy().copy() for t in ref)
         out = _outputs(count, cap)
-        ctx.find_triggers_noalloc(seg, params, thr, W, *out, merge=merge)
+        ctx.find_triggers_noalloc(seg, params, thr, W, *out, merge=merge, precision=prec)
         torch.cuda.synchronize()
         p, t, c = (v.cpu().numpy() for v in out)
         k = min(int(rc[0]), cap)
-        print(f"n = 2^{n.bit_length() - 1}, {count} templates: {int(rc[0])} triggers")
+        print(f"precision {prec}, n = 2^{n.bit_length() - 1}, {count} templates: "
+              f"{int(rc[0])} triggers")
         assert int(rc[0]) > 0
         assert int(c[0]) == int(rc[0])
         assert np.array_equal(p, rp)
