@@ -40,7 +40,8 @@ constexpr int kSlots = 3;
 
 // Per-call trigger bookkeeping (device), kSlots slot sets.
 struct TrigWork {
-  unsigned long long* ppart;   // [kSlots][B][n2/j]  peak key per pass-2 workgroup
+  unsigned long long* ppart;   // [kSlots][B][n2]    peak keys of the second pass
+                               //                    (per workgroup or per wave)
   unsigned long long* wkeys;   // [kSlots][B][nwin]  window key per template
   unsigned long long* mkey;    // [kSlots][nwin]     merge key per window
   int* cnt;                    // [kSlots][B]        triggers per template

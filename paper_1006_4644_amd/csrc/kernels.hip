@@ -796,8 +796,9 @@ struct P2Args {
   int64_t t0;                // bank index of the batch's first template
   int nb;
   // trigger mode
-  u64* ppart;                // [nb][ntile2] per-workgroup peak keys
-  int ntile2;                // pass-2 workgroups per template
+  u64* ppart;                // [nb][ntile2] peak keys of the second pass
+  int ntile2;                // peak keys per template: one per workgroup, or
+                             // one per wave with wave-owned columns
   u64* wkeys;                // [nb][nwin]
   u64* mkey;                 // [nwin] per window: max over the batch of
                              // (rho^2 bits, complemented template index)
