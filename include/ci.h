@@ -171,7 +171,14 @@ typedef struct ci_tdparams {
 
 /* --- context ------------------------------------------------------------ */
 
-/* Create a context bound to HIP device `device`.  *out receives the handle. */
+/* Create a context bound to HIP device `device`.  *out receives the handle.
+ * Environment overrides, applied to the new context (a value that the
+ * corresponding setter would reject fails the call with CI_EINVAL and no
+ * context):
+ *   CI_BATCH=<templates>   as ci_set_batch;
+ *   CI_TUNE=<log2n>:<precision>:<tile_c>,<tile_j>,<p2_per_cu>,<batch>,
+ *           <streams>[,<p2_wave>]   as ci_set_tune, entries separated by ';'
+ *           (precision 0 FP32, 1 split BF16, 2 split FP16). */
 int ci_ctx_create(int device, ci_ctx** out);
 /* Frees the context's workspaces.  Segments created on it that are still
  * alive are detached: their buffers stay valid until ci_segment_destroy,

@@ -890,6 +890,47 @@ const char* ci_last_error(const ci_ctx* ctx) {
   return ctx ? ctx->err.c_str() : g_err.c_str();
 }
 
+// CI_BATCH and CI_TUNE (see ci_ctx_create) applied through the setters,
+// which validate them; CI_OK when neither is set.
+int apply_env_overrides(ci_ctx* c) {
+  if (const char* b = getenv("CI_BATCH")) {
+    char* end = nullptr;
+    const long long v = strtoll(b, &end, 10);
+    if (end == b || *end != '\0')
+      return fail(c, CI_EINVAL, "CI_BATCH='%s' is not an integer", b);
+    const int rc = ci_set_batch(c, v);
+    if (rc != CI_OK) return rc;
+  }
+  if (const char* t = getenv("CI_TUNE")) {
+    const std::string all(t);
+    size_t pos = 0;
+    while (pos <= all.size()) {
+      const size_t semi = all.find(';', pos);
+      const std::string ent = all.substr(pos, semi == std::string::npos ? std::string::npos : semi - pos);
+      pos = semi == std::string::npos ? all.size() + 1 : semi + 1;
+      if (ent.empty()) continue;
+      ci_tune cfg;
+      memset(&cfg, 0, sizeof cfg);
+      long long batch = 0;
+      int used = 0;
+      const int got = sscanf(ent.c_str(), "%d:%d:%d,%d,%d,%lld,%d%n", &cfg.log2n, &cfg.precision,
+                             &cfg.tile_c, &cfg.tile_j, &cfg.p2_per_cu, &batch, &cfg.streams, &used);
+      if (got != 7) return fail(c, CI_EINVAL, "CI_TUNE entry '%s' is not L:P:c,j,p2,batch,streams[,p2_wave]", ent.c_str());
+      if (ent[used] == ',') {
+        int more = 0;
+        if (sscanf(ent.c_str() + used, ",%d%n", &cfg.p2_wave, &more) != 1)
+          return fail(c, CI_EINVAL, "CI_TUNE entry '%s': bad p2_wave", ent.c_str());
+        used += more;
+      }
+      if (ent[used] != '\0') return fail(c, CI_EINVAL, "CI_TUNE entry '%s': trailing text", ent.c_str());
+      cfg.batch = batch;
+      const int rc = ci_set_tune(c, &cfg);
+      if (rc != CI_OK) return rc;
+    }
+  }
+  return CI_OK;
+}
+
 int ci_ctx_create(int device, ci_ctx** out) {
   if (!out) return fail(nullptr, CI_EINVAL, "null output handle");
   int ndev = 0;
@@ -908,6 +949,12 @@ int ci_ctx_create(int device, ci_ctx** out) {
   if (!c) return fail(nullptr, CI_ENOMEM, "context allocation");
   c->device = device;
   c->scratch = sp;
+  const int rc = apply_env_overrides(c);
+  if (rc != CI_OK) {
+    const std::string msg = c->err;
+    (void)ci_ctx_destroy(c);
+    return fail(nullptr, rc, "%s", msg.c_str());
+  }
   *out = c;
   return CI_OK;
 }

@@ -162,7 +162,7 @@ __global__ __launch_bounds__(kSegThreads) void k_seg_final(const SegDev* __restr
                                                            const double2* __restrict__ fpw) {
   __shared__ double sh[kSegThreads];
   const int64_t kl = sd->k_low;
-  const double df = sd->df, g = sd->g;
+  const double g = sd->g;
   const int64_t base = (int64_t)blockIdx.x * kSegBlock + threadIdx.x * kSegPer;
   double v[kSegPer];
   double s = 0.0;

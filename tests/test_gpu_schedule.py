@@ -404,3 +404,32 @@ def test_tile_shapes_accepted_and_checked(ctx):
     assert cfg["rejected"] == 0 and cfg["candidates"] >= 8
     ctx.set_tune(21, ci.SPLIT_BF16)
     seg.close()
+
+
+def test_environment_overrides(gpu_lib, monkeypatch):
+    """CI_TUNE and CI_BATCH apply at context creation through the setters'
+    validation; a value a setter would reject fails the creation loudly."""
+    monkeypatch.setenv("CI_TUNE", "20:0:8,8,0,512,1,1;18:1:4,8,3,1024,2")
+    monkeypatch.setenv("CI_BATCH", "96")
+    ctx = gpu_lib.context(0)
+    try:
+        t = ctx.get_tune(20, ci.FP32)
+        assert (t["tile_c"], t["tile_j"], t["p2_per_cu"], t["batch"], t["streams"],
+                t["p2_wave"]) == (8, 8, 0, 512, 1, 1)
+        assert not t["tuned"]
+        t = ctx.get_tune(18, ci.SPLIT_BF16)
+        assert (t["tile_c"], t["tile_j"], t["p2_per_cu"], t["batch"], t["streams"],
+                t["p2_wave"]) == (4, 8, 3, 1024, 2, 0)
+    finally:
+        ctx.close()
+    for bad in ("20:0:8,8,0,512", "20:0:6,8,0,512,1", "15:0:8,8,0,512,1", "20:0:8,8,0,512,1,1x",
+                "20:3:8,8,0,512,1"):
+        monkeypatch.setenv("CI_TUNE", bad)
+        with pytest.raises(ci.CiError) as e:
+            gpu_lib.context(0)
+        assert e.value.code == ci.EINVAL, bad
+    monkeypatch.delenv("CI_TUNE")
+    monkeypatch.setenv("CI_BATCH", "lots")
+    with pytest.raises(ci.CiError) as e:
+        gpu_lib.context(0)
+    assert "CI_BATCH" in str(e.value)
