@@ -181,6 +181,26 @@ def copy_probe_gbs():
     return 2 * (n * 8) / (ms / 1e3) / 1e9
 
 
+def device_record(device=0):
+    """The GPU the run used: name, architecture, compute units, memory, and
+    (when rocm-smi answers within a few seconds) its current clocks."""
+    import subprocess
+    import torch
+    p = torch.cuda.get_device_properties(device)
+    rec = {"name": p.name, "arch": getattr(p, "gcnArchName", ""),
+           "compute_units": p.multi_processor_count,
+           "memory_gib": round(p.total_memory / 2**30, 1)}
+    try:
+        r = subprocess.run(["rocm-smi", "--showclocks", "--json"], capture_output=True,
+                           text=True, timeout=10)
+        if r.returncode == 0:
+            card = next(iter(json.loads(r.stdout).values()))
+            rec["clocks"] = {k: v for k, v in card.items() if "clock" in k.lower()}
+    except Exception:  # clocks are informational only
+        pass
+    return rec
+
+
 def hbm_probes(ctx):
     """The device's streaming ceilings with the library's probe kernels
     (16-byte non-temporal accesses, 2 GiB per direction): write-only,
@@ -573,6 +593,7 @@ def run_classes(args, lib, ctx, wl):
                           "speedup_vs_headline": round(v2 / value, 3),
                           "path_hbm_frac": round(gbs2 / HBM_PEAK_GBS, 4)}
         out["precision_paths"] = paths
+    out["device"] = device_record(0)
     for seg, *_ in inputs:
         seg.close()
     ctx.close()
@@ -780,6 +801,7 @@ def main():
                   "gpu_speedup_vs_all_core": round(value / allc["value"], 1),
                   "gpu_speedup_vs_single_core": round(value / single["value"], 1)}
         out["cpu_baseline"] = cb
+    out["device"] = device_record(0)
     seg.close()
     ctx.close()
     print(json.dumps(out), flush=True)
