@@ -65,8 +65,11 @@ def kernel_source_hash() -> str:
 def parse():
     p = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     p.add_argument("--gpus", type=int, default=1)
-    p.add_argument("--steps", type=int, default=20)
-    p.add_argument("--warmup", type=int, default=3)
+    # default: 100 timed steps after 20 warm-ups (~0.4 s of timed work for
+    # the 1024-template bank at 2^20; the first tens of milliseconds run
+    # before the clocks settle), fewer for the workloads whose step is long
+    p.add_argument("--steps", type=int, default=None)
+    p.add_argument("--warmup", type=int, default=None)
     p.add_argument("--workload", default="fp32-2^20")
     p.add_argument("--batch", type=int, default=0, help="templates per batch (0: built-in)")
     p.add_argument("--cpu-seconds", type=float, default=15.0,
@@ -101,7 +104,15 @@ def parse():
     p.add_argument("--tune", default="",
                    help="explicit launch configuration C,J,P2,BATCH[,STREAMS[,P2_WAVE]] "
                         "(skips the autotuner)")
-    return p.parse_args()
+    args = p.parse_args()
+    # (steps, warmup) by workload: about a second of timed work or less
+    long_steps = {"precision-2^20": (20, 5), "3g-2^21": (1, 1)}
+    dsteps, dwarm = long_steps.get(args.workload, (100, 20))
+    if args.steps is None:
+        args.steps = dsteps
+    if args.warmup is None:
+        args.warmup = dwarm
+    return args
 
 
 def configure(ctx, ci, args, tune_calls):
@@ -183,7 +194,9 @@ def copy_probe_gbs():
 
 def device_record(device=0):
     """The GPU the run used: name, architecture, compute units, memory, and
-    (when rocm-smi answers within a few seconds) its current clocks."""
+    (when rocm-smi answers within a few seconds) its clocks as read at the
+    end of the run, after the timed work (idle levels, not the clocks of the
+    timed steps)."""
     import subprocess
     import torch
     p = torch.cuda.get_device_properties(device)
@@ -195,7 +208,7 @@ def device_record(device=0):
                            text=True, timeout=10)
         if r.returncode == 0:
             card = next(iter(json.loads(r.stdout).values()))
-            rec["clocks"] = {k: v for k, v in card.items() if "clock" in k.lower()}
+            rec["clocks_at_end"] = {k: v for k, v in card.items() if "clock" in k.lower()}
     except Exception:  # clocks are informational only
         pass
     return rec
