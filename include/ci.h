@@ -459,7 +459,10 @@ typedef struct {
  * those outside it but within the covering radius are moved to the
  * nearest point of its boundary.  out_host[0 .. min(count, cap)) receives
  * (m1, m2) with m1 >= m2; *count the number placed (CI_ETRUNC when above
- * cap; cap = 0 and out_host = NULL query the count). */
+ * cap; cap = 0 and out_host = NULL query the count).  The metric samples
+ * and the lattice rows are computed on up to 16 host threads, joined in a
+ * fixed order: the result does not depend on the thread count.  Safe to
+ * call from several threads at once. */
 int ci_make_bank_lattice(const ci_lattice_spec* spec, const double* psd_host, int64_t n,
                          double fs, double f_low, ci_template* out_host, int64_t cap,
                          int64_t* count);

@@ -12,6 +12,8 @@
 #include <stdio.h>
 
 #include <algorithm>
+#include <atomic>
+#include <thread>
 #include <vector>
 
 #include "ci_impl.h"
@@ -107,6 +109,30 @@ bool metric_at(const double* psd, int64_t n, double fs, double f_low, double m1,
 struct P2 {
   double x, y;
 };
+
+// Runs f(i) for every i in [0, n) on up to 16 host threads. Each i writes
+// only its own slot, so what the caller assembles afterwards does not depend
+// on the number of threads; a thread that cannot be started leaves its share
+// to the others.
+template <class F>
+void parallel_for(int64_t n, const F& f) {
+  const unsigned hw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  const int64_t nt = std::min<int64_t>(n, hw);
+  std::atomic<int64_t> next{0};
+  const auto run = [&] {
+    for (int64_t i; (i = next.fetch_add(1, std::memory_order_relaxed)) < n;) f(i);
+  };
+  std::vector<std::thread> th;
+  for (int64_t t = 1; t < nt; ++t) {
+    try {
+      th.emplace_back(run);
+    } catch (...) {
+      break;
+    }
+  }
+  run();
+  for (std::thread& t : th) t.join();
+}
 
 // Closest point to p on segment [a, b].
 P2 closest_on_segment(P2 p, P2 a, P2 b) {
@@ -249,22 +275,29 @@ int ci_make_bank_lattice(const ci_lattice_spec* spec, const double* psd_host, in
       chirp_times(m1, m2, f_low, &t.x, &t.y);
       region.push_back(t);
     }
-  // metric samples on a log grid of (m1 >= m2)
+  // metric samples on a log grid of (m1 >= m2), computed in parallel and
+  // kept in grid order
   struct Sample {
     P2 t;
     double g[3];
   };
-  std::vector<Sample> samples;
   const int G = 24;
+  std::vector<P2> grid;
   for (int i = 0; i < G; ++i)
-    for (int j = 0; j <= i; ++j) {
-      const double m1 = lo * pow(hi / lo, (double)i / (G - 1));
-      const double m2 = lo * pow(hi / lo, (double)j / (G - 1));
-      Sample sm;
-      if (!metric_at(psd_host, n, fs, f_low, m1, m2, sm.g)) continue;
-      chirp_times(m1, m2, f_low, &sm.t.x, &sm.t.y);
-      samples.push_back(sm);
-    }
+    for (int j = 0; j <= i; ++j)
+      grid.push_back(P2{lo * pow(hi / lo, (double)i / (G - 1)), lo * pow(hi / lo, (double)j / (G - 1))});
+  std::vector<Sample> all(grid.size());
+  std::vector<char> ok(grid.size(), 0);
+  parallel_for((int64_t)grid.size(), [&](int64_t q) {
+    const double m1 = grid[(size_t)q].x, m2 = grid[(size_t)q].y;
+    Sample& sm = all[(size_t)q];
+    if (!metric_at(psd_host, n, fs, f_low, m1, m2, sm.g)) return;
+    chirp_times(m1, m2, f_low, &sm.t.x, &sm.t.y);
+    ok[(size_t)q] = 1;
+  });
+  std::vector<Sample> samples;
+  for (size_t q = 0; q < grid.size(); ++q)
+    if (ok[q]) samples.push_back(all[q]);
   if (samples.empty()) return ci::report_error(CI_EINVAL, "no template of the range has a band");
   double t0min = 1e300, t0max = -1e300;
   for (const P2& p : region) {
@@ -281,7 +314,15 @@ int ci_make_bank_lattice(const ci_lattice_spec* spec, const double* psd_host, in
   std::nth_element(g00.begin(), g00.begin() + g00.size() / 2, g00.end());
   const double extent = sqrt(g00[g00.size() / 2]) * (t0max - t0min);
   const int K = (int)std::min(12.0, std::max(1.0, floor(extent / (10.0 * R))));
-  std::vector<ci_template> out;
+  // Each strip is set up in turn (polygon, bounding metric, bounds); its
+  // lattice rows are then placed in parallel, in blocks whose results are
+  // joined in strip and row order.
+  struct Strip {
+    std::vector<P2> pu;
+    double l00, l10, l11, sq, xmin, xmax, ymin, ymax;
+    int64_t rows;
+  };
+  std::vector<Strip> strips;
   double work = 0.0;
   for (int st = 0; st < K; ++st) {
     const double a = t0min * pow(t0max / t0min, (double)st / K);
@@ -312,23 +353,45 @@ int ci_make_bank_lattice(const ci_lattice_spec* spec, const double* psd_host, in
     for (const Sample* sm : in) gs.push_back(sm->g);
     double gc[3];
     bounding_metric(gs, ref->g, gc);
-    const double l00 = sqrt(gc[0]), l10 = gc[1] / l00, l11 = sqrt(gc[2] - l10 * l10);
+    Strip sp;
+    sp.l00 = sqrt(gc[0]);
+    sp.l10 = gc[1] / sp.l00;
+    sp.l11 = sqrt(gc[2] - sp.l10 * sp.l10);
     const double scale = 1.05;
     // u = sqrt(scale) L^T tau: the bounding metric is the identity in u
-    const double sq = sqrt(scale);
-    std::vector<P2> pu;
-    for (const P2& t : poly) pu.push_back(P2{sq * (l00 * t.x + l10 * t.y), sq * l11 * t.y});
+    sp.sq = sqrt(scale);
+    for (const P2& t : poly)
+      sp.pu.push_back(P2{sp.sq * (sp.l00 * t.x + sp.l10 * t.y), sp.sq * sp.l11 * t.y});
     double xmin = 1e300, xmax = -1e300, ymin = 1e300, ymax = -1e300;
-    for (const P2& p : pu) {
+    for (const P2& p : sp.pu) {
       xmin = std::min(xmin, p.x); xmax = std::max(xmax, p.x);
       ymin = std::min(ymin, p.y); ymax = std::max(ymax, p.y);
     }
-    xmin -= R; xmax += R; ymin -= R; ymax += R;
-    work += ((ymax - ymin) / dy + 1) * ((xmax - xmin) / side + 1);
+    sp.xmin = xmin - R; sp.xmax = xmax + R; sp.ymin = ymin - R; sp.ymax = ymax + R;
+    work += ((sp.ymax - sp.ymin) / dy + 1) * ((sp.xmax - sp.xmin) / side + 1);
     if (work > 5e7) return ci::report_error(CI_EINVAL, "lattice too large (over 5e7 points)");
-    for (int64_t r = 0; ymin + r * dy <= ymax; ++r) {
-      const double y = ymin + r * dy, x0 = xmin + ((r & 1) ? 0.5 * side : 0.0);
-      for (int64_t c = 0; x0 + c * side <= xmax; ++c) {
+    sp.rows = 0;
+    while (sp.ymin + sp.rows * dy <= sp.ymax) ++sp.rows;
+    strips.push_back(std::move(sp));
+  }
+  const int64_t kRowBlock = 16;
+  struct Block {
+    size_t strip;
+    int64_t r0, r1;
+  };
+  std::vector<Block> blocks;
+  for (size_t i = 0; i < strips.size(); ++i)
+    for (int64_t r = 0; r < strips[i].rows; r += kRowBlock)
+      blocks.push_back(Block{i, r, std::min(strips[i].rows, r + kRowBlock)});
+  std::vector<std::vector<ci_template>> placed(blocks.size());
+  parallel_for((int64_t)blocks.size(), [&](int64_t bi) {
+    const Block& bk = blocks[(size_t)bi];
+    const Strip& sp = strips[bk.strip];
+    const std::vector<P2>& pu = sp.pu;
+    std::vector<ci_template>& dst = placed[(size_t)bi];
+    for (int64_t r = bk.r0; r < bk.r1; ++r) {
+      const double y = sp.ymin + r * dy, x0 = sp.xmin + ((r & 1) ? 0.5 * side : 0.0);
+      for (int64_t c = 0; x0 + c * side <= sp.xmax; ++c) {
         P2 p{x0 + c * side, y};
         if (!inside(pu, p)) {
           // within the covering radius of the strip: move onto its boundary
@@ -342,7 +405,7 @@ int ci_make_bank_lattice(const ci_lattice_spec* spec, const double* psd_host, in
           if (bd > R * R) continue;
           p = best;
         }
-        const double t3 = p.y / (sq * l11), t0 = (p.x / sq - l10 * t3) / l00;
+        const double t3 = p.y / (sp.sq * sp.l11), t0 = (p.x / sp.sq - sp.l10 * t3) / sp.l00;
         double M, eta;
         m_eta(t0, t3, f_low, &M, &eta);
         if (!(eta > 0)) continue;
@@ -351,10 +414,12 @@ int ci_make_bank_lattice(const ci_lattice_spec* spec, const double* psd_host, in
         ci_template tm;
         tm.m1 = std::min(std::max(0.5 * mt * (1.0 + d), lo), hi);
         tm.m2 = std::min(std::max(0.5 * mt * (1.0 - d), lo), tm.m1);
-        out.push_back(tm);
+        dst.push_back(tm);
       }
     }
-  }
+  });
+  std::vector<ci_template> out;
+  for (const std::vector<ci_template>& v : placed) out.insert(out.end(), v.begin(), v.end());
   *count = (int64_t)out.size();
   const int64_t k = std::min<int64_t>(cap, (int64_t)out.size());
   for (int64_t i = 0; i < k; ++i) out_host[i] = out[(size_t)i];
