@@ -247,36 +247,43 @@ __device__ __forceinline__ int xcd_remap(int bid, int nblk) {
 // pass 1: generate + correlate + first four-step pass
 // ---------------------------------------------------------------------------
 
-// v with t(v) = t (t < 0) for a time-domain template: Newton's method in
-// FP64 from the Newtonian guess t = -K v^-8, kept inside [v_low, v_end],
-// until the step falls below 1e-15 v.
-__device__ __forceinline__ double td_solve_v(const ci_tdparams& T, double t) {
+// w = 1/v with t(v) = t (t < 0) for a time-domain template.  In w the
+// chirp time is a polynomial, t = -K w^3 (w^5 + tau_2 w^3 + tau_3 w^2 +
+// tau_4 w + tau_5), so Newton's method needs no division: the residual is
+// evaluated in FP64 and divided by the derivative through its FP32
+// reciprocal, which still converges to FP64 accuracy (once close, each
+// step shrinks the error by ~1e-7 or better).  Started from the Newtonian
+// guess w = (-t / K)^{1/8}, kept inside [1/v_end, 1/v_low], until the step
+// falls below 1e-15 w.
+__device__ __forceinline__ double td_solve_w(const ci_tdparams& T, double t) {
   const float q = (float)(-t / T.K);
-  double v = (double)__builtin_amdgcn_exp2f(-0.125f * __builtin_amdgcn_logf(q));
-  v = fmin(fmax(v, T.v_low), T.v_end);
+  const double wlo = 1.0 / T.v_end, whi = 1.0 / T.v_low;
+  double w = (double)__builtin_amdgcn_exp2f(0.125f * __builtin_amdgcn_logf(q));
+  w = fmin(fmax(w, wlo), whi);
   for (int it = 0; it < 40; ++it) {
-    const double iv = 1.0 / v;
-    const double iv2 = iv * iv, iv4 = iv2 * iv2, iv8 = iv4 * iv4;
-    const double s = fma(v * v, fma(v, fma(v, fma(v, T.tau[3], T.tau[2]), T.tau[1]), T.tau[0]), 1.0);
-    const double R = fma(v * v, fma(v, fma(v, fma(v, T.r[3], T.r[2]), T.r[1]), T.r[0]), 1.0);
-    const double f = fma(-T.K * iv8, s, -t);
-    const double d = 8.0 * T.K * iv8 * iv * R;
-    double vn = v - f / d;
-    vn = fmin(fmax(vn, T.v_low), T.v_end);
-    const bool done = fabs(vn - v) <= 1e-15 * v;
-    v = vn;
+    const double w2 = w * w;
+    const double p = fma(w, fma(w, fma(w, fma(w, w, T.tau[0]), T.tau[1]), T.tau[2]), T.tau[3]);
+    const double g = fma(-T.K * w2 * w, p, -t);
+    const double dp = fma(w, fma(w, fma(w, fma(8.0 * w, w, 6.0 * T.tau[0]), 5.0 * T.tau[1]),
+                                 4.0 * T.tau[2]),
+                          3.0 * T.tau[3]);
+    const float rc = __builtin_amdgcn_rcpf((float)(-T.K * w2 * dp));
+    double wn = fma(-g, (double)rc, w);
+    wn = fmin(fmax(wn, wlo), whi);
+    const bool done = fabs(wn - w) <= 1e-15 * w;
+    w = wn;
     if (done) break;
   }
-  return v;
+  return w;
 }
 
-// Gravitational-wave phase 2 phi(v) in revolutions, reduced to [-1/2, 1/2]
-// in FP64.
-__device__ __forceinline__ float td_phase_frac(const ci_tdparams& T, double v) {
-  const double iv = 1.0 / v;
-  const double iv2 = iv * iv, iv5 = iv2 * iv2 * iv;
-  const double s = fma(v * v, fma(v, fma(v, T.p[2], T.p[1]), T.p[0]), 1.0);
-  const double phi = -T.P * fma(iv5, s, T.p[3] * log(v));
+// Gravitational-wave phase 2 phi in revolutions from w = 1/v, reduced to
+// [-1/2, 1/2] in FP64: 2 phi = -(2 P) (w^5 + p_2 w^3 + p_3 w^2 + p_4 w -
+// p_5 log w), the TaylorT2 phase v^-5 (1 + p_2 v^2 + p_3 v^3 + p_4 v^4) +
+// p_5 log v written in w.
+__device__ __forceinline__ float td_phase_frac(const ci_tdparams& T, double w) {
+  const double poly = w * fma(w, fma(w, fma(w, w, T.p[0]), T.p[1]), T.p[2]);
+  const double phi = -T.P * fma(-T.p[3], log(w), poly);
   const double r = phi * 0.31830988618379067;  // phi / pi
   return (float)(r - rint(r));
 }
@@ -293,9 +300,9 @@ __global__ __launch_bounds__(256) void k_td_gen(const SegDev* __restrict__ sd,
   const int64_t m = n - j;
   float2 o = make_float2(0.f, 0.f);
   if (!(T.flags & CI_TMPL_EMPTY) && m >= T.m_lo && m <= T.m_hi) {
-    const double v = td_solve_v(T, -(double)m / sd->fs);
-    const float fr = td_phase_frac(T, v);
-    const float a = (float)(v * v);
+    const double w = td_solve_w(T, -(double)m / sd->fs);
+    const float fr = td_phase_frac(T, w);
+    const float a = __builtin_amdgcn_rcpf((float)(w * w));
     o = make_float2(a * __builtin_amdgcn_cosf(fr), a * __builtin_amdgcn_sinf(fr));
   }
   u[(size_t)b * n + j] = o;
@@ -617,9 +624,9 @@ struct SrcGen {
   __device__ __forceinline__ float2 operator()(int j) const {
     const int64_t m = n - j;
     if ((T.flags & CI_TMPL_EMPTY) || m < T.m_lo || m > T.m_hi) return make_float2(0.f, 0.f);
-    const double v = td_solve_v(T, -(double)m / fs);
-    const float fr = td_phase_frac(T, v);
-    const float a = (float)(v * v);
+    const double w = td_solve_w(T, -(double)m / fs);
+    const float fr = td_phase_frac(T, w);
+    const float a = __builtin_amdgcn_rcpf((float)(w * w));
     return make_float2(a * __builtin_amdgcn_cosf(fr), a * __builtin_amdgcn_sinf(fr));
   }
 };
@@ -647,7 +654,15 @@ __global__ __launch_bounds__(C * N2 / 16) void k_pass1_mem(P1Args a) {
   __syncthreads();
 
   const int bid = xcd_remap(blockIdx.x, gridDim.x);
-  const int b = bid / TILES, tile = bid % TILES;
+  const int b = bid / TILES;
+  int tile = bid % TILES;
+  if constexpr (MODE == 1) {
+    // The correlator reads each bin k and its mirror n - k, which lies in
+    // column N1 - k1: tiles m and TILES - 1 - m run next to each other on
+    // one XCD, so that the second read of a value finds it in that XCD's L2.
+    const int i = tile;
+    tile = (i & 1) ? TILES - 1 - (i >> 1) : (i >> 1);
+  }
   const float2* vb = a.uv + (size_t)b * N;
   if constexpr (MODE == 0) {
     pass1_tile<N1, N2, C, 16, false>(a, SrcMem{vb}, b, tile, lds, twl, t, c);
