@@ -203,6 +203,12 @@ def device_record(device=0):
     rec = {"name": p.name, "arch": getattr(p, "gcnArchName", ""),
            "compute_units": p.multi_processor_count,
            "memory_gib": round(p.total_memory / 2**30, 1)}
+    # Under a profiler its preloaded library initialises the GPU in every
+    # child process too, and rocm-smi's interpreter hop would then replace
+    # such a process: no clock query there.
+    if any(k.startswith("ROCPROF") for k in os.environ) or \
+            "rocprof" in os.environ.get("LD_PRELOAD", ""):
+        return rec
     try:
         r = subprocess.run(["rocm-smi", "--showclocks", "--json"], capture_output=True,
                            text=True, timeout=10)
