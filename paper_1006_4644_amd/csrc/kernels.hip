@@ -1156,9 +1156,12 @@ __device__ __forceinline__ void pass2_post(const float2 (&x)[16], const P2Args& 
 // Persistent pass 2: each workgroup walks tiles item = blockIdx.x + k G
 // and prefetches the next tile's column inputs into registers while it
 // transforms the current one, so that a CU keeps loads in flight during
-// its butterflies.
+// its butterflies.  Four waves per SIMD (at most 128 registers) except for
+// 2048-point rows in workgroups of 512 threads, whose radix-8 stage and
+// prefetch need more: two waves per SIMD there, so that nothing spills.
 template <int N1, int N2, int C, int J>
-__global__ __launch_bounds__(J * N1 / 16, 4) void k_pass2_trig(P2Args a) {
+__global__ __launch_bounds__(J * N1 / 16, (N1 >= 2048 && J * N1 / 16 <= 512) ? 2 : 4)
+    void k_pass2_trig(P2Args a) {
   constexpr int TILES = N2 / J;
   using K = Col<N1, J>;
   extern __shared__ float2 lds[];
@@ -1586,11 +1589,11 @@ __global__ __launch_bounds__(J * 64, N1 <= 1024 ? 4 : 1) void k_p2mx(P2Args a) {
 // the kernel boundary makes every workgroup's results visible to it, with
 // no device-scope fence (each of which writes back a whole L2) inside
 // either kernel.
-// At most 128 registers up to n1 = 1024 (at 2048 that would spill), so
-// that the finalisers take less of the register file from the first pass
-// they overlap.
+// At most 128 registers up to n1 = 1024, so that the finalisers take less
+// of the register file from the first pass they overlap; at 2048 the
+// column's FP64 recompute needs more than 256, so one wave per SIMD.
 template <int N1, int N2, int C>
-__global__ __launch_bounds__(256, N1 <= 1024 ? 4 : 2) void k_fin(P2Args a) {
+__global__ __launch_bounds__(256, N1 <= 1024 ? 4 : 1) void k_fin(P2Args a) {
   extern __shared__ float2 lds[];
   finalize_template<N1, N2, C>(a, blockIdx.x, lds);
 }
