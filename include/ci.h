@@ -576,7 +576,7 @@ typedef struct {
                            over: 2 (one batch's second pass overlaps the
                            next batch's first) or 1 (in order); 0 means 2 */
   int32_t p2_wave;      /* FP32 second pass at n1 = 512 or 1024 (2^17 ..
-                           2^20): 1 hands each column to one wave after its
+                           2^21): 1 hands each column to one wave after its
                            first stage (one cross-wave exchange, per-wave
                            post-pass), 0 keeps the columns spread over the
                            workgroup; ignored elsewhere */

@@ -468,7 +468,7 @@ int check_job(Ctx* ctx, Job& jb, int32_t precision, float thr, int64_t window) {
   if (jb.cap > 0 && !jb.trig) return fail(ctx, CI_EINVAL, "null d_trig with cap > 0");
   const int l2 = jb.seg->plan.log2n;
   jb.cfg = ctx->tune[l2][precision];
-  jb.plan = plan_for(l2, jb.cfg.c, jb.cfg.j);
+  jb.plan = plan_for(l2, jb.cfg.c, jb.cfg.j, precision);
   rc = check_plan(ctx, jb.plan, precision);
   if (rc != CI_OK) return rc;
   jb.nwin = (N + window - 1) / window;
@@ -803,7 +803,7 @@ int td_batches(Ctx* ctx, const Seg* seg, const ci_tdparams* d_tdp, int64_t n, hi
   memset(&a, 0, sizeof a);
   a.seg = seg;
   const Tune& t = ctx->tune[seg->plan.log2n][CI_FP32];
-  a.plan = plan_for(seg->plan.log2n, t.c, t.j);
+  a.plan = plan_for(seg->plan.log2n, t.c, t.j, CI_FP32);
   rc = check_plan(ctx, a.plan, CI_FP32);
   if (rc != CI_OK) return rc;
   a.bmax = (int)B;
@@ -1072,7 +1072,8 @@ int ci_segment_create(ci_ctx* ctx, const ci_segment_spec* spec, const void* d_xt
   s->ctx = ctx;
   s->device = ctx->device;
   s->spec = *spec;
-  s->plan = plan_for(l2, 8, 4);
+  // the matrix-core tables below follow the split paths' factorisation
+  s->plan = plan_for(l2, 8, 4, CI_SPLIT_BF16);
   SegDev& h = s->host;
   h.n = spec->n;
   h.half = spec->n / 2;
@@ -1253,7 +1254,7 @@ int ci_matched_filter(ci_ctx* ctx, const ci_segment* seg, const ci_tparams* d_pa
   a.seg = seg;
   {
     const Tune& t = ctx->tune[seg->plan.log2n][precision];
-    a.plan = plan_for(seg->plan.log2n, t.c, t.j);
+    a.plan = plan_for(seg->plan.log2n, t.c, t.j, precision);
   }
   rc = check_plan(ctx, a.plan, precision);
   if (rc != CI_OK) return rc;
@@ -1997,7 +1998,7 @@ int ci_set_tune(ci_ctx* ctx, const ci_tune* cfg) {
   {
     DeviceGuard dg(ctx->device);
     if (!dg.ok) return fail(ctx, CI_EHIP, "cannot select device %d", ctx->device);
-    const int rc = check_plan(ctx, plan_for(cfg->log2n, cfg->tile_c, cfg->tile_j), cfg->precision);
+    const int rc = check_plan(ctx, plan_for(cfg->log2n, cfg->tile_c, cfg->tile_j, cfg->precision), cfg->precision);
     if (rc != CI_OK) return rc;
   }
   Tune& t = ctx->tune[cfg->log2n][cfg->precision];
@@ -2111,7 +2112,7 @@ int ci_autotune(ci_ctx* ctx, const ci_segment* seg, const ci_tparams* d_params, 
     c.c = tiles[i][0];
     c.j = tiles[i][1];
     if (c.c == best.c && c.j == best.j) continue;
-    if (plan_fits(plan_for(l2, c.c, c.j), precision) != hipSuccess) continue;
+    if (plan_fits(plan_for(l2, c.c, c.j, precision), precision) != hipSuccess) continue;
     float ms = 0.f;
     bool same = false;
     rc = trial(c, &ms, &same);
@@ -2121,12 +2122,14 @@ int ci_autotune(ci_ctx* ctx, const ci_segment* seg, const ci_tparams* d_params, 
   // the FP32 second pass with wave-owned columns (n1 = 512 or 1024), at
   // both second-pass tile widths (its LDS and registers differ from the
   // other second pass's, so its best width may too)
-  for (int jw = 4; jw <= 8 && rc == CI_OK && precision == CI_FP32 && l2 >= 17 && l2 <= 20;
+  const int n1_of_l2 = plan_for(l2, 4, 4, CI_FP32).n1;
+  for (int jw = 4; jw <= 8 && rc == CI_OK && precision == CI_FP32 &&
+                   (n1_of_l2 == 512 || n1_of_l2 == 1024);
        jw += 4) {
     Tune c = best;
     c.p2_wave = 1;
     c.j = jw;
-    if (plan_fits(plan_for(l2, c.c, c.j), precision) != hipSuccess) continue;
+    if (plan_fits(plan_for(l2, c.c, c.j, precision), precision) != hipSuccess) continue;
     float ms = 0.f;
     bool same = false;
     rc = trial(c, &ms, &same);
@@ -2171,7 +2174,7 @@ int ci_autotune(ci_ctx* ctx, const ci_segment* seg, const ci_tparams* d_params, 
     const int64_t bs1[6] = {best.batch, b0, b0 * 2, b0 * 4, b0 * 8, b0 / 2};
     const int jws[2] = {best.j, best.j == 4 ? 8 : 4};
     for (int w = 0; w < 2 && rc == CI_OK; ++w) {
-      if (plan_fits(plan_for(l2, best.c, jws[w]), precision) != hipSuccess) continue;
+      if (plan_fits(plan_for(l2, best.c, jws[w], precision), precision) != hipSuccess) continue;
       for (int i = 0; i < 6 && rc == CI_OK; ++i) {
         if (bs1[i] < 0 || bs1[i] > 4096 || (bs1[i] > 0 && bs1[i] >= 2 * n)) continue;
         Tune c = best;

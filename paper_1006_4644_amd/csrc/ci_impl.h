@@ -31,7 +31,10 @@ struct Plan {
   int j;            // j2 columns per pass-2 workgroup
 };
 
-Plan plan_for(int log2n, int c, int j);
+// The factorisation n = n1 n2 of a length for a precision: square, or
+// n1 = 2 n2; at 2^21 the FP32 path takes n1 = n2 / 2 instead, so that its
+// second pass can hand each 1024-point column to one wave.
+Plan plan_for(int log2n, int c, int j, int precision);
 
 // Slot sets of the intermediate and of the trigger bookkeeping in flight:
 // batch b uses slot b % kSlots, so a batch's first pass can start while the

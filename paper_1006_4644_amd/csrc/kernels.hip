@@ -1894,7 +1894,7 @@ __global__ __launch_bounds__(kChiThreads) void k_chisq(const SegDev* __restrict_
 // host launchers
 // ---------------------------------------------------------------------------
 
-Plan plan_for(int log2n, int c, int j) {
+Plan plan_for(int log2n, int c, int j, int precision) {
   Plan p;
   p.log2n = log2n;
   switch (log2n) {
@@ -1903,7 +1903,13 @@ Plan plan_for(int log2n, int c, int j) {
     case 18: p.n1 = 512; p.n2 = 512; break;
     case 19: p.n1 = 1024; p.n2 = 512; break;
     case 20: p.n1 = 1024; p.n2 = 1024; break;
-    case 21: p.n1 = 2048; p.n2 = 1024; break;
+    case 21:
+      // FP32: 1024-point second-pass columns (wave-owned, ~5.0 TB/s against
+      // ~3.5 for 2048-point ones), 2048-point first-pass columns; the split
+      // paths keep 2048 x 1024, where their first pass is faster
+      p.n1 = precision == CI_FP32 ? 1024 : 2048;
+      p.n2 = precision == CI_FP32 ? 2048 : 1024;
+      break;
     default: p.n1 = p.n2 = 0;
   }
   p.c = (c == 4 || c == 8) ? c : 4;
@@ -2243,14 +2249,15 @@ struct Inst {
 };
 
 template <int C, int J, typename F>
-hipError_t dispatch_n(int log2n, F f) {
-  switch (log2n) {
+hipError_t dispatch_n(const Plan& p, F f) {
+  switch (p.log2n) {
     case 16: return f(Inst<256, 256, C, J>());
     case 17: return f(Inst<512, 256, C, J>());
     case 18: return f(Inst<512, 512, C, J>());
     case 19: return f(Inst<1024, 512, C, J>());
     case 20: return f(Inst<1024, 1024, C, J>());
-    case 21: return f(Inst<2048, 1024, C, J>());
+    case 21:
+      return p.n1 == 1024 ? f(Inst<1024, 2048, C, J>()) : f(Inst<2048, 1024, C, J>());
     default: return hipErrorInvalidValue;
   }
 }
@@ -2259,10 +2266,10 @@ hipError_t dispatch_n(int log2n, F f) {
 // workgroup (4 or 8 each).
 template <typename F>
 hipError_t dispatch(const Plan& p, F f) {
-  if (p.c == 4 && p.j == 4) return dispatch_n<4, 4>(p.log2n, f);
-  if (p.c == 4 && p.j == 8) return dispatch_n<4, 8>(p.log2n, f);
-  if (p.c == 8 && p.j == 4) return dispatch_n<8, 4>(p.log2n, f);
-  if (p.c == 8 && p.j == 8) return dispatch_n<8, 8>(p.log2n, f);
+  if (p.c == 4 && p.j == 4) return dispatch_n<4, 4>(p, f);
+  if (p.c == 4 && p.j == 8) return dispatch_n<4, 8>(p, f);
+  if (p.c == 8 && p.j == 4) return dispatch_n<8, 4>(p, f);
+  if (p.c == 8 && p.j == 8) return dispatch_n<8, 8>(p, f);
   return hipErrorInvalidValue;
 }
 

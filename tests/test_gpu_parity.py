@@ -388,7 +388,7 @@ def test_tile_shapes(ctx, tc, tj, log2n):
 
 
 @pytest.mark.parametrize("tj", [4, 8])
-@pytest.mark.parametrize("log2n", [17, 18, 19, 20])
+@pytest.mark.parametrize("log2n", [17, 18, 19, 20, 21])
 def test_second_pass_wave_columns(ctx, tj, log2n):
     """The FP32 second pass with wave-owned columns after its first stage
     (p2_wave) gives the default second pass's peaks and trigger lists bit
