@@ -1,9 +1,11 @@
 """The search without allocation (ci_find_triggers_noalloc, the library's
 fixed per-GPU scratch) against the ordinary search (ci_find_triggers, the
-context's workspaces), through the C ABI: two calls in a row, the second on
-a smaller input, each equal to the ordinary search bit for bit (the same
-kernels and arithmetic; only the batch size and the schedule differ, and
-no launch configuration changes the results)."""
+context's workspaces), through the C ABI: three calls in a row, each on a
+smaller input than the one before (2^21, where the scratch holds one
+template per batch and FP32 and the split paths factor the length
+differently, then 2^20 and 2^17), each equal to the ordinary search bit for
+bit (the same kernels and arithmetic; only the batch size and the schedule
+differ, and no launch configuration changes the results)."""
 import numpy as np
 import pytest
 
@@ -34,8 +36,8 @@ def test_noalloc_matches_find_triggers(gpu_lib, prec):
     import torch
     ctx = gpu_lib.context(0)
     cap = 1 << 14
-    # (samples, templates, window, merge); the second call is smaller
-    cases = [(1 << 20, 9, 4096, True), (1 << 17, 5, 1024, False)]
+    # (samples, templates, window, merge); each call smaller than the last
+    cases = [(1 << 21, 3, 4096, True), (1 << 20, 9, 4096, True), (1 << 17, 5, 1024, False)]
     for i, (n, count, W, merge) in enumerate(cases):
         seg, params = _case(ctx, n, count, 4100 + i)
         thr = 4.0
