@@ -429,6 +429,10 @@ __device__ __forceinline__ void st_nt(float2* p, float2 v) {
   __builtin_nontemporal_store(v.y, &p->y);
 }
 __device__ __forceinline__ void st_nt(unsigned* p, unsigned v) { __builtin_nontemporal_store(v, p); }
+typedef float f4s __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ void st_nt16(float2* p, f4s v) {
+  __builtin_nontemporal_store(v, reinterpret_cast<f4s*>(p));
+}
 __device__ __forceinline__ float2 ld_nt(const float2* p) {
   return make_float2(__builtin_nontemporal_load(&p->x), __builtin_nontemporal_load(&p->y));
 }
@@ -470,6 +474,27 @@ struct SrcSpa {
     return v;
   }
 };
+
+// Lane (c, t) of a first-pass workgroup of C N2 / 16 threads.  FP32 output:
+// columns c and c + 1 (c even) sit 16 lanes apart in one wave (lane bit 4
+// is the low bit of c), so that the store can pair them with one row swap;
+// each half wave still covers C consecutive columns of 32 / C consecutive
+// rows, as with the columns in lane order, so its LDS and memory accesses
+// touch the same addresses together.  FP16 output (4-byte stores, which
+// lose their coalescing when neighbouring lanes hold alternate columns):
+// the columns in lane order.
+template <int C, bool H>
+__device__ __forceinline__ void p1_lane(unsigned tid, unsigned& c, unsigned& t) {
+  if constexpr (H) {
+    c = tid % C;
+    t = tid / C;
+  } else {
+    constexpr unsigned CH = C / 2;
+    const unsigned l = tid & 63u, w = tid >> 6;
+    c = 2u * (l % CH) + ((l >> 4) & 1u);
+    t = w * (64u / C) + (l >> 5) * (16u / CH) + (l & 15u) / CH;
+  }
+}
 
 // Pass-1 body for one tile.  Q: number of stage-1 inputs per lane that can
 // be nonzero (m < Q), chosen per template from its upper band edge.
@@ -532,9 +557,27 @@ __device__ __forceinline__ void pass1_tile(const P1Args& a, const Src& src, int 
 #pragma unroll
     for (int r = 0; r < 16; ++r) st_nt(&yt[o + K::off(r) * C], f2h(x[r]));
   } else {
+    // Registers r and r + 1 hold rows off(r) and off(r) + D.  One row swap
+    // per component (lanes as p1_lane places them) gives the lane of the
+    // even column both columns' values of row off(r), and the lane 16 above
+    // it (the odd column) both of row off(r + 1): each stores 16 bytes
+    // (measured: pass 1 ~3 % faster than one 8-byte store per value).
+    constexpr int D = K::off(1) - K::off(0);
     float2* yt = a.y + (size_t)b * N + (size_t)tile * N2 * C;
+    float2* pb = yt + (o & ~1u) + ((c & 1u) ? D * C : 0);
 #pragma unroll
-    for (int r = 0; r < 16; ++r) st_nt(&yt[o + K::off(r) * C], x[r]);
+    for (int r = 0; r < 16; r += 2) {
+      const auto re = __builtin_amdgcn_permlane16_swap(__float_as_uint(x[r].x),
+                                                       __float_as_uint(x[r + 1].x), false, false);
+      const auto im = __builtin_amdgcn_permlane16_swap(__float_as_uint(x[r].y),
+                                                       __float_as_uint(x[r + 1].y), false, false);
+      f4s v;
+      v.x = __uint_as_float(re[0]);
+      v.y = __uint_as_float(im[0]);
+      v.z = __uint_as_float(re[1]);
+      v.w = __uint_as_float(im[1]);
+      st_nt16(pb + K::off(r) * C, v);
+    }
   }
 }
 
@@ -545,7 +588,8 @@ __global__ __launch_bounds__(C * N2 / 16) void k_pass1(P1Args a) {
   constexpr int TILES = N1 / C;
   extern __shared__ float2 lds[];
   const unsigned tid = threadIdx.x;
-  const unsigned c = tid % C, t = tid / C;
+  unsigned c, t;
+  p1_lane<C, H>(tid, c, t);
 
   if (a.wkeys) {
     const int64_t gid = blockIdx.x * (int64_t)blockDim.x + tid;
@@ -641,7 +685,8 @@ __global__ __launch_bounds__(C * N2 / 16) void k_pass1_mem(P1Args a) {
   constexpr int TILES = N1 / C;
   extern __shared__ float2 lds[];
   const unsigned tid = threadIdx.x;
-  const unsigned c = tid % C, t = tid / C;
+  unsigned c, t;
+  p1_lane<C, false>(tid, c, t);
 
   if (a.wkeys) {
     const int64_t gid = blockIdx.x * (int64_t)blockDim.x + tid;
