@@ -453,6 +453,10 @@ __device__ __forceinline__ float2 buf_ld_nt(__amdgpu_buffer_rsrc_t r, unsigned v
 __device__ __forceinline__ unsigned buf_ld(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
   return __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0);
 }
+// 16 bytes at voff + soff (non-temporal).
+__device__ __forceinline__ f4s buf_ld16_nt(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+  return __builtin_bit_cast(f4s, __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, (int)soff, 2));
+}
 
 // w_N^e for 0 <= e < N from the two-level table.
 __device__ __forceinline__ float2 tw_n(const float2* __restrict__ twa,
@@ -1072,6 +1076,39 @@ __device__ __forceinline__ void load_item(float2 (&x)[16], const P2Args& a, int 
   for (int q = 0; q < 16; ++q) x[q] = buf_ld_nt(r, voff, q * QS);
 }
 
+// load_item in 16-byte loads, for lanes placed by p2w_lane: the lane of
+// row t (t even) loads rows t and t + 1 of register q, the lane 16 above it
+// (row t + 1) the same two rows of register q + 1, q even; voff =
+// p2_lane_off(cc, t & ~1) + (t & 1) QS.  The values stay as loaded, so that
+// a prefetch does not wait for them; unpair_item hands each lane its own.
+template <int N1, int N2, int C, int J>
+__device__ __forceinline__ void load_item_pairs(f4s (&v)[8], const P2Args& a, int item,
+                                                unsigned voff) {
+  constexpr int N = N1 * N2;
+  constexpr int TILES = N2 / J;
+  constexpr unsigned QS = (N1 / 16) * N2 * (unsigned)sizeof(float2);
+  const int b = item / TILES, tile = item % TILES;
+  const unsigned first = (unsigned)tile * J * C;
+  const __amdgpu_buffer_rsrc_t r =
+      buf_rsrc(a.y + (size_t)b * N + first, (N - first) * (unsigned)sizeof(float2));
+#pragma unroll
+  for (int i = 0; i < 8; ++i) v[i] = buf_ld16_nt(r, voff, 2 * i * QS);
+}
+// One row swap per component: the lane of row t keeps (t, q) and receives
+// (t, q + 1); the lane of row t + 1 receives (t + 1, q) and keeps
+// (t + 1, q + 1).
+__device__ __forceinline__ void unpair_item(const f4s (&v)[8], float2 (&x)[16]) {
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const auto re = __builtin_amdgcn_permlane16_swap(__float_as_uint(v[i].x),
+                                                     __float_as_uint(v[i].z), false, false);
+    const auto im = __builtin_amdgcn_permlane16_swap(__float_as_uint(v[i].y),
+                                                     __float_as_uint(v[i].w), false, false);
+    x[2 * i] = make_float2(__uint_as_float(re[0]), __uint_as_float(im[0]));
+    x[2 * i + 1] = make_float2(__uint_as_float(re[1]), __uint_as_float(im[1]));
+  }
+}
+
 // Post-pass of one pass-2 tile (workgroup of NW waves).  r2[i], i < K, are
 // this lane's |z|^2 values (-1 outside the search range) in increasing
 // sample index j = jof(i).  Samples above the threshold raise their
@@ -1246,8 +1283,11 @@ __device__ __forceinline__ void wave_lds_sync() { asm volatile("s_waitcnt lgkmcn
 // ---------------------------------------------------------------------------
 // The column DFT of k_pass2_trig with the same arithmetic in the same order,
 // laid out so that only one exchange crosses waves.  Lanes load and run
-// stage 1 as there (column cc = tid % J, t = tid / J: coalesced 512-byte
-// reads of the intermediate).  The exchange after stage 1 hands every
+// stage 1 on (column cc, row t) as there, with rows t and t + 1 placed 16
+// lanes apart so that the intermediate is read in 16-byte loads (a wave's
+// load covers the same whole runs of J x C contiguous elements as 8-byte
+// loads in lane order, for two registers at once; measured: that pass ~3 %
+// faster).  The exchange after stage 1 hands every
 // column to Lp consecutive lanes of one wave (cb = tid / Lp, tb = tid %
 // Lp); the exchange between stage 2 and the radix-R3 stage then stays
 // inside the wave (its own column's LDS, no workgroup barrier), and the
@@ -1278,7 +1318,13 @@ __global__ __launch_bounds__(J * N1 / 16, 4) void k_pass2w(P2Args a) {
   constexpr int TILES = N2 / J;
   extern __shared__ float2 lds[];
   const unsigned tid = threadIdx.x;
-  const unsigned cc = tid % J, t = tid / J;         // load / stage-1 layout
+  // load / stage-1 layout: column cc, row t, with rows t and t + 1 (t
+  // even) 16 lanes apart in one wave and each half wave covering J
+  // columns of 32 / J consecutive rows (as with the columns in lane order)
+  const unsigned l64 = tid & 63u;
+  const unsigned cc = l64 % J;
+  const unsigned t = (tid >> 6) * (64u / J) + ((l64 >> 4) & 1u) +
+                     2u * ((l64 / J) & (16u / J - 1u)) + (l64 >> 5) * (32u / J);
   const unsigned cb = tid / Lp, tb = tid % Lp;      // stage-2 / stage-3 layout
   const unsigned a0 = tb / R3, s2 = tb % R3;
   const unsigned lane = tid & 63, wave = tid >> 6;
@@ -1368,16 +1414,16 @@ __global__ __launch_bounds__(J * N1 / 16, 4) void k_pass2w(P2Args a) {
     wave_post<16>(r2, jof, a, b, ((size_t)b * TILES + tile) * W::NW + wave, lane);
   };
 
-  const unsigned voff = p2_lane_off<N1, N2, C>(cc, t);
-  float2 xn[16];
+  constexpr unsigned QS = Lp * N2 * (unsigned)sizeof(float2);
+  const unsigned voff = p2_lane_off<N1, N2, C>(cc, t & ~1u) + (t & 1u) * QS;
+  f4s vn[8];
   const int G = gridDim.x;
   int item = blockIdx.x;
-  if (item < total) load_item<N1, N2, C, J>(xn, a, item, voff);
+  if (item < total) load_item_pairs<N1, N2, C, J>(vn, a, item, voff);
   for (; item < total; item += G) {
     float2 x[16];
-#pragma unroll
-    for (int r = 0; r < 16; ++r) x[r] = xn[r];
-    if (item + G < total) load_item<N1, N2, C, J>(xn, a, item + G, voff);
+    unpair_item(vn, x);
+    if (item + G < total) load_item_pairs<N1, N2, C, J>(vn, a, item + G, voff);
     tile_body(x, item);
   }
 }
