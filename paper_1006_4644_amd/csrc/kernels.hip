@@ -479,17 +479,23 @@ struct SrcSpa {
   }
 };
 
-// Lane (c, t) of a first-pass workgroup of C N2 / 16 threads.  FP32 output:
-// columns c and c + 1 (c even) sit 16 lanes apart in one wave (lane bit 4
-// is the low bit of c), so that the store can pair them with one row swap;
-// each half wave still covers C consecutive columns of 32 / C consecutive
-// rows, as with the columns in lane order, so its LDS and memory accesses
-// touch the same addresses together.  FP16 output (4-byte stores, which
-// lose their coalescing when neighbouring lanes hold alternate columns):
-// the columns in lane order.
-template <int C, bool H>
+// Output forms of the first pass: FP16 pairs (one 4-byte store per value),
+// FP32 (one 8-byte store per value) and FP32 in 16-byte stores of two
+// columns' values.
+enum P1Out { kOutF16 = 0, kOutF32 = 1, kOutF32Pair = 2 };
+
+// Lane (c, t) of a first-pass workgroup of C N2 / 16 threads.  Paired FP32
+// output: columns c and c + 1 (c even) sit 16 lanes apart in one wave (lane
+// bit 4 is the low bit of c), so that the store can pair them with one row
+// swap; each half wave still covers C consecutive columns of 32 / C
+// consecutive rows, as with the columns in lane order, so its LDS and
+// memory accesses touch the same addresses together.  Otherwise the
+// columns in lane order: 4-byte FP16 stores lose their coalescing when
+// neighbouring lanes hold alternate columns, and so do the scattered 8-byte
+// loads of the two-polarization correlator.
+template <int C, int OUT>
 __device__ __forceinline__ void p1_lane(unsigned tid, unsigned& c, unsigned& t) {
-  if constexpr (H) {
+  if constexpr (OUT != kOutF32Pair) {
     c = tid % C;
     t = tid / C;
   } else {
@@ -503,7 +509,7 @@ __device__ __forceinline__ void p1_lane(unsigned tid, unsigned& c, unsigned& t) 
 // Pass-1 body for one tile.  Q: number of stage-1 inputs per lane that can
 // be nonzero (m < Q), chosen per template from its upper band edge.
 // src(k) gives the input Z_k.
-template <int N1, int N2, int C, int Q, bool H, class Src>
+template <int N1, int N2, int C, int Q, int OUT, class Src>
 __device__ __forceinline__ void pass1_tile(const P1Args& a, const Src& src, int b, int tile,
                                            float2* lds, const float2* twl, unsigned t,
                                            unsigned c) {
@@ -556,10 +562,14 @@ __device__ __forceinline__ void pass1_tile(const P1Args& a, const Src& src, int 
   }
 
   const unsigned o = t * C + c;
-  if constexpr (H) {
+  if constexpr (OUT == kOutF16) {
     unsigned* yt = reinterpret_cast<unsigned*>(a.y) + (size_t)b * N + (size_t)tile * N2 * C;
 #pragma unroll
     for (int r = 0; r < 16; ++r) st_nt(&yt[o + K::off(r) * C], f2h(x[r]));
+  } else if constexpr (OUT == kOutF32) {
+    float2* yt = a.y + (size_t)b * N + (size_t)tile * N2 * C;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) st_nt(&yt[o + K::off(r) * C], x[r]);
   } else {
     // Registers r and r + 1 hold rows off(r) and off(r) + D.  One row swap
     // per component (lanes as p1_lane places them) gives the lane of the
@@ -592,8 +602,9 @@ __global__ __launch_bounds__(C * N2 / 16) void k_pass1(P1Args a) {
   constexpr int TILES = N1 / C;
   extern __shared__ float2 lds[];
   const unsigned tid = threadIdx.x;
+  constexpr int OUT = H ? kOutF16 : kOutF32Pair;
   unsigned c, t;
-  p1_lane<C, H>(tid, c, t);
+  p1_lane<C, OUT>(tid, c, t);
 
   if (a.wkeys) {
     const int64_t gid = blockIdx.x * (int64_t)blockDim.x + tid;
@@ -615,9 +626,9 @@ __global__ __launch_bounds__(C * N2 / 16) void k_pass1(P1Args a) {
   // m <= (k_high / N1) / Lp.  The choice is uniform over the workgroup.
   const int mneed = P.k_high >= P.k_low ? (P.k_high / N1) / Lp + 1 : 1;
   const SrcSpa src{P, a.w};
-  if (mneed <= 2) pass1_tile<N1, N2, C, 2, H>(a, src, b, tile, lds, twl, t, c);
-  else if (mneed <= 4) pass1_tile<N1, N2, C, 4, H>(a, src, b, tile, lds, twl, t, c);
-  else pass1_tile<N1, N2, C, 8, H>(a, src, b, tile, lds, twl, t, c);
+  if (mneed <= 2) pass1_tile<N1, N2, C, 2, OUT>(a, src, b, tile, lds, twl, t, c);
+  else if (mneed <= 4) pass1_tile<N1, N2, C, 4, OUT>(a, src, b, tile, lds, twl, t, c);
+  else pass1_tile<N1, N2, C, 8, OUT>(a, src, b, tile, lds, twl, t, c);
 }
 
 // ---------------------------------------------------------------------------
@@ -689,8 +700,11 @@ __global__ __launch_bounds__(C * N2 / 16) void k_pass1_mem(P1Args a) {
   constexpr int TILES = N1 / C;
   extern __shared__ float2 lds[];
   const unsigned tid = threadIdx.x;
+  // the correlator (MODE 1) reads three scattered values per bin: columns
+  // in lane order, 8-byte stores
+  constexpr int OUT = MODE == 1 ? kOutF32 : kOutF32Pair;
   unsigned c, t;
-  p1_lane<C, false>(tid, c, t);
+  p1_lane<C, OUT>(tid, c, t);
 
   if (a.wkeys) {
     const int64_t gid = blockIdx.x * (int64_t)blockDim.x + tid;
@@ -714,10 +728,10 @@ __global__ __launch_bounds__(C * N2 / 16) void k_pass1_mem(P1Args a) {
   }
   const float2* vb = a.uv + (size_t)b * N;
   if constexpr (MODE == 0) {
-    pass1_tile<N1, N2, C, 16, false>(a, SrcMem{vb}, b, tile, lds, twl, t, c);
+    pass1_tile<N1, N2, C, 16, OUT>(a, SrcMem{vb}, b, tile, lds, twl, t, c);
   } else if constexpr (MODE == 2) {
     const ci_tdparams& T = a.tdp[b];
-    pass1_tile<N1, N2, C, 16, false>(a, SrcGen{T, (int64_t)N, a.sd->fs}, b, tile, lds, twl, t,
+    pass1_tile<N1, N2, C, 16, OUT>(a, SrcGen{T, (int64_t)N, a.sd->fs}, b, tile, lds, twl, t,
                                      c);
   } else {
     // sigma^2 sums in a fixed order
@@ -733,7 +747,7 @@ __global__ __launch_bounds__(C * N2 / 16) void k_pass1_mem(P1Args a) {
     const float ap = live ? (float)(0.5 * sqrt(4.0 * df / sp) / g) : 0.f;
     const float ac = live ? (float)(0.5 * sqrt(4.0 * df / sc) / g) : 0.f;
     const SrcTd src{vb, a.w0, ap, ac, T.k_low, N / 2, N};
-    pass1_tile<N1, N2, C, 16, false>(a, src, b, tile, lds, twl, t, c);
+    pass1_tile<N1, N2, C, 16, OUT>(a, src, b, tile, lds, twl, t, c);
   }
 }
 
