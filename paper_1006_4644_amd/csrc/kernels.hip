@@ -492,18 +492,20 @@ enum P1Out { kOutF16 = 0, kOutF32 = 1, kOutF32Pair = 2 };
 // memory accesses touch the same addresses together.  Otherwise the
 // columns in lane order: 4-byte FP16 stores lose their coalescing when
 // neighbouring lanes hold alternate columns, and so do the scattered 8-byte
-// loads of the two-polarization correlator.
+// loads of the two-polarization correlator.  Returned as values (through
+// out-parameters the FP16 pass lost its stores' constant offsets: 99
+// registers instead of 75).
 template <int C, int OUT>
-__device__ __forceinline__ void p1_lane(unsigned tid, unsigned& c, unsigned& t) {
-  if constexpr (OUT != kOutF32Pair) {
-    c = tid % C;
-    t = tid / C;
-  } else {
-    constexpr unsigned CH = C / 2;
-    const unsigned l = tid & 63u, w = tid >> 6;
-    c = 2u * (l % CH) + ((l >> 4) & 1u);
-    t = w * (64u / C) + (l >> 5) * (16u / CH) + (l & 15u) / CH;
-  }
+__device__ __forceinline__ unsigned p1_col(unsigned tid) {
+  if constexpr (OUT != kOutF32Pair) return tid % C;
+  const unsigned l = tid & 63u;
+  return 2u * (l % (C / 2)) + ((l >> 4) & 1u);
+}
+template <int C, int OUT>
+__device__ __forceinline__ unsigned p1_row(unsigned tid) {
+  if constexpr (OUT != kOutF32Pair) return tid / C;
+  const unsigned l = tid & 63u;
+  return (tid >> 6) * (64u / C) + (l >> 5) * (32u / C) + (l & 15u) / (C / 2);
 }
 
 // Pass-1 body for one tile.  Q: number of stage-1 inputs per lane that can
@@ -572,7 +574,7 @@ __device__ __forceinline__ void pass1_tile(const P1Args& a, const Src& src, int 
     for (int r = 0; r < 16; ++r) st_nt(&yt[o + K::off(r) * C], x[r]);
   } else {
     // Registers r and r + 1 hold rows off(r) and off(r) + D.  One row swap
-    // per component (lanes as p1_lane places them) gives the lane of the
+    // per component (lanes as p1_col and p1_row place them) gives the lane of the
     // even column both columns' values of row off(r), and the lane 16 above
     // it (the odd column) both of row off(r + 1): each stores 16 bytes
     // (measured: pass 1 ~3 % faster than one 8-byte store per value).
@@ -603,8 +605,7 @@ __global__ __launch_bounds__(C * N2 / 16) void k_pass1(P1Args a) {
   extern __shared__ float2 lds[];
   const unsigned tid = threadIdx.x;
   constexpr int OUT = H ? kOutF16 : kOutF32Pair;
-  unsigned c, t;
-  p1_lane<C, OUT>(tid, c, t);
+  const unsigned c = p1_col<C, OUT>(tid), t = p1_row<C, OUT>(tid);
 
   if (a.wkeys) {
     const int64_t gid = blockIdx.x * (int64_t)blockDim.x + tid;
@@ -703,8 +704,7 @@ __global__ __launch_bounds__(C * N2 / 16) void k_pass1_mem(P1Args a) {
   // the correlator (MODE 1) reads three scattered values per bin: columns
   // in lane order, 8-byte stores
   constexpr int OUT = MODE == 1 ? kOutF32 : kOutF32Pair;
-  unsigned c, t;
-  p1_lane<C, OUT>(tid, c, t);
+  const unsigned c = p1_col<C, OUT>(tid), t = p1_row<C, OUT>(tid);
 
   if (a.wkeys) {
     const int64_t gid = blockIdx.x * (int64_t)blockDim.x + tid;
