@@ -1726,11 +1726,13 @@ __global__ __launch_bounds__(J * N1 / 16) void k_pass2_series(P2Args a) {
   load_pass2<N1, N2, C, J>(x, yb, j2, t);
   fft_col<N1, J>(x, lds, t, cc, a.tw);
 
+  // non-temporal like the intermediate (a batch of series outlasts every
+  // cache; measured: the two-polarization form 1 % faster)
   float2* zt = a.z + (size_t)b * N;
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
     const int j1 = Col<N1, J>::out(t, r);
-    zt[j2 + N2 * j1] = x[r];
+    st_nt(&zt[j2 + N2 * j1], x[r]);
   }
 }
 
