@@ -623,7 +623,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the search "
-              "shards by template bank across GPUs, but this build measures one "
+              "shards by template bank across GPUs; the benchmark measures one "
               "GPU's share.", file=sys.stderr)
         sys.exit(2)
 
