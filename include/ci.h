@@ -71,7 +71,7 @@ extern "C" {
 #define CI_ENOMEM (-2)        /* device or host allocation failed          */
 #define CI_EHIP (-3)          /* a HIP runtime call or launch failed       */
 #define CI_ETRUNC (-4)        /* capacity overflow seen on the host       */
-#define CI_EUNSUPPORTED (-5)  /* valid request this build does not handle  */
+#define CI_EUNSUPPORTED (-5)  /* valid request the library does not handle */
 
 /* arithmetic of the inverse transform */
 #define CI_FP32 0        /* FP32 VALU butterflies, FP32 intermediate        */
